@@ -1,0 +1,206 @@
+/*
+ * magnus.h -- C ABI of a gfx950 (MI355X) sparse matrix-matrix product
+ * C = A * B in CSR, by Gustavson's row-wise method with the intermediate
+ * products of long rows reordered into column chunks whose accumulators fit
+ * the 160 KiB of LDS of a compute unit (MAGNUS, ICS '25).
+ *
+ * Problem statement (Section 2.1, Eq. 1): row i of C is the sum over the
+ * stored entries (i, j) of A of A_ij times row j of B.  Matrices are CSR
+ * (Section 2.1): rowptr (n + 1 entries), col and val (nnz entries each).
+ *
+ * Conventions for every call:
+ *   - Every pointer inside a magnus_csr_t / magnus_csr_out_t is a DEVICE
+ *     pointer on the handle's device.  Host pointers are named as such.
+ *   - The caller owns A, B and C's buffers; the library never frees them.
+ *     Device memory the library needs for a plan is obtained through the
+ *     handle's allocator (magnus_set_allocator; default hipMalloc/hipFree)
+ *     and released by magnus_plan_destroy.
+ *   - Work is ordered on the stream passed in.  magnus_plan and
+ *     magnus_execute synchronise that stream once each (to read back sizes).
+ *   - Nothing throws across the ABI; each call returns a magnus_status_t.
+ *     On MAGNUS_ERR_HIP, magnus_last_error(h) holds the HIP error text.
+ *   - A handle is not thread safe; use one handle per host thread.
+ *
+ * Semantics of C (readings of the paper recorded with the implementation):
+ *   - C's rows list strictly ascending columns;
+ *   - a column present in the structure of a row is kept even when its
+ *     value sums to zero (the structure is that of the dense accumulator's
+ *     bitmap, Algorithm 1); stored zeros of A or B count as structure;
+ *   - every sum starts at +0.0, so no entry of C is -0.0;
+ *   - B's rows must list strictly ascending columns (validated only when
+ *     magnus_options_t.validate is set);
+ *   - C.val has A's and B's value type; C.col has B's column type; C's row
+ *     pointer type is the caller's choice (int64 is required once nnz(C) or a
+ *     row offset reaches 2^31).
+ */
+#ifndef MAGNUS_H
+#define MAGNUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MAGNUS_OK = 0,
+  MAGNUS_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad enum */
+  MAGNUS_ERR_SHAPE = 2,          /* A.ncols != B.nrows, or C's shape wrong */
+  MAGNUS_ERR_DTYPE = 3,          /* mixed value / index types */
+  MAGNUS_ERR_INVALID_CSR = 4,    /* only with options.validate */
+  MAGNUS_ERR_INDEX_OVERFLOW = 5, /* nnz(C) does not fit C's row pointer type */
+  MAGNUS_ERR_CAPACITY = 6,       /* C.capacity < nnz(C); *nnz_out = nnz(C) */
+  MAGNUS_ERR_WORKSPACE = 7,      /* caller workspace too small */
+  MAGNUS_ERR_OOM = 8,            /* the allocator returned null */
+  MAGNUS_ERR_REJECTED = 9,       /* server: request can never fit */
+  MAGNUS_ERR_HIP = 10,           /* a HIP call failed; see magnus_last_error */
+  MAGNUS_ERR_NOT_READY = 11,     /* server: result not complete yet */
+  MAGNUS_ERR_INTERNAL = 12       /* a device-side consistency check failed */
+} magnus_status_t;
+
+typedef enum { MAGNUS_I32 = 0, MAGNUS_I64 = 1 } magnus_itype_t;
+typedef enum { MAGNUS_F32 = 0, MAGNUS_F64 = 1 } magnus_vtype_t;
+
+/* Row categories (Section 3.1): SORT rows are accumulated by sorting their
+ * intermediate product (expand-sort-compress, Algorithm 2), DENSE rows by a
+ * dense accumulator over the row's column range (Algorithm 1), CHUNKED rows
+ * by reordering into column chunks first (Algorithm 3) then accumulating each
+ * chunk.  EMPTY rows form no product. */
+typedef enum {
+  MAGNUS_CAT_AUTO = -1,
+  MAGNUS_CAT_SORT = 0,
+  MAGNUS_CAT_DENSE = 1,
+  MAGNUS_CAT_CHUNKED = 2,
+  MAGNUS_CAT_EMPTY = 3
+} magnus_category_t;
+
+/* Input CSR descriptor (device pointers, read only). */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  int32_t rowptr_type; /* magnus_itype_t */
+  int32_t col_type;    /* magnus_itype_t */
+  int32_t val_type;    /* magnus_vtype_t */
+  int32_t _pad;
+  const void* rowptr;
+  const void* col;
+  const void* val;
+} magnus_csr_t;
+
+/* Output CSR descriptor (device pointers, caller-allocated).  rowptr holds
+ * nrows + 1 entries of rowptr_type; col/val hold capacity entries. */
+typedef struct {
+  int64_t nrows, ncols, capacity;
+  int32_t rowptr_type;
+  int32_t col_type;
+  int32_t val_type;
+  int32_t _pad;
+  void* rowptr;
+  void* col;
+  void* val;
+} magnus_csr_out_t;
+
+/* Tuning and behaviour.  magnus_options_default() fills the defaults; a zero
+ * or negative field means "chosen by the chunk-count model". */
+typedef struct {
+  int32_t force_category; /* MAGNUS_CAT_AUTO or a category for all non-empty rows */
+  int32_t sort_max;       /* rows with ip < sort_max are SORT rows (<= 1024) */
+  int32_t chunk_shift;    /* log2 of the chunk length of CHUNKED rows (<= 16) */
+  int32_t bin_dense_min;  /* a chunk with >= this many products uses the dense accumulator */
+  int32_t tile_products;  /* products per binning tile (power of two, 512..8192) */
+  int32_t dense_block;    /* threads per dense-accumulator workgroup (256, 512, 1024) */
+  int64_t batch_products; /* products per row batch of CHUNKED rows (0: from workspace cap) */
+  int64_t max_workspace_bytes; /* cap on the plan's device memory (0: 40% of free memory) */
+  int32_t validate;       /* 1: check CSR invariants of A and B (one extra pass) */
+  int32_t lds_bytes;      /* LDS budget per workgroup (0: device maximum) */
+  int32_t sort_group_max; /* products per packed sort group of small chunks (<= 1024) */
+  int32_t _reserved[5];
+} magnus_options_t;
+
+/* Sizes the plan reports (host struct). */
+typedef struct {
+  int64_t ip_total;        /* intermediate products, sum over (i,j) in A of nnz(B_j) */
+  int64_t flops;           /* 2 * ip_total */
+  int64_t nnz_c;           /* exact nnz of C (precise symbolic phase) */
+  int64_t max_row_ip;
+  int64_t rows_by_category[4]; /* SORT, DENSE, CHUNKED, EMPTY */
+  int64_t ip_by_category[4];
+  int64_t n_batches;       /* row batches of CHUNKED rows */
+  int64_t n_bins;          /* chunks (bins) over all CHUNKED rows */
+  int64_t plan_bytes;      /* device memory held by the plan */
+  int32_t chunk_shift;     /* chosen chunk length = 2^chunk_shift */
+  int32_t sort_max;
+  int32_t bin_dense_min;
+  int32_t tile_products;
+  double symbolic_ms;      /* device time of the symbolic phase (events) */
+} magnus_plan_info_t;
+
+typedef struct magnus_handle_s* magnus_handle_t;
+typedef struct magnus_plan_s* magnus_plan_t;
+
+/* Allocator: alloc(bytes, stream, ctx) returns device memory or NULL;
+ * free(ptr, bytes, stream, ctx) releases it. */
+typedef void* (*magnus_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*magnus_free_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
+
+const char* magnus_status_string(magnus_status_t s);
+const char* magnus_last_error(magnus_handle_t h);
+void magnus_options_default(magnus_options_t* opts);
+
+/* Lifecycle.  device: HIP device ordinal; opts may be NULL (defaults). */
+magnus_status_t magnus_create(magnus_handle_t* h, int device, const magnus_options_t* opts);
+magnus_status_t magnus_destroy(magnus_handle_t h);
+magnus_status_t magnus_set_options(magnus_handle_t h, const magnus_options_t* opts);
+magnus_status_t magnus_set_allocator(magnus_handle_t h, magnus_alloc_fn alloc, magnus_free_fn free_,
+                                     void* ctx);
+
+/* Plan: the setup phase (chunk-count model, intermediate-product count per
+ * row, categorisation; Section 3.1) and the precise symbolic phase (exact
+ * nnz of every row of C followed by a prefix sum; Section 2.1).  Synchronises
+ * `stream` once.  On success *plan owns device memory until
+ * magnus_plan_destroy; A and B must stay unchanged until then.  info may be
+ * NULL. */
+magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                            void* stream, magnus_plan_t* plan, magnus_plan_info_t* info);
+
+/* Numeric phase: writes C.rowptr, C.col, C.val (C.capacity >= info.nnz_c,
+ * C.nrows == A.nrows, C.ncols == B.ncols).  *nnz_out (host) receives nnz(C).
+ * Returns MAGNUS_ERR_CAPACITY (nothing written) when capacity is short.
+ * Does not synchronise the stream. */
+magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t plan, const magnus_csr_t* A,
+                               const magnus_csr_t* B, const magnus_csr_out_t* C, int64_t* nnz_out,
+                               void* stream);
+
+magnus_status_t magnus_plan_destroy(magnus_plan_t plan);
+magnus_status_t magnus_plan_get_info(magnus_plan_t plan, magnus_plan_info_t* info);
+
+/* Intermediate-product count per row (the setup phase's per-row count,
+ * Section 3.1 / n_interProd of Section 4.3).  ip_out: device int64[A.nrows];
+ * *ip_total (host) receives the sum.  Synchronises the stream. */
+magnus_status_t magnus_row_ip(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                              int64_t* ip_out, int64_t* ip_total, void* stream);
+
+/* Chunk-count model (Section 3.5, Eqs. 2-7) evaluated as printed, for any
+ * cache size: m_c columns, s_cache the cache the fine-level structures must
+ * fit, s_line the cache line, s_dense_accum bytes per accumulator column.
+ * Host only.  Outputs: fine chunk count, coarse chunk count, m_CmaxL2. */
+magnus_status_t magnus_paper_chunk_model(int64_t m_c, int64_t s_cache, int64_t s_line,
+                                         double s_dense_accum, int64_t* n_chunks_fine,
+                                         int64_t* n_chunks_coarse, int64_t* m_cmax);
+
+/* The gfx950 chunk length: the largest power-of-two column range whose dense
+ * accumulator (values plus one bitmap bit per column) fits lds_bytes, capped
+ * at 2^16 so chunk-local columns fit 16 bits.  Host only. */
+magnus_status_t magnus_gpu_chunk_shift(int32_t val_type, int64_t lds_bytes, int32_t* shift);
+
+/* Building block: exclusive prefix sum of n int64 values (device in/out, may
+ * alias).  *total (host, may be NULL) receives the sum; synchronises only
+ * when total is requested. */
+magnus_status_t magnus_exclusive_scan_i64(magnus_handle_t h, const int64_t* in, int64_t* out,
+                                          int64_t n, int64_t* total, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAGNUS_H */

@@ -1,0 +1,120 @@
+"""ctypes declarations of the C ABI in include/magnus.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmagnus.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "magnus.h")
+
+c_i64 = ctypes.c_int64
+c_i32 = ctypes.c_int32
+c_vp = ctypes.c_void_p
+
+
+class CsrDesc(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("nnz", c_i64),
+                ("rowptr_type", c_i32), ("col_type", c_i32), ("val_type", c_i32), ("_pad", c_i32),
+                ("rowptr", c_vp), ("col", c_vp), ("val", c_vp)]
+
+
+class CsrOutDesc(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("capacity", c_i64),
+                ("rowptr_type", c_i32), ("col_type", c_i32), ("val_type", c_i32), ("_pad", c_i32),
+                ("rowptr", c_vp), ("col", c_vp), ("val", c_vp)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("force_category", c_i32), ("sort_max", c_i32), ("chunk_shift", c_i32),
+                ("bin_dense_min", c_i32), ("tile_products", c_i32), ("dense_block", c_i32),
+                ("batch_products", c_i64), ("max_workspace_bytes", c_i64), ("validate", c_i32),
+                ("lds_bytes", c_i32), ("sort_group_max", c_i32), ("_reserved", c_i32 * 5)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("ip_total", c_i64), ("flops", c_i64), ("nnz_c", c_i64), ("max_row_ip", c_i64),
+                ("rows_by_category", c_i64 * 4), ("ip_by_category", c_i64 * 4),
+                ("n_batches", c_i64), ("n_bins", c_i64), ("plan_bytes", c_i64),
+                ("chunk_shift", c_i32), ("sort_max", c_i32), ("bin_dense_min", c_i32),
+                ("tile_products", c_i32), ("symbolic_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, ctypes.c_size_t, c_vp, c_vp)
+FREE_FN = ctypes.CFUNCTYPE(None, c_vp, ctypes.c_size_t, c_vp, c_vp)
+
+STATUS = {}
+_lib = None
+
+
+def _parse_status():
+    src = open(HEADER).read()
+    for name, val in re.findall(r"(MAGNUS_(?:OK|ERR_[A-Z_]+))\s*=\s*(\d+)", src):
+        STATUS[int(val)] = name
+
+
+def declared_symbols():
+    """Function names declared in include/magnus.h."""
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(magnus_[a-z0-9_]+)\s*\(", src)))
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.magnus_status_string.argtypes = [c_i32]
+    lib.magnus_status_string.restype = ctypes.c_char_p
+    lib.magnus_last_error.argtypes = [c_vp]
+    lib.magnus_last_error.restype = ctypes.c_char_p
+    lib.magnus_options_default.argtypes = [P(Options)]
+    lib.magnus_options_default.restype = None
+    lib.magnus_create.argtypes = [P(c_vp), c_i32, P(Options)]
+    lib.magnus_destroy.argtypes = [c_vp]
+    lib.magnus_set_options.argtypes = [c_vp, P(Options)]
+    lib.magnus_set_allocator.argtypes = [c_vp, ALLOC_FN, FREE_FN, c_vp]
+    lib.magnus_plan.argtypes = [c_vp, P(CsrDesc), P(CsrDesc), c_vp, P(c_vp), P(PlanInfo)]
+    lib.magnus_execute.argtypes = [c_vp, c_vp, P(CsrDesc), P(CsrDesc), P(CsrOutDesc), P(c_i64),
+                                   c_vp]
+    lib.magnus_plan_destroy.argtypes = [c_vp]
+    lib.magnus_plan_get_info.argtypes = [c_vp, P(PlanInfo)]
+    lib.magnus_row_ip.argtypes = [c_vp, P(CsrDesc), P(CsrDesc), c_vp, P(c_i64), c_vp]
+    lib.magnus_paper_chunk_model.argtypes = [c_i64, c_i64, c_i64, ctypes.c_double, P(c_i64),
+                                             P(c_i64), P(c_i64)]
+    lib.magnus_gpu_chunk_shift.argtypes = [c_i32, c_i64, P(c_i32)]
+    lib.magnus_exclusive_scan_i64.argtypes = [c_vp, c_vp, c_vp, c_i64, P(c_i64), c_vp]
+    for fn in declared_symbols():
+        f = getattr(lib, fn)
+        if fn not in ("magnus_status_string", "magnus_last_error", "magnus_options_default"):
+            f.restype = c_i32
+    _parse_status()
+    _lib = lib
+    return lib
+
+
+class MagnusError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{where}: {self.name}" + (f" ({detail})" if detail else ""))
+
+
+def check(code: int, where: str, handle=None):
+    if code != 0:
+        detail = ""
+        if handle is not None and code == 10:
+            detail = (load().magnus_last_error(handle) or b"").decode(errors="replace")
+        raise MagnusError(code, where, detail)

@@ -1,0 +1,217 @@
+"""Python binding of the C ABI: torch tensors in and out, every step of the
+product runs in the HIP library.  torch provides device memory (through the
+library's allocator hook) and streams."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import CsrDesc, CsrOutDesc, Options, PlanInfo, check
+
+_ITYPE = {torch.int32: 0, torch.int64: 1}
+_VTYPE = {torch.float32: 0, torch.float64: 1}
+CATEGORY = {"auto": -1, "sort": 0, "dense": 1, "chunked": 2}
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix in device memory: rowptr (int32/int64), col (int32/int64),
+    val (float32/float64)."""
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_host(cls, M, device="cuda:0"):
+        """From any object with nrows, ncols and numpy rowptr/col/val."""
+        rp = torch.from_numpy(M.rowptr).to(device)
+        col = torch.from_numpy(M.col).to(device)
+        val = torch.from_numpy(M.val).to(device)
+        return cls(int(M.nrows), int(M.ncols), rp, col, val)
+
+    def desc(self) -> CsrDesc:
+        d = CsrDesc()
+        d.nrows, d.ncols, d.nnz = self.nrows, self.ncols, self.nnz
+        d.rowptr_type = _ITYPE[self.rowptr.dtype]
+        d.col_type = _ITYPE[self.col.dtype]
+        d.val_type = _VTYPE[self.val.dtype]
+        d.rowptr = self.rowptr.data_ptr()
+        d.col = self.col.data_ptr() if self.col.numel() else None
+        d.val = self.val.data_ptr() if self.val.numel() else None
+        return d
+
+    def to_host(self):
+        return (self.rowptr.cpu().numpy(), self.col.cpu().numpy(), self.val.cpu().numpy())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+class Context:
+    """A library handle bound to one device, with torch's caching allocator
+    behind the library's device allocations."""
+
+    def __init__(self, device: int = 0, **options):
+        self.lib = _lib.load()
+        self.device = device
+        self.handle = ctypes.c_void_p()
+        self.opts = Options()
+        self.lib.magnus_options_default(ctypes.byref(self.opts))
+        self._apply(options)
+        check(self.lib.magnus_create(ctypes.byref(self.handle), device, ctypes.byref(self.opts)),
+              "magnus_create")
+        dev = torch.device("cuda", device)
+
+        def _alloc(n, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(n), dev, int(stream or 0))
+            except Exception:
+                return None
+
+        def _free(p, n, stream, ctx):
+            torch.cuda.caching_allocator_delete(int(p))
+
+        self._alloc_cb = _lib.ALLOC_FN(_alloc)
+        self._free_cb = _lib.FREE_FN(_free)
+        check(self.lib.magnus_set_allocator(self.handle, self._alloc_cb, self._free_cb, None),
+              "magnus_set_allocator")
+
+    def _apply(self, options):
+        for k, v in options.items():
+            if k == "force_category" and isinstance(v, str):
+                v = CATEGORY[v]
+            if not hasattr(self.opts, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(self.opts, k, int(v))
+
+    def set_options(self, **options):
+        self._apply(options)
+        check(self.lib.magnus_set_options(self.handle, ctypes.byref(self.opts)),
+              "magnus_set_options")
+
+    def close(self):
+        if self.handle:
+            self.lib.magnus_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- calls
+    def plan(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> "Plan":
+        s, keep = _stream_ptr(stream)
+        da, db = A.desc(), B.desc()
+        p = ctypes.c_void_p()
+        info = PlanInfo()
+        check(self.lib.magnus_plan(self.handle, ctypes.byref(da), ctypes.byref(db), s,
+                                   ctypes.byref(p), ctypes.byref(info)), "magnus_plan",
+              self.handle)
+        return Plan(self, p, info, A, B)
+
+    def row_ip(self, A: DeviceCSR, B: DeviceCSR, stream=None):
+        s, keep = _stream_ptr(stream)
+        out = torch.empty(max(A.nrows, 1), dtype=torch.int64, device=A.rowptr.device)
+        tot = ctypes.c_int64()
+        da, db = A.desc(), B.desc()
+        check(self.lib.magnus_row_ip(self.handle, ctypes.byref(da), ctypes.byref(db),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.byref(tot), s),
+              "magnus_row_ip", self.handle)
+        return out[:A.nrows], tot.value
+
+    def exclusive_scan(self, x: torch.Tensor, stream=None):
+        s, keep = _stream_ptr(stream)
+        assert x.dtype == torch.int64 and x.is_contiguous()
+        out = torch.empty_like(x)
+        tot = ctypes.c_int64()
+        check(self.lib.magnus_exclusive_scan_i64(
+            self.handle, ctypes.c_void_p(x.data_ptr()) if x.numel() else None,
+            ctypes.c_void_p(out.data_ptr()) if x.numel() else None, x.numel(), ctypes.byref(tot),
+            s), "magnus_exclusive_scan_i64", self.handle)
+        return out, tot.value
+
+    def spgemm(self, A: DeviceCSR, B: DeviceCSR, rowptr_dtype=torch.int64, stream=None):
+        p = self.plan(A, B, stream)
+        try:
+            return p.execute(rowptr_dtype=rowptr_dtype, stream=stream)
+        finally:
+            p.destroy()
+
+
+class Plan:
+    def __init__(self, ctx: Context, ptr, info: PlanInfo, A, B):
+        self.ctx, self.ptr, self.info, self.A, self.B = ctx, ptr, info, A, B
+
+    @property
+    def nnz(self) -> int:
+        return int(self.info.nnz_c)
+
+    def alloc_output(self, rowptr_dtype=torch.int64, capacity=None) -> DeviceCSR:
+        dev = self.A.rowptr.device
+        cap = self.nnz if capacity is None else capacity
+        return DeviceCSR(self.A.nrows, self.B.ncols,
+                         torch.empty(self.A.nrows + 1, dtype=rowptr_dtype, device=dev),
+                         torch.empty(max(cap, 0), dtype=self.B.col.dtype, device=dev),
+                         torch.empty(max(cap, 0), dtype=self.A.val.dtype, device=dev))
+
+    def execute(self, C: DeviceCSR | None = None, rowptr_dtype=torch.int64, stream=None):
+        s, keep = _stream_ptr(stream)
+        if C is None:
+            C = self.alloc_output(rowptr_dtype)
+        d = CsrOutDesc()
+        d.nrows, d.ncols, d.capacity = C.nrows, C.ncols, C.col.numel()
+        d.rowptr_type = _ITYPE[C.rowptr.dtype]
+        d.col_type = _ITYPE[C.col.dtype]
+        d.val_type = _VTYPE[C.val.dtype]
+        d.rowptr = C.rowptr.data_ptr()
+        d.col = C.col.data_ptr() if C.col.numel() else None
+        d.val = C.val.data_ptr() if C.val.numel() else None
+        nnz = ctypes.c_int64()
+        da, db = self.A.desc(), self.B.desc()
+        check(self.ctx.lib.magnus_execute(self.ctx.handle, self.ptr, ctypes.byref(da),
+                                          ctypes.byref(db), ctypes.byref(d), ctypes.byref(nnz), s),
+              "magnus_execute", self.ctx.handle)
+        return C
+
+    def destroy(self):
+        if self.ptr:
+            self.ctx.lib.magnus_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def paper_chunk_model(m_c: int, s_cache: int, s_line: int, s_dense_accum: float):
+    """Eqs. 2-7 (host only): (n_chunks_fine, n_chunks_coarse, m_CmaxL2)."""
+    lib = _lib.load()
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib.magnus_paper_chunk_model(m_c, s_cache, s_line, float(s_dense_accum),
+                                       ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+          "magnus_paper_chunk_model")
+    return a.value, b.value, c.value
+
+
+def gpu_chunk_shift(f64: bool, lds_bytes: int) -> int:
+    lib = _lib.load()
+    s = ctypes.c_int32()
+    check(lib.magnus_gpu_chunk_shift(1 if f64 else 0, lds_bytes, ctypes.byref(s)),
+          "magnus_gpu_chunk_shift")
+    return s.value

@@ -1,0 +1,684 @@
+// CHUNKED rows: reorder each row's intermediate product into column chunks
+// of 2^shift columns (histogram, prefix sum, reorder; Algorithm 3), then
+// accumulate every chunk on chip (Section 3.4): a dense accumulator in LDS for
+// chunks with many products, a wavefront sort for small ones, several
+// consecutive small chunks of a row packed into one sort (Section 4.1.1
+// combines chunks so a sort is near its best size).
+//
+// Work units: a row's products (in the order of Eq. 1) are cut into tiles of
+// `tile` products; one workgroup bins one tile.  Per (row, chunk, tile) the
+// tile's count is stored in a table whose prefix sum (row-major, chunk, then
+// tile) gives every tile a private, contiguous destination inside every chunk,
+// so the reorder needs no global atomics and is deterministic.
+#include "common.h"
+#include "kernels.h"
+#include "dispatch.h"
+
+namespace mg {
+
+MG_INLINE void wave_sync2() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// geometry of CHUNKED rows
+// ---------------------------------------------------------------------------
+__global__ void k_chunk_geom(const int32_t* rows, const int64_t* ip, const int64_t* minc,
+                             const int64_t* maxc, int64_t nch, int shift, int tile, int64_t* nb,
+                             int64_t* nt, int64_t* tabsz, int64_t* ipr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nch) return;
+  const int32_t r = rows[k];
+  const int64_t b = (maxc[r] >> shift) - (minc[r] >> shift) + 1;
+  const int64_t t = (ip[r] + tile - 1) / tile;
+  nb[k] = b;
+  nt[k] = t;
+  tabsz[k] = b * t;
+  ipr[k] = ip[r];
+}
+
+hipError_t launch_chunk_geom(const ChunkGeom& g, hipStream_t st) {
+  // ipBase doubles as the per-row ip input of its own scan (in place)
+  if (g.nch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chunk_geom, (unsigned)((g.nch + 255) / 256), 256, 0, st, g.rows, g.ip,
+                     g.minc, g.maxc, g.nch, g.shift, g.tile, g.nb, g.nt, g.tabsz, g.ipBase);
+  return hipGetLastError();
+}
+
+// first_of[s] = first CHUNKED row whose product range starts in [s*W, (s+1)*W)
+// bases[s*4 + {0,1,2,3}] = ipBase, tileBase, tabBase, binBase at that row
+__global__ void k_batch_bounds(const int64_t* ipBase, const int64_t* tileBase,
+                               const int64_t* tabBase, const int64_t* binBase, int64_t nch,
+                               int64_t W, int32_t* first_of, int64_t* bases) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nch) return;
+  const int64_t s = ipBase[k] / W;
+  if (k == 0 || ipBase[k - 1] / W != s) {
+    first_of[s] = (int32_t)k;
+    bases[s * 4 + 0] = ipBase[k];
+    bases[s * 4 + 1] = tileBase[k];
+    bases[s * 4 + 2] = tabBase[k];
+    bases[s * 4 + 3] = binBase[k];
+  }
+}
+
+hipError_t launch_batch_bounds(const ChunkGeom& g, int64_t W, int32_t* first_of, int64_t* bases,
+                                hipStream_t st) {
+  if (g.nch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_bounds, (unsigned)((g.nch + 255) / 256), 256, 0, st, g.ipBase,
+                     g.tileBase, g.tabBase, g.binBase, g.nch, W, first_of, bases);
+  return hipGetLastError();
+}
+
+// aoff[e] = offset of A entry e's products inside its row (exclusive scan of
+// B row lengths along the row); one wave per CHUNKED row
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(256) k_aoff(const RP* __restrict__ arp, const CI* __restrict__ acol,
+                                              const RP* __restrict__ brp, const int32_t* rows,
+                                              int64_t nrows, int64_t* aoff) {
+  const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
+  if (k >= nrows) return;
+  const int l = lane();
+  const int32_t r = rows[k];
+  const int64_t a0 = arp[r], a1 = arp[r + 1];
+  int64_t carry = 0;
+  for (int64_t e0 = a0; e0 < a1; e0 += MG_WAVE) {
+    const int64_t e = e0 + l;
+    int64_t len = 0;
+    if (e < a1) {
+      const int64_t j = acol[e];
+      len = (int64_t)brp[j + 1] - (int64_t)brp[j];
+    }
+    const int64_t inc = wave_incl_scan(len);
+    if (e < a1) aoff[e] = carry + inc - len;
+    carry += __shfl(inc, MG_WAVE - 1, MG_WAVE);
+  }
+}
+
+__global__ void k_tiles(const int64_t* nt, const int64_t* tileBase, int64_t k0, int64_t k1,
+                        int32_t* tile_row) {
+  const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
+  const int64_t b = tileBase[k], n = nt[k];
+  for (int64_t t = 0; t < n; ++t) tile_row[b + t] = (int32_t)k;
+}
+
+hipError_t launch_tiles(const int64_t* nt, const int64_t* tileBase, int64_t k0, int64_t k1,
+                        int32_t* tile_row, hipStream_t st) {
+  if (k1 <= k0) return hipSuccess;
+  hipLaunchKernelGGL(k_tiles, (unsigned)((k1 - k0 + 255) / 256), 256, 0, st, nt, tileBase, k0, k1,
+                     tile_row);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tile expansion shared by the histogram and reorder passes: the workgroup
+// walks the A entries overlapping its product range [p0, p1) in windows of
+// blockDim entries; each window's entry offsets sit in LDS and every thread
+// finds the owner of its product by binary search.
+// ---------------------------------------------------------------------------
+constexpr int BIN_BS = 256;
+
+struct TileCtx {
+  int64_t row, k, ti, p0, p1, a0, a1, e0, base_bin, nbk, ntk, tabk;
+};
+
+template <typename RP>
+MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t* tile_row,
+                          const RP* arp, const int64_t* aoff, TileCtx& c) {
+  const int64_t tg = b.tile0 + blockIdx.x;
+  c.k = tile_row[tg];
+  c.ti = tg - g.tileBase[c.k];
+  c.row = g.rows[c.k];
+  c.p0 = c.ti * (int64_t)g.tile;
+  const int64_t ipr = g.ip[c.row];
+  c.p1 = (c.p0 + g.tile < ipr) ? (c.p0 + g.tile) : ipr;
+  c.a0 = arp[c.row];
+  c.a1 = arp[c.row + 1];
+  c.base_bin = g.minc[c.row] >> g.shift;
+  c.nbk = g.nb[c.k];
+  c.ntk = g.nt[c.k];
+  c.tabk = g.tabBase[c.k];
+  // first entry whose products reach past p0: largest e with aoff[e] <= p0
+  int64_t lo = c.a0, hi = c.a1;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (aoff[mid] <= c.p0) lo = mid; else hi = mid;
+  }
+  c.e0 = lo;
+}
+
+// Calls f(col, bval_index, aval) for every product of the tile.
+template <typename RP, typename CI, typename V, bool WANT_VAL, typename F>
+MG_INLINE void tile_products(const TileCtx& c, const CI* __restrict__ acol, const V* __restrict__ aval,
+                             const RP* __restrict__ brp, const int64_t* __restrict__ aoff,
+                             int64_t* w_pre, int64_t* w_b0, V* w_av, F&& f) {
+  const int t = threadIdx.x;
+  for (int64_t eb = c.e0; eb < c.a1; eb += BIN_BS) {
+    const int64_t e = eb + t;
+    int64_t pre = INT64_MAX / 2, b0 = 0;
+    V av = (V)0;
+    if (e < c.a1) {
+      pre = aoff[e] - c.p0;
+      const int64_t j = acol[e];
+      b0 = brp[j];
+      if (WANT_VAL) av = aval[e];
+    }
+    w_pre[t] = pre;
+    w_b0[t] = b0;
+    if (WANT_VAL) w_av[t] = av;
+    const int nvalid = (int)((c.a1 - eb) < BIN_BS ? (c.a1 - eb) : BIN_BS);
+    __syncthreads();
+    // products of this window inside [0, p1 - p0)
+    const int64_t wstart = w_pre[0] > 0 ? w_pre[0] : 0;
+    int64_t wend;
+    if (eb + BIN_BS < c.a1) wend = aoff[eb + BIN_BS] - c.p0;
+    else wend = c.p1 - c.p0;
+    if (wend > c.p1 - c.p0) wend = c.p1 - c.p0;
+    for (int64_t q = wstart + t; q < wend; q += BIN_BS) {
+      const int kk = upper_index(w_pre, 0, nvalid, q);
+      const int64_t bi = w_b0[kk] + (q - w_pre[kk]);
+      f(q, bi, WANT_VAL ? w_av[kk] : (V)0);
+    }
+    __syncthreads();
+    if (wend >= c.p1 - c.p0) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Histogram pass: per tile, products per chunk.
+// ---------------------------------------------------------------------------
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(BIN_BS)
+    k_bin_hist(const RP* __restrict__ arp, const CI* __restrict__ acol, const RP* __restrict__ brp,
+               const CI* __restrict__ bcol, ChunkGeom g, BatchArgs b,
+               const int32_t* __restrict__ tile_row, const int64_t* __restrict__ aoff,
+               int32_t* tab_cnt) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  int64_t* w_pre = (int64_t*)dsm;          // BIN_BS
+  int64_t* w_b0 = w_pre + BIN_BS;            // BIN_BS
+  int32_t* hist = (int32_t*)(w_b0 + BIN_BS); // nb
+  TileCtx c;
+  tile_setup<RP>(g, b, tile_row, arp, aoff, c);
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) hist[q] = 0;
+  __syncthreads();
+  tile_products<RP, CI, float, false>(c, acol, (const float*)nullptr, brp, aoff, w_pre, w_b0,
+                                      (float*)nullptr, [&](int64_t, int64_t bi, float) {
+                                        const int64_t bin = ((int64_t)bcol[bi] >> g.shift) - c.base_bin;
+                                        atomicAdd(&hist[bin], 1);
+                                      });
+  __syncthreads();
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS)
+    tab_cnt[c.tabk + q * c.ntk + c.ti] = hist[q];
+}
+
+// ---------------------------------------------------------------------------
+// Reorder pass: stage the tile's products in LDS grouped by chunk (counting
+// sort with the tile's own histogram), then copy each chunk's run to the
+// tile's slot of that chunk: contiguous, coalesced stores.
+// ---------------------------------------------------------------------------
+size_t bin_scatter_lds(int f64, int tile, int64_t max_nb) {
+  const size_t vs = f64 ? 8 : 4;
+  return BIN_BS * 8 * 3 + (size_t)max_nb * 8 + 16 + (size_t)tile * (2 + 2) + 16 +
+         (size_t)tile * vs + 64;
+}
+
+template <typename RP, typename CI, typename V, bool NUMERIC>
+__global__ void __launch_bounds__(BIN_BS)
+    k_bin_scatter(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
+                  const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
+                  ChunkGeom g, BatchArgs b, const int32_t* __restrict__ tile_row,
+                  const int64_t* __restrict__ aoff, const int32_t* __restrict__ tab_cnt,
+                  const int64_t* __restrict__ tab_off, uint16_t* ws_col, V* ws_val,
+                  DevStats* stats) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  int64_t* w_pre = (int64_t*)dsm;                     // BIN_BS
+  int64_t* w_b0 = w_pre + BIN_BS;                     // BIN_BS
+  V* w_av = (V*)(w_b0 + BIN_BS);                      // BIN_BS
+  int32_t* loc = (int32_t*)((char*)w_av + BIN_BS * 8);  // nb (w_av padded to 8 B entries)
+  TileCtx c;
+  tile_setup<RP>(g, b, tile_row, arp, aoff, c);
+  int32_t* cur = loc + c.nbk;                          // nb
+  uint16_t* st_col = (uint16_t*)(((uintptr_t)(cur + c.nbk) + 15) & ~(uintptr_t)15);
+  uint16_t* st_bin = st_col + g.tile;
+  V* st_val = (V*)(((uintptr_t)(st_bin + g.tile) + 15) & ~(uintptr_t)15);
+  __shared__ int64_t sh_w[4];
+  __shared__ int64_t sh_tot;
+
+  // local chunk offsets = exclusive scan of this tile's counts
+  {
+    const int64_t per = (c.nbk + BIN_BS - 1) / BIN_BS;
+    const int64_t q0 = threadIdx.x * per;
+    int64_t s = 0;
+    for (int64_t q = q0; q < q0 + per && q < c.nbk; ++q) s += tab_cnt[c.tabk + q * c.ntk + c.ti];
+    const int64_t inc = wave_incl_scan(s);
+    const int wv = threadIdx.x / MG_WAVE;
+    if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
+    __syncthreads();
+    int64_t before = 0;
+    for (int v = 0; v < wv; ++v) before += sh_w[v];
+    if (threadIdx.x == BIN_BS - 1) sh_tot = before + inc;
+    int64_t run = before + inc - s;
+    for (int64_t q = q0; q < q0 + per && q < c.nbk; ++q) {
+      loc[q] = (int32_t)run;
+      cur[q] = 0;
+      run += tab_cnt[c.tabk + q * c.ntk + c.ti];
+    }
+  }
+  __syncthreads();
+  if (sh_tot != c.p1 - c.p0) {
+    if (threadIdx.x == 0) atomicOr(&stats->err, ERR_BIN_OVERFLOW);
+    return;
+  }
+  const int64_t lmask = ((int64_t)1 << g.shift) - 1;
+  tile_products<RP, CI, V, NUMERIC>(c, acol, aval, brp, aoff, w_pre, w_b0, w_av,
+                                    [&](int64_t, int64_t bi, V av) {
+                                      const int64_t col = bcol[bi];
+                                      const int bin = (int)((col >> g.shift) - c.base_bin);
+                                      const int pos = loc[bin] + atomicAdd(&cur[bin], 1);
+                                      st_col[pos] = (uint16_t)(col & lmask);
+                                      st_bin[pos] = (uint16_t)bin;
+                                      if (NUMERIC) st_val[pos] = av * bval[bi];
+                                    });
+  __syncthreads();
+  const int64_t nloc = c.p1 - c.p0;
+  for (int64_t s = threadIdx.x; s < nloc; s += BIN_BS) {
+    const int bin = st_bin[s];
+    const int64_t dst = tab_off[c.tabk + (int64_t)bin * c.ntk + c.ti] + (s - loc[bin]);
+    ws_col[dst] = st_col[s];
+    if (NUMERIC) ws_val[dst] = st_val[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chunk start / size and work items
+// ---------------------------------------------------------------------------
+__global__ void k_bin_stats(ChunkGeom g, BatchArgs b, const int64_t* tab_off, int64_t* bin_start,
+                            int64_t* bin_cnt, int32_t* bin_row) {
+  const int64_t k = b.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= b.k1) return;
+  const int64_t nbk = g.nb[k], ntk = g.nt[k], tb = g.tabBase[k], bb = g.binBase[k];
+  for (int64_t q = 0; q < nbk; ++q) {
+    const int64_t e = tb + q * ntk;
+    const int64_t e1 = e + ntk;
+    const int64_t s = tab_off[e];
+    const int64_t en = (e1 < b.tab0 + b.ntab) ? tab_off[e1] : b.nip;
+    bin_start[bb + q] = s;
+    bin_cnt[bb + q] = en - s;
+    bin_row[bb + q] = (int32_t)k;
+  }
+}
+
+// per row: dense chunks become single items; runs of small consecutive chunks
+// (<= 64 chunks, <= group_max products) become packed sort items
+__global__ void k_bin_group(ChunkGeom g, BatchArgs b, const int64_t* bin_cnt, int64_t dense_min,
+                            int64_t group_max, int64_t* dense_items, int64_t* sort_items,
+                            int32_t* item_counts, int64_t item_base) {
+  const int64_t k = b.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= b.k1) return;
+  const int64_t nbk = g.nb[k], bb = g.binBase[k];
+  int64_t gs = -1, gn = 0, gc = 0;
+  for (int64_t q = 0; q < nbk; ++q) {
+    const int64_t cnt = bin_cnt[bb + q];
+    if (cnt >= dense_min) {
+      if (gs >= 0) {
+        const int idx = atomicAdd(&item_counts[1], 1);
+        sort_items[2 * (item_base + idx)] = gs;
+        sort_items[2 * (item_base + idx) + 1] = gn;
+        gs = -1; gn = 0; gc = 0;
+      }
+      const int idx = atomicAdd(&item_counts[0], 1);
+      dense_items[item_base + idx] = bb + q;
+      continue;
+    }
+    if (gs >= 0 && (gc + cnt > group_max || gn >= 64)) {
+      const int idx = atomicAdd(&item_counts[1], 1);
+      sort_items[2 * (item_base + idx)] = gs;
+      sort_items[2 * (item_base + idx) + 1] = gn;
+      gs = -1; gn = 0; gc = 0;
+    }
+    if (gs < 0) gs = bb + q;
+    ++gn;
+    gc += cnt;
+  }
+  if (gs >= 0) {
+    const int idx = atomicAdd(&item_counts[1], 1);
+    sort_items[2 * (item_base + idx)] = gs;
+    sort_items[2 * (item_base + idx) + 1] = gn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense chunk accumulation: one workgroup per chunk; LDS values (numeric) and
+// one bitmap bit per column; write-out in column order.
+// ---------------------------------------------------------------------------
+size_t bin_dense_lds(int f64, int shift) {
+  const size_t L = (size_t)1 << shift;
+  return L * (f64 ? 8 : 4) + (L / 32) * 4 + 64;
+}
+
+template <typename V, bool NUMERIC>
+__global__ void __launch_bounds__(1024)
+    k_accum_dense(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
+                  int64_t item_base, const int64_t* __restrict__ bin_start,
+                  const int64_t* __restrict__ bin_cnt, const int32_t* __restrict__ bin_row,
+                  const uint16_t* __restrict__ ws_col, const V* __restrict__ ws_val,
+                  int64_t* bin_nnz, const int64_t* __restrict__ bin_out, void* ccol_, int col64,
+                  V* cval) {
+  if ((int64_t)blockIdx.x >= item_counts[0]) return;
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int BS = blockDim.x;
+  const int64_t L = (int64_t)1 << g.shift;
+  V* acc = (V*)dsm;
+  uint32_t* bits = (uint32_t*)(dsm + (NUMERIC ? L * sizeof(V) : 0));
+  __shared__ int64_t sh_w[16];
+  const int t = threadIdx.x;
+  const int64_t gb = items[item_base + blockIdx.x];
+  const int64_t s0 = bin_start[gb], cnt = bin_cnt[gb];
+  const int64_t nwords = L / 32;
+  for (int64_t q = t; q < nwords; q += BS) bits[q] = 0u;
+  if (NUMERIC)
+    for (int64_t q = t; q < L; q += BS) acc[q] = (V)0;
+  __syncthreads();
+  // 4 products in flight per thread
+  int64_t q = t;
+  for (; q + 3 * BS < cnt; q += 4 * BS) {
+    uint32_t c4[4];
+    V v4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c4[u] = ws_col[s0 + q + u * BS];
+      if (NUMERIC) v4[u] = ws_val[s0 + q + u * BS];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
+      if (NUMERIC) atomicAdd(&acc[c4[u]], v4[u]);
+    }
+  }
+  for (; q < cnt; q += BS) {
+    const uint32_t c = ws_col[s0 + q];
+    atomicOr(&bits[c >> 5], 1u << (c & 31));
+    if (NUMERIC) atomicAdd(&acc[c], ws_val[s0 + q]);
+  }
+  __syncthreads();
+  const int64_t wpt = (nwords + BS - 1) / BS;
+  const int64_t w0 = t * wpt, w1 = (w0 + wpt < nwords) ? (w0 + wpt) : nwords;
+  int64_t my = 0;
+  for (int64_t w = w0; w < w1; ++w) my += __popc(bits[w]);
+  const int wv = t / MG_WAVE, nw = BS / MG_WAVE;
+  const int64_t inc = wave_incl_scan(my);
+  if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
+  __syncthreads();
+  int64_t before = 0, total = 0;
+  for (int v = 0; v < nw; ++v) {
+    if (v < wv) before += sh_w[v];
+    total += sh_w[v];
+  }
+  if (!NUMERIC) {
+    if (t == 0) bin_nnz[gb] = total;
+    return;
+  }
+  const int64_t k = bin_row[gb];
+  const int64_t colbase = ((g.minc[g.rows[k]] >> g.shift) + (gb - g.binBase[k])) << g.shift;
+  int64_t pos = bin_out[gb] + before + inc - my;
+  for (int64_t w = w0; w < w1; ++w) {
+    uint32_t bb = bits[w];
+    while (bb) {
+      const int bit = __ffs(bb) - 1;
+      bb &= bb - 1;
+      const int64_t lc = w * 32 + bit;
+      if (col64) ((int64_t*)ccol_)[pos] = colbase + lc;
+      else ((int32_t*)ccol_)[pos] = (int32_t)(colbase + lc);
+      cval[pos] = acc[lc];
+      ++pos;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packed sort of small chunks: one wave per item of <= 64 consecutive chunks
+// of one row and <= 64*E products; key = (chunk offset << shift) | local col,
+// i.e. the column relative to the item's first chunk.
+// ---------------------------------------------------------------------------
+constexpr int AS_WAVES = 4;
+
+template <typename V, int E, bool NUMERIC>
+MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const int64_t* bin_start,
+                               const int64_t* bin_cnt, const int32_t* bin_row,
+                               const uint16_t* ws_col, const V* ws_val, int64_t* bin_nnz,
+                               const int64_t* bin_out, void* ccol_, int col64, V* cval,
+                               int64_t* s_bs, int32_t* s_cnt) {
+  const int l = lane();
+  const int64_t start = bin_start[g0];
+  const int64_t endp = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1];
+  const int P = (int)(endp - start);
+  if (l < nbg) {
+    s_bs[l] = bin_start[g0 + l] - start;
+    s_cnt[l] = 0;
+  }
+  wave_sync2();
+  uint32_t k[E];
+  V v[NUMERIC ? E : 1];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = e * MG_WAVE + l;
+    if (x < P) {
+      const int bo = upper_index(s_bs, 0, nbg, (int64_t)x);
+      k[e] = ((uint32_t)bo << g.shift) | (uint32_t)ws_col[start + x];
+      if (NUMERIC) v[e] = ws_val[start + x];
+    } else {
+      k[e] = 0xFFFFFFFFu;
+      if (NUMERIC) v[e] = (V)0;
+    }
+  }
+  if (NUMERIC) bitonic_sort_pairs<E>(k, *reinterpret_cast<V(*)[E]>(v));
+  else bitonic_sort_keys<E>(k);
+  const uint32_t prevk = __shfl_up(k[E - 1], 1, MG_WAVE);
+  bool head[E];
+  int hc = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = l * E + e;
+    const uint32_t pk = (e == 0) ? prevk : k[e - 1];
+    head[e] = (x < P) && (x == 0 || k[e] != pk);
+    hc += head[e] ? 1 : 0;
+  }
+  if (!NUMERIC) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (head[e]) atomicAdd(&s_cnt[k[e] >> g.shift], 1);
+    wave_sync2();
+    if (l < nbg) bin_nnz[g0 + l] = s_cnt[l];
+    return;
+  } else {
+    const int hinc = wave_incl_scan(hc);
+    const int hbase = hinc - hc;
+    V t = (V)0;
+    bool anyh = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (head[e]) { t = (V)0 + v[e]; anyh = true; }
+      else t = t + v[e];
+    }
+    V s = t;
+    bool f = anyh;
+#pragma unroll
+    for (int d = 1; d < MG_WAVE; d <<= 1) {
+      const V ps = __shfl_up(s, d, MG_WAVE);
+      const int pf = __shfl_up((int)f, d, MG_WAVE);
+      if (l >= d && !f) { s = ps + s; f = pf != 0; }
+    }
+    V carry = __shfl_up(s, 1, MG_WAVE);
+    if (l == 0) carry = (V)0;
+    const uint32_t nextk = __shfl_down(k[0], 1, MG_WAVE);
+    const int64_t kk = bin_row[g0];
+    const int64_t colbase = ((g.minc[g.rows[kk]] >> g.shift) + (g0 - g.binBase[kk])) << g.shift;
+    const int64_t obase = bin_out[g0];
+    V run = carry;
+    int hr = hbase;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      if (head[e]) { run = (V)0 + v[e]; ++hr; }
+      else run = run + v[e];
+      const uint32_t nk = (e == E - 1) ? nextk : k[e + 1];
+      const bool tail = (x < P) && (x == P - 1 || nk != k[e]);
+      if (tail) {
+        const int64_t pos = obase + hr - 1;
+        const int64_t col = colbase + (int64_t)k[e];
+        if (col64) ((int64_t*)ccol_)[pos] = col;
+        else ((int32_t*)ccol_)[pos] = (int32_t)col;
+        cval[pos] = run;
+      }
+    }
+  }
+}
+
+template <typename V, bool NUMERIC>
+__global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
+    k_accum_sort(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
+                 int64_t item_base, const int64_t* __restrict__ bin_start,
+                 const int64_t* __restrict__ bin_cnt, const int32_t* __restrict__ bin_row,
+                 const uint16_t* __restrict__ ws_col, const V* __restrict__ ws_val,
+                 int64_t* bin_nnz, const int64_t* __restrict__ bin_out, void* ccol_, int col64,
+                 V* cval) {
+  __shared__ int64_t s_bs[AS_WAVES][MG_WAVE];
+  __shared__ int32_t s_cnt[AS_WAVES][MG_WAVE];
+  const int w = threadIdx.x / MG_WAVE;
+  const int64_t it = (int64_t)blockIdx.x * AS_WAVES + w;
+  if (it >= item_counts[1]) return;
+  const int64_t g0 = items[2 * (item_base + it)];
+  const int nbg = (int)items[2 * (item_base + it) + 1];
+  const int64_t P = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1] - bin_start[g0];
+  if (P <= 64)
+    accum_sort_item<V, 1, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+  else if (P <= 128)
+    accum_sort_item<V, 2, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+  else if (P <= 256)
+    accum_sort_item<V, 4, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+  else if (P <= 512)
+    accum_sort_item<V, 8, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+  else
+    accum_sort_item<V, 16, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val,
+                                    bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+}
+
+// rownnz of CHUNKED rows (count) / output offset of every chunk (numeric)
+__global__ void k_bin_rows(ChunkGeom g, int64_t k0, int64_t k1, const int64_t* bin_nnz,
+                           int64_t* rownnz, const int64_t* crp, int64_t* bin_out, int to_out) {
+  const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
+  const int64_t nbk = g.nb[k], bb = g.binBase[k];
+  const int32_t r = g.rows[k];
+  int64_t s = to_out ? crp[r] : 0;
+  for (int64_t q = 0; q < nbk; ++q) {
+    if (to_out) bin_out[bb + q] = s;
+    s += bin_nnz[bb + q];
+  }
+  if (!to_out) rownnz[r] = s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_aoff(const Mats& M, const int32_t* rows, int64_t nrows, int64_t* aoff,
+                       hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nrows + 3) / 4);
+  MG_DISPATCH2(M, hipLaunchKernelGGL((k_aoff<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
+                                      (const CI*)M.acol, (const RP*)M.brp, rows, nrows, aoff));
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+                            const int32_t* tile_row, const int64_t* aoff, int32_t* tab_cnt,
+                            int64_t max_nb, hipStream_t st) {
+  if (b.ntiles <= 0) return hipSuccess;
+  const size_t lds = BIN_BS * 8 * 2 + (size_t)max_nb * 4 + 64;
+  MG_DISPATCH2(M, {
+    auto kf = k_bin_hist<RP, CI>;
+    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,
+                       (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, b, tile_row,
+                       aoff, tab_cnt);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
+                               const int32_t* tile_row, const int64_t* aoff,
+                               const int32_t* tab_cnt, const int64_t* tab_off, uint16_t* ws_col,
+                               void* ws_val, int64_t max_nb, DevStats* stats, hipStream_t st) {
+  if (b.ntiles <= 0) return hipSuccess;
+  const size_t lds = bin_scatter_lds(M.f64, g.tile, max_nb);
+#define MG_SC(V)                                                                                   \
+  MG_DISPATCH2(M, {                                                                               \
+    auto kf = numeric ? k_bin_scatter<RP, CI, V, true> : k_bin_scatter<RP, CI, V, false>;          \
+    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+    hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                  \
+                       (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,   \
+                       (const V*)M.bval, g, b, tile_row, aoff, tab_cnt, tab_off, ws_col,           \
+                       (V*)ws_val, stats);                                                         \
+  });
+  if (M.f64) { MG_SC(double) } else { MG_SC(float) }
+#undef MG_SC
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_items(const ChunkGeom& g, const BatchArgs& b, const int64_t* tab_off,
+                             int64_t* bin_start, int64_t* bin_cnt, int32_t* bin_row,
+                             int64_t dense_min, int64_t group_max, int64_t* dense_items,
+                             int64_t* sort_items, int32_t* item_counts, hipStream_t st) {
+  const int64_t nr = b.k1 - b.k0;
+  if (nr <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nr + 255) / 256);
+  hipLaunchKernelGGL(k_bin_stats, grid, 256, 0, st, g, b, tab_off, bin_start, bin_cnt, bin_row);
+  hipLaunchKernelGGL(k_bin_group, grid, 256, 0, st, g, b, (const int64_t*)bin_cnt, dense_min,
+                     group_max, dense_items, sort_items, item_counts, b.bin0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric, int f64,
+                             const int64_t* bin_start, const int64_t* bin_cnt,
+                             const int32_t* bin_row, const int64_t* dense_items,
+                             const int64_t* sort_items, const int32_t* item_counts,
+                             const uint16_t* ws_col, const void* ws_val, int64_t* bin_nnz,
+                             const int64_t* bin_out, void* ccol, int col64, void* cval,
+                             int dense_block, hipStream_t st) {
+  if (b.nbins <= 0) return hipSuccess;
+  const size_t lds = bin_dense_lds(f64, g.shift);
+  const unsigned gd = (unsigned)b.nbins;
+  const unsigned gs = (unsigned)((b.nbins + AS_WAVES - 1) / AS_WAVES);
+#define MG_AC(V)                                                                                  \
+  {                                                                                               \
+    auto kd = numeric ? k_accum_dense<V, true> : k_accum_dense<V, false>;                         \
+    hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_items, item_counts, b.bin0,         \
+                       bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
+                       ccol, col64, (V*)cval);                                                    \
+    auto ks = numeric ? k_accum_sort<V, true> : k_accum_sort<V, false>;                           \
+    hipLaunchKernelGGL(ks, gs, AS_WAVES * MG_WAVE, 0, st, g, sort_items, item_counts, b.bin0,     \
+                       bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
+                       ccol, col64, (V*)cval);                                                    \
+  }
+  if (f64) MG_AC(double) else MG_AC(float)
+#undef MG_AC
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_rows(const ChunkGeom& g, int64_t k0, int64_t k1, const int64_t* bin_nnz,
+                           int64_t* rownnz, const int64_t* crp, int64_t* bin_out, bool to_out,
+                           hipStream_t st) {
+  if (k1 <= k0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin_rows, (unsigned)((k1 - k0 + 255) / 256), 256, 0, st, g, k0, k1, bin_nnz,
+                     rownnz, crp, bin_out, to_out ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace mg

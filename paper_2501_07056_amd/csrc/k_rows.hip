@@ -1,0 +1,410 @@
+// Row-level kernels: the setup phase (per-row intermediate-product count and
+// column range, row categorisation; Section 3.1) and DENSE rows (dense
+// accumulator over the row's column range; Algorithm 1).  The accumulator
+// kernel runs in two modes: count
+// (precise symbolic phase: exact nnz per row, Section 2.1) and numeric (values
+// written straight into C at the row offsets the symbolic phase produced).
+#include "common.h"
+#include "kernels.h"
+#include "dispatch.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// wave-private LDS: order LDS writes of this wave before other lanes read
+// ---------------------------------------------------------------------------
+MG_INLINE void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// Setup: ip_i = sum over entries (i,j) of nnz(B_j); minc/maxc = smallest /
+// largest column over those B rows (B rows sorted); class of the row.
+// G lanes cooperate on one row.
+// ---------------------------------------------------------------------------
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, const CI* __restrict__ acol,
+                                                 const RP* __restrict__ brp, const CI* __restrict__ bcol,
+                                                 int64_t n, int G, ClassParams cp, int64_t* ip,
+                                                 int64_t* minc, int64_t* maxc, int32_t* cls,
+                                                 DevStats* stats) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gt / G;
+  const int sub = (int)(gt % G);
+  int64_t s = 0, mn = INT64_MAX, mx = -1;
+  if (row < n) {
+    const int64_t p0 = arp[row], p1 = arp[row + 1];
+    for (int64_t p = p0 + sub; p < p1; p += G) {
+      const int64_t j = acol[p];
+      const int64_t b0 = brp[j], b1 = brp[j + 1];
+      if (b1 > b0) {
+        s += b1 - b0;
+        const int64_t f = bcol[b0], l = bcol[b1 - 1];
+        mn = f < mn ? f : mn;
+        mx = l > mx ? l : mx;
+      }
+    }
+  }
+  for (int d = G >> 1; d >= 1; d >>= 1) {
+    s += __shfl_xor(s, d, G);
+    int64_t a = __shfl_xor(mn, d, G);
+    int64_t b = __shfl_xor(mx, d, G);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  unsigned long long my_ip = 0, my_range = 0;
+  int cat = -1;
+  if (row < n && sub == 0) {
+    int c;
+    const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
+    if (s == 0) {
+      c = CLS_EMPTY;
+      mn = 0;
+      mx = -1;
+      cat = 3;
+    } else {
+      int want = cp.force;
+      if (want < 0) want = (s < cp.sort_max) ? 0 : (range <= cp.dense_max ? 1 : 2);
+      if (want == 0 && s > SORT_CAP) want = (range <= cp.dense_max) ? 1 : 2;
+      if (want == 1 && range > cp.dense_max) want = 2;
+      if (want == 0) {
+        int lg = 0;
+        while (((int64_t)1 << lg) < s) ++lg;
+        c = lg;
+      } else {
+        c = (want == 1) ? CLS_DENSE : CLS_CHUNKED;
+      }
+      cat = want;
+    }
+    ip[row] = s;
+    minc[row] = mn;
+    maxc[row] = mx;
+    cls[row] = c;
+    my_ip = (unsigned long long)s;
+    my_range = (unsigned long long)range;
+  }
+  // block-level reduction of the statistics, then one atomic per block
+  __shared__ unsigned long long sh[6 + 8];
+  if (threadIdx.x < 14) sh[threadIdx.x] = 0;
+  __syncthreads();
+  if (cat >= 0) {
+    atomicAdd(&sh[0], my_ip);
+    atomicMax(&sh[1], my_ip);
+    atomicMax(&sh[2], my_range);
+    atomicAdd(&sh[6 + cat], my_ip);
+    atomicAdd(&sh[10 + cat], 1ull);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&stats->ip_total, sh[0]);
+    atomicMax(&stats->max_ip, sh[1]);
+    atomicMax(&stats->max_range, sh[2]);
+    for (int k = 0; k < 4; ++k) {
+      if (sh[6 + k]) atomicAdd(&stats->ip_cat[k], sh[6 + k]);
+      if (sh[10 + k]) atomicAdd(&stats->rows_cat[k], sh[10 + k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSR validation (only on request): rowptr monotone from 0, columns in range,
+// rows of B strictly ascending.
+// ---------------------------------------------------------------------------
+template <typename RP, typename CI>
+__global__ void k_validate(const RP* rp, const CI* col, int64_t n, int64_t ncols, int64_t nnz,
+                           int strict_sorted, DevStats* stats) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  bool bad = false;
+  if (i == 0 && rp[0] != 0) bad = true;
+  if (i == n && (int64_t)rp[n] != nnz) bad = true;
+  if (i < n) {
+    const int64_t p0 = rp[i], p1 = rp[i + 1];
+    if (p1 < p0 || p0 < 0 || p1 > nnz) {
+      bad = true;
+    } else {
+      int64_t prev = -1;
+      for (int64_t p = p0; p < p1; ++p) {
+        const int64_t c = col[p];
+        if (c < 0 || c >= ncols) { bad = true; break; }
+        if (strict_sorted && c <= prev) { bad = true; break; }
+        prev = c;
+      }
+    }
+  }
+  if (bad) atomicOr(&stats->err, ERR_INVALID_CSR);
+}
+
+// ---------------------------------------------------------------------------
+// Stable partition of rows by class (counts per block, scan, scatter).
+// ---------------------------------------------------------------------------
+constexpr int CL_BS = 256;
+
+__global__ void __launch_bounds__(CL_BS) k_class_count(const int32_t* cls, int64_t n, int32_t* cnt,
+                                                        int64_t nblk) {
+  __shared__ int32_t h[NCLS];
+  if (threadIdx.x < NCLS) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * CL_BS + threadIdx.x;
+  if (i < n) atomicAdd(&h[cls[i]], 1);
+  __syncthreads();
+  if (threadIdx.x < NCLS) cnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(CL_BS) k_class_scatter(const int32_t* cls, int64_t n,
+                                                          const int64_t* off, int64_t nblk,
+                                                          int32_t* list) {
+  __shared__ int32_t wc[CL_BS / MG_WAVE][NCLS];
+  const int64_t i = (int64_t)blockIdx.x * CL_BS + threadIdx.x;
+  const int c = (i < n) ? cls[i] : -1;
+  const int w = threadIdx.x / MG_WAVE;
+  int my_rank = 0;
+  for (int k = 0; k < NCLS; ++k) {
+    uint64_t m = ballot(c == k);
+    if (c == k) my_rank = rank_below(m);
+    if (lane() == 0) wc[w][k] = popc64(m);
+  }
+  __syncthreads();
+  if (c >= 0) {
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += wc[v][c];
+    list[off[(int64_t)c * nblk + blockIdx.x] + before + my_rank] = (int32_t)i;
+  }
+}
+
+__global__ void k_class_offsets(const int64_t* off, int64_t nblk, int64_t n, int64_t* list_off) {
+  const int c = threadIdx.x;
+  if (c < NCLS) list_off[c] = off[(int64_t)c * nblk];
+  if (c == 0) list_off[NCLS] = n;
+}
+
+size_t classify_temp_bytes(int64_t n) {
+  const int64_t nblk = (n + CL_BS - 1) / CL_BS;
+  const int64_t tab = (int64_t)NCLS * nblk;
+  return (size_t)tab * 4 + (size_t)tab * 8 + scan_temp_bytes(tab) + 256;
+}
+
+hipError_t launch_classify(const int32_t* cls, int64_t n, int32_t* list, int64_t* list_off,
+                           void* temp, hipStream_t st) {
+  const int64_t nblk = (n + CL_BS - 1) / CL_BS;
+  const int64_t tab = (int64_t)NCLS * nblk;
+  char* t = (char*)temp;
+  int32_t* cnt = (int32_t*)t;
+  t += ((size_t)tab * 4 + 255) / 256 * 256;
+  int64_t* off = (int64_t*)t;
+  t += ((size_t)tab * 8 + 255) / 256 * 256;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_class_count, (unsigned)nblk, CL_BS, 0, st, cls, n, cnt, nblk);
+    hipError_t e = scan_excl_i32(cnt, off, tab, nullptr, nullptr, t, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_class_scatter, (unsigned)nblk, CL_BS, 0, st, cls, n, (const int64_t*)off,
+                       nblk, list);
+    hipLaunchKernelGGL(k_class_offsets, 1, 64, 0, st, (const int64_t*)off, nblk, n, list_off);
+  } else {
+    hipError_t e = hipMemsetAsync(list_off, 0, sizeof(int64_t) * (NCLS + 1), st);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// DENSE rows.  One workgroup per row; the dense accumulator covers the row's
+// column range [minc, maxc] (<= 2^shift columns): values in LDS plus one
+// bitmap bit per column (Algorithm 1 with the bitmap as a bit array).  The
+// write-out walks the bitmap in column order.
+// ---------------------------------------------------------------------------
+size_t dense_rows_lds(int f64, int shift, int block) {
+  const size_t L = (size_t)1 << shift;
+  return L * (f64 ? 8 : 4) + (L / 32) * 4 + (size_t)block * (4 + 8 + 8) + 64;
+}
+
+template <typename V>
+MG_INLINE int64_t block_excl_scan64(int64_t v, int64_t* sh_w, int64_t& total) {
+  const int t = threadIdx.x, wv = t / MG_WAVE, nw = blockDim.x / MG_WAVE;
+  const int64_t inc = wave_incl_scan(v);
+  if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
+  __syncthreads();
+  int64_t before = 0;
+  total = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int64_t s = sh_w[k];
+    if (k < wv) before += s;
+    total += s;
+  }
+  __syncthreads();
+  return before + inc - v;
+}
+
+template <typename RP, typename CI, typename V, bool NUMERIC>
+__global__ void __launch_bounds__(1024)
+    k_dense_rows(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
+                 const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
+                 const int32_t* __restrict__ list, const int64_t* __restrict__ minc,
+                 const int64_t* __restrict__ maxc, int shift, int64_t* rownnz,
+                 const int64_t* __restrict__ crp, CI* ccol, V* cval) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int BS = blockDim.x;
+  const int64_t L = (int64_t)1 << shift;
+  V* acc = (V*)dsm;
+  uint32_t* bits = (uint32_t*)(dsm + L * sizeof(V));
+  int32_t* w_pre = (int32_t*)(bits + L / 32);
+  int64_t* w_b0 = (int64_t*)(((uintptr_t)(w_pre + BS + 1) + 7) & ~(uintptr_t)7);
+  V* w_av = (V*)(w_b0 + BS);
+  __shared__ int64_t sh_w[16];
+
+  const int t = threadIdx.x;
+  const int32_t row = list[blockIdx.x];
+  const int64_t mn = minc[row];
+  const int64_t range = maxc[row] - mn + 1;
+  const int64_t nwords = (range + 31) / 32;
+  for (int64_t q = t; q < nwords; q += BS) bits[q] = 0u;
+  if (NUMERIC)
+    for (int64_t q = t; q < range; q += BS) acc[q] = (V)0;
+  __syncthreads();
+
+  const int64_t a0 = arp[row], a1 = arp[row + 1];
+  for (int64_t e0 = a0; e0 < a1; e0 += BS) {
+    const int64_t e = e0 + t;
+    int len = 0;
+    int64_t b0 = 0;
+    V av = (V)0;
+    if (e < a1) {
+      const int64_t j = acol[e];
+      b0 = brp[j];
+      len = (int)((int64_t)brp[j + 1] - b0);
+      if (NUMERIC) av = aval[e];
+    }
+    int64_t tot;
+    const int64_t pre = block_excl_scan64<V>(len, sh_w, tot);
+    w_pre[t] = (int32_t)pre;
+    w_b0[t] = b0;
+    w_av[t] = av;
+    const int nvalid = (int)((a1 - e0) < BS ? (a1 - e0) : BS);
+    __syncthreads();
+    for (int64_t q = t; q < tot; q += BS) {
+      const int k = upper_index(w_pre, 0, nvalid, (int32_t)q);
+      const int64_t bi = w_b0[k] + (q - w_pre[k]);
+      const int64_t lc = (int64_t)bcol[bi] - mn;
+      atomicOr(&bits[lc >> 5], 1u << (lc & 31));
+      if (NUMERIC) atomicAdd(&acc[lc], w_av[k] * bval[bi]);
+    }
+    __syncthreads();
+  }
+
+  // write-out / count: thread t owns a contiguous run of bitmap words
+  const int64_t wpt = (nwords + BS - 1) / BS;
+  const int64_t w0 = t * wpt, w1 = (w0 + wpt < nwords) ? (w0 + wpt) : nwords;
+  int64_t cnt = 0;
+  for (int64_t q = w0; q < w1; ++q) cnt += __popc(bits[q]);
+  int64_t total;
+  const int64_t base = block_excl_scan64<V>(cnt, sh_w, total);
+  if (!NUMERIC) {
+    if (t == 0) rownnz[row] = total;
+    return;
+  }
+  int64_t pos = crp[row] + base;
+  for (int64_t q = w0; q < w1; ++q) {
+    uint32_t b = bits[q];
+    while (b) {
+      const int bit = __ffs(b) - 1;
+      b &= b - 1;
+      const int64_t lc = q * 32 + bit;
+      ccol[pos] = (CI)(mn + lc);
+      cval[pos] = acc[lc];
+      ++pos;
+    }
+  }
+}
+
+template <typename RP, typename CI, typename V>
+static hipError_t dense_rows_t(const Mats& M, bool numeric, const int32_t* list, int64_t count,
+                               const int64_t* minc, const int64_t* maxc, int shift, int block,
+                               int64_t* rownnz, const int64_t* crp, void* ccol, void* cval,
+                               hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const size_t lds = dense_rows_lds(sizeof(V) == 8, shift, block);
+  auto kn = k_dense_rows<RP, CI, V, true>;
+  auto kc = k_dense_rows<RP, CI, V, false>;
+  if (numeric) {
+    hipFuncSetAttribute((const void*)kn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kn, (unsigned)count, block, lds, st, (const RP*)M.arp, (const CI*)M.acol,
+                       (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol, (const V*)M.bval,
+                       list, minc, maxc, shift, rownnz, crp, (CI*)ccol, (V*)cval);
+  } else {
+    hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kc, (unsigned)count, block, lds, st, (const RP*)M.arp, (const CI*)M.acol,
+                       (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol, (const V*)M.bval,
+                       list, minc, maxc, shift, rownnz, crp, (CI*)ccol, (V*)cval);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, (unsigned)((n + 255) / 256), 256, 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_write_rowptr(const int64_t* crp, int64_t n1, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n1) out[i] = (T)crp[i];
+}
+hipError_t launch_write_rowptr(const int64_t* crp, int64_t n, void* out, int out64,
+                               hipStream_t st) {
+  const int64_t n1 = n + 1;
+  const unsigned g = (unsigned)((n1 + 255) / 256);
+  if (out64) hipLaunchKernelGGL(k_write_rowptr<int64_t>, g, 256, 0, st, crp, n1, (int64_t*)out);
+  else hipLaunchKernelGGL(k_write_rowptr<int32_t>, g, 256, 0, st, crp, n1, (int32_t*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowinfo(const Mats& M, int64_t a_nnz, const ClassParams& cp, int64_t* ip,
+                          int64_t* minc, int64_t* maxc, int32_t* cls, DevStats* stats,
+                          hipStream_t st) {
+  if (M.n == 0) return hipSuccess;
+  // lanes per row: the power of two nearest the mean row length of A, 1..64
+  const int64_t avg = M.n ? (a_nnz + M.n - 1) / M.n : 1;
+  int G = 1;
+  while (G < 64 && G < avg) G <<= 1;
+  const int64_t threads = M.n * G;
+  const unsigned grid = (unsigned)((threads + 255) / 256);
+  MG_DISPATCH2(M, hipLaunchKernelGGL((k_rowinfo<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
+                                     (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, M.n,
+                                     G, cp, ip, minc, maxc, cls, stats));
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats* stats,
+                           hipStream_t st) {
+  // A: columns in [0, k), rows sorted not required; B: columns in [0, m), strictly ascending
+  const unsigned ga = (unsigned)((M.n + 1 + 255) / 256);
+  const unsigned gb = (unsigned)((M.k + 1 + 255) / 256);
+  MG_DISPATCH2(M, {
+    hipLaunchKernelGGL((k_validate<RP, CI>), ga, 256, 0, st, (const RP*)M.arp, (const CI*)M.acol,
+                       M.n, M.k, a_nnz, 0, stats);
+    hipLaunchKernelGGL((k_validate<RP, CI>), gb, 256, 0, st, (const RP*)M.brp, (const CI*)M.bcol,
+                       M.k, M.m, b_nnz, 1, stats);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_rows(const Mats& M, bool numeric, const int32_t* list, int64_t begin,
+                             int64_t count, const int64_t* minc, const int64_t* maxc, int shift,
+                             int block, int64_t* rownnz, const int64_t* crp, void* ccol,
+                             void* cval, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  MG_DISPATCH3(M, e = (dense_rows_t<RP, CI, V>(M, numeric, list + begin, count, minc, maxc, shift,
+                                                block, rownnz, crp, ccol, cval, st)));
+  return e;
+}
+
+}  // namespace mg

@@ -1,0 +1,11 @@
+// Declaration of the SORT-row launcher template (defined in k_sort_impl.h,
+// instantiated per value and row-pointer type in k_sort_*.hip).
+#pragma once
+#include "kernels.h"
+
+namespace mg {
+template <typename RP, typename CI, typename V>
+hipError_t sort_rows_cls(const Mats& M, int cls, bool numeric, const int32_t* list, int64_t count,
+                         const int64_t* minc, int colbits, int64_t* rownnz, const int64_t* crp,
+                         void* ccol, void* cval, DevStats* stats, hipStream_t st);
+}  // namespace mg

@@ -1,0 +1,252 @@
+#pragma once
+// SORT rows (expand, sort, merge; Algorithm 2) in two modes: count (precise
+// symbolic phase, Section 2.1) and numeric (values written straight into C at
+// the row offsets the symbolic phase produced).
+#include "common.h"
+#include "kernels.h"
+#include "k_sort_decl.h"
+
+namespace mg {
+
+MG_INLINE void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// SORT rows.  One wave per tile of R consecutive rows of one size class; the
+// tile's products (<= 64*E) are gathered into wave-private LDS with a
+// composite key (slot << colbits | col - minc), sorted by a register bitonic
+// network, then merged: count mode counts distinct keys per row, numeric mode
+// sums runs of equal keys (each run starting from +0.0) and writes them in
+// ascending column order at the row's offset in C.
+// ---------------------------------------------------------------------------
+constexpr int SR_WAVES = 4;
+
+template <typename K>
+MG_INLINE K key_max() { return (K)~(K)0; }
+
+template <typename RP, typename CI, typename V, int E, typename K, bool NUMERIC>
+__global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
+    k_sort_rows(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
+                const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
+                const int32_t* __restrict__ list, int64_t count, int R, int colbits,
+                const int64_t* __restrict__ minc, int64_t* rownnz, const int64_t* __restrict__ crp,
+                CI* ccol, V* cval, DevStats* stats) {
+  constexpr int CAP = MG_WAVE * E;
+  __shared__ K s_key[SR_WAVES][CAP];
+  __shared__ V s_val[SR_WAVES][NUMERIC ? CAP : 1];
+  __shared__ int32_t s_pre[SR_WAVES][MG_WAVE + 1];
+  __shared__ int64_t s_b0[SR_WAVES][MG_WAVE];
+  __shared__ V s_av[SR_WAVES][MG_WAVE];
+  __shared__ int32_t s_wslot[SR_WAVES][MG_WAVE];
+  __shared__ int64_t s_ent[SR_WAVES][MG_WAVE + 1];
+  __shared__ int64_t s_apos[SR_WAVES][MG_WAVE];
+  __shared__ int64_t s_minc[SR_WAVES][MG_WAVE];
+  __shared__ int32_t s_row[SR_WAVES][MG_WAVE];
+  __shared__ int32_t s_aux[SR_WAVES][MG_WAVE];
+
+  const int w = threadIdx.x / MG_WAVE;
+  const int l = lane();
+  const int64_t tile = (int64_t)blockIdx.x * SR_WAVES + w;
+  const int64_t r0 = tile * R;
+  if (r0 >= count) return;  // whole wave leaves together
+  const int nr = (int)((count - r0) < R ? (count - r0) : R);
+
+  int64_t ne = 0;
+  if (l < nr) {
+    const int32_t row = list[r0 + l];
+    const int64_t a0 = arp[row];
+    ne = (int64_t)arp[row + 1] - a0;
+    s_row[w][l] = row;
+    s_apos[w][l] = a0;
+    s_minc[w][l] = minc[row];
+  }
+  const int64_t einc = wave_incl_scan(ne);
+  s_ent[w][l] = einc - ne;
+  const int64_t ntot = __shfl(einc, MG_WAVE - 1, MG_WAVE);
+  if (l == 0) s_ent[w][MG_WAVE] = ntot;
+  s_aux[w][l] = 0;
+  wave_sync();
+
+  const K kmask = ((K)1 << colbits) - 1;
+  int P = 0;
+  for (int64_t f0 = 0; f0 < ntot; f0 += MG_WAVE) {
+    const int64_t f = f0 + l;
+    int len = 0, slot = 0;
+    int64_t b0 = 0;
+    V av = (V)0;
+    if (f < ntot) {
+      slot = upper_index(s_ent[w], 0, nr, f);
+      const int64_t p = s_apos[w][slot] + (f - s_ent[w][slot]);
+      const int64_t j = acol[p];
+      b0 = brp[j];
+      len = (int)((int64_t)brp[j + 1] - b0);
+      if (NUMERIC) av = aval[p];
+    }
+    const int inc = wave_incl_scan(len);
+    const int tot = __shfl(inc, MG_WAVE - 1, MG_WAVE);
+    s_pre[w][l] = inc - len;
+    s_b0[w][l] = b0;
+    s_av[w][l] = av;
+    s_wslot[w][l] = slot;
+    const int nvalid = (int)((ntot - f0) < MG_WAVE ? (ntot - f0) : MG_WAVE);
+    wave_sync();
+    if (P + tot > CAP) {
+      if (l == 0) atomicOr(&stats->err, ERR_STAGE_OVERFLOW);
+      return;
+    }
+    for (int q = l; q < tot; q += MG_WAVE) {
+      const int k = upper_index(s_pre[w], 0, nvalid, q);
+      const int64_t bi = s_b0[w][k] + (q - s_pre[w][k]);
+      const int64_t col = bcol[bi];
+      const int s = s_wslot[w][k];
+      s_key[w][P + q] = ((K)s << colbits) | (K)(col - s_minc[w][s]);
+      if (NUMERIC) s_val[w][P + q] = s_av[w][k] * bval[bi];
+    }
+    P += tot;
+    wave_sync();
+  }
+
+  // load (striped: the network sorts whatever order it is given)
+  K k[E];
+  V v[NUMERIC ? E : 1];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = e * MG_WAVE + l;
+    k[e] = (x < P) ? s_key[w][x] : key_max<K>();
+    if (NUMERIC) v[e] = (x < P) ? s_val[w][x] : (V)0;
+  }
+  if (NUMERIC) bitonic_sort_pairs<E>(k, *reinterpret_cast<V(*)[E]>(v));
+  else bitonic_sort_keys<E>(k);
+
+  // heads of runs of equal keys (blocked layout: element x = l*E + e)
+  const K prevk = __shfl_up(k[E - 1], 1, MG_WAVE);
+  bool head[E];
+  int hc = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = l * E + e;
+    const K pk = (e == 0) ? prevk : k[e - 1];
+    head[e] = (x < P) && (x == 0 || k[e] != pk);
+    hc += head[e] ? 1 : 0;
+  }
+  if (!NUMERIC) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (head[e]) atomicAdd(&s_aux[w][(int)(k[e] >> colbits)], 1);
+    wave_sync();
+    if (l < nr) rownnz[s_row[w][l]] = s_aux[w][l];
+    return;
+  } else {
+    const int hinc = wave_incl_scan(hc);
+    const int hbase = hinc - hc;
+    // rank of the first head of each slot
+    int hr = hbase;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      const K pk = (e == 0) ? prevk : k[e - 1];
+      if (head[e]) {
+        if (x == 0 || (k[e] >> colbits) != (pk >> colbits)) s_aux[w][(int)(k[e] >> colbits)] = hr;
+        ++hr;
+      }
+    }
+    // segmented sums: per lane (has_head, sum of its trailing run), then a
+    // segmented inclusive scan across lanes for the carry into each lane
+    V t = (V)0;
+    bool anyh = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (head[e]) { t = (V)0 + v[e]; anyh = true; }
+      else t = t + v[e];
+    }
+    V s = t;
+    bool f = anyh;
+#pragma unroll
+    for (int d = 1; d < MG_WAVE; d <<= 1) {
+      const V ps = __shfl_up(s, d, MG_WAVE);
+      const int pf = __shfl_up((int)f, d, MG_WAVE);
+      if (l >= d && !f) { s = ps + s; f = pf != 0; }
+    }
+    V carry = __shfl_up(s, 1, MG_WAVE);
+    if (l == 0) carry = (V)0;
+    wave_sync();
+    const K nextk = __shfl_down(k[0], 1, MG_WAVE);
+    V run = carry;
+    hr = hbase;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      if (head[e]) { run = (V)0 + v[e]; ++hr; }
+      else run = run + v[e];
+      const K nk = (e == E - 1) ? nextk : k[e + 1];
+      const bool tail = (x < P) && (x == P - 1 || nk != k[e]);
+      if (tail) {
+        const int sl = (int)(k[e] >> colbits);
+        const int64_t pos = crp[s_row[w][sl]] + (hr - 1 - s_aux[w][sl]);
+        ccol[pos] = (CI)(s_minc[w][sl] + (int64_t)(k[e] & kmask));
+        cval[pos] = run;
+      }
+    }
+  }
+}
+
+template <typename RP, typename CI, typename V, int E, typename K>
+static hipError_t sort_rows_t(const Mats& M, bool numeric, const int32_t* list, int64_t count,
+                              int R, int colbits, const int64_t* minc, int64_t* rownnz,
+                              const int64_t* crp, void* ccol, void* cval, DevStats* stats,
+                              hipStream_t st) {
+  const int64_t tiles = (count + R - 1) / R;
+  const unsigned grid = (unsigned)((tiles + SR_WAVES - 1) / SR_WAVES);
+  if (grid == 0) return hipSuccess;
+  if (numeric)
+    hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, true>), grid, SR_WAVES * MG_WAVE, 0, st,
+                       (const RP*)M.arp, (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp,
+                       (const CI*)M.bcol, (const V*)M.bval, list, count, R, colbits, minc, rownnz,
+                       crp, (CI*)ccol, (V*)cval, stats);
+  else
+    hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, false>), grid, SR_WAVES * MG_WAVE, 0, st,
+                       (const RP*)M.arp, (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp,
+                       (const CI*)M.bcol, (const V*)M.bval, list, count, R, colbits, minc, rownnz,
+                       crp, (CI*)ccol, (V*)cval, stats);
+  return hipGetLastError();
+}
+
+template <typename RP, typename CI, typename V>
+hipError_t sort_rows_cls(const Mats& M, int cls, bool numeric, const int32_t* list,
+                                int64_t count, const int64_t* minc, int colbits, int64_t* rownnz,
+                                const int64_t* crp, void* ccol, void* cval, DevStats* stats,
+                                hipStream_t st) {
+  // class c holds rows with ip in (2^(c-1), 2^c]: E = max(1, 2^c / 64) per
+  // lane, R = 64 * E / 2^c rows per wave
+  const int E = (cls <= 6) ? 1 : (1 << (cls - 6));
+  const int R = (cls <= 6) ? (64 >> cls) : 1;
+  int slotbits = 0;
+  while ((1 << slotbits) < R) ++slotbits;
+  const bool k64 = (colbits + slotbits) > 31;
+#define MG_SR(EE)                                                                               \
+  if (E == EE) {                                                                                \
+    if (k64)                                                                                    \
+      return sort_rows_t<RP, CI, V, EE, uint64_t>(M, numeric, list, count, R, colbits, minc,    \
+                                                  rownnz, crp, ccol, cval, stats, st);          \
+    return sort_rows_t<RP, CI, V, EE, uint32_t>(M, numeric, list, count, R, colbits, minc,      \
+                                                rownnz, crp, ccol, cval, stats, st);            \
+  }
+  MG_SR(1) MG_SR(2) MG_SR(4) MG_SR(8) MG_SR(16)
+#undef MG_SR
+  return hipErrorInvalidValue;
+}
+
+
+#define MG_SORT_INSTANTIATE(RP, V)                                                               \
+  template hipError_t sort_rows_cls<RP, int32_t, V>(const Mats&, int, bool, const int32_t*,      \
+                                                     int64_t, const int64_t*, int, int64_t*,     \
+                                                     const int64_t*, void*, void*, DevStats*,    \
+                                                     hipStream_t);                               \
+  template hipError_t sort_rows_cls<RP, int64_t, V>(const Mats&, int, bool, const int32_t*,      \
+                                                     int64_t, const int64_t*, int, int64_t*,     \
+                                                     const int64_t*, void*, void*, DevStats*,    \
+                                                     hipStream_t);
+
+}  // namespace mg

@@ -1,0 +1,141 @@
+// Internal launch interface between the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mg {
+
+// Row classes: 0..10 are SORT rows with ip in (2^(c-1), 2^c]; then DENSE,
+// CHUNKED, EMPTY.
+constexpr int NSORT_CLS = 11;
+constexpr int CLS_DENSE = 11;
+constexpr int CLS_CHUNKED = 12;
+constexpr int CLS_EMPTY = 13;
+constexpr int NCLS = 16;
+constexpr int SORT_CAP = 1024;  // products one wave sorts (64 lanes x 16)
+
+// Device-side statistics of a plan (one struct in device memory).
+struct DevStats {
+  unsigned long long ip_total;
+  unsigned long long max_ip;
+  unsigned long long max_range;
+  unsigned long long ip_cat[4];
+  unsigned long long rows_cat[4];
+  unsigned int err;  // bit flags, see ERR_*
+  unsigned int pad;
+};
+constexpr unsigned ERR_STAGE_OVERFLOW = 1u;
+constexpr unsigned ERR_INVALID_CSR = 2u;
+constexpr unsigned ERR_BIN_OVERFLOW = 4u;
+
+// Device views of A (n x k) and B (k x m) sharing index types.
+struct Mats {
+  const void *arp, *acol, *aval;
+  const void *brp, *bcol, *bval;
+  int64_t n, k, m;
+  int rp64, col64, f64;
+};
+
+struct ClassParams {
+  int64_t sort_max;   // SORT iff ip < sort_max (<= SORT_CAP)
+  int64_t dense_max;  // DENSE iff column range <= dense_max
+  int force;          // -1 auto, else category
+};
+
+size_t scan_temp_bytes(int64_t n);
+hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total,
+                         const int64_t* carry, void* temp, hipStream_t st);
+hipError_t scan_excl_i32(const int32_t* in, int64_t* out, int64_t n, int64_t* total,
+                         const int64_t* carry, void* temp, hipStream_t st);
+
+// --- row level (k_rows.hip) ---
+hipError_t launch_rowinfo(const Mats& M, int64_t a_nnz, const ClassParams& cp, int64_t* ip,
+                          int64_t* minc, int64_t* maxc, int32_t* cls, DevStats* stats,
+                          hipStream_t st);
+hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats* stats,
+                           hipStream_t st);
+// Stable partition of rows by class: list (int32 row ids) and list_off[NCLS+1].
+size_t classify_temp_bytes(int64_t n);
+hipError_t launch_classify(const int32_t* cls, int64_t n, int32_t* list, int64_t* list_off,
+                           void* temp, hipStream_t st);
+// SORT rows of class c (count mode writes rownnz; numeric writes C).
+hipError_t launch_sort_rows(const Mats& M, int cls, bool numeric, const int32_t* list,
+                            int64_t begin, int64_t count, const int64_t* minc, int colbits,
+                            int64_t* rownnz, const int64_t* crp, void* ccol, void* cval,
+                            DevStats* stats, hipStream_t st);
+// DENSE rows: one workgroup per row, column range <= 2^shift.
+hipError_t launch_dense_rows(const Mats& M, bool numeric, const int32_t* list, int64_t begin,
+                             int64_t count, const int64_t* minc, const int64_t* maxc, int shift,
+                             int block, int64_t* rownnz, const int64_t* crp, void* ccol,
+                             void* cval, hipStream_t st);
+size_t dense_rows_lds(int f64, int shift, int block);
+
+// --- chunked rows (k_bins.hip) ---
+struct ChunkGeom {
+  // per CHUNKED row k (list order), all int64 arrays of nchunked(+1) entries
+  const int32_t* rows;   // row ids (slice of the class list)
+  const int64_t* ip;     // per-row ip (indexed by row id)
+  const int64_t* minc;   // per-row min column (by row id)
+  const int64_t* maxc;   // per-row max column (by row id)
+  int64_t* nb;           // bins per row                      [nch]
+  int64_t* nt;           // tiles per row                     [nch]
+  int64_t* tabsz;        // nb*nt                             [nch]
+  int64_t* binBase;      // exclusive scan of nb              [nch+1]
+  int64_t* tileBase;     // exclusive scan of nt              [nch+1]
+  int64_t* tabBase;      // exclusive scan of tabsz           [nch+1]
+  int64_t* ipBase;       // exclusive scan of ip              [nch+1]
+  int64_t nch;
+  int shift;             // chunk length 2^shift
+  int tile;              // products per tile (power of two)
+};
+hipError_t launch_chunk_geom(const ChunkGeom& g, hipStream_t st);
+// first_of[s] (int32, pre-filled with -1) and bases[4*s] for batch slots of W products
+hipError_t launch_batch_bounds(const ChunkGeom& g, int64_t W, int32_t* first_of, int64_t* bases,
+                               hipStream_t st);
+hipError_t launch_aoff(const Mats& M, const int32_t* rows, int64_t nrows, int64_t* aoff,
+                       hipStream_t st);
+hipError_t launch_tiles(const int64_t* nt, const int64_t* tileBase, int64_t k0, int64_t k1,
+                        int32_t* tile_row, hipStream_t st);
+
+struct BatchArgs {
+  int64_t k0, k1;          // CHUNKED list range of the batch
+  int64_t tile0, ntiles;   // global tile range
+  int64_t tab0, ntab;      // global table range
+  int64_t bin0, nbins;     // global bin range
+  int64_t ip0, nip;        // global product range (batch workspace offset = ip - ip0)
+};
+hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+                           const int32_t* tile_row, const int64_t* aoff, int32_t* tab_cnt,
+                           int64_t max_nb, hipStream_t st);
+hipError_t launch_bin_scatter(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
+                              const int32_t* tile_row, const int64_t* aoff, const int32_t* tab_cnt,
+                              const int64_t* tab_off, uint16_t* ws_col, void* ws_val,
+                              int64_t max_nb, DevStats* stats, hipStream_t st);
+size_t bin_scatter_lds(int f64, int tile, int64_t max_nb);
+// chunk start / size / row from the table; items: dense chunks and packed sort groups
+hipError_t launch_bin_items(const ChunkGeom& g, const BatchArgs& b, const int64_t* tab_off,
+                            int64_t* bin_start, int64_t* bin_cnt, int32_t* bin_row,
+                            int64_t dense_min, int64_t group_max, int64_t* dense_items,
+                            int64_t* sort_items, int32_t* item_counts, hipStream_t st);
+hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric, int f64,
+                            const int64_t* bin_start, const int64_t* bin_cnt,
+                            const int32_t* bin_row, const int64_t* dense_items,
+                            const int64_t* sort_items, const int32_t* item_counts,
+                            const uint16_t* ws_col, const void* ws_val, int64_t* bin_nnz,
+                            const int64_t* bin_out, void* ccol, int col64, void* cval,
+                            int dense_block, hipStream_t st);
+size_t bin_dense_lds(int f64, int shift);
+// per CHUNKED row: rownnz = sum of its bins' nnz (count mode) / bin output
+// offsets from crp (numeric prep)
+hipError_t launch_bin_rows(const ChunkGeom& g, int64_t k0, int64_t k1, const int64_t* bin_nnz,
+                           int64_t* rownnz, const int64_t* crp, int64_t* bin_out, bool to_out,
+                           hipStream_t st);
+
+// --- misc (k_rows.hip) ---
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+hipError_t launch_write_rowptr(const int64_t* crp, int64_t n, void* out, int out64,
+                               hipStream_t st);
+
+}  // namespace mg

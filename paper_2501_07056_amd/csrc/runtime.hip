@@ -1,0 +1,710 @@
+// Host runtime and C ABI: plans the setup and precise symbolic phases, then
+// runs the numeric phase into caller-owned C (see include/magnus.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "magnus.h"
+
+using namespace mg;
+
+struct magnus_handle_s {
+  int device = 0;
+  magnus_options_t opts{};
+  magnus_alloc_fn alloc_fn = nullptr;
+  magnus_free_fn free_fn = nullptr;
+  void* alloc_ctx = nullptr;
+  std::string err;
+  int lds_max = 65536;
+  int cus = 0;
+};
+
+namespace {
+
+struct Alloc {
+  void* p;
+  size_t n;
+};
+
+void* default_alloc(size_t n, void*, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, n ? n : 1) != hipSuccess) return nullptr;
+  return p;
+}
+void default_free(void* p, size_t, void*, void*) { (void)hipFree(p); }
+
+int bits_for(int64_t range) {
+  int b = 1;
+  while (b < 62 && ((int64_t)1 << b) < range) ++b;
+  return b;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct magnus_plan_s {
+  magnus_handle_s* h = nullptr;
+  hipStream_t st = nullptr;
+  std::vector<Alloc> allocs;
+  Mats M{};
+  int64_t a_nnz = 0, b_nnz = 0, n = 0;
+  int vtype = 0, itype_rp = 0, itype_col = 0;
+  // per-row arrays
+  int64_t *ip = nullptr, *minc = nullptr, *maxc = nullptr, *crp = nullptr;
+  int32_t *cls = nullptr, *list = nullptr;
+  int64_t* list_off = nullptr;
+  DevStats* stats = nullptr;
+  void* temp = nullptr;
+  int64_t h_list_off[NCLS + 1]{};
+  DevStats h_stats{};
+  int shift = 13, colbits = 1, dense_block = 256, tile = 4096;
+  int64_t sort_max = 1025, dense_min = 1024, group_max = 1024;
+  // CHUNKED rows
+  int64_t nch = 0, max_nb = 1;
+  ChunkGeom g{};
+  int64_t *aoff = nullptr, *tab_off = nullptr;
+  int32_t *tile_row = nullptr, *tab_cnt = nullptr, *bin_row = nullptr, *item_counts = nullptr;
+  int64_t *bin_start = nullptr, *bin_cnt = nullptr, *bin_nnz = nullptr, *bin_out = nullptr;
+  int64_t *dense_items = nullptr, *sort_items = nullptr;
+  uint16_t* ws_col = nullptr;
+  void* ws_val = nullptr;
+  void* tab_temp = nullptr;
+  int64_t ws_products = 0;
+  std::vector<BatchArgs> batches;
+  int64_t nnz_c = 0;
+  magnus_plan_info_t info{};
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+namespace {
+
+magnus_status_t fail_hip(magnus_handle_s* h, hipError_t e, const char* where) {
+  if (h) h->err = std::string(where) + ": " + hipGetErrorString(e);
+  return MAGNUS_ERR_HIP;
+}
+
+#define HIPCHK(expr)                                      \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return fail_hip(h, e_, #expr);  \
+  } while (0)
+
+void* palloc(magnus_plan_s* P, size_t bytes) {
+  magnus_handle_s* h = P->h;
+  bytes = align256(bytes ? bytes : 1);
+  void* p = h->alloc_fn ? h->alloc_fn(bytes, (void*)P->st, h->alloc_ctx)
+                        : default_alloc(bytes, nullptr, nullptr);
+  if (p) P->allocs.push_back({p, bytes});
+  return p;
+}
+
+void plan_free_all(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  for (auto& a : P->allocs) {
+    if (h && h->free_fn) h->free_fn(a.p, a.n, (void*)P->st, h->alloc_ctx);
+    else default_free(a.p, a.n, nullptr, nullptr);
+  }
+  P->allocs.clear();
+  if (P->pinned) (void)hipHostFree(P->pinned);
+  P->pinned = nullptr;
+}
+
+magnus_status_t check_csr(const magnus_csr_t* X) {
+  if (!X) return MAGNUS_ERR_INVALID_ARG;
+  if (X->nrows < 0 || X->ncols < 0 || X->nnz < 0) return MAGNUS_ERR_INVALID_ARG;
+  if ((X->rowptr_type != MAGNUS_I32 && X->rowptr_type != MAGNUS_I64) ||
+      (X->col_type != MAGNUS_I32 && X->col_type != MAGNUS_I64) ||
+      (X->val_type != MAGNUS_F32 && X->val_type != MAGNUS_F64))
+    return MAGNUS_ERR_INVALID_ARG;
+  if (!X->rowptr) return MAGNUS_ERR_INVALID_ARG;
+  if (X->nnz > 0 && (!X->col || !X->val)) return MAGNUS_ERR_INVALID_ARG;
+  if (X->rowptr_type == MAGNUS_I32 && X->nnz > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  if (X->col_type == MAGNUS_I32 && X->ncols > (int64_t)INT32_MAX + 1) return MAGNUS_ERR_INDEX_OVERFLOW;
+  return MAGNUS_OK;
+}
+
+magnus_status_t readback(magnus_plan_s* P, const std::vector<std::pair<const void*, size_t>>& src,
+                         std::vector<void*> dst) {
+  magnus_handle_s* h = P->h;
+  size_t tot = 0;
+  for (auto& s : src) tot += align256(s.second);
+  if (tot > P->pinned_bytes) {
+    if (P->pinned) (void)hipHostFree(P->pinned);
+    P->pinned = nullptr;
+    HIPCHK(hipHostMalloc(&P->pinned, tot, hipHostMallocDefault));
+    P->pinned_bytes = tot;
+  }
+  size_t off = 0;
+  for (auto& s : src) {
+    if (s.second) HIPCHK(hipMemcpyAsync((char*)P->pinned + off, s.first, s.second,
+                                        hipMemcpyDeviceToHost, P->st));
+    off += align256(s.second);
+  }
+  HIPCHK(hipStreamSynchronize(P->st));
+  off = 0;
+  for (size_t i = 0; i < src.size(); ++i) {
+    if (src[i].second) memcpy(dst[i], (char*)P->pinned + off, src[i].second);
+    off += align256(src[i].second);
+  }
+  return MAGNUS_OK;
+}
+
+int default_shift(int f64, int lds_budget) {
+  // largest 2^s with s_val * 2^s + 2^s / 8 bytes <= half the LDS budget (two
+  // dense workgroups per CU), capped at 2^16 (16-bit chunk-local columns)
+  const double per = (f64 ? 8.0 : 4.0) + 0.125;
+  int s = 8;
+  while (s < 16 && per * (double)((int64_t)1 << (s + 1)) + 1024 <= lds_budget / 2.0) ++s;
+  return s;
+}
+
+magnus_status_t setup_chunked(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  const magnus_options_t& o = h->opts;
+  const int64_t nch = P->nch;
+  ChunkGeom& g = P->g;
+  g.rows = P->list + P->h_list_off[CLS_CHUNKED];
+  g.ip = P->ip;
+  g.minc = P->minc;
+  g.maxc = P->maxc;
+  g.nch = nch;
+  g.shift = P->shift;
+  g.tile = P->tile;
+  int64_t* geo = (int64_t*)palloc(P, sizeof(int64_t) * (3 * nch + 4 * (nch + 1)));
+  if (!geo) return MAGNUS_ERR_OOM;
+  g.nb = geo;
+  g.nt = geo + nch;
+  g.tabsz = geo + 2 * nch;
+  g.binBase = geo + 3 * nch;
+  g.tileBase = g.binBase + (nch + 1);
+  g.tabBase = g.tileBase + (nch + 1);
+  g.ipBase = g.tabBase + (nch + 1);
+  void* tmp = palloc(P, scan_temp_bytes(nch + 1));
+  if (!tmp) return MAGNUS_ERR_OOM;
+  HIPCHK(launch_chunk_geom(g, P->st));
+  HIPCHK(scan_excl_i64(g.nb, g.binBase, nch, g.binBase + nch, nullptr, tmp, P->st));
+  HIPCHK(scan_excl_i64(g.nt, g.tileBase, nch, g.tileBase + nch, nullptr, tmp, P->st));
+  HIPCHK(scan_excl_i64(g.tabsz, g.tabBase, nch, g.tabBase + nch, nullptr, tmp, P->st));
+  HIPCHK(scan_excl_i64(g.ipBase, g.ipBase, nch, g.ipBase + nch, nullptr, tmp, P->st));
+
+  // products per batch
+  const int64_t vs = P->M.f64 ? 8 : 4;
+  int64_t W = o.batch_products;
+  if (W <= 0) {
+    int64_t budget = o.max_workspace_bytes;
+    if (budget <= 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      budget = (int64_t)(0.25 * (double)fr);
+    }
+    W = budget / (2 + vs);
+  }
+  const int64_t ipch = (int64_t)P->h_stats.ip_cat[2];
+  if (W < (int64_t)P->h_stats.max_ip) W = (int64_t)P->h_stats.max_ip;
+  if (W < 1) W = 1;
+  const int64_t nslots = ipch / W + 1;
+  int32_t* first_of = (int32_t*)palloc(P, sizeof(int32_t) * nslots);
+  int64_t* bases = (int64_t*)palloc(P, sizeof(int64_t) * 4 * nslots);
+  if (!first_of || !bases) return MAGNUS_ERR_OOM;
+  HIPCHK(hipMemsetAsync(first_of, 0xFF, sizeof(int32_t) * nslots, P->st));
+  HIPCHK(launch_batch_bounds(g, W, first_of, bases, P->st));
+  std::vector<int32_t> h_first(nslots);
+  std::vector<int64_t> h_bases(4 * nslots);
+  int64_t tots[4];
+  magnus_status_t s = readback(
+      P,
+      {{first_of, sizeof(int32_t) * nslots},
+       {bases, sizeof(int64_t) * 4 * nslots},
+       {g.ipBase + nch, 8},
+       {g.tileBase + nch, 8},
+       {g.tabBase + nch, 8},
+       {g.binBase + nch, 8}},
+      {h_first.data(), h_bases.data(), &tots[0], &tots[1], &tots[2], &tots[3]});
+  if (s != MAGNUS_OK) return s;
+  // batches in slot order
+  std::vector<int64_t> starts;
+  for (int64_t q = 0; q < nslots; ++q)
+    if (h_first[q] >= 0) starts.push_back(q);
+  P->batches.clear();
+  P->ws_products = 0;
+  int64_t max_ntab = 0, max_tiles = 0;
+  for (size_t b = 0; b < starts.size(); ++b) {
+    const int64_t q = starts[b];
+    BatchArgs ba{};
+    ba.k0 = h_first[q];
+    ba.ip0 = h_bases[4 * q + 0];
+    ba.tile0 = h_bases[4 * q + 1];
+    ba.tab0 = h_bases[4 * q + 2];
+    ba.bin0 = h_bases[4 * q + 3];
+    if (b + 1 < starts.size()) {
+      const int64_t q2 = starts[b + 1];
+      ba.k1 = h_first[q2];
+      ba.nip = h_bases[4 * q2 + 0] - ba.ip0;
+      ba.ntiles = h_bases[4 * q2 + 1] - ba.tile0;
+      ba.ntab = h_bases[4 * q2 + 2] - ba.tab0;
+      ba.nbins = h_bases[4 * q2 + 3] - ba.bin0;
+    } else {
+      ba.k1 = nch;
+      ba.nip = tots[0] - ba.ip0;
+      ba.ntiles = tots[1] - ba.tile0;
+      ba.ntab = tots[2] - ba.tab0;
+      ba.nbins = tots[3] - ba.bin0;
+    }
+    P->ws_products = std::max(P->ws_products, ba.nip);
+    max_ntab = std::max(max_ntab, ba.ntab);
+    max_tiles = std::max(max_tiles, ba.ntiles);
+    P->batches.push_back(ba);
+  }
+  if (max_tiles > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  const int64_t ntiles = tots[1], ntab = tots[2], nbins = tots[3];
+  const int64_t nbat = (int64_t)P->batches.size();
+  P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
+  P->tile_row = (int32_t*)palloc(P, sizeof(int32_t) * ntiles);
+  P->tab_cnt = (int32_t*)palloc(P, sizeof(int32_t) * ntab);
+  P->tab_off = (int64_t*)palloc(P, sizeof(int64_t) * ntab);
+  P->bin_start = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_cnt = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_nnz = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_out = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_row = (int32_t*)palloc(P, sizeof(int32_t) * nbins);
+  P->dense_items = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->sort_items = (int64_t*)palloc(P, sizeof(int64_t) * 2 * nbins);
+  P->item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2 * nbat);
+  P->ws_col = (uint16_t*)palloc(P, sizeof(uint16_t) * P->ws_products);
+  P->ws_val = palloc(P, (size_t)vs * P->ws_products);
+  P->tab_temp = palloc(P, scan_temp_bytes(max_ntab));
+  if (!P->aoff || !P->tile_row || !P->tab_cnt || !P->tab_off || !P->bin_start || !P->bin_cnt ||
+      !P->bin_nnz || !P->bin_out || !P->bin_row || !P->dense_items || !P->sort_items ||
+      !P->item_counts || !P->ws_col || !P->ws_val || !P->tab_temp)
+    return MAGNUS_ERR_OOM;
+  HIPCHK(hipMemsetAsync(P->item_counts, 0, sizeof(int32_t) * 2 * nbat, P->st));
+  HIPCHK(hipMemsetAsync(P->bin_nnz, 0, sizeof(int64_t) * nbins, P->st));
+  HIPCHK(launch_aoff(P->M, g.rows, nch, P->aoff, P->st));
+  HIPCHK(launch_tiles(g.nt, g.tileBase, 0, nch, P->tile_row, P->st));
+  P->info.n_batches = nbat;
+  P->info.n_bins = nbins;
+  return MAGNUS_OK;
+}
+
+magnus_status_t run_chunked(magnus_plan_s* P, bool numeric, void* ccol, int col64, void* cval) {
+  magnus_handle_s* h = P->h;
+  for (size_t bi = 0; bi < P->batches.size(); ++bi) {
+    const BatchArgs& b = P->batches[bi];
+    int32_t* ic = P->item_counts + 2 * bi;
+    if (!numeric) {
+      HIPCHK(launch_bin_hist(P->M, P->g, b, P->tile_row, P->aoff, P->tab_cnt, P->max_nb, P->st));
+      HIPCHK(scan_excl_i32(P->tab_cnt + b.tab0, P->tab_off + b.tab0, b.ntab, nullptr, nullptr,
+                           P->tab_temp, P->st));
+    } else {
+      HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, nullptr, P->crp, P->bin_out, true,
+                             P->st));
+    }
+    HIPCHK(launch_bin_scatter(P->M, P->g, b, numeric, P->tile_row, P->aoff, P->tab_cnt, P->tab_off,
+                              P->ws_col, P->ws_val, P->max_nb, P->stats, P->st));
+    if (!numeric)
+      HIPCHK(launch_bin_items(P->g, b, P->tab_off, P->bin_start, P->bin_cnt, P->bin_row,
+                              P->dense_min, P->group_max, P->dense_items, P->sort_items, ic,
+                              P->st));
+    HIPCHK(launch_bin_accum(P->g, b, numeric, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
+                            P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
+                            P->bin_out, ccol, col64, cval, P->dense_block, P->st));
+    if (!numeric)
+      HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false,
+                             P->st));
+  }
+  return MAGNUS_OK;
+}
+
+magnus_status_t run_rows(magnus_plan_s* P, bool numeric, void* ccol, void* cval) {
+  magnus_handle_s* h = P->h;
+  for (int c = 0; c < NSORT_CLS; ++c) {
+    const int64_t cnt = P->h_list_off[c + 1] - P->h_list_off[c];
+    if (cnt > 0)
+      HIPCHK(launch_sort_rows(P->M, c, numeric, P->list, P->h_list_off[c], cnt, P->minc,
+                              P->colbits, P->crp, P->crp, ccol, cval, P->stats, P->st));
+  }
+  const int64_t nd = P->h_list_off[CLS_DENSE + 1] - P->h_list_off[CLS_DENSE];
+  if (nd > 0)
+    HIPCHK(launch_dense_rows(P->M, numeric, P->list, P->h_list_off[CLS_DENSE], nd, P->minc,
+                             P->maxc, P->shift, P->dense_block, P->crp, P->crp, ccol, cval,
+                             P->st));
+  return MAGNUS_OK;
+}
+
+magnus_status_t make_mats(const magnus_csr_t* A, const magnus_csr_t* B, Mats& M) {
+  magnus_status_t s = check_csr(A);
+  if (s != MAGNUS_OK) return s;
+  s = check_csr(B);
+  if (s != MAGNUS_OK) return s;
+  if (A->ncols != B->nrows) return MAGNUS_ERR_SHAPE;
+  if (A->rowptr_type != B->rowptr_type || A->col_type != B->col_type ||
+      A->val_type != B->val_type)
+    return MAGNUS_ERR_DTYPE;
+  if (A->nrows > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  M.arp = A->rowptr;
+  M.acol = A->col;
+  M.aval = A->val;
+  M.brp = B->rowptr;
+  M.bcol = B->col;
+  M.bval = B->val;
+  M.n = A->nrows;
+  M.k = A->ncols;
+  M.m = B->ncols;
+  M.rp64 = A->rowptr_type == MAGNUS_I64;
+  M.col64 = A->col_type == MAGNUS_I64;
+  M.f64 = A->val_type == MAGNUS_F64;
+  return MAGNUS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* magnus_status_string(magnus_status_t s) {
+  switch (s) {
+    case MAGNUS_OK: return "MAGNUS_OK";
+    case MAGNUS_ERR_INVALID_ARG: return "MAGNUS_ERR_INVALID_ARG";
+    case MAGNUS_ERR_SHAPE: return "MAGNUS_ERR_SHAPE";
+    case MAGNUS_ERR_DTYPE: return "MAGNUS_ERR_DTYPE";
+    case MAGNUS_ERR_INVALID_CSR: return "MAGNUS_ERR_INVALID_CSR";
+    case MAGNUS_ERR_INDEX_OVERFLOW: return "MAGNUS_ERR_INDEX_OVERFLOW";
+    case MAGNUS_ERR_CAPACITY: return "MAGNUS_ERR_CAPACITY";
+    case MAGNUS_ERR_WORKSPACE: return "MAGNUS_ERR_WORKSPACE";
+    case MAGNUS_ERR_OOM: return "MAGNUS_ERR_OOM";
+    case MAGNUS_ERR_REJECTED: return "MAGNUS_ERR_REJECTED";
+    case MAGNUS_ERR_HIP: return "MAGNUS_ERR_HIP";
+    case MAGNUS_ERR_NOT_READY: return "MAGNUS_ERR_NOT_READY";
+    case MAGNUS_ERR_INTERNAL: return "MAGNUS_ERR_INTERNAL";
+  }
+  return "MAGNUS_ERR_UNKNOWN";
+}
+
+const char* magnus_last_error(magnus_handle_t h) { return h ? h->err.c_str() : ""; }
+
+void magnus_options_default(magnus_options_t* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->force_category = MAGNUS_CAT_AUTO;
+  o->sort_max = 0;
+  o->chunk_shift = 0;
+  o->bin_dense_min = 0;
+  o->tile_products = 0;
+  o->dense_block = 0;
+  o->batch_products = 0;
+  o->max_workspace_bytes = 0;
+  o->validate = 0;
+  o->lds_bytes = 0;
+  o->sort_group_max = 0;
+}
+
+magnus_status_t magnus_create(magnus_handle_t* out, int device, const magnus_options_t* opts) {
+  if (!out) return MAGNUS_ERR_INVALID_ARG;
+  *out = nullptr;
+  magnus_handle_s* h = new magnus_handle_s();
+  h->device = device;
+  magnus_options_default(&h->opts);
+  if (opts) h->opts = *opts;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev) {
+    h->err = "no such HIP device";
+    delete h;
+    return e != hipSuccess ? MAGNUS_ERR_HIP : MAGNUS_ERR_INVALID_ARG;
+  }
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess)
+    h->lds_max = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
+    h->cus = v;
+  *out = h;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_destroy(magnus_handle_t h) {
+  delete h;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_set_options(magnus_handle_t h, const magnus_options_t* o) {
+  if (!h || !o) return MAGNUS_ERR_INVALID_ARG;
+  h->opts = *o;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_set_allocator(magnus_handle_t h, magnus_alloc_fn a, magnus_free_fn f,
+                                     void* ctx) {
+  if (!h || (!a) != (!f)) return MAGNUS_ERR_INVALID_ARG;
+  h->alloc_fn = a;
+  h->free_fn = f;
+  h->alloc_ctx = ctx;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_gpu_chunk_shift(int32_t val_type, int64_t lds_bytes, int32_t* shift) {
+  if (!shift || lds_bytes <= 0 || (val_type != MAGNUS_F32 && val_type != MAGNUS_F64))
+    return MAGNUS_ERR_INVALID_ARG;
+  *shift = default_shift(val_type == MAGNUS_F64, (int)std::min<int64_t>(lds_bytes, 1 << 30));
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_paper_chunk_model(int64_t m_c, int64_t s_cache, int64_t s_line,
+                                         double s_dense_accum, int64_t* nf, int64_t* nco,
+                                         int64_t* mcmax) {
+  if (m_c < 1 || s_cache < 1 || s_line < 1 || !(s_dense_accum > 0) || !nf || !nco || !mcmax)
+    return MAGNUS_ERR_INVALID_ARG;
+  // Eq. 2-7 of Section 3.5; m_C ceiled to a power of two, m_CmaxL2 floored,
+  // fine chunk counts rounded to the power of two nearest in log2
+  int64_t mc = 1;
+  while (mc < m_c) mc <<= 1;
+  const double sc = 4.0 + 4.0 + 2.0 * (double)s_line;
+  auto nearest = [](double x) -> int64_t {
+    if (x <= 1.0) return 1;
+    const double e = std::log2(x);
+    const double lo = std::floor(e);
+    return (int64_t)1 << (int)((e - lo >= 0.5) ? lo + 1 : lo);
+  };
+  const double mx = (double)s_cache * (double)s_cache / (4.0 * s_dense_accum * sc);
+  int64_t m2 = 1;
+  while ((double)(m2 * 2) <= mx) m2 <<= 1;
+  *mcmax = m2;
+  const bool fits = 2.0 * std::sqrt((double)mc * s_dense_accum * sc) < (double)s_cache;
+  if (fits) {
+    *nf = std::min<int64_t>(nearest(std::sqrt((double)mc * s_dense_accum / sc)), mc);
+    *nco = 1;
+  } else {
+    *nf = std::min<int64_t>(nearest(std::sqrt((double)m2 * s_dense_accum / sc)), m2);
+    *nco = std::max<int64_t>(1, mc / m2);
+  }
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                            void* stream, magnus_plan_t* out, magnus_plan_info_t* info) {
+  if (!h || !out) return MAGNUS_ERR_INVALID_ARG;
+  *out = nullptr;
+  Mats M{};
+  magnus_status_t s = make_mats(A, B, M);
+  if (s != MAGNUS_OK) return s;
+  HIPCHK(hipSetDevice(h->device));
+  magnus_plan_s* P = new magnus_plan_s();
+  P->h = h;
+  P->st = (hipStream_t)stream;
+  P->M = M;
+  P->a_nnz = A->nnz;
+  P->b_nnz = B->nnz;
+  P->n = A->nrows;
+  P->vtype = A->val_type;
+  P->itype_rp = A->rowptr_type;
+  P->itype_col = A->col_type;
+  const magnus_options_t& o = h->opts;
+  const int lds = o.lds_bytes > 0 ? std::min(o.lds_bytes, h->lds_max) : h->lds_max;
+  P->shift = o.chunk_shift > 0 ? std::min(o.chunk_shift, 16) : default_shift(M.f64, lds);
+  P->sort_max = o.sort_max > 0 ? std::min<int64_t>(o.sort_max, SORT_CAP + 1) : SORT_CAP + 1;
+  P->group_max = o.sort_group_max > 0 ? std::min<int64_t>(o.sort_group_max, SORT_CAP) : SORT_CAP;
+  P->dense_min = o.bin_dense_min > 0 ? o.bin_dense_min : P->group_max;
+  if (P->dense_min > P->group_max + 1) P->dense_min = P->group_max + 1;
+  P->tile = o.tile_products > 0 ? o.tile_products : 4096;
+  if (P->tile < 256 || P->tile > 16384 || (P->tile & (P->tile - 1))) P->tile = 4096;
+  P->dense_block = (o.dense_block == 512 || o.dense_block == 1024) ? o.dense_block : 256;
+
+  auto cleanup = [&](magnus_status_t st) {
+    plan_free_all(P);
+    delete P;
+    return st;
+  };
+  const int64_t n = P->n;
+  P->stats = (DevStats*)palloc(P, sizeof(DevStats));
+  P->ip = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(n, 1));
+  P->minc = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(n, 1));
+  P->maxc = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(n, 1));
+  P->crp = (int64_t*)palloc(P, sizeof(int64_t) * (n + 1));
+  P->cls = (int32_t*)palloc(P, sizeof(int32_t) * std::max<int64_t>(n, 1));
+  P->list = (int32_t*)palloc(P, sizeof(int32_t) * std::max<int64_t>(n, 1));
+  P->list_off = (int64_t*)palloc(P, sizeof(int64_t) * (NCLS + 1));
+  P->temp = palloc(P, std::max(classify_temp_bytes(n), scan_temp_bytes(n + 1)) + 1024);
+  if (!P->stats || !P->ip || !P->minc || !P->maxc || !P->crp || !P->cls || !P->list ||
+      !P->list_off || !P->temp)
+    return cleanup(MAGNUS_ERR_OOM);
+
+#define PCHK(expr)                                        \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return cleanup(fail_hip(h, e_, #expr)); \
+  } while (0)
+#define SCHK(expr)                                        \
+  do {                                                    \
+    magnus_status_t s_ = (expr);                          \
+    if (s_ != MAGNUS_OK) return cleanup(s_);              \
+  } while (0)
+
+  hipEvent_t ev0, ev1;
+  PCHK(hipEventCreate(&ev0));
+  PCHK(hipEventCreate(&ev1));
+  PCHK(hipEventRecord(ev0, P->st));
+  PCHK(hipMemsetAsync(P->stats, 0, sizeof(DevStats), P->st));
+  if (o.validate) PCHK(launch_validate(M, A->nnz, B->nnz, P->stats, P->st));
+  ClassParams cp{};
+  cp.sort_max = P->sort_max;
+  cp.dense_max = (int64_t)1 << P->shift;
+  cp.force = (o.force_category >= 0 && o.force_category <= 2) ? o.force_category : -1;
+  PCHK(launch_rowinfo(M, A->nnz, cp, P->ip, P->minc, P->maxc, P->cls, P->stats, P->st));
+  PCHK(launch_classify(P->cls, n, P->list, P->list_off, P->temp, P->st));
+  SCHK(readback(P, {{P->stats, sizeof(DevStats)}, {P->list_off, sizeof(int64_t) * (NCLS + 1)}},
+                {&P->h_stats, P->h_list_off}));
+  if (P->h_stats.err & ERR_INVALID_CSR) return cleanup(MAGNUS_ERR_INVALID_CSR);
+  P->colbits = bits_for((int64_t)std::max<unsigned long long>(1, P->h_stats.max_range));
+  P->max_nb = (int64_t)(P->h_stats.max_range >> P->shift) + 2;
+  P->nch = P->h_list_off[CLS_CHUNKED + 1] - P->h_list_off[CLS_CHUNKED];
+  if (P->max_nb > 65535 && P->nch > 0) return cleanup(MAGNUS_ERR_INVALID_ARG);
+  if (P->nch > 0) SCHK(setup_chunked(P));
+
+  // precise symbolic phase: exact nnz per row, then the row offsets of C
+  PCHK(launch_fill_i64(P->crp, n + 1, 0, P->st));
+  SCHK(run_rows(P, false, nullptr, nullptr));
+  if (P->nch > 0) SCHK(run_chunked(P, false, nullptr, 0, nullptr));
+  PCHK(scan_excl_i64(P->crp, P->crp, n + 1, nullptr, nullptr, P->temp, P->st));
+  PCHK(hipEventRecord(ev1, P->st));
+  int64_t nnzc = 0;
+  DevStats st2{};
+  SCHK(readback(P, {{P->crp + n, 8}, {P->stats, sizeof(DevStats)}}, {&nnzc, &st2}));
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, ev0, ev1);
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (st2.err & (ERR_STAGE_OVERFLOW | ERR_BIN_OVERFLOW)) {
+    h->err = "device consistency check failed in the symbolic phase";
+    return cleanup(MAGNUS_ERR_INTERNAL);
+  }
+  P->nnz_c = nnzc;
+
+  magnus_plan_info_t& I = P->info;
+  I.ip_total = (int64_t)P->h_stats.ip_total;
+  I.flops = 2 * I.ip_total;
+  I.nnz_c = nnzc;
+  I.max_row_ip = (int64_t)P->h_stats.max_ip;
+  for (int k = 0; k < 4; ++k) {
+    I.rows_by_category[k] = (int64_t)P->h_stats.rows_cat[k];
+    I.ip_by_category[k] = (int64_t)P->h_stats.ip_cat[k];
+  }
+  size_t held = 0;
+  for (auto& a : P->allocs) held += a.n;
+  I.plan_bytes = (int64_t)held;
+  I.chunk_shift = P->shift;
+  I.sort_max = (int32_t)P->sort_max;
+  I.bin_dense_min = (int32_t)P->dense_min;
+  I.tile_products = P->tile;
+  I.symbolic_ms = ms;
+  if (info) *info = I;
+  *out = P;
+  return MAGNUS_OK;
+#undef PCHK
+#undef SCHK
+}
+
+magnus_status_t magnus_plan_get_info(magnus_plan_t P, magnus_plan_info_t* info) {
+  if (!P || !info) return MAGNUS_ERR_INVALID_ARG;
+  *info = P->info;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t P, const magnus_csr_t* A,
+                               const magnus_csr_t* B, const magnus_csr_out_t* C, int64_t* nnz_out,
+                               void* stream) {
+  if (!h || !P || !C) return MAGNUS_ERR_INVALID_ARG;
+  Mats M{};
+  magnus_status_t s = make_mats(A, B, M);
+  if (s != MAGNUS_OK) return s;
+  if (M.n != P->n || A->nnz != P->a_nnz || B->nnz != P->b_nnz) return MAGNUS_ERR_SHAPE;
+  if (C->nrows != A->nrows || C->ncols != B->ncols) return MAGNUS_ERR_SHAPE;
+  if (C->val_type != A->val_type || C->col_type != B->col_type) return MAGNUS_ERR_DTYPE;
+  if (C->rowptr_type != MAGNUS_I32 && C->rowptr_type != MAGNUS_I64) return MAGNUS_ERR_INVALID_ARG;
+  if (nnz_out) *nnz_out = P->nnz_c;
+  if (C->capacity < P->nnz_c) return MAGNUS_ERR_CAPACITY;
+  if (C->rowptr_type == MAGNUS_I32 && P->nnz_c > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  if (!C->rowptr || (P->nnz_c > 0 && (!C->col || !C->val))) return MAGNUS_ERR_INVALID_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  P->M = M;  // same shapes; the pointers of this call are used
+  P->st = (hipStream_t)stream;
+  magnus_status_t r = run_rows(P, true, C->col, C->val);
+  if (r != MAGNUS_OK) return r;
+  if (P->nch > 0) {
+    r = run_chunked(P, true, C->col, C->col_type == MAGNUS_I64, C->val);
+    if (r != MAGNUS_OK) return r;
+  }
+  HIPCHK(launch_write_rowptr(P->crp, P->n, C->rowptr, C->rowptr_type == MAGNUS_I64, P->st));
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_plan_destroy(magnus_plan_t P) {
+  if (!P) return MAGNUS_OK;
+  plan_free_all(P);
+  delete P;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_row_ip(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                              int64_t* ip_out, int64_t* ip_total, void* stream) {
+  if (!h || !ip_out) return MAGNUS_ERR_INVALID_ARG;
+  Mats M{};
+  magnus_status_t s = make_mats(A, B, M);
+  if (s != MAGNUS_OK) return s;
+  HIPCHK(hipSetDevice(h->device));
+  magnus_plan_s tmp;
+  tmp.h = h;
+  tmp.st = (hipStream_t)stream;
+  const int64_t n = A->nrows;
+  int64_t* minc = (int64_t*)palloc(&tmp, sizeof(int64_t) * std::max<int64_t>(n, 1));
+  int64_t* maxc = (int64_t*)palloc(&tmp, sizeof(int64_t) * std::max<int64_t>(n, 1));
+  int32_t* cls = (int32_t*)palloc(&tmp, sizeof(int32_t) * std::max<int64_t>(n, 1));
+  DevStats* stats = (DevStats*)palloc(&tmp, sizeof(DevStats));
+  if (!minc || !maxc || !cls || !stats) {
+    plan_free_all(&tmp);
+    return MAGNUS_ERR_OOM;
+  }
+  ClassParams cp{SORT_CAP + 1, 1 << 13, -1};
+  hipError_t e = hipMemsetAsync(stats, 0, sizeof(DevStats), tmp.st);
+  if (e == hipSuccess) e = launch_rowinfo(M, A->nnz, cp, ip_out, minc, maxc, cls, stats, tmp.st);
+  DevStats hs{};
+  magnus_status_t r = MAGNUS_OK;
+  if (e != hipSuccess) r = fail_hip(h, e, "launch_rowinfo");
+  else r = readback(&tmp, {{stats, sizeof(DevStats)}}, {&hs});
+  plan_free_all(&tmp);
+  if (r == MAGNUS_OK && ip_total) *ip_total = (int64_t)hs.ip_total;
+  return r;
+}
+
+magnus_status_t magnus_exclusive_scan_i64(magnus_handle_t h, const int64_t* in, int64_t* out,
+                                          int64_t n, int64_t* total, void* stream) {
+  if (!h || n < 0 || (n > 0 && (!in || !out))) return MAGNUS_ERR_INVALID_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  magnus_plan_s tmp;
+  tmp.h = h;
+  tmp.st = (hipStream_t)stream;
+  void* t = palloc(&tmp, scan_temp_bytes(n) + 64);
+  int64_t* dtot = (int64_t*)palloc(&tmp, 64);
+  if (!t || !dtot) {
+    plan_free_all(&tmp);
+    return MAGNUS_ERR_OOM;
+  }
+  hipError_t e = scan_excl_i64(in, out, n, dtot, nullptr, t, tmp.st);
+  magnus_status_t r = MAGNUS_OK;
+  if (e != hipSuccess) r = fail_hip(h, e, "scan");
+  else if (total) r = readback(&tmp, {{dtot, 8}}, {total});
+  else {
+    // the scratch is released below; wait for the scan to finish with it
+    e = hipStreamSynchronize(tmp.st);
+    if (e != hipSuccess) r = fail_hip(h, e, "sync");
+  }
+  plan_free_all(&tmp);
+  return r;
+}
+
+}  // extern "C"

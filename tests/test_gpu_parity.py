@@ -1,0 +1,197 @@
+"""Parity of the HIP path with the CPU oracle (GPU).  Every case runs the
+product through the C ABI and compares element by element: structure exactly,
+values bit-exactly on integer data and within rtol * sum|a_ik b_kj| otherwise
+(rtol 1e-12 for f64, 1e-5 for f32)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from workloads import CSR
+
+from gpu_util import compare, gpu_product, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2501_07056_amd as mg
+    c = mg.Context(0)
+    yield c
+    c.close()
+
+
+CATS = ["auto", "sort", "dense", "chunked"]
+
+
+@pytest.mark.parametrize("cat", CATS)
+def test_config1_bit_exact(ctx, cat):
+    A, B = wl.config1()
+    log(f"config1 cat={cat}")
+    rp, col, val, info = gpu_product(ctx, A, B, force_category=cat)
+    ref = oracle.spgemm(A, B)
+    compare(rp, col, val, ref, np.float64, exact=True)
+    assert info["ip_total"] == 262144
+    assert info["nnz_c"] == ref.nnz
+
+
+@pytest.mark.parametrize("cat", CATS)
+@pytest.mark.parametrize("vt", [np.float64, np.float32])
+def test_er_random_values(ctx, cat, vt):
+    A = wl.erdos_renyi(3000, 5000, 12, wl.seed(80), val_dtype=vt)
+    B = wl.erdos_renyi(5000, 20000, 20, wl.seed(81), val_dtype=vt)
+    log(f"er cat={cat} vt={vt.__name__}")
+    rp, col, val, info = gpu_product(ctx, A, B, force_category=cat)
+    compare(rp, col, val, oracle.spgemm(A, B), vt, exact=False)
+
+
+@pytest.mark.parametrize("cat", CATS)
+def test_rmat_mixed(ctx, cat):
+    A, _ = wl.config2(11)
+    log(f"rmat11 cat={cat}")
+    rp, col, val, info = gpu_product(ctx, A, A, force_category=cat)
+    compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
+
+
+def test_rmat_auto_small_chunks(ctx):
+    """Small chunk length so CHUNKED rows span many chunks and tiles."""
+    A, _ = wl.config2(12)
+    log("rmat12 shift=8 tile=512")
+    rp, col, val, info = gpu_product(ctx, A, A, force_category="chunked", chunk_shift=8,
+                                     tile_products=512, batch_products=200000)
+    assert info["n_batches"] > 1
+    compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
+    ctx.set_options(chunk_shift=0, tile_products=0, batch_products=0)
+
+
+@pytest.mark.parametrize("rpt", [np.int32, np.int64])
+@pytest.mark.parametrize("cit", [np.int32, np.int64])
+@pytest.mark.parametrize("vt", [np.float32, np.float64])
+def test_index_and_value_types(ctx, rpt, cit, vt):
+    A = wl.erdos_renyi(700, 900, 9, wl.seed(82), val_kind="int", val_dtype=vt, rowptr_dtype=rpt,
+                       col_dtype=cit)
+    B = wl.erdos_renyi(900, 1 << 15, 30, wl.seed(83), val_kind="int", val_dtype=vt,
+                       rowptr_dtype=rpt, col_dtype=cit)
+    log(f"types rp={rpt.__name__} col={cit.__name__} v={vt.__name__}")
+    for cat in CATS:
+        rp, col, val, info = gpu_product(ctx, A, B, force_category=cat)
+        compare(rp, col, val, oracle.spgemm(A, B), vt, exact=True)
+    ctx.set_options(force_category="auto")
+
+
+def test_banded(ctx):
+    A = wl.banded(20000, 64, 8, wl.seed(84))
+    log("banded")
+    for cat in CATS:
+        rp, col, val, info = gpu_product(ctx, A, A, force_category=cat)
+        compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
+    ctx.set_options(force_category="auto")
+
+
+def test_edge_cases(ctx):
+    log("edge cases")
+    # empty matrix
+    E = CSR(0, 5, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    B = wl.erdos_renyi(5, 7, 2, wl.seed(85))
+    rp, col, val, info = gpu_product(ctx, E, B)
+    assert len(rp) == 1 and rp[0] == 0 and len(col) == 0
+    # 1x1
+    one = CSR(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([3.0]))
+    rp, col, val, info = gpu_product(ctx, one, one)
+    assert list(rp) == [0, 1] and list(col) == [0] and list(val) == [9.0]
+    # cancellation to zero is kept; -0.0 becomes +0.0
+    A = CSR(2, 2, np.array([0, 2, 3]), np.array([0, 1, 0], np.int32), np.array([1.0, 1.0, 1.0]))
+    Bm = CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([2.0, -2.0]))
+    for cat in CATS:
+        rp, col, val, info = gpu_product(ctx, A, Bm, force_category=cat)
+        assert list(rp) == [0, 1, 2] and list(col) == [0, 0]
+        assert val[0] == 0.0 and not np.signbit(val[0]) and val[1] == 2.0
+    Bz = CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([-0.0, -0.0]))
+    for cat in CATS:
+        rp, col, val, info = gpu_product(ctx, A, Bz, force_category=cat)
+        assert not np.signbit(val).any()
+    ctx.set_options(force_category="auto")
+    # empty rows in A, rows of B that are empty, non-square
+    A = wl.erdos_renyi(400, 300, 5, wl.seed(86))
+    rpA = A.rowptr.astype(np.int64).copy()
+    keep = np.ones(A.nnz, bool)
+    for i in range(0, 400, 7):
+        keep[rpA[i]:rpA[i + 1]] = False
+    cnt = np.array([keep[rpA[i]:rpA[i + 1]].sum() for i in range(400)])
+    A2 = CSR(400, 300, np.concatenate([[0], np.cumsum(cnt)]), A.col[keep], A.val[keep])
+    Bs = wl.erdos_renyi(300, 50000, 7, wl.seed(87))
+    rpB = Bs.rowptr.astype(np.int64)
+    keepB = np.ones(Bs.nnz, bool)
+    for j in range(0, 300, 5):
+        keepB[rpB[j]:rpB[j + 1]] = False
+    cntB = np.array([keepB[rpB[j]:rpB[j + 1]].sum() for j in range(300)])
+    B2 = CSR(300, 50000, np.concatenate([[0], np.cumsum(cntB)]), Bs.col[keepB], Bs.val[keepB])
+    for cat in CATS:
+        rp, col, val, info = gpu_product(ctx, A2, B2, force_category=cat)
+        compare(rp, col, val, oracle.spgemm(A2, B2), np.float64, exact=False)
+    ctx.set_options(force_category="auto")
+
+
+def test_chunk_boundary_columns(ctx):
+    """Columns at k*chunkLen - 1 and k*chunkLen, several chunk lengths."""
+    log("chunk boundaries")
+    for shift in (8, 10, 13):
+        L = 1 << shift
+        cols = sorted({c for k in range(1, 9) for c in (k * L - 1, k * L, k * L + 1)})
+        m = 9 * L + 5
+        rows = 64
+        A = wl.erdos_renyi(rows, 40, 40, wl.seed(88), val_kind="int")
+        # every B row holds all boundary columns
+        rpB = np.arange(41, dtype=np.int64) * len(cols)
+        colB = np.tile(np.array(cols, np.int32), 40)
+        valB = wl.values(len(colB), wl.seed(89), "int", np.float64)
+        B = CSR(40, m, rpB, colB, valB)
+        for cat in CATS:
+            rp, col, val, info = gpu_product(ctx, A, B, force_category=cat, chunk_shift=shift)
+            compare(rp, col, val, oracle.spgemm(A, B), np.float64, exact=True)
+    ctx.set_options(force_category="auto", chunk_shift=0)
+
+
+def test_shape_and_type_errors(ctx):
+    import paper_2501_07056_amd as mg
+    A = wl.erdos_renyi(10, 6, 2, wl.seed(90))
+    B = wl.erdos_renyi(7, 6, 2, wl.seed(91))
+    dA, dB = mg.DeviceCSR.from_host(A), mg.DeviceCSR.from_host(B)
+    with pytest.raises(mg.MagnusError) as e:
+        ctx.plan(dA, dB)
+    assert e.value.name == "MAGNUS_ERR_SHAPE"
+    B2 = wl.erdos_renyi(6, 6, 2, wl.seed(92), val_dtype=np.float32)
+    with pytest.raises(mg.MagnusError) as e:
+        ctx.plan(dA, mg.DeviceCSR.from_host(B2))
+    assert e.value.name == "MAGNUS_ERR_DTYPE"
+
+
+def test_capacity_error(ctx):
+    import torch
+
+    import paper_2501_07056_amd as mg
+    A = wl.erdos_renyi(100, 100, 5, wl.seed(93))
+    dA = mg.DeviceCSR.from_host(A)
+    p = ctx.plan(dA, dA)
+    C = p.alloc_output(torch.int64, capacity=p.nnz - 1)
+    with pytest.raises(mg.MagnusError) as e:
+        p.execute(C)
+    assert e.value.name == "MAGNUS_ERR_CAPACITY"
+    p.destroy()
+
+
+def test_row_ip_and_scan(ctx):
+    import torch
+
+    import paper_2501_07056_amd as mg
+    A, _ = wl.config2(12)
+    dA = mg.DeviceCSR.from_host(A)
+    ip, tot = ctx.row_ip(dA, dA)
+    ref = oracle.ip(A, A)
+    assert np.array_equal(ip.cpu().numpy(), ref) and tot == ref.sum()
+    x = torch.randint(0, 1 << 40, (3_000_001,), dtype=torch.int64, device="cuda")
+    out, total = ctx.exclusive_scan(x)
+    xc = x.cpu()
+    want = torch.cumsum(xc, 0) - xc
+    assert torch.equal(out.cpu(), want) and total == int(xc.sum())
