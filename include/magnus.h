@@ -127,6 +127,8 @@ typedef struct {
   int64_t ip_by_category[4];
   int64_t n_batches;       /* row batches of CHUNKED rows */
   int64_t n_bins;          /* chunks (bins) over all CHUNKED rows */
+  int64_t n_dense_chunks;  /* chunks accumulated by the dense LDS accumulator */
+  int64_t n_sort_groups;   /* packed sort work items of small chunks */
   int64_t plan_bytes;      /* device memory held by the plan */
   int32_t chunk_shift;     /* chosen chunk length = 2^chunk_shift */
   int32_t sort_max;

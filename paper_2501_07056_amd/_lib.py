@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("ip_total", c_i64), ("flops", c_i64), ("nnz_c", c_i64), ("max_row_ip", c_i64),
                 ("rows_by_category", c_i64 * 4), ("ip_by_category", c_i64 * 4),
-                ("n_batches", c_i64), ("n_bins", c_i64), ("plan_bytes", c_i64),
+                ("n_batches", c_i64), ("n_bins", c_i64), ("n_dense_chunks", c_i64),
+                ("n_sort_groups", c_i64), ("plan_bytes", c_i64),
                 ("chunk_shift", c_i32), ("sort_max", c_i32), ("bin_dense_min", c_i32),
                 ("tile_products", c_i32), ("symbolic_ms", ctypes.c_double)]
 

@@ -65,6 +65,26 @@ MG_INLINE int rank_below(uint64_t mask) {
   return __popcll(below);
 }
 
+// Runs of equal keys over consecutive active lanes (call with every lane of
+// the current exec mask holding a key).  head_lane: the first lane of this
+// lane's run; len: the run's length (meaningful on the head lane).  A caller
+// updates a shared counter once per run instead of once per lane: lanes of a
+// wave walking a sorted B row mostly fall into the same chunk, and per-lane
+// atomics on one LDS word serialise.
+MG_INLINE void wave_run(uint32_t key, int& head_lane, int& len) {
+  const int l = lane();
+  const uint32_t prev = __shfl_up(key, 1, MG_WAVE);
+  const uint64_t act = __ballot(1);
+  const bool h = (l == 0) || !((act >> (l - 1)) & 1ull) || prev != key;
+  const uint64_t hm = __ballot(h);
+  const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
+  head_lane = 63 - __clzll(hm & upto);
+  const uint64_t above = (l == 63) ? 0ull : (~0ull << (l + 1));
+  const uint64_t stop = (hm | ~act) & above;
+  const int end = stop ? (__ffsll((unsigned long long)stop) - 1) : MG_WAVE;
+  len = end - l;
+}
+
 // Largest index k in [lo, hi) with pre[k] <= x (pre ascending, pre[lo] <= x).
 template <typename T, typename S>
 MG_INLINE int upper_index(const T* pre, int lo, int hi, S x) {
@@ -76,92 +96,94 @@ MG_INLINE int upper_index(const T* pre, int lo, int hi, S x) {
 }
 
 // -------------------------------------------------------------------------
-// Bitonic sort of N = 64 * E keys held in blocked layout: lane l owns
-// elements l*E .. l*E+E-1 in registers k[0..E-1] (payload v[] follows its
-// key).  Ascending.  For equal keys both partners keep their own element, so
-// no payload is duplicated or lost.
+// Lane exchange v <- v of lane (l ^ LM) without the LDS crossbar where the
+// distance allows: DPP quad permutes (1, 2), DPP row rotates (4, 8) and the
+// gfx950 permlane swaps (16, 32).  The lane layouts of the rotate and swap
+// forms were checked against __shfl_xor on the device.
 // -------------------------------------------------------------------------
-template <int E, typename K>
-MG_INLINE void cas_local(K* k, int a, int b, bool up) {
-  K x = k[a], y = k[b];
-  bool sw = up ? (y < x) : (x < y);
-  if (sw) { k[a] = y; k[b] = x; }
-}
-template <int E, typename K, typename V>
-MG_INLINE void cas_local(K* k, V* v, int a, int b, bool up) {
-  K x = k[a], y = k[b];
-  bool sw = up ? (y < x) : (x < y);
-  if (sw) {
-    k[a] = y; k[b] = x;
-    V t = v[a]; v[a] = v[b]; v[b] = t;
+template <int LM>
+MG_INLINE uint32_t xshfl32(uint32_t v) {
+  if constexpr (LM == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+  } else if constexpr (LM == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+  } else if constexpr (LM == 4) {
+    const uint32_t a = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124, 0xF, 0xF, true);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12C, 0xF, 0xF, true);
+    return (lane() & 4) ? a : b;
+  } else if constexpr (LM == 8) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);
+  } else if constexpr (LM == 16) {
+    const auto q = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return ((lane() >> 4) & 1) ? q[0] : q[1];
+  } else if constexpr (LM == 32) {
+    const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane() < 32) ? q[1] : q[0];
+  } else {
+    return __shfl_xor(v, LM, MG_WAVE);
   }
+}
+template <int LM, typename T>
+MG_INLINE T xshfl(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, xshfl32<LM>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = xshfl32<LM>((uint32_t)u), hi = xshfl32<LM>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(T, lo | (hi << 32));
+  }
+}
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+// -------------------------------------------------------------------------
+// Bitonic sort of N = 64 * E keys held in blocked layout: lane l owns
+// elements l*E .. l*E+E-1 in registers k[0..E-1].  Ascending.  The network
+// is generated at compile time (every stage's distance is a template
+// constant), and every compare-exchange is a branch-free min/max select.
+// -------------------------------------------------------------------------
+template <int E, int SIZE, int STRIDE, typename K>
+MG_INLINE void bitonic_stage(K (&k)[E]) {
+  const int l = lane();
+  if constexpr (STRIDE < E) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((e & STRIDE) == 0) {
+        // direction of this pair: bit SIZE of the element index l*E + e
+        bool up;
+        if constexpr (SIZE < E) up = (e & SIZE) == 0;
+        else up = ((l * E) & SIZE) == 0;
+        const K x = k[e], y = k[e | STRIDE];
+        const K mn = x < y ? x : y, mx = x < y ? y : x;
+        k[e] = up ? mn : mx;
+        k[e | STRIDE] = up ? mx : mn;
+      }
+    }
+  } else {
+    constexpr int LM = STRIDE / E;
+    const bool lower = (l & LM) == 0;
+    const bool up = ((l * E) & SIZE) == 0;
+    const bool keep_min = (lower == up);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const K p = xshfl<LM>(k[e]);
+      const K mn = p < k[e] ? p : k[e], mx = p < k[e] ? k[e] : p;
+      k[e] = keep_min ? mn : mx;
+    }
+  }
+  if constexpr (STRIDE > 1) bitonic_stage<E, SIZE, STRIDE / 2>(k);
+}
+
+template <int E, int SIZE, typename K>
+MG_INLINE void bitonic_merge_from(K (&k)[E]) {
+  bitonic_stage<E, SIZE, SIZE / 2>(k);
+  if constexpr (SIZE < MG_WAVE * E) bitonic_merge_from<E, SIZE * 2>(k);
 }
 
 template <int E, typename K>
 MG_INLINE void bitonic_sort_keys(K (&k)[E]) {
-  const int l = lane();
-  constexpr int N = MG_WAVE * E;
-#pragma unroll
-  for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride >= 1; stride >>= 1) {
-      if (stride < E) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if ((e & stride) == 0) {
-            int x = l * E + e;
-            bool up = (x & size) == 0;
-            cas_local<E>(k, e, e | stride, up);
-          }
-        }
-      } else {
-        const int lm = stride / E;
-        const bool lower = (l & lm) == 0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          int x = l * E + e;
-          bool up = (x & size) == 0;
-          K p = __shfl_xor(k[e], lm, MG_WAVE);
-          bool take = (lower == up) ? (p < k[e]) : (k[e] < p);
-          if (take) k[e] = p;
-        }
-      }
-    }
-  }
-}
-
-template <int E, typename K, typename V>
-MG_INLINE void bitonic_sort_pairs(K (&k)[E], V (&v)[E]) {
-  const int l = lane();
-  constexpr int N = MG_WAVE * E;
-#pragma unroll
-  for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride >= 1; stride >>= 1) {
-      if (stride < E) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if ((e & stride) == 0) {
-            int x = l * E + e;
-            bool up = (x & size) == 0;
-            cas_local<E>(k, v, e, e | stride, up);
-          }
-        }
-      } else {
-        const int lm = stride / E;
-        const bool lower = (l & lm) == 0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          int x = l * E + e;
-          bool up = (x & size) == 0;
-          K p = __shfl_xor(k[e], lm, MG_WAVE);
-          V pv = __shfl_xor(v[e], lm, MG_WAVE);
-          bool take = (lower == up) ? (p < k[e]) : (k[e] < p);
-          if (take) { k[e] = p; v[e] = pv; }
-        }
-      }
-    }
-  }
+  bitonic_merge_from<E, 2>(k);
 }
 
 }  // namespace mg

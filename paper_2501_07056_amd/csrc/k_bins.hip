@@ -10,6 +10,8 @@
 // tile's count is stored in a table whose prefix sum (row-major, chunk, then
 // tile) gives every tile a private, contiguous destination inside every chunk,
 // so the reorder needs no global atomics and is deterministic.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "dispatch.h"
@@ -149,40 +151,76 @@ MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t*
   c.e0 = lo;
 }
 
-// Calls f(col, bval_index, aval) for every product of the tile.
-template <typename RP, typename CI, typename V, bool WANT_VAL, typename F>
-MG_INLINE void tile_products(const TileCtx& c, const CI* __restrict__ acol, const V* __restrict__ aval,
-                             const RP* __restrict__ brp, const int64_t* __restrict__ aoff,
-                             int64_t* w_pre, int64_t* w_b0, V* w_av, F&& f) {
+// Calls f(q, col, prod) for every product q in [0, p1 - p0) of a row's
+// product range [p0, p1) (the order of Eq. 1), where col is the product's
+// column and prod = a_ij * b_jk (only when WANT_VAL).  The A entries
+// overlapping the range are staged in LDS in windows of BS entries (their
+// product offsets relative to p0, B row starts, A values); threads take
+// products striped by BS, so the B loads of a wave are contiguous, and each
+// thread advances its owning entry incrementally (one LDS read per product
+// while it stays inside the same B row, a binary search when it jumps).  Four
+// products per thread are gathered before any is used.
+template <int BS, typename RP, typename CI, typename V, bool WANT_VAL, typename F>
+MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
+                               const CI* __restrict__ acol, const V* __restrict__ aval,
+                               const RP* __restrict__ brp, const CI* __restrict__ bcol,
+                               const V* __restrict__ bval, const int64_t* __restrict__ aoff,
+                               int32_t* w_pre, int64_t* w_b0, V* w_av, F&& f) {
+  // offsets relative to p0 fit 32 bits: the range spans < 2^31 products and a
+  // B row holds < 2^31 entries
   const int t = threadIdx.x;
-  for (int64_t eb = c.e0; eb < c.a1; eb += BIN_BS) {
+  const int32_t span = (int32_t)(p1 - p0);
+  for (int64_t eb = e0; eb < a1; eb += BS) {
     const int64_t e = eb + t;
-    int64_t pre = INT64_MAX / 2, b0 = 0;
+    int64_t pre = INT32_MAX;
+    int64_t b0 = 0;
     V av = (V)0;
-    if (e < c.a1) {
-      pre = aoff[e] - c.p0;
+    if (e < a1) {
+      pre = aoff[e] - p0;
+      if (pre > INT32_MAX) pre = INT32_MAX;
       const int64_t j = acol[e];
       b0 = brp[j];
       if (WANT_VAL) av = aval[e];
     }
-    w_pre[t] = pre;
+    w_pre[t] = (int32_t)pre;
     w_b0[t] = b0;
     if (WANT_VAL) w_av[t] = av;
-    const int nvalid = (int)((c.a1 - eb) < BIN_BS ? (c.a1 - eb) : BIN_BS);
+    const int nvalid = (int)((a1 - eb) < BS ? (a1 - eb) : BS);
     __syncthreads();
-    // products of this window inside [0, p1 - p0)
-    const int64_t wstart = w_pre[0] > 0 ? w_pre[0] : 0;
-    int64_t wend;
-    if (eb + BIN_BS < c.a1) wend = aoff[eb + BIN_BS] - c.p0;
-    else wend = c.p1 - c.p0;
-    if (wend > c.p1 - c.p0) wend = c.p1 - c.p0;
-    for (int64_t q = wstart + t; q < wend; q += BIN_BS) {
-      const int kk = upper_index(w_pre, 0, nvalid, q);
-      const int64_t bi = w_b0[kk] + (q - w_pre[kk]);
-      f(q, bi, WANT_VAL ? w_av[kk] : (V)0);
+    const int32_t wstart = w_pre[0] > 0 ? w_pre[0] : 0;
+    int64_t we = (eb + BS < a1) ? (aoff[eb + BS] - p0) : (int64_t)span;
+    const int32_t wend = (int32_t)(we < span ? we : span);
+    int k = -1;
+    for (int32_t qb = wstart + t; qb < wend; qb += 4 * BS) {
+      int64_t bi[4];
+      V a4[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t q = qb + u * BS;
+        ok[u] = q < wend;
+        bi[u] = 0;
+        a4[u] = (V)0;
+        if (ok[u]) {
+          if (k < 0 || (k + 1 < nvalid && w_pre[k + 1] <= q))
+            k = upper_index(w_pre, k < 0 ? 0 : k + 1, nvalid, q);
+          bi[u] = w_b0[k] + (int64_t)(q - w_pre[k]);
+          if (WANT_VAL) a4[u] = w_av[k];
+        }
+      }
+      int64_t c4[4];
+      V v4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c4[u] = ok[u] ? (int64_t)bcol[bi[u]] : 0;
+        if (WANT_VAL) v4[u] = ok[u] ? a4[u] * bval[bi[u]] : (V)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (ok[u]) f(qb + u * BS, c4[u], WANT_VAL ? v4[u] : (V)0);
     }
     __syncthreads();
-    if (wend >= c.p1 - c.p0) break;
+    if (wend >= span) break;
   }
 }
 
@@ -196,18 +234,21 @@ __global__ void __launch_bounds__(BIN_BS)
                const int32_t* __restrict__ tile_row, const int64_t* __restrict__ aoff,
                int32_t* tab_cnt) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  int64_t* w_pre = (int64_t*)dsm;          // BIN_BS
-  int64_t* w_b0 = w_pre + BIN_BS;            // BIN_BS
-  int32_t* hist = (int32_t*)(w_b0 + BIN_BS); // nb
+  int32_t* w_pre = (int32_t*)dsm;                        // BIN_BS
+  int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);            // BIN_BS
+  int32_t* hist = (int32_t*)(w_b0 + BIN_BS);               // nb
   TileCtx c;
   tile_setup<RP>(g, b, tile_row, arp, aoff, c);
   for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) hist[q] = 0;
   __syncthreads();
-  tile_products<RP, CI, float, false>(c, acol, (const float*)nullptr, brp, aoff, w_pre, w_b0,
-                                      (float*)nullptr, [&](int64_t, int64_t bi, float) {
-                                        const int64_t bin = ((int64_t)bcol[bi] >> g.shift) - c.base_bin;
-                                        atomicAdd(&hist[bin], 1);
-                                      });
+  expand_products<BIN_BS, RP, CI, float, false>(
+      c.p0, c.p1, c.e0, c.a1, acol, (const float*)nullptr, brp, bcol, (const float*)nullptr, aoff,
+      w_pre, w_b0, (float*)nullptr, [&](int32_t, int64_t col, float) {
+        const uint32_t bin = (uint32_t)((col >> g.shift) - c.base_bin);
+        int hl, len;
+        wave_run(bin, hl, len);
+        if (lane() == hl) atomicAdd(&hist[bin], len);
+      });
   __syncthreads();
   for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS)
     tab_cnt[c.tabk + q * c.ntk + c.ti] = hist[q];
@@ -221,7 +262,7 @@ __global__ void __launch_bounds__(BIN_BS)
 size_t bin_scatter_lds(int f64, int tile, int64_t max_nb) {
   const size_t vs = f64 ? 8 : 4;
   return BIN_BS * 8 * 3 + (size_t)max_nb * 8 + 16 + (size_t)tile * (2 + 2) + 16 +
-         (size_t)tile * vs + 64;
+         (size_t)tile * vs + 16 + (size_t)max_nb * 8 + 64;
 }
 
 template <typename RP, typename CI, typename V, bool NUMERIC>
@@ -233,8 +274,8 @@ __global__ void __launch_bounds__(BIN_BS)
                   const int64_t* __restrict__ tab_off, uint16_t* ws_col, V* ws_val,
                   DevStats* stats) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  int64_t* w_pre = (int64_t*)dsm;                     // BIN_BS
-  int64_t* w_b0 = w_pre + BIN_BS;                     // BIN_BS
+  int32_t* w_pre = (int32_t*)dsm;                     // BIN_BS
+  int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);       // BIN_BS
   V* w_av = (V*)(w_b0 + BIN_BS);                      // BIN_BS
   int32_t* loc = (int32_t*)((char*)w_av + BIN_BS * 8);  // nb (w_av padded to 8 B entries)
   TileCtx c;
@@ -272,22 +313,162 @@ __global__ void __launch_bounds__(BIN_BS)
     return;
   }
   const int64_t lmask = ((int64_t)1 << g.shift) - 1;
-  tile_products<RP, CI, V, NUMERIC>(c, acol, aval, brp, aoff, w_pre, w_b0, w_av,
-                                    [&](int64_t, int64_t bi, V av) {
-                                      const int64_t col = bcol[bi];
-                                      const int bin = (int)((col >> g.shift) - c.base_bin);
-                                      const int pos = loc[bin] + atomicAdd(&cur[bin], 1);
-                                      st_col[pos] = (uint16_t)(col & lmask);
-                                      st_bin[pos] = (uint16_t)bin;
-                                      if (NUMERIC) st_val[pos] = av * bval[bi];
-                                    });
+  expand_products<BIN_BS, RP, CI, V, NUMERIC>(
+      c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
+      [&](int32_t, int64_t col, V pv) {
+        const int bin = (int)((col >> g.shift) - c.base_bin);
+        const int pos = loc[bin] + atomicAdd(&cur[bin], 1);
+        st_col[pos] = (uint16_t)(col & lmask);
+        st_bin[pos] = (uint16_t)bin;
+        if (NUMERIC) st_val[pos] = pv;
+      });
+  __syncthreads();
+  // cur[] is free now: reuse it (as int64 pairs would not fit) for the
+  // destination of each chunk relative to the staging index
+  int64_t* dst = (int64_t*)(((uintptr_t)(st_val + g.tile) + 15) & ~(uintptr_t)15);
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS)
+    dst[q] = tab_off[c.tabk + q * c.ntk + c.ti] - loc[q];
   __syncthreads();
   const int64_t nloc = c.p1 - c.p0;
   for (int64_t s = threadIdx.x; s < nloc; s += BIN_BS) {
-    const int bin = st_bin[s];
-    const int64_t dst = tab_off[c.tabk + (int64_t)bin * c.ntk + c.ti] + (s - loc[bin]);
-    ws_col[dst] = st_col[s];
-    if (NUMERIC) ws_val[dst] = st_val[s];
+    const int64_t d = dst[st_bin[s]] + s;
+    ws_col[d] = st_col[s];
+    if (NUMERIC) ws_val[d] = st_val[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Symbolic phase of a CHUNKED row with the whole row's column bitmap in LDS
+// (the symbolic phase needs only the bitmap, Section 3.5: s_denseAccum = 1).
+// One workgroup per row: every product sets its column bit and counts into
+// its chunk; then per chunk the distinct columns (popcount of the chunk's
+// bits) and the products are written, and the row's nnz.
+// ---------------------------------------------------------------------------
+constexpr int RB_BS = 1024;
+
+size_t row_bitmap_lds(int shift, int64_t max_nb) {
+  const size_t words = ((size_t)max_nb << shift) / 32;
+  return words * 4 + (size_t)max_nb * 4 + RB_BS * 16 + 64;
+}
+
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(RB_BS)
+    k_row_bitmap(const RP* __restrict__ arp, const CI* __restrict__ acol, const RP* __restrict__ brp,
+                 const CI* __restrict__ bcol, ChunkGeom g, const int64_t* __restrict__ aoff,
+                 int64_t* bin_nnz, int64_t* bin_cnt, int32_t* bin_row, int64_t* rownnz) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int64_t k = blockIdx.x;
+  const int32_t row = g.rows[k];
+  const int64_t nbk = g.nb[k], bb = g.binBase[k];
+  const int sh = g.shift;
+  const int64_t base = (g.minc[row] >> sh) << sh;
+  const int64_t nwords = (nbk << sh) >> 5;
+  int32_t* w_pre = (int32_t*)dsm;
+  int64_t* w_b0 = (int64_t*)(dsm + RB_BS * 8);
+  uint32_t* bits = (uint32_t*)(w_b0 + RB_BS);
+  int32_t* cnt = (int32_t*)(bits + nwords);
+  __shared__ unsigned long long tot;
+  for (int64_t q = threadIdx.x; q < nwords; q += RB_BS) bits[q] = 0u;
+  for (int64_t q = threadIdx.x; q < nbk; q += RB_BS) cnt[q] = 0;
+  if (threadIdx.x == 0) tot = 0;
+  __syncthreads();
+  const int64_t a0 = arp[row], a1 = arp[row + 1];
+  expand_products<RB_BS, RP, CI, float, false>(
+      0, g.ip[row], a0, a1, acol, (const float*)nullptr, brp, bcol, (const float*)nullptr, aoff,
+      w_pre, w_b0, (float*)nullptr, [&](int32_t, int64_t col, float) {
+        const uint32_t lc = (uint32_t)(col - base);
+        atomicOr(&bits[lc >> 5], 1u << (lc & 31));
+        const uint32_t bin = lc >> sh;
+        int hl, len;
+        wave_run(bin, hl, len);
+        if (lane() == hl) atomicAdd(&cnt[bin], len);
+      });
+  __syncthreads();
+  // one wave per chunk: popcount of the chunk's words
+  const int w = threadIdx.x / MG_WAVE, nw = RB_BS / MG_WAVE;
+  const int64_t wpb = ((int64_t)1 << sh) >> 5;
+  for (int64_t b = w; b < nbk; b += nw) {
+    unsigned long long s = 0;
+    for (int64_t q = lane(); q < wpb; q += MG_WAVE) s += __popc(bits[b * wpb + q]);
+    s = wave_sum(s);
+    if (lane() == 0) {
+      bin_nnz[bb + b] = (int64_t)s;
+      bin_cnt[bb + b] = cnt[b];
+      bin_row[bb + b] = (int32_t)k;
+      atomicAdd(&tot, s);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) rownnz[row] = (int64_t)tot;
+}
+
+// ---------------------------------------------------------------------------
+// Numeric reorder of a tile with chunk ranges reserved by atomics: the tile's
+// products are gathered once into LDS (unsorted, with their chunk), counted
+// per chunk, each chunk's range inside its bin is reserved with one atomic
+// add on that bin's cursor, the products are ranked within their chunk, and
+// every chunk's run is copied out contiguously.
+// ---------------------------------------------------------------------------
+size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb) {
+  const size_t vs = f64 ? 8 : 4;
+  return BIN_BS * (8 + 8 + 8) + (size_t)max_nb * (4 + 8) + 16 + (size_t)tile * (4 + 4) + 16 +
+         (size_t)tile * vs + 64;
+}
+
+template <typename RP, typename CI, typename V>
+__global__ void __launch_bounds__(BIN_BS)
+    k_bin_scatter2(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
+                   const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
+                   ChunkGeom g, BatchArgs b, const int32_t* __restrict__ tile_row,
+                   const int64_t* __restrict__ aoff, const int64_t* __restrict__ bin_start,
+                   unsigned long long* bin_cursor, uint16_t* ws_col, V* ws_val) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  int32_t* w_pre = (int32_t*)dsm;
+  int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);
+  V* w_av = (V*)(w_b0 + BIN_BS);
+  TileCtx c;
+  tile_setup<RP>(g, b, tile_row, arp, aoff, c);
+  int32_t* hist = (int32_t*)((char*)w_av + BIN_BS * 8);
+  int64_t* dst = (int64_t*)(((uintptr_t)(hist + c.nbk) + 15) & ~(uintptr_t)15);
+  uint32_t* u_word = (uint32_t*)(dst + c.nbk);
+  uint32_t* u_rank = u_word + g.tile;
+  V* u_val = (V*)(((uintptr_t)(u_rank + g.tile) + 15) & ~(uintptr_t)15);
+
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) hist[q] = 0;
+  __syncthreads();
+  const int64_t lmask = ((int64_t)1 << g.shift) - 1;
+  // gather once; the chunk counter's old value is the product's rank inside
+  // this tile's run of that chunk
+  expand_products<BIN_BS, RP, CI, V, true>(
+      c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
+      [&](int32_t q, int64_t col, V pv) {
+        const uint32_t bin = (uint32_t)((col >> g.shift) - c.base_bin);
+        int hl, len;
+        wave_run(bin, hl, len);
+        int r = 0;
+        if (lane() == hl) r = atomicAdd(&hist[bin], len);
+        r = __shfl(r, hl, MG_WAVE);
+        u_word[q] = (bin << 16) | (uint32_t)(col & lmask);
+        u_rank[q] = (uint32_t)(r + (lane() - hl));
+        u_val[q] = pv;
+      });
+  __syncthreads();
+  // reserve each chunk's run inside its bin with one atomic add
+  const int64_t gb = g.binBase[c.k];
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) {
+    const int h = hist[q];
+    if (h > 0) {
+      const unsigned long long r = atomicAdd(&bin_cursor[gb + q], (unsigned long long)h);
+      dst[q] = bin_start[gb + q] + (int64_t)r;
+    }
+  }
+  __syncthreads();
+  const int32_t nloc = (int32_t)(c.p1 - c.p0);
+  for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
+    const uint32_t w = u_word[q];
+    const int64_t d = dst[w >> 16] + u_rank[q];
+    ws_col[d] = (uint16_t)(w & 0xFFFFu);
+    ws_val[d] = u_val[q];
   }
 }
 
@@ -365,74 +546,87 @@ __global__ void __launch_bounds__(1024)
                   const int64_t* __restrict__ bin_cnt, const int32_t* __restrict__ bin_row,
                   const uint16_t* __restrict__ ws_col, const V* __restrict__ ws_val,
                   int64_t* bin_nnz, const int64_t* __restrict__ bin_out, void* ccol_, int col64,
-                  V* cval) {
-  if ((int64_t)blockIdx.x >= item_counts[0]) return;
+                  V* cval, unsigned int* work) {
+  // persistent: each workgroup takes chunks from a counter; the accumulator
+  // and bitmap are cleared once, and afterwards only the touched entries are
+  // reset during the write-out, so a chunk costs O(products + chunk/32)
   extern __shared__ __align__(16) unsigned char dsm[];
   const int BS = blockDim.x;
   const int64_t L = (int64_t)1 << g.shift;
   V* acc = (V*)dsm;
   uint32_t* bits = (uint32_t*)(dsm + (NUMERIC ? L * sizeof(V) : 0));
   __shared__ int64_t sh_w[16];
+  __shared__ unsigned int sh_item;
   const int t = threadIdx.x;
-  const int64_t gb = items[item_base + blockIdx.x];
-  const int64_t s0 = bin_start[gb], cnt = bin_cnt[gb];
+  const int64_t nitems = item_counts[0];
   const int64_t nwords = L / 32;
   for (int64_t q = t; q < nwords; q += BS) bits[q] = 0u;
   if (NUMERIC)
     for (int64_t q = t; q < L; q += BS) acc[q] = (V)0;
-  __syncthreads();
-  // 4 products in flight per thread
-  int64_t q = t;
-  for (; q + 3 * BS < cnt; q += 4 * BS) {
-    uint32_t c4[4];
-    V v4[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      c4[u] = ws_col[s0 + q + u * BS];
-      if (NUMERIC) v4[u] = ws_val[s0 + q + u * BS];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
-      if (NUMERIC) atomicAdd(&acc[c4[u]], v4[u]);
-    }
-  }
-  for (; q < cnt; q += BS) {
-    const uint32_t c = ws_col[s0 + q];
-    atomicOr(&bits[c >> 5], 1u << (c & 31));
-    if (NUMERIC) atomicAdd(&acc[c], ws_val[s0 + q]);
-  }
-  __syncthreads();
   const int64_t wpt = (nwords + BS - 1) / BS;
   const int64_t w0 = t * wpt, w1 = (w0 + wpt < nwords) ? (w0 + wpt) : nwords;
-  int64_t my = 0;
-  for (int64_t w = w0; w < w1; ++w) my += __popc(bits[w]);
   const int wv = t / MG_WAVE, nw = BS / MG_WAVE;
-  const int64_t inc = wave_incl_scan(my);
-  if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
-  __syncthreads();
-  int64_t before = 0, total = 0;
-  for (int v = 0; v < nw; ++v) {
-    if (v < wv) before += sh_w[v];
-    total += sh_w[v];
-  }
-  if (!NUMERIC) {
-    if (t == 0) bin_nnz[gb] = total;
-    return;
-  }
-  const int64_t k = bin_row[gb];
-  const int64_t colbase = ((g.minc[g.rows[k]] >> g.shift) + (gb - g.binBase[k])) << g.shift;
-  int64_t pos = bin_out[gb] + before + inc - my;
-  for (int64_t w = w0; w < w1; ++w) {
-    uint32_t bb = bits[w];
-    while (bb) {
-      const int bit = __ffs(bb) - 1;
-      bb &= bb - 1;
-      const int64_t lc = w * 32 + bit;
-      if (col64) ((int64_t*)ccol_)[pos] = colbase + lc;
-      else ((int32_t*)ccol_)[pos] = (int32_t)(colbase + lc);
-      cval[pos] = acc[lc];
-      ++pos;
+  for (;;) {
+    __syncthreads();
+    if (t == 0) sh_item = atomicAdd(work, 1u);
+    __syncthreads();
+    const int64_t it = sh_item;
+    if (it >= nitems) break;
+    const int64_t gb = items[item_base + it];
+    const int64_t s0 = bin_start[gb], cnt = bin_cnt[gb];
+    int64_t q = t;
+    for (; q + 3 * BS < cnt; q += 4 * BS) {
+      uint32_t c4[4];
+      V v4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c4[u] = ws_col[s0 + q + u * BS];
+        if (NUMERIC) v4[u] = ws_val[s0 + q + u * BS];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
+        if (NUMERIC) atomicAdd(&acc[c4[u]], v4[u]);
+      }
+    }
+    for (; q < cnt; q += BS) {
+      const uint32_t c = ws_col[s0 + q];
+      atomicOr(&bits[c >> 5], 1u << (c & 31));
+      if (NUMERIC) atomicAdd(&acc[c], ws_val[s0 + q]);
+    }
+    __syncthreads();
+    int64_t my = 0;
+    for (int64_t w = w0; w < w1; ++w) my += __popc(bits[w]);
+    const int64_t inc = wave_incl_scan(my);
+    if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    for (int v = 0; v < nw; ++v) {
+      if (v < wv) before += sh_w[v];
+      total += sh_w[v];
+    }
+    if (!NUMERIC) {
+      if (t == 0) bin_nnz[gb] = total;
+      for (int64_t w = w0; w < w1; ++w) bits[w] = 0u;
+      continue;
+    }
+    const int64_t k = bin_row[gb];
+    const int64_t colbase = ((g.minc[g.rows[k]] >> g.shift) + (gb - g.binBase[k])) << g.shift;
+    int64_t pos = bin_out[gb] + before + inc - my;
+    for (int64_t w = w0; w < w1; ++w) {
+      uint32_t bb = bits[w];
+      if (!bb) continue;
+      bits[w] = 0u;
+      while (bb) {
+        const int bit = __ffs(bb) - 1;
+        bb &= bb - 1;
+        const int64_t lc = w * 32 + bit;
+        if (col64) ((int64_t*)ccol_)[pos] = colbase + lc;
+        else ((int32_t*)ccol_)[pos] = (int32_t)(colbase + lc);
+        cval[pos] = acc[lc];
+        acc[lc] = (V)0;
+        ++pos;
+      }
     }
   }
 }
@@ -449,7 +643,12 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
                                const int64_t* bin_cnt, const int32_t* bin_row,
                                const uint16_t* ws_col, const V* ws_val, int64_t* bin_nnz,
                                const int64_t* bin_out, void* ccol_, int col64, V* cval,
-                               int64_t* s_bs, int32_t* s_cnt) {
+                               int64_t* s_bs, int32_t* s_cnt, V* s_v) {
+  // numeric keys carry the element index in their low bits, so the network
+  // moves one 32-bit word per element and the sum of a run follows the
+  // elements' order in the workspace; values are fetched from LDS afterwards
+  constexpr int CAP = MG_WAVE * E;
+  constexpr int IDXB = NUMERIC ? ilog2c(CAP) : 0;
   const int l = lane();
   const int64_t start = bin_start[g0];
   const int64_t endp = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1];
@@ -460,29 +659,28 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
   }
   wave_sync2();
   uint32_t k[E];
-  V v[NUMERIC ? E : 1];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int x = e * MG_WAVE + l;
     if (x < P) {
       const int bo = upper_index(s_bs, 0, nbg, (int64_t)x);
-      k[e] = ((uint32_t)bo << g.shift) | (uint32_t)ws_col[start + x];
-      if (NUMERIC) v[e] = ws_val[start + x];
+      const uint32_t key = ((uint32_t)bo << g.shift) | (uint32_t)ws_col[start + x];
+      k[e] = NUMERIC ? ((key << IDXB) | (uint32_t)x) : key;
+      if (NUMERIC) s_v[x] = ws_val[start + x];
     } else {
       k[e] = 0xFFFFFFFFu;
-      if (NUMERIC) v[e] = (V)0;
     }
   }
-  if (NUMERIC) bitonic_sort_pairs<E>(k, *reinterpret_cast<V(*)[E]>(v));
-  else bitonic_sort_keys<E>(k);
-  const uint32_t prevk = __shfl_up(k[E - 1], 1, MG_WAVE);
+  bitonic_sort_keys<E>(k);
+  wave_sync2();
+  const uint32_t prevk = __shfl_up(k[E - 1], 1, MG_WAVE) >> IDXB;
   bool head[E];
   int hc = 0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int x = l * E + e;
-    const uint32_t pk = (e == 0) ? prevk : k[e - 1];
-    head[e] = (x < P) && (x == 0 || k[e] != pk);
+    const uint32_t pk = (e == 0) ? prevk : (k[e - 1] >> IDXB);
+    head[e] = (x < P) && (x == 0 || (k[e] >> IDXB) != pk);
     hc += head[e] ? 1 : 0;
   }
   if (!NUMERIC) {
@@ -493,6 +691,12 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
     if (l < nbg) bin_nnz[g0 + l] = s_cnt[l];
     return;
   } else {
+    V v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      v[e] = (x < P) ? s_v[k[e] & (CAP - 1)] : (V)0;
+    }
     const int hinc = wave_incl_scan(hc);
     const int hbase = hinc - hc;
     V t = (V)0;
@@ -512,7 +716,7 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
     }
     V carry = __shfl_up(s, 1, MG_WAVE);
     if (l == 0) carry = (V)0;
-    const uint32_t nextk = __shfl_down(k[0], 1, MG_WAVE);
+    const uint32_t nextk = __shfl_down(k[0], 1, MG_WAVE) >> IDXB;
     const int64_t kk = bin_row[g0];
     const int64_t colbase = ((g.minc[g.rows[kk]] >> g.shift) + (g0 - g.binBase[kk])) << g.shift;
     const int64_t obase = bin_out[g0];
@@ -523,11 +727,12 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
       const int x = l * E + e;
       if (head[e]) { run = (V)0 + v[e]; ++hr; }
       else run = run + v[e];
-      const uint32_t nk = (e == E - 1) ? nextk : k[e + 1];
-      const bool tail = (x < P) && (x == P - 1 || nk != k[e]);
+      const uint32_t key = k[e] >> IDXB;
+      const uint32_t nk = (e == E - 1) ? nextk : (k[e + 1] >> IDXB);
+      const bool tail = (x < P) && (x == P - 1 || nk != key);
       if (tail) {
         const int64_t pos = obase + hr - 1;
-        const int64_t col = colbase + (int64_t)k[e];
+        const int64_t col = colbase + (int64_t)key;
         if (col64) ((int64_t*)ccol_)[pos] = col;
         else ((int32_t*)ccol_)[pos] = (int32_t)col;
         cval[pos] = run;
@@ -546,6 +751,7 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
                  V* cval) {
   __shared__ int64_t s_bs[AS_WAVES][MG_WAVE];
   __shared__ int32_t s_cnt[AS_WAVES][MG_WAVE];
+  __shared__ V s_v[AS_WAVES][NUMERIC ? SORT_CAP : 1];
   const int w = threadIdx.x / MG_WAVE;
   const int64_t it = (int64_t)blockIdx.x * AS_WAVES + w;
   if (it >= item_counts[1]) return;
@@ -554,19 +760,19 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
   const int64_t P = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1] - bin_start[g0];
   if (P <= 64)
     accum_sort_item<V, 1, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else if (P <= 128)
     accum_sort_item<V, 2, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else if (P <= 256)
     accum_sort_item<V, 4, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else if (P <= 512)
     accum_sort_item<V, 8, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else
     accum_sort_item<V, 16, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val,
-                                    bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w]);
+                                    bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
 }
 
 // rownnz of CHUNKED rows (count) / output offset of every chunk (numeric)
@@ -650,10 +856,11 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
                              const int64_t* sort_items, const int32_t* item_counts,
                              const uint16_t* ws_col, const void* ws_val, int64_t* bin_nnz,
                              const int64_t* bin_out, void* ccol, int col64, void* cval,
-                             int dense_block, hipStream_t st) {
+                             int dense_block, unsigned int* work, int persistent_wgs,
+                             hipStream_t st) {
   if (b.nbins <= 0) return hipSuccess;
   const size_t lds = bin_dense_lds(f64, g.shift);
-  const unsigned gd = (unsigned)b.nbins;
+  const unsigned gd = (unsigned)std::min<int64_t>(b.nbins, persistent_wgs);
   const unsigned gs = (unsigned)((b.nbins + AS_WAVES - 1) / AS_WAVES);
 #define MG_AC(V)                                                                                  \
   {                                                                                               \
@@ -661,7 +868,7 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
     hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_items, item_counts, b.bin0,         \
                        bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
-                       ccol, col64, (V*)cval);                                                    \
+                       ccol, col64, (V*)cval, work);                                              \
     auto ks = numeric ? k_accum_sort<V, true> : k_accum_sort<V, false>;                           \
     hipLaunchKernelGGL(ks, gs, AS_WAVES * MG_WAVE, 0, st, g, sort_items, item_counts, b.bin0,     \
                        bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
@@ -669,6 +876,51 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
   }
   if (f64) MG_AC(double) else MG_AC(float)
 #undef MG_AC
+  return hipGetLastError();
+}
+
+hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
+                             int64_t max_nb, int64_t* bin_nnz, int64_t* bin_cnt, int32_t* bin_row,
+                             int64_t* rownnz, hipStream_t st) {
+  if (g.nch <= 0) return hipSuccess;
+  const size_t lds = row_bitmap_lds(g.shift, max_nb);
+  MG_DISPATCH2(M, {
+    auto kf = k_row_bitmap<RP, CI>;
+    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kf, (unsigned)g.nch, RB_BS, lds, st, (const RP*)M.arp, (const CI*)M.acol,
+                       (const RP*)M.brp, (const CI*)M.bcol, g, aoff, bin_nnz, bin_cnt, bin_row,
+                       rownnz);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+                               const int32_t* tile_row, const int64_t* aoff,
+                               const int64_t* bin_start, unsigned long long* bin_cursor,
+                               uint16_t* ws_col, void* ws_val, int64_t max_nb, hipStream_t st) {
+  if (b.ntiles <= 0) return hipSuccess;
+  const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb);
+#define MG_SC2(V)                                                                                 \
+  MG_DISPATCH2(M, {                                                                               \
+    auto kf = k_bin_scatter2<RP, CI, V>;                                                          \
+    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                 \
+                       (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
+                       (const V*)M.bval, g, b, tile_row, aoff, bin_start, bin_cursor, ws_col,     \
+                       (V*)ws_val);                                                               \
+  });
+  if (M.f64) { MG_SC2(double) } else { MG_SC2(float) }
+#undef MG_SC2
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_group(const ChunkGeom& g, const BatchArgs& b, const int64_t* bin_cnt,
+                            int64_t dense_min, int64_t group_max, int64_t* dense_items,
+                            int64_t* sort_items, int32_t* item_counts, hipStream_t st) {
+  const int64_t nr = b.k1 - b.k0;
+  if (nr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin_group, (unsigned)((nr + 255) / 256), 256, 0, st, g, b, bin_cnt,
+                     dense_min, group_max, dense_items, sort_items, item_counts, b.bin0);
   return hipGetLastError();
 }
 

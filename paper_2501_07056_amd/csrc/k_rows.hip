@@ -29,71 +29,81 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
                                                  int64_t n, int G, ClassParams cp, int64_t* ip,
                                                  int64_t* minc, int64_t* maxc, int32_t* cls,
                                                  DevStats* stats) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = gt / G;
-  const int sub = (int)(gt % G);
-  int64_t s = 0, mn = INT64_MAX, mx = -1;
-  if (row < n) {
-    const int64_t p0 = arp[row], p1 = arp[row + 1];
-    for (int64_t p = p0 + sub; p < p1; p += G) {
-      const int64_t j = acol[p];
-      const int64_t b0 = brp[j], b1 = brp[j + 1];
-      if (b1 > b0) {
-        s += b1 - b0;
-        const int64_t f = bcol[b0], l = bcol[b1 - 1];
-        mn = f < mn ? f : mn;
-        mx = l > mx ? l : mx;
-      }
-    }
-  }
-  for (int d = G >> 1; d >= 1; d >>= 1) {
-    s += __shfl_xor(s, d, G);
-    int64_t a = __shfl_xor(mn, d, G);
-    int64_t b = __shfl_xor(mx, d, G);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
-  unsigned long long my_ip = 0, my_range = 0;
-  int cat = -1;
-  if (row < n && sub == 0) {
-    int c;
-    const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
-    if (s == 0) {
-      c = CLS_EMPTY;
-      mn = 0;
-      mx = -1;
-      cat = 3;
-    } else {
-      int want = cp.force;
-      if (want < 0) want = (s < cp.sort_max) ? 0 : (range <= cp.dense_max ? 1 : 2);
-      if (want == 0 && s > SORT_CAP) want = (range <= cp.dense_max) ? 1 : 2;
-      if (want == 1 && range > cp.dense_max) want = 2;
-      if (want == 0) {
-        int lg = 0;
-        while (((int64_t)1 << lg) < s) ++lg;
-        c = lg;
-      } else {
-        c = (want == 1) ? CLS_DENSE : CLS_CHUNKED;
-      }
-      cat = want;
-    }
-    ip[row] = s;
-    minc[row] = mn;
-    maxc[row] = mx;
-    cls[row] = c;
-    my_ip = (unsigned long long)s;
-    my_range = (unsigned long long)range;
-  }
-  // block-level reduction of the statistics, then one atomic per block
-  __shared__ unsigned long long sh[6 + 8];
+  // grid-stride over groups of G lanes per row; the statistics of all rows a
+  // block visits are combined in LDS and added to the global totals once per
+  // block (a global atomic per block on a handful of addresses would
+  // serialise in L2 across hundreds of thousands of blocks)
+  __shared__ unsigned long long sh[14];
   if (threadIdx.x < 14) sh[threadIdx.x] = 0;
   __syncthreads();
-  if (cat >= 0) {
-    atomicAdd(&sh[0], my_ip);
-    atomicMax(&sh[1], my_ip);
-    atomicMax(&sh[2], my_range);
-    atomicAdd(&sh[6 + cat], my_ip);
-    atomicAdd(&sh[10 + cat], 1ull);
+  const int64_t groups_per_block = blockDim.x / G;
+  const int sub = (int)(threadIdx.x % G);
+  unsigned long long l_ip = 0, l_max = 0, l_rng = 0, l_ipc[4] = {0, 0, 0, 0}, l_rc[4] = {0, 0, 0, 0};
+  for (int64_t rb = (int64_t)blockIdx.x * groups_per_block; rb < n;
+       rb += (int64_t)gridDim.x * groups_per_block) {
+    const int64_t row = rb + threadIdx.x / G;
+    int64_t s = 0, mn = INT64_MAX, mx = -1;
+    if (row < n) {
+      const int64_t p0 = arp[row], p1 = arp[row + 1];
+      for (int64_t p = p0 + sub; p < p1; p += G) {
+        const int64_t j = acol[p];
+        const int64_t b0 = brp[j], b1 = brp[j + 1];
+        if (b1 > b0) {
+          s += b1 - b0;
+          const int64_t f = bcol[b0], l = bcol[b1 - 1];
+          mn = f < mn ? f : mn;
+          mx = l > mx ? l : mx;
+        }
+      }
+    }
+    for (int d = G >> 1; d >= 1; d >>= 1) {
+      s += __shfl_xor(s, d, G);
+      const int64_t a = __shfl_xor(mn, d, G);
+      const int64_t b = __shfl_xor(mx, d, G);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+    if (row < n && sub == 0) {
+      int c, cat;
+      const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
+      if (s == 0) {
+        c = CLS_EMPTY;
+        mn = 0;
+        mx = -1;
+        cat = 3;
+      } else {
+        int want = cp.force;
+        if (want < 0) want = (s < cp.sort_max) ? 0 : (range <= cp.dense_max ? 1 : 2);
+        if (want == 0 && s > SORT_CAP) want = (range <= cp.dense_max) ? 1 : 2;
+        if (want == 1 && range > cp.dense_max) want = 2;
+        if (want == 0) {
+          int lg = 0;
+          while (((int64_t)1 << lg) < s) ++lg;
+          c = lg;
+        } else {
+          c = (want == 1) ? CLS_DENSE : CLS_CHUNKED;
+        }
+        cat = want;
+      }
+      ip[row] = s;
+      minc[row] = mn;
+      maxc[row] = mx;
+      cls[row] = c;
+      l_ip += (unsigned long long)s;
+      l_max = (unsigned long long)s > l_max ? (unsigned long long)s : l_max;
+      l_rng = (unsigned long long)range > l_rng ? (unsigned long long)range : l_rng;
+      l_ipc[cat] += (unsigned long long)s;
+      l_rc[cat] += 1;
+    }
+  }
+  if (sub == 0) {
+    atomicAdd(&sh[0], l_ip);
+    atomicMax(&sh[1], l_max);
+    atomicMax(&sh[2], l_rng);
+    for (int k = 0; k < 4; ++k) {
+      if (l_ipc[k]) atomicAdd(&sh[6 + k], l_ipc[k]);
+      if (l_rc[k]) atomicAdd(&sh[10 + k], l_rc[k]);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -376,7 +386,8 @@ hipError_t launch_rowinfo(const Mats& M, int64_t a_nnz, const ClassParams& cp, i
   int G = 1;
   while (G < 64 && G < avg) G <<= 1;
   const int64_t threads = M.n * G;
-  const unsigned grid = (unsigned)((threads + 255) / 256);
+  const int64_t want = (threads + 255) / 256;
+  const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
   MG_DISPATCH2(M, hipLaunchKernelGGL((k_rowinfo<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
                                      (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, M.n,
                                      G, cp, ip, minc, maxc, cls, stats));

@@ -108,17 +108,29 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
     wave_sync();
   }
 
-  // load (striped: the network sorts whatever order it is given)
+  // load (striped: the network sorts whatever order it is given).  In
+  // numeric mode the key carries the element's staging index in its low
+  // IDXB bits: the network moves one word per element, runs of equal keys
+  // sum in staging order, and values are fetched from LDS after the sort.
+  constexpr int IDXB = NUMERIC ? ilog2c(CAP) : 0;
   K k[E];
-  V v[NUMERIC ? E : 1];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int x = e * MG_WAVE + l;
-    k[e] = (x < P) ? s_key[w][x] : key_max<K>();
-    if (NUMERIC) v[e] = (x < P) ? s_val[w][x] : (V)0;
+    k[e] = (x < P) ? ((s_key[w][x] << IDXB) | (NUMERIC ? (K)x : (K)0)) : key_max<K>();
   }
-  if (NUMERIC) bitonic_sort_pairs<E>(k, *reinterpret_cast<V(*)[E]>(v));
-  else bitonic_sort_keys<E>(k);
+  bitonic_sort_keys<E>(k);
+  V v[NUMERIC ? E : 1];
+  if (NUMERIC) {
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      v[e] = (x < P) ? s_val[w][(int)(k[e] & (K)(CAP - 1))] : (V)0;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) k[e] >>= IDXB;
 
   // heads of runs of equal keys (blocked layout: element x = l*E + e)
   const K prevk = __shfl_up(k[E - 1], 1, MG_WAVE);
@@ -132,11 +144,23 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
     hc += head[e] ? 1 : 0;
   }
   if (!NUMERIC) {
+    // distinct keys of a row = head rank at the next row's first element (or
+    // the wave's total) minus the rank at this row's first element; every
+    // row of the tile has at least one product, so each slot has a first
+    const int hinc = wave_incl_scan(hc);
+    const int htot = __shfl(hinc, MG_WAVE - 1, MG_WAVE);
+    int hr = hinc - hc;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (head[e]) atomicAdd(&s_aux[w][(int)(k[e] >> colbits)], 1);
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      const K pk = (e == 0) ? prevk : k[e - 1];
+      if (head[e]) {
+        if (x == 0 || (k[e] >> colbits) != (pk >> colbits)) s_aux[w][(int)(k[e] >> colbits)] = hr;
+        ++hr;
+      }
+    }
     wave_sync();
-    if (l < nr) rownnz[s_row[w][l]] = s_aux[w][l];
+    if (l < nr) rownnz[s_row[w][l]] = ((l + 1 < nr) ? s_aux[w][l + 1] : htot) - s_aux[w][l];
     return;
   } else {
     const int hinc = wave_incl_scan(hc);
@@ -224,7 +248,11 @@ hipError_t sort_rows_cls(const Mats& M, int cls, bool numeric, const int32_t* li
   const int R = (cls <= 6) ? (64 >> cls) : 1;
   int slotbits = 0;
   while ((1 << slotbits) < R) ++slotbits;
-  const bool k64 = (colbits + slotbits) > 31;
+  int capbits = 0;
+  while ((1 << capbits) < 64 * E) ++capbits;
+  // count mode keeps keys below 2^31 (all-ones marks padding); numeric keys
+  // add the staging index and may use all 32 bits (see the kernel)
+  const bool k64 = numeric ? (colbits + slotbits + capbits) > 32 : (colbits + slotbits) > 31;
 #define MG_SR(EE)                                                                               \
   if (E == EE) {                                                                                \
     if (k64)                                                                                    \

@@ -125,8 +125,25 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
                             const int64_t* sort_items, const int32_t* item_counts,
                             const uint16_t* ws_col, const void* ws_val, int64_t* bin_nnz,
                             const int64_t* bin_out, void* ccol, int col64, void* cval,
-                            int dense_block, hipStream_t st);
+                            int dense_block, unsigned int* work, int persistent_wgs,
+                            hipStream_t st);
 size_t bin_dense_lds(int f64, int shift);
+// symbolic phase of CHUNKED rows with the row's bitmap in LDS (needs
+// row_bitmap_lds bytes); writes chunk nnz, chunk product counts, chunk row
+// and row nnz
+size_t row_bitmap_lds(int shift, int64_t max_nb);
+hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
+                             int64_t max_nb, int64_t* bin_nnz, int64_t* bin_cnt, int32_t* bin_row,
+                             int64_t* rownnz, hipStream_t st);
+// numeric reorder with chunk ranges reserved by atomic adds on bin cursors
+size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb);
+hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+                               const int32_t* tile_row, const int64_t* aoff,
+                               const int64_t* bin_start, unsigned long long* bin_cursor,
+                               uint16_t* ws_col, void* ws_val, int64_t max_nb, hipStream_t st);
+hipError_t launch_bin_group(const ChunkGeom& g, const BatchArgs& b, const int64_t* bin_cnt,
+                            int64_t dense_min, int64_t group_max, int64_t* dense_items,
+                            int64_t* sort_items, int32_t* item_counts, hipStream_t st);
 // per CHUNKED row: rownnz = sum of its bins' nnz (count mode) / bin output
 // offsets from crp (numeric prep)
 hipError_t launch_bin_rows(const ChunkGeom& g, int64_t k0, int64_t k1, const int64_t* bin_nnz,

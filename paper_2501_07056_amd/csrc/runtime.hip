@@ -64,7 +64,8 @@ struct magnus_plan_s {
   void* temp = nullptr;
   int64_t h_list_off[NCLS + 1]{};
   DevStats h_stats{};
-  int shift = 13, colbits = 1, dense_block = 256, tile = 4096;
+  int shift = 13, colbits = 1, dense_block = 256, tile = 2048, lds_budget = 65536;
+  int persistent_wgs = 512;
   int64_t sort_max = 1025, dense_min = 1024, group_max = 1024;
   // CHUNKED rows
   int64_t nch = 0, max_nb = 1;
@@ -73,6 +74,9 @@ struct magnus_plan_s {
   int32_t *tile_row = nullptr, *tab_cnt = nullptr, *bin_row = nullptr, *item_counts = nullptr;
   int64_t *bin_start = nullptr, *bin_cnt = nullptr, *bin_nnz = nullptr, *bin_out = nullptr;
   int64_t *dense_items = nullptr, *sort_items = nullptr;
+  unsigned long long* bin_cursor = nullptr;
+  unsigned int* work_ctr = nullptr;  // one counter per batch and phase
+  bool bitmap_symbolic = false;
   uint16_t* ws_col = nullptr;
   void* ws_val = nullptr;
   void* tab_temp = nullptr;
@@ -266,10 +270,21 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   if (max_tiles > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
   const int64_t ntiles = tots[1], ntab = tots[2], nbins = tots[3];
   const int64_t nbat = (int64_t)P->batches.size();
+  P->bitmap_symbolic = row_bitmap_lds(P->shift, P->max_nb) <= (size_t)P->lds_budget;
   P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
   P->tile_row = (int32_t*)palloc(P, sizeof(int32_t) * ntiles);
-  P->tab_cnt = (int32_t*)palloc(P, sizeof(int32_t) * ntab);
-  P->tab_off = (int64_t*)palloc(P, sizeof(int64_t) * ntab);
+  if (!P->bitmap_symbolic) {
+    P->tab_cnt = (int32_t*)palloc(P, sizeof(int32_t) * ntab);
+    P->tab_off = (int64_t*)palloc(P, sizeof(int64_t) * ntab);
+    P->tab_temp = palloc(P, scan_temp_bytes(max_ntab));
+    if (!P->tab_cnt || !P->tab_off || !P->tab_temp) return MAGNUS_ERR_OOM;
+  } else {
+    P->tab_temp = palloc(P, scan_temp_bytes(nbins));
+    if (!P->tab_temp) return MAGNUS_ERR_OOM;
+  }
+  P->bin_cursor = (unsigned long long*)palloc(P, sizeof(unsigned long long) * nbins);
+  P->work_ctr = (unsigned int*)palloc(P, sizeof(int64_t) * 2 * nbat);
+  if (!P->work_ctr) return MAGNUS_ERR_OOM;
   P->bin_start = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
   P->bin_cnt = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
   P->bin_nnz = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
@@ -280,10 +295,9 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   P->item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2 * nbat);
   P->ws_col = (uint16_t*)palloc(P, sizeof(uint16_t) * P->ws_products);
   P->ws_val = palloc(P, (size_t)vs * P->ws_products);
-  P->tab_temp = palloc(P, scan_temp_bytes(max_ntab));
-  if (!P->aoff || !P->tile_row || !P->tab_cnt || !P->tab_off || !P->bin_start || !P->bin_cnt ||
-      !P->bin_nnz || !P->bin_out || !P->bin_row || !P->dense_items || !P->sort_items ||
-      !P->item_counts || !P->ws_col || !P->ws_val || !P->tab_temp)
+  if (!P->aoff || !P->tile_row || !P->bin_start || !P->bin_cnt || !P->bin_nnz || !P->bin_out ||
+      !P->bin_row || !P->dense_items || !P->sort_items || !P->item_counts || !P->ws_col ||
+      !P->ws_val || !P->bin_cursor)
     return MAGNUS_ERR_OOM;
   HIPCHK(hipMemsetAsync(P->item_counts, 0, sizeof(int32_t) * 2 * nbat, P->st));
   HIPCHK(hipMemsetAsync(P->bin_nnz, 0, sizeof(int64_t) * nbins, P->st));
@@ -294,31 +308,61 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   return MAGNUS_OK;
 }
 
-magnus_status_t run_chunked(magnus_plan_s* P, bool numeric, void* ccol, int col64, void* cval) {
+// Symbolic phase of CHUNKED rows: exact nnz per chunk and per row, chunk
+// sizes and starts, and the accumulation work items of every batch.
+magnus_status_t chunked_symbolic(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  if (P->bitmap_symbolic) {
+    HIPCHK(launch_row_bitmap(P->M, P->g, P->aoff, P->max_nb, P->bin_nnz, P->bin_cnt, P->bin_row,
+                             P->crp, P->st));
+    for (size_t bi = 0; bi < P->batches.size(); ++bi) {
+      const BatchArgs& b = P->batches[bi];
+      HIPCHK(scan_excl_i64(P->bin_cnt + b.bin0, P->bin_start + b.bin0, b.nbins, nullptr, nullptr,
+                           P->tab_temp, P->st));
+      HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
+                              P->sort_items, P->item_counts + 2 * bi, P->st));
+    }
+    return MAGNUS_OK;
+  }
+  for (size_t bi = 0; bi < P->batches.size(); ++bi) {
+    const BatchArgs& b = P->batches[bi];
+    int32_t* ic = P->item_counts + 2 * bi;
+    HIPCHK(launch_bin_hist(P->M, P->g, b, P->tile_row, P->aoff, P->tab_cnt, P->max_nb, P->st));
+    HIPCHK(scan_excl_i32(P->tab_cnt + b.tab0, P->tab_off + b.tab0, b.ntab, nullptr, nullptr,
+                         P->tab_temp, P->st));
+    HIPCHK(launch_bin_scatter(P->M, P->g, b, false, P->tile_row, P->aoff, P->tab_cnt, P->tab_off,
+                              P->ws_col, P->ws_val, P->max_nb, P->stats, P->st));
+    HIPCHK(launch_bin_items(P->g, b, P->tab_off, P->bin_start, P->bin_cnt, P->bin_row,
+                            P->dense_min, P->group_max, P->dense_items, P->sort_items, ic, P->st));
+    unsigned int* wk = P->work_ctr + 4 * bi;
+    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    HIPCHK(launch_bin_accum(P->g, b, false, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
+                            P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
+                            P->bin_out, nullptr, 0, nullptr, P->dense_block, wk,
+                            P->persistent_wgs, P->st));
+    HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false, P->st));
+  }
+  return MAGNUS_OK;
+}
+
+// Numeric phase of CHUNKED rows, batch by batch: chunk output offsets in C,
+// reorder into the workspace, accumulate every chunk into C.
+magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* cval) {
   magnus_handle_s* h = P->h;
   for (size_t bi = 0; bi < P->batches.size(); ++bi) {
     const BatchArgs& b = P->batches[bi];
     int32_t* ic = P->item_counts + 2 * bi;
-    if (!numeric) {
-      HIPCHK(launch_bin_hist(P->M, P->g, b, P->tile_row, P->aoff, P->tab_cnt, P->max_nb, P->st));
-      HIPCHK(scan_excl_i32(P->tab_cnt + b.tab0, P->tab_off + b.tab0, b.ntab, nullptr, nullptr,
-                           P->tab_temp, P->st));
-    } else {
-      HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, nullptr, P->crp, P->bin_out, true,
-                             P->st));
-    }
-    HIPCHK(launch_bin_scatter(P->M, P->g, b, numeric, P->tile_row, P->aoff, P->tab_cnt, P->tab_off,
-                              P->ws_col, P->ws_val, P->max_nb, P->stats, P->st));
-    if (!numeric)
-      HIPCHK(launch_bin_items(P->g, b, P->tab_off, P->bin_start, P->bin_cnt, P->bin_row,
-                              P->dense_min, P->group_max, P->dense_items, P->sort_items, ic,
-                              P->st));
-    HIPCHK(launch_bin_accum(P->g, b, numeric, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
+    HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, nullptr, P->crp, P->bin_out, true,
+                           P->st));
+    HIPCHK(launch_fill_i64((int64_t*)P->bin_cursor + b.bin0, b.nbins, 0, P->st));
+    HIPCHK(launch_bin_scatter2(P->M, P->g, b, P->tile_row, P->aoff, P->bin_start, P->bin_cursor,
+                               P->ws_col, P->ws_val, P->max_nb, P->st));
+    unsigned int* wk = P->work_ctr + 4 * bi + 2;
+    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    HIPCHK(launch_bin_accum(P->g, b, true, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
                             P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
-                            P->bin_out, ccol, col64, cval, P->dense_block, P->st));
-    if (!numeric)
-      HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false,
-                             P->st));
+                            P->bin_out, ccol, col64, cval, P->dense_block, wk,
+                            P->persistent_wgs, P->st));
   }
   return MAGNUS_OK;
 }
@@ -506,14 +550,21 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   P->itype_col = A->col_type;
   const magnus_options_t& o = h->opts;
   const int lds = o.lds_bytes > 0 ? std::min(o.lds_bytes, h->lds_max) : h->lds_max;
+  P->lds_budget = lds;
   P->shift = o.chunk_shift > 0 ? std::min(o.chunk_shift, 16) : default_shift(M.f64, lds);
   P->sort_max = o.sort_max > 0 ? std::min<int64_t>(o.sort_max, SORT_CAP + 1) : SORT_CAP + 1;
   P->group_max = o.sort_group_max > 0 ? std::min<int64_t>(o.sort_group_max, SORT_CAP) : SORT_CAP;
   P->dense_min = o.bin_dense_min > 0 ? o.bin_dense_min : P->group_max;
   if (P->dense_min > P->group_max + 1) P->dense_min = P->group_max + 1;
-  P->tile = o.tile_products > 0 ? o.tile_products : 4096;
-  if (P->tile < 256 || P->tile > 16384 || (P->tile & (P->tile - 1))) P->tile = 4096;
+  P->tile = o.tile_products > 0 ? o.tile_products : 2048;
+  if (P->tile < 256 || P->tile > 16384 || (P->tile & (P->tile - 1))) P->tile = 2048;
   P->dense_block = (o.dense_block == 512 || o.dense_block == 1024) ? o.dense_block : 256;
+  {
+    // dense accumulator workgroups resident per CU, from its LDS footprint
+    const size_t dl = bin_dense_lds(M.f64, P->shift);
+    const int per_cu = std::max<int>(1, (int)(h->lds_max / std::max<size_t>(dl, 1)));
+    P->persistent_wgs = std::max(1, h->cus) * std::min(per_cu, 2048 / P->dense_block);
+  }
 
   auto cleanup = [&](magnus_status_t st) {
     plan_free_all(P);
@@ -569,12 +620,19 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   // precise symbolic phase: exact nnz per row, then the row offsets of C
   PCHK(launch_fill_i64(P->crp, n + 1, 0, P->st));
   SCHK(run_rows(P, false, nullptr, nullptr));
-  if (P->nch > 0) SCHK(run_chunked(P, false, nullptr, 0, nullptr));
+  if (P->nch > 0) SCHK(chunked_symbolic(P));
   PCHK(scan_excl_i64(P->crp, P->crp, n + 1, nullptr, nullptr, P->temp, P->st));
   PCHK(hipEventRecord(ev1, P->st));
   int64_t nnzc = 0;
   DevStats st2{};
-  SCHK(readback(P, {{P->crp + n, 8}, {P->stats, sizeof(DevStats)}}, {&nnzc, &st2}));
+  std::vector<int32_t> icounts(2 * P->batches.size() + 2, 0);
+  SCHK(readback(P, {{P->crp + n, 8}, {P->stats, sizeof(DevStats)},
+                    {P->item_counts, sizeof(int32_t) * 2 * P->batches.size()}},
+                {&nnzc, &st2, icounts.data()}));
+  for (size_t b = 0; b < P->batches.size(); ++b) {
+    P->info.n_dense_chunks += icounts[2 * b];
+    P->info.n_sort_groups += icounts[2 * b + 1];
+  }
   float ms = 0;
   (void)hipEventElapsedTime(&ms, ev0, ev1);
   (void)hipEventDestroy(ev0);
@@ -636,7 +694,7 @@ magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t P, const magnus_
   magnus_status_t r = run_rows(P, true, C->col, C->val);
   if (r != MAGNUS_OK) return r;
   if (P->nch > 0) {
-    r = run_chunked(P, true, C->col, C->col_type == MAGNUS_I64, C->val);
+    r = chunked_numeric(P, C->col, C->col_type == MAGNUS_I64, C->val);
     if (r != MAGNUS_OK) return r;
   }
   HIPCHK(launch_write_rowptr(P->crp, P->n, C->rowptr, C->rowptr_type == MAGNUS_I64, P->st));

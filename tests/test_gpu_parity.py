@@ -65,6 +65,21 @@ def test_rmat_auto_small_chunks(ctx):
     ctx.set_options(chunk_shift=0, tile_products=0, batch_products=0)
 
 
+def test_rmat_table_symbolic(ctx):
+    """LDS budget too small for a whole row's bitmap: the symbolic phase of
+    CHUNKED rows goes through per-tile histograms, reorder and per-chunk
+    counting instead."""
+    A, _ = wl.config2(12)
+    log("rmat12 table symbolic")
+    for shift in (8, 10):
+        rp, col, val, info = gpu_product(ctx, A, A, force_category="chunked", chunk_shift=shift,
+                                         tile_products=1024, lds_bytes=16384,
+                                         batch_products=300000)
+        compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
+    ctx.set_options(chunk_shift=0, tile_products=0, batch_products=0, lds_bytes=0,
+                    force_category="auto")
+
+
 @pytest.mark.parametrize("rpt", [np.int32, np.int64])
 @pytest.mark.parametrize("cit", [np.int32, np.int64])
 @pytest.mark.parametrize("vt", [np.float32, np.float64])
