@@ -1,0 +1,371 @@
+"""Benchmark of the gfx950 SpGEMM path on one MI355X.
+
+One step = the whole product C = A*B as the paper times it (setup + symbolic +
+numeric, Section 4.2): plan (setup, precise symbolic phase), allocation of C,
+numeric phase, release.  Inputs are resident in device memory before the
+timed region starts.
+
+Default workload: C = A*A with A the scale-20 R-MAT matrix (2^20 rows,
+a=.57, b=c=.19, d=.05, 16 draws per row, duplicates merged, f64 values
+uniform in [-1, 1), int32 indices, int64 row pointers for C), the R-MAT
+workload of Section 4.2 / Table 3.
+
+The JSON line carries:
+  value        GFLOP/s = 2 * intermediate products / time per step
+  roofline     the dominant kernel's algorithmic bytes per launch over its
+               event-timed duration, against the 8 TB/s HBM peak
+  ideal_volume the paper's ideal data volume (Eqs. 8-9) over the step time
+  cpu_baseline the CPU oracle timed on a bounded sample of the same rows
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpGEMM GFLOP/s + % HBM roofline; batched/served vs per-call, p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def src_digest() -> str:
+    h = hashlib.sha1()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2501_07056_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:12]
+
+
+def workload(name: str):
+    import workloads as wl
+    if name == "rmat20":
+        A, B = wl.config2(20)
+        return A, B, {"workload": "R-MAT scale 20, C = A*A", "n": A.nrows, "edge_factor": 16,
+                      "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "values": "f64 uniform [-1,1)",
+                      "index": "int32", "c_rowptr": "int64"}
+    if name.startswith("rmat"):
+        sc = int(name[4:])
+        A, B = wl.config2(sc)
+        return A, B, {"workload": f"R-MAT scale {sc}, C = A*A", "n": A.nrows, "index": "int32",
+                      "values": "f64", "c_rowptr": "int64"}
+    if name.startswith("er"):
+        lg = int(name[2:])
+        A, B = wl.config3(lg)
+        return A, B, {"workload": f"Erdos-Renyi 2^{lg} x 2^{lg}, 16 per row, C = A*B",
+                      "n": A.nrows, "values": "f32 uniform [-1,1)", "index": "int32 col, int64 rowptr",
+                      "c_rowptr": "int64"}
+    if name == "cfg1":
+        A, B = wl.config1()
+        return A, B, {"workload": "Erdos-Renyi 4096 x 4096, 8 per row, integer f64, C = A*A",
+                      "n": A.nrows, "index": "int32", "c_rowptr": "int64"}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def ideal_volume(A, B, ip, nnz_c, c_rp_bytes=8):
+    # Eqs. 8-9 with each array's own width
+    import oracle
+    r, w = oracle.ideal_volume(A.nrows, A.nnz, ip, A.nrows, nnz_c,
+                               s_rp_a=A.rowptr.dtype.itemsize, s_rp_b=B.rowptr.dtype.itemsize,
+                               s_col_a=A.col.dtype.itemsize, s_col_b=B.col.dtype.itemsize,
+                               s_val=A.val.dtype.itemsize, s_rp_c=c_rp_bytes,
+                               s_col_c=B.col.dtype.itemsize)
+    return r + w
+
+
+def stored_traffic(kernel: str, wl_name: str):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter
+    summaries, if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl_name}.md")
+    if not os.path.exists(path):
+        return None, None
+    for line in open(path):
+        if line.startswith("traffic-json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("src_sha") != src_digest():
+                return None, "stale"
+            k = d.get("kernels", {}).get(kernel)
+            if k is None:
+                return None, "absent"
+            return float(k["bytes_per_launch"]), d.get("note")
+    return None, None
+
+
+def cpu_baseline(A, B, ip_rows, seconds: float, seed: int = 7):
+    """Oracle rate on rows drawn with probability proportional to their
+    intermediate-product count (so the sample has the workload's mix)."""
+    import numpy as np
+
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    cum = np.cumsum(ip_rows.astype(np.float64))
+    total = cum[-1]
+    rng = np.random.default_rng(seed)
+
+    def pick(budget):
+        rows, got = set(), 0
+        while got < budget and len(rows) < len(ip_rows):
+            r = int(np.searchsorted(cum, rng.random() * total, side="right"))
+            r = min(r, len(ip_rows) - 1)
+            if r not in rows and ip_rows[r] > 0:
+                rows.add(r)
+                got += int(ip_rows[r])
+        return np.array(sorted(rows), dtype=np.int64)
+
+    # grow a calibration sample until it runs for a tenth of the budget, then
+    # size the measured sample for about `seconds`
+    budget, rate = 4e6, None
+    while True:
+        cal = pick(budget)
+        t0 = time.perf_counter()
+        oracle.spgemm(A, B, cal, nthreads=cores)
+        dt = time.perf_counter() - t0
+        rate = max(1.0, ip_rows[cal].sum() / max(1e-6, dt))
+        if dt >= 0.1 * seconds or budget >= 0.25 * total:
+            break
+        budget *= 4
+    rows = pick(min(rate * seconds, 0.5 * total))
+    t0 = time.perf_counter()
+    ref = oracle.spgemm(A, B, rows, nthreads=cores)
+    dt = time.perf_counter() - t0
+    ipw = int(ip_rows[rows].sum())
+    res = {"value": 2.0 * ipw / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{len(rows)} rows drawn with probability proportional to their "
+                     f"intermediate products ({ipw} products, {dt:.1f} s)",
+           "seconds": dt}
+    return res, rows, ref
+
+
+# library profile names -> kernel symbols they launch
+KERNEL_SYMBOLS = {
+    "bin_scatter (numeric reorder)": ["k_bin_scatter2<"],
+    "bin_accum (numeric, dense+sort chunks)": ["k_accum_dense<double, true>", "k_accum_sort<double, true>",
+                                               "k_accum_dense<float, true>", "k_accum_sort<float, true>"],
+    "row_bitmap (symbolic, chunked rows)": ["k_row_bitmap<"],
+    "sort_rows (numeric)": ["k_sort_rows<"],
+    "rowinfo (setup)": ["k_rowinfo<"],
+}
+
+
+def _pmc_totals(d, counter):
+    import csv
+    tot = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            t = tot.setdefault(name, [0.0, set()])
+            t[0] += float(r["Counter_Value"])
+            t[1].add(r["Dispatch_Id"])
+    return {k: (v[0], len(v[1])) for k, v in tot.items()}
+
+
+def pmc_summary(args):
+    fetch_d, write_d, cf_d, cw_d = args.pmc_summary
+    fetch, write = _pmc_totals(fetch_d, "FETCH_SIZE"), _pmc_totals(write_d, "WRITE_SIZE")
+    cfe, cwr = _pmc_totals(cf_d, "FETCH_SIZE"), _pmc_totals(cw_d, "WRITE_SIZE")
+    ck = [k for k in cfe if "k_stream_copy" in k]
+    cw = [k for k in cwr if "k_stream_copy" in k]
+    f_fetch = args.copy_bytes * cfe[ck[0]][1] / (cfe[ck[0]][0] * 1024.0)
+    f_write = args.copy_bytes * cwr[cw[0]][1] / (cwr[cw[0]][0] * 1024.0)
+    kernels = {}
+    lines = []
+    for lib_name, pats in KERNEL_SYMBOLS.items():
+        fk = sum(v[0] for k, v in fetch.items() if any(p in k for p in pats))
+        wk = sum(v[0] for k, v in write.items() if any(p in k for p in pats))
+        # dispatches of the first matching symbol = launches of the grouped kernel
+        nd = max([v[1] for k, v in fetch.items() if any(p in k for p in pats[:1])] or [0])
+        if nd == 0:
+            continue
+        b = (fk * f_fetch + wk * f_write) * 1024.0 / nd
+        kernels[lib_name] = {"bytes_per_launch": b, "fetch_kib_per_launch": fk / nd,
+                             "write_kib_per_launch": wk / nd, "launches": nd}
+        lines.append(f"| {lib_name} | {nd} | {fk / nd:.4g} | {wk / nd:.4g} | {b / 1e9:.3f} |")
+    d = {"src_sha": src_digest(), "copy_factor_fetch": f_fetch, "copy_factor_write": f_write,
+         "kernels": kernels,
+         "note": "FETCH_SIZE / WRITE_SIZE KiB per dispatch scaled by the plain copy kernel's factors"}
+    out = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.md")
+    with open(out, "w") as fh:
+        fh.write(f"# HBM traffic per launch, workload {args.workload}\n\n")
+        fh.write("Counters: `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (separate runs) of\n"
+                 f"`python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu`, and of\n"
+                 f"`python bench.py --copy-probe {args.copy_bytes}` for the scale factors\n"
+                 f"(copy of {args.copy_bytes} bytes: fetch factor {f_fetch:.4f}, write factor {f_write:.4f}).\n\n")
+        fh.write("| kernel | launches | FETCH KiB/launch | WRITE KiB/launch | scaled GB/launch |\n|---|---|---|---|---|\n")
+        fh.write("\n".join(lines) + "\n\n")
+        fh.write("traffic-json:" + json.dumps(d) + "\n")
+    log(f"[bench] wrote {out}")
+
+
+def trace_summary(args):
+    import csv
+    files = glob.glob(os.path.join(args.trace_summary, "**", "*kernel_stats.csv"), recursive=True)
+    rows = list(csv.DictReader(open(files[0])))
+    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}.md")
+    with open(out, "w") as fh:
+        fh.write(f"# Kernel time, workload {args.workload}\n\n")
+        fh.write(f"Command: `{args.trace_command}`\n\n")
+        fh.write("| kernel | calls | total ms | average us | % |\n|---|---|---|---|---|\n")
+        for r in rows[:25]:
+            name = r["Name"].replace("|", "/")
+            if len(name) > 90:
+                name = name[:90] + "..."
+            fh.write(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
+    log(f"[bench] wrote {out}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--option", action="append", default=[],
+                    help="library option name=value (repeatable)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run the plain copy kernel on this many bytes (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                       "COPY_WRITE_DIR"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs into profiles/traffic_<workload>.md")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 32)
+    ap.add_argument("--trace-summary", metavar="STATS_DIR",
+                    help="turn a rocprofv3 --kernel-trace --stats CSV into profiles/kernels_<workload>.md")
+    ap.add_argument("--trace-command", default="")
+    args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
+    if args.trace_summary:
+        trace_summary(args)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(this build measures a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2501_07056_amd as mg
+
+    t0 = time.time()
+    A, B, cfg = workload(args.workload)
+    log(f"[bench] {cfg['workload']}: generated in {time.time() - t0:.1f} s, nnz(A)={A.nnz}")
+    dA = mg.DeviceCSR.from_host(A)
+    dB = dA if B is A else mg.DeviceCSR.from_host(B)
+    opts = {}
+    for o in args.option:
+        k, v = o.split("=", 1)
+        opts[k] = int(v) if v.lstrip("-").isdigit() else v
+    ctx = mg.Context(0, **opts)
+    torch.cuda.synchronize()
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            ctx.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        ctx.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        k = ctx.profile_read()[0]
+        log(f"[bench] copy {args.copy_probe} bytes: {k['bytes'] / k['ms'] / 1e6:.1f} GB/s (events)")
+        return
+
+    def step():
+        p = ctx.plan(dA, dB)
+        C = p.execute(rowptr_dtype=torch.int64)
+        info = p.info.as_dict()
+        p.destroy()
+        return C, info
+
+    for i in range(args.warmup):
+        C, info = step()
+        del C
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i} done")
+
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        C, info = step()
+        if i + 1 < args.steps:
+            del C
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    kstats = ctx.profile_read()
+    ms = 1e3 * elapsed / args.steps
+    ip = int(info["ip_total"])
+    nnz_c = int(info["nnz_c"])
+    gflops = 2.0 * ip / (ms / 1e3) / 1e9
+    log(f"[bench] {args.steps} steps: {ms:.2f} ms/step, {gflops:.1f} GFLOP/s")
+
+    # dominant kernel and its roofline (algorithmic bytes / event time)
+    kstats.sort(key=lambda k: -k["ms"])
+    dom = kstats[0]
+    ach = (dom["bytes"] / dom["launches"]) / ((dom["ms"] / dom["launches"]) / 1e3) / 1e9
+    traffic, tnote = stored_traffic(dom["name"], args.workload)
+    roof = {"bound": "hbm", "kernel": dom["name"], "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+            "ms_per_launch": dom["ms"] / dom["launches"], "launches": dom["launches"]}
+    vid = ideal_volume(A, B, ip, nnz_c)
+    ideal = {"bytes": vid, "frac_of_peak": round(vid / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4),
+             "t_ideal_ms": vid / (HBM_PEAK_GBS * 1e9) * 1e3}
+    kernels = [{"name": k["name"], "ms_per_step": round(k["ms"] / args.steps, 3),
+                "GBps": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in kstats]
+
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        ipr, _ = ctx.row_ip(dA, dB)
+        ipr = ipr.cpu().numpy()
+        cpu, rows, ref = cpu_baseline(A, B, ipr, args.cpu_seconds)
+        # the sampled rows of the last timed C against the oracle
+        rp = C.rowptr.cpu().numpy()
+        idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+        it = torch.from_numpy(idx).to(C.col.device)
+        gcol = C.col[it].cpu().numpy().astype(np.int64)
+        gval = C.val[it].cpu().numpy().astype(np.float64)
+        ok_struct = bool(np.array_equal(np.diff(ref.rowptr), rp[rows + 1] - rp[rows]) and
+                         np.array_equal(gcol, ref.col))
+        rtol = 1e-12 if A.val.dtype == np.float64 else 1e-5
+        err = np.abs(gval - ref.ref) / np.maximum(ref.abssum, 1e-300)
+        parity = {"rows": int(len(rows)), "entries": int(len(gcol)), "structure_equal": ok_struct,
+                  "max_err_over_abssum": float(err.max()) if len(err) else 0.0,
+                  "within_rtol": bool(ok_struct and (err <= rtol).all()), "rtol": rtol}
+        log(f"[bench] cpu oracle {cpu['value']:.3f} GFLOP/s on {cpu['cores']} cores; "
+            f"sample parity {parity['within_rtol']}")
+
+    dtype = "f64" if A.val.dtype == np.float64 else "f32"
+    cfg.update({"nnz_A": int(A.nnz), "intermediate_products": ip, "nnz_C": nnz_c,
+                "categories_rows": info["rows_by_category"], "chunk_shift": info["chunk_shift"],
+                "batches": info["n_batches"], "options": opts})
+    out = {"metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": cfg, "roofline": roof, "ideal_volume": ideal,
+           "kernels": kernels, "cpu_baseline": cpu, "sample_parity": parity,
+           "src_sha": src_digest()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,7 +114,8 @@ typedef struct {
   int32_t validate;       /* 1: check CSR invariants of A and B (one extra pass) */
   int32_t lds_bytes;      /* LDS budget per workgroup (0: device maximum) */
   int32_t sort_group_max; /* products per packed sort group of small chunks (<= 1024) */
-  int32_t _reserved[5];
+  int32_t stream_hints;   /* non-temporal accesses: 1 workspace stores, 2 workspace loads, 4 C stores */
+  int32_t _reserved[4];
 } magnus_options_t;
 
 /* Sizes the plan reports (host struct). */
@@ -125,6 +126,7 @@ typedef struct {
   int64_t max_row_ip;
   int64_t rows_by_category[4]; /* SORT, DENSE, CHUNKED, EMPTY */
   int64_t ip_by_category[4];
+  int64_t nnz_by_category[4];  /* nnz of C in the rows of each category */
   int64_t n_batches;       /* row batches of CHUNKED rows */
   int64_t n_bins;          /* chunks (bins) over all CHUNKED rows */
   int64_t n_dense_chunks;  /* chunks accumulated by the dense LDS accumulator */
@@ -194,6 +196,28 @@ magnus_status_t magnus_paper_chunk_model(int64_t m_c, int64_t s_cache, int64_t s
  * accumulator (values plus one bitmap bit per column) fits lds_bytes, capped
  * at 2^16 so chunk-local columns fit 16 bits.  Host only. */
 magnus_status_t magnus_gpu_chunk_shift(int32_t val_type, int64_t lds_bytes, int32_t* shift);
+
+/* Per-kernel timing.  While enabled, the library brackets each launch of its
+ * main kernels with HIP events on the launch stream and records the
+ * algorithmic bytes the launch must move (its inputs read once and outputs
+ * written once, counted from the sizes it processes).  magnus_profile_read
+ * waits for the recorded events, returns up to max entries aggregated by
+ * kernel name (*n receives the count) and clears the records. */
+typedef struct {
+  char name[40];
+  int64_t launches;
+  double ms;     /* summed event time */
+  double bytes;  /* summed algorithmic bytes */
+} magnus_kernel_stat_t;
+magnus_status_t magnus_profile_enable(magnus_handle_t h, int on);
+magnus_status_t magnus_profile_read(magnus_handle_t h, magnus_kernel_stat_t* out, int max, int* n);
+
+/* Plain device-to-device copy of `bytes` bytes (16-byte vectors): the
+ * streaming reference of Section 4.3 for the achievable bandwidth, and the
+ * known-size kernel that memory counters are scaled against.  Does not
+ * synchronise. */
+magnus_status_t magnus_stream_copy(magnus_handle_t h, void* dst, const void* src, size_t bytes,
+                                   void* stream);
 
 /* Building block: exclusive prefix sum of n int64 values (device in/out, may
  * alias).  *total (host, may be NULL) receives the sum; synchronises only

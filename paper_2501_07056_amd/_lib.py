@@ -30,12 +30,14 @@ class Options(ctypes.Structure):
     _fields_ = [("force_category", c_i32), ("sort_max", c_i32), ("chunk_shift", c_i32),
                 ("bin_dense_min", c_i32), ("tile_products", c_i32), ("dense_block", c_i32),
                 ("batch_products", c_i64), ("max_workspace_bytes", c_i64), ("validate", c_i32),
-                ("lds_bytes", c_i32), ("sort_group_max", c_i32), ("_reserved", c_i32 * 5)]
+                ("lds_bytes", c_i32), ("sort_group_max", c_i32), ("stream_hints", c_i32),
+                ("_reserved", c_i32 * 4)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("ip_total", c_i64), ("flops", c_i64), ("nnz_c", c_i64), ("max_row_ip", c_i64),
                 ("rows_by_category", c_i64 * 4), ("ip_by_category", c_i64 * 4),
+                ("nnz_by_category", c_i64 * 4),
                 ("n_batches", c_i64), ("n_bins", c_i64), ("n_dense_chunks", c_i64),
                 ("n_sort_groups", c_i64), ("plan_bytes", c_i64),
                 ("chunk_shift", c_i32), ("sort_max", c_i32), ("bin_dense_min", c_i32),
@@ -47,6 +49,11 @@ class PlanInfo(ctypes.Structure):
             v = getattr(self, name)
             d[name] = list(v) if isinstance(v, ctypes.Array) else v
         return d
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", c_i64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_vp, ctypes.c_size_t, c_vp, c_vp)
@@ -97,6 +104,9 @@ def load(path: str = LIB_PATH):
                                              P(c_i64), P(c_i64)]
     lib.magnus_gpu_chunk_shift.argtypes = [c_i32, c_i64, P(c_i32)]
     lib.magnus_exclusive_scan_i64.argtypes = [c_vp, c_vp, c_vp, c_i64, P(c_i64), c_vp]
+    lib.magnus_profile_enable.argtypes = [c_vp, c_i32]
+    lib.magnus_profile_read.argtypes = [c_vp, P(KernelStat), c_i32, P(c_i32)]
+    lib.magnus_stream_copy.argtypes = [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
     for fn in declared_symbols():
         f = getattr(lib, fn)
         if fn not in ("magnus_status_string", "magnus_last_error", "magnus_options_default"):

@@ -81,7 +81,10 @@ class Context:
                 return None
 
         def _free(p, n, stream, ctx):
-            torch.cuda.caching_allocator_delete(int(p))
+            try:
+                torch.cuda.caching_allocator_delete(int(p))
+            except Exception:  # interpreter shutdown: torch already torn down
+                pass
 
         self._alloc_cb = _lib.ALLOC_FN(_alloc)
         self._free_cb = _lib.FREE_FN(_free)
@@ -143,6 +146,27 @@ class Context:
             ctypes.c_void_p(out.data_ptr()) if x.numel() else None, x.numel(), ctypes.byref(tot),
             s), "magnus_exclusive_scan_i64", self.handle)
         return out, tot.value
+
+    def profile(self, on: bool = True):
+        check(self.lib.magnus_profile_enable(self.handle, 1 if on else 0), "magnus_profile_enable")
+
+    def profile_read(self):
+        """Per-kernel launches, event milliseconds and algorithmic bytes since
+        the last read (waits for the recorded events)."""
+        arr = (_lib.KernelStat * 64)()
+        n = ctypes.c_int32()
+        check(self.lib.magnus_profile_read(self.handle, arr, 64, ctypes.byref(n)),
+              "magnus_profile_read", self.handle)
+        return [{"name": arr[i].name.decode(), "launches": int(arr[i].launches),
+                 "ms": float(arr[i].ms), "bytes": float(arr[i].bytes)} for i in range(n.value)]
+
+    def stream_copy(self, dst: torch.Tensor, src: torch.Tensor, stream=None):
+        s, keep = _stream_ptr(stream)
+        nbytes = src.numel() * src.element_size()
+        assert dst.numel() * dst.element_size() >= nbytes
+        check(self.lib.magnus_stream_copy(self.handle, ctypes.c_void_p(dst.data_ptr()),
+                                          ctypes.c_void_p(src.data_ptr()), nbytes, s),
+              "magnus_stream_copy", self.handle)
 
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, rowptr_dtype=torch.int64, stream=None):
         p = self.plan(A, B, stream)

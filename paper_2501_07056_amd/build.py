@@ -13,13 +13,18 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmagnus.so")
 OBJ = os.path.join(ROOT, "_build")
+# extra compiler flags and an alternative output, for experiment builds
+EXTRA = os.environ.get("MAGNUS_EXTRA_FLAGS", "").split()
+if os.environ.get("MAGNUS_LIB_OUT"):
+    OUT = os.path.abspath(os.environ["MAGNUS_LIB_OUT"])
+    OBJ = OUT + ".objs"
 ARCH = os.environ.get("MAGNUS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          # packed fp32 instructions are left to nobody: keep them out of codegen
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument"]
+         "-Wno-unused-command-line-argument"] + EXTRA
 
 
 def _hipcc():

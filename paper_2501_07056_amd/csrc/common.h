@@ -18,6 +18,27 @@ MG_INLINE int64_t ld64(const T* p, int64_t i) { return (int64_t)p[i]; }
 
 MG_INLINE int lane() { return (int)__lane_id(); }
 
+// Streaming accesses for data touched once (the reordered intermediate
+// product and C): non-temporal, so they do not evict B's rows and the
+// accumulators' neighbours from L2 and the memory-side cache.  This is the
+// role of the non-temporal stores of the reorder in Section 3.2.
+// Access classes that may take the non-temporal forms (a compile-time mask:
+// the hint is instruction encoding, so it cannot be chosen at run time).
+constexpr int HINT_WS_STORE = 1, HINT_WS_LOAD = 2, HINT_C_STORE = 4;
+#ifndef MG_NT_MASK
+#define MG_NT_MASK 1
+#endif
+template <int CLASS, typename T>
+MG_INLINE void st_stream(T* p, T v) {
+  if constexpr ((MG_NT_MASK & CLASS) != 0) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <int CLASS, typename T>
+MG_INLINE T ld_stream(const T* p) {
+  if constexpr ((MG_NT_MASK & CLASS) != 0) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // Wave-wide inclusive prefix sum (64 lanes).
 template <typename T>
 MG_INLINE T wave_incl_scan(T v) {

@@ -78,12 +78,13 @@ hipError_t launch_batch_bounds(const ChunkGeom& g, int64_t W, int32_t* first_of,
 template <typename RP, typename CI>
 __global__ void __launch_bounds__(256) k_aoff(const RP* __restrict__ arp, const CI* __restrict__ acol,
                                               const RP* __restrict__ brp, const int32_t* rows,
-                                              int64_t nrows, int64_t* aoff) {
+                                              int64_t nrows, int64_t* aoff, int64_t* ent) {
   const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
   if (k >= nrows) return;
   const int l = lane();
   const int32_t r = rows[k];
   const int64_t a0 = arp[r], a1 = arp[r + 1];
+  if (l == 0) ent[k] = a1 - a0;
   int64_t carry = 0;
   for (int64_t e0 = a0; e0 < a1; e0 += MG_WAVE) {
     const int64_t e = e0 + l;
@@ -128,7 +129,8 @@ struct TileCtx {
 
 template <typename RP>
 MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t* tile_row,
-                          const RP* arp, const int64_t* aoff, TileCtx& c) {
+                          const RP* arp, const int64_t* aoff, TileCtx& c,
+                          const int64_t* tile_e0 = nullptr) {
   const int64_t tg = b.tile0 + blockIdx.x;
   c.k = tile_row[tg];
   c.ti = tg - g.tileBase[c.k];
@@ -142,6 +144,10 @@ MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t*
   c.nbk = g.nb[c.k];
   c.ntk = g.nt[c.k];
   c.tabk = g.tabBase[c.k];
+  if (tile_e0) {
+    c.e0 = tile_e0[tg];
+    return;
+  }
   // first entry whose products reach past p0: largest e with aoff[e] <= p0
   int64_t lo = c.a0, hi = c.a1;
   while (hi - lo > 1) {
@@ -149,6 +155,25 @@ MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t*
     if (aoff[mid] <= c.p0) lo = mid; else hi = mid;
   }
   c.e0 = lo;
+}
+
+// First A entry of every tile (largest e with aoff[e] <= the tile's first
+// product), one thread per tile: the searches' latencies overlap here instead
+// of stalling every reorder workgroup at its start.
+template <typename RP>
+__global__ void k_tile_e0(const RP* __restrict__ arp, ChunkGeom g, const int32_t* tile_row,
+                          const int64_t* __restrict__ aoff, int64_t ntiles, int64_t* tile_e0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int64_t k = tile_row[t];
+  const int64_t p0 = (t - g.tileBase[k]) * (int64_t)g.tile;
+  const int32_t row = g.rows[k];
+  int64_t lo = arp[row], hi = arp[row + 1];
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (aoff[mid] <= p0) lo = mid; else hi = mid;
+  }
+  tile_e0[t] = lo;
 }
 
 // Calls f(q, col, prod) for every product q in [0, p1 - p0) of a row's
@@ -332,8 +357,8 @@ __global__ void __launch_bounds__(BIN_BS)
   const int64_t nloc = c.p1 - c.p0;
   for (int64_t s = threadIdx.x; s < nloc; s += BIN_BS) {
     const int64_t d = dst[st_bin[s]] + s;
-    ws_col[d] = st_col[s];
-    if (NUMERIC) ws_val[d] = st_val[s];
+    st_stream<HINT_WS_STORE>(&ws_col[d], st_col[s]);
+    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], st_val[s]);
   }
 }
 
@@ -420,14 +445,15 @@ __global__ void __launch_bounds__(BIN_BS)
     k_bin_scatter2(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
                    const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
                    ChunkGeom g, BatchArgs b, const int32_t* __restrict__ tile_row,
-                   const int64_t* __restrict__ aoff, const int64_t* __restrict__ bin_start,
-                   unsigned long long* bin_cursor, uint16_t* ws_col, V* ws_val) {
+                   const int64_t* __restrict__ aoff, const int64_t* __restrict__ tile_e0,
+                   const int64_t* __restrict__ bin_start, unsigned long long* bin_cursor,
+                   uint16_t* ws_col, V* ws_val) {
   extern __shared__ __align__(16) unsigned char dsm[];
   int32_t* w_pre = (int32_t*)dsm;
   int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);
   V* w_av = (V*)(w_b0 + BIN_BS);
   TileCtx c;
-  tile_setup<RP>(g, b, tile_row, arp, aoff, c);
+  tile_setup<RP>(g, b, tile_row, arp, aoff, c, tile_e0);
   int32_t* hist = (int32_t*)((char*)w_av + BIN_BS * 8);
   int64_t* dst = (int64_t*)(((uintptr_t)(hist + c.nbk) + 15) & ~(uintptr_t)15);
   uint32_t* u_word = (uint32_t*)(dst + c.nbk);
@@ -467,8 +493,8 @@ __global__ void __launch_bounds__(BIN_BS)
   for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
     const uint32_t w = u_word[q];
     const int64_t d = dst[w >> 16] + u_rank[q];
-    ws_col[d] = (uint16_t)(w & 0xFFFFu);
-    ws_val[d] = u_val[q];
+    st_stream<HINT_WS_STORE>(&ws_col[d], (uint16_t)(w & 0xFFFFu));
+    st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
   }
 }
 
@@ -580,8 +606,8 @@ __global__ void __launch_bounds__(1024)
       V v4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        c4[u] = ws_col[s0 + q + u * BS];
-        if (NUMERIC) v4[u] = ws_val[s0 + q + u * BS];
+        c4[u] = ld_stream<HINT_WS_LOAD>(&ws_col[s0 + q + u * BS]);
+        if (NUMERIC) v4[u] = ld_stream<HINT_WS_LOAD>(&ws_val[s0 + q + u * BS]);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -590,9 +616,9 @@ __global__ void __launch_bounds__(1024)
       }
     }
     for (; q < cnt; q += BS) {
-      const uint32_t c = ws_col[s0 + q];
+      const uint32_t c = ld_stream<HINT_WS_LOAD>(&ws_col[s0 + q]);
       atomicOr(&bits[c >> 5], 1u << (c & 31));
-      if (NUMERIC) atomicAdd(&acc[c], ws_val[s0 + q]);
+      if (NUMERIC) atomicAdd(&acc[c], ld_stream<HINT_WS_LOAD>(&ws_val[s0 + q]));
     }
     __syncthreads();
     int64_t my = 0;
@@ -621,9 +647,9 @@ __global__ void __launch_bounds__(1024)
         const int bit = __ffs(bb) - 1;
         bb &= bb - 1;
         const int64_t lc = w * 32 + bit;
-        if (col64) ((int64_t*)ccol_)[pos] = colbase + lc;
-        else ((int32_t*)ccol_)[pos] = (int32_t)(colbase + lc);
-        cval[pos] = acc[lc];
+        if (col64) st_stream<HINT_C_STORE>(&((int64_t*)ccol_)[pos], (int64_t)(colbase + lc));
+        else st_stream<HINT_C_STORE>(&((int32_t*)ccol_)[pos], (int32_t)(colbase + lc));
+        st_stream<HINT_C_STORE>(&cval[pos], acc[lc]);
         acc[lc] = (V)0;
         ++pos;
       }
@@ -664,9 +690,9 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
     const int x = e * MG_WAVE + l;
     if (x < P) {
       const int bo = upper_index(s_bs, 0, nbg, (int64_t)x);
-      const uint32_t key = ((uint32_t)bo << g.shift) | (uint32_t)ws_col[start + x];
+      const uint32_t key = ((uint32_t)bo << g.shift) | (uint32_t)ld_stream<HINT_WS_LOAD>(&ws_col[start + x]);
       k[e] = NUMERIC ? ((key << IDXB) | (uint32_t)x) : key;
-      if (NUMERIC) s_v[x] = ws_val[start + x];
+      if (NUMERIC) s_v[x] = ld_stream<HINT_WS_LOAD>(&ws_val[start + x]);
     } else {
       k[e] = 0xFFFFFFFFu;
     }
@@ -733,9 +759,9 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
       if (tail) {
         const int64_t pos = obase + hr - 1;
         const int64_t col = colbase + (int64_t)key;
-        if (col64) ((int64_t*)ccol_)[pos] = col;
-        else ((int32_t*)ccol_)[pos] = (int32_t)col;
-        cval[pos] = run;
+        if (col64) st_stream<HINT_C_STORE>(&((int64_t*)ccol_)[pos], (int64_t)col);
+        else st_stream<HINT_C_STORE>(&((int32_t*)ccol_)[pos], (int32_t)col);
+        st_stream<HINT_C_STORE>(&cval[pos], run);
       }
     }
   }
@@ -794,11 +820,11 @@ __global__ void k_bin_rows(ChunkGeom g, int64_t k0, int64_t k1, const int64_t* b
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_aoff(const Mats& M, const int32_t* rows, int64_t nrows, int64_t* aoff,
-                       hipStream_t st) {
+                       int64_t* ent, hipStream_t st) {
   if (nrows <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((nrows + 3) / 4);
   MG_DISPATCH2(M, hipLaunchKernelGGL((k_aoff<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
-                                      (const CI*)M.acol, (const RP*)M.brp, rows, nrows, aoff));
+                                      (const CI*)M.acol, (const RP*)M.brp, rows, nrows, aoff, ent));
   return hipGetLastError();
 }
 
@@ -894,10 +920,24 @@ hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* a
   return hipGetLastError();
 }
 
+hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile_row,
+                          const int64_t* aoff, int64_t ntiles, int64_t* tile_e0, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((ntiles + 255) / 256);
+  if (M.rp64)
+    hipLaunchKernelGGL(k_tile_e0<int64_t>, grid, 256, 0, st, (const int64_t*)M.arp, g, tile_row,
+                       aoff, ntiles, tile_e0);
+  else
+    hipLaunchKernelGGL(k_tile_e0<int32_t>, grid, 256, 0, st, (const int32_t*)M.arp, g, tile_row,
+                       aoff, ntiles, tile_e0);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
                                const int32_t* tile_row, const int64_t* aoff,
-                               const int64_t* bin_start, unsigned long long* bin_cursor,
-                               uint16_t* ws_col, void* ws_val, int64_t max_nb, hipStream_t st) {
+                               const int64_t* tile_e0, const int64_t* bin_start,
+                               unsigned long long* bin_cursor, uint16_t* ws_col, void* ws_val,
+                               int64_t max_nb, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
   const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb);
 #define MG_SC2(V)                                                                                 \
@@ -906,8 +946,8 @@ hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArg
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                 \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
-                       (const V*)M.bval, g, b, tile_row, aoff, bin_start, bin_cursor, ws_col,     \
-                       (V*)ws_val);                                                               \
+                       (const V*)M.bval, g, b, tile_row, aoff, tile_e0, bin_start, bin_cursor,    \
+                       ws_col, (V*)ws_val);                                                       \
   });
   if (M.f64) { MG_SC2(double) } else { MG_SC2(float) }
 #undef MG_SC2

@@ -33,18 +33,20 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
   // block visits are combined in LDS and added to the global totals once per
   // block (a global atomic per block on a handful of addresses would
   // serialise in L2 across hundreds of thousands of blocks)
-  __shared__ unsigned long long sh[14];
-  if (threadIdx.x < 14) sh[threadIdx.x] = 0;
+  __shared__ unsigned long long sh[18];
+  if (threadIdx.x < 18) sh[threadIdx.x] = 0;
   __syncthreads();
   const int64_t groups_per_block = blockDim.x / G;
   const int sub = (int)(threadIdx.x % G);
   unsigned long long l_ip = 0, l_max = 0, l_rng = 0, l_ipc[4] = {0, 0, 0, 0}, l_rc[4] = {0, 0, 0, 0};
+  unsigned long long l_ent[4] = {0, 0, 0, 0};
   for (int64_t rb = (int64_t)blockIdx.x * groups_per_block; rb < n;
        rb += (int64_t)gridDim.x * groups_per_block) {
     const int64_t row = rb + threadIdx.x / G;
-    int64_t s = 0, mn = INT64_MAX, mx = -1;
+    int64_t s = 0, mn = INT64_MAX, mx = -1, nent = 0;
     if (row < n) {
       const int64_t p0 = arp[row], p1 = arp[row + 1];
+      nent = p1 - p0;
       for (int64_t p = p0 + sub; p < p1; p += G) {
         const int64_t j = acol[p];
         const int64_t b0 = brp[j], b1 = brp[j + 1];
@@ -94,6 +96,7 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
       l_rng = (unsigned long long)range > l_rng ? (unsigned long long)range : l_rng;
       l_ipc[cat] += (unsigned long long)s;
       l_rc[cat] += 1;
+      l_ent[cat] += (unsigned long long)nent;
     }
   }
   if (sub == 0) {
@@ -103,6 +106,7 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
     for (int k = 0; k < 4; ++k) {
       if (l_ipc[k]) atomicAdd(&sh[6 + k], l_ipc[k]);
       if (l_rc[k]) atomicAdd(&sh[10 + k], l_rc[k]);
+      if (l_ent[k]) atomicAdd(&sh[14 + k], l_ent[k]);
     }
   }
   __syncthreads();
@@ -113,6 +117,7 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
     for (int k = 0; k < 4; ++k) {
       if (sh[6 + k]) atomicAdd(&stats->ip_cat[k], sh[6 + k]);
       if (sh[10 + k]) atomicAdd(&stats->rows_cat[k], sh[10 + k]);
+      if (sh[14 + k]) atomicAdd(&stats->ent_cat[k], sh[14 + k]);
     }
   }
 }
@@ -320,8 +325,8 @@ __global__ void __launch_bounds__(1024)
       const int bit = __ffs(b) - 1;
       b &= b - 1;
       const int64_t lc = q * 32 + bit;
-      ccol[pos] = (CI)(mn + lc);
-      cval[pos] = acc[lc];
+      st_stream<HINT_C_STORE>(&ccol[pos], (CI)(mn + lc));
+      st_stream<HINT_C_STORE>(&cval[pos], acc[lc]);
       ++pos;
     }
   }
@@ -353,6 +358,71 @@ static hipError_t dense_rows_t(const Mats& M, bool numeric, const int32_t* list,
 // ---------------------------------------------------------------------------
 // misc
 // ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cat_nnz(const int32_t* cls, const int64_t* rownnz, int64_t n,
+                                                 DevStats* stats) {
+  __shared__ unsigned long long sh[4];
+  if (threadIdx.x < 4) sh[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long loc[4] = {0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = cls[i];
+    const int cat = c < CLS_DENSE ? 0 : (c == CLS_DENSE ? 1 : (c == CLS_CHUNKED ? 2 : 3));
+    loc[cat] += (unsigned long long)rownnz[i];
+  }
+  for (int k = 0; k < 4; ++k) {
+    const unsigned long long v = wave_sum(loc[k]);
+    if (lane() == 0 && v) atomicAdd(&sh[k], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 && sh[threadIdx.x]) atomicAdd(&stats->nnz_cat[threadIdx.x], sh[threadIdx.x]);
+}
+hipError_t launch_cat_nnz(const int32_t* cls, const int64_t* rownnz, int64_t n, DevStats* stats,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t want = (n + 255) / 256;
+  hipLaunchKernelGGL(k_cat_nnz, (unsigned)(want < 2048 ? want : 2048), 256, 0, st, cls, rownnz, n,
+                     stats);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_rows(const int64_t* v, const int32_t* rows, int64_t nrows, int64_t* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nrows) out[k] = v[rows[k]];
+}
+hipError_t launch_gather_rows(const int64_t* v, const int32_t* rows, int64_t nrows, int64_t* out,
+                              hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, (unsigned)((nrows + 255) / 256), 256, 0, st, v, rows, nrows,
+                     out);
+  return hipGetLastError();
+}
+
+// Plain streaming copy (16-byte vectors, grid-stride): the reference for the
+// achievable HBM bandwidth and for scaling the memory counters.
+__global__ void __launch_bounds__(256) k_stream_copy(uint4* __restrict__ dst,
+                                                     const uint4* __restrict__ src, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_copy_tail(unsigned char* dst, const unsigned char* src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 > 0) {
+    const int64_t want = (n16 + 255) / 256;
+    hipLaunchKernelGGL(k_stream_copy, (unsigned)(want < 256 * 64 ? want : 256 * 64), 256, 0, st,
+                       (uint4*)dst, (const uint4*)src, n16);
+  }
+  const int64_t tail = (int64_t)(bytes - (size_t)n16 * 16);
+  if (tail > 0)
+    hipLaunchKernelGGL(k_copy_tail, 1, 64, 0, st, (unsigned char*)dst + n16 * 16,
+                       (const unsigned char*)src + n16 * 16, tail);
+  return hipGetLastError();
+}
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

@@ -209,8 +209,8 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
       if (tail) {
         const int sl = (int)(k[e] >> colbits);
         const int64_t pos = crp[s_row[w][sl]] + (hr - 1 - s_aux[w][sl]);
-        ccol[pos] = (CI)(s_minc[w][sl] + (int64_t)(k[e] & kmask));
-        cval[pos] = run;
+        st_stream<HINT_C_STORE>(&ccol[pos], (CI)(s_minc[w][sl] + (int64_t)(k[e] & kmask)));
+        st_stream<HINT_C_STORE>(&cval[pos], run);
       }
     }
   }

@@ -23,6 +23,8 @@ struct DevStats {
   unsigned long long max_range;
   unsigned long long ip_cat[4];
   unsigned long long rows_cat[4];
+  unsigned long long ent_cat[4];   // A entries of the rows of each category
+  unsigned long long nnz_cat[4];   // nnz of C in the rows of each category
   unsigned int err;  // bit flags, see ERR_*
   unsigned int pad;
 };
@@ -89,13 +91,22 @@ struct ChunkGeom {
   int64_t nch;
   int shift;             // chunk length 2^shift
   int tile;              // products per tile (power of two)
+  int hints;             // HINT_* bits: non-temporal access classes
 };
 hipError_t launch_chunk_geom(const ChunkGeom& g, hipStream_t st);
 // first_of[s] (int32, pre-filled with -1) and bases[4*s] for batch slots of W products
 hipError_t launch_batch_bounds(const ChunkGeom& g, int64_t W, int32_t* first_of, int64_t* bases,
                                hipStream_t st);
+// aoff of every A entry of the CHUNKED rows; ent[k] = A entries of row k
 hipError_t launch_aoff(const Mats& M, const int32_t* rows, int64_t nrows, int64_t* aoff,
-                       hipStream_t st);
+                       int64_t* ent, hipStream_t st);
+// per category: sum of rownnz (before the scan) into stats->nnz_cat
+hipError_t launch_cat_nnz(const int32_t* cls, const int64_t* rownnz, int64_t n, DevStats* stats,
+                          hipStream_t st);
+// out[k] = v[rows[k]]
+hipError_t launch_gather_rows(const int64_t* v, const int32_t* rows, int64_t nrows, int64_t* out,
+                              hipStream_t st);
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_tiles(const int64_t* nt, const int64_t* tileBase, int64_t k0, int64_t k1,
                         int32_t* tile_row, hipStream_t st);
 
@@ -105,6 +116,7 @@ struct BatchArgs {
   int64_t tab0, ntab;      // global table range
   int64_t bin0, nbins;     // global bin range
   int64_t ip0, nip;        // global product range (batch workspace offset = ip - ip0)
+  int64_t nent, nnz_out;   // A entries of the batch's rows; nnz of C they produce
 };
 hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
                            const int32_t* tile_row, const int64_t* aoff, int32_t* tab_cnt,
@@ -139,8 +151,12 @@ hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* a
 size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb);
 hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
                                const int32_t* tile_row, const int64_t* aoff,
-                               const int64_t* bin_start, unsigned long long* bin_cursor,
-                               uint16_t* ws_col, void* ws_val, int64_t max_nb, hipStream_t st);
+                               const int64_t* tile_e0, const int64_t* bin_start,
+                               unsigned long long* bin_cursor, uint16_t* ws_col, void* ws_val,
+                               int64_t max_nb, hipStream_t st);
+// first A entry of every tile
+hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile_row,
+                          const int64_t* aoff, int64_t ntiles, int64_t* tile_e0, hipStream_t st);
 hipError_t launch_bin_group(const ChunkGeom& g, const BatchArgs& b, const int64_t* bin_cnt,
                             int64_t dense_min, int64_t group_max, int64_t* dense_items,
                             int64_t* sort_items, int32_t* item_counts, hipStream_t st);

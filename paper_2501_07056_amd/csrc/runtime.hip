@@ -15,6 +15,13 @@
 using namespace mg;
 
 struct magnus_handle_s {
+  struct PRec {
+    const char* name;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof = false;
+  std::vector<PRec> recs;
   int device = 0;
   magnus_options_t opts{};
   magnus_alloc_fn alloc_fn = nullptr;
@@ -66,11 +73,12 @@ struct magnus_plan_s {
   DevStats h_stats{};
   int shift = 13, colbits = 1, dense_block = 256, tile = 2048, lds_budget = 65536;
   int persistent_wgs = 512;
+  int hints = 0;
   int64_t sort_max = 1025, dense_min = 1024, group_max = 1024;
   // CHUNKED rows
   int64_t nch = 0, max_nb = 1;
   ChunkGeom g{};
-  int64_t *aoff = nullptr, *tab_off = nullptr;
+  int64_t *aoff = nullptr, *tab_off = nullptr, *tile_e0 = nullptr;
   int32_t *tile_row = nullptr, *tab_cnt = nullptr, *bin_row = nullptr, *item_counts = nullptr;
   int64_t *bin_start = nullptr, *bin_cnt = nullptr, *bin_nnz = nullptr, *bin_out = nullptr;
   int64_t *dense_items = nullptr, *sort_items = nullptr;
@@ -84,6 +92,8 @@ struct magnus_plan_s {
   std::vector<BatchArgs> batches;
   int64_t nnz_c = 0;
   magnus_plan_info_t info{};
+  int64_t *ent = nullptr, *entBase = nullptr, *nnzr = nullptr, *nnzBase = nullptr;
+  double s_rp = 4, s_col = 4, s_val = 8;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
 };
@@ -120,6 +130,27 @@ void plan_free_all(magnus_plan_s* P) {
   if (P->pinned) (void)hipHostFree(P->pinned);
   P->pinned = nullptr;
 }
+
+// Brackets one launch (or a group of launches) with events when profiling.
+struct ProfScope {
+  magnus_handle_s* h;
+  hipStream_t st;
+  const char* name;
+  double bytes;
+  hipEvent_t a{}, b{};
+  bool on;
+  ProfScope(magnus_handle_s* h_, hipStream_t st_, const char* name_, double bytes_)
+      : h(h_), st(st_), name(name_), bytes(bytes_), on(h_ && h_->prof) {
+    if (on) {
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+          hipEventRecord(a, st) != hipSuccess)
+        on = false;
+    }
+  }
+  ~ProfScope() {
+    if (on && hipEventRecord(b, st) == hipSuccess) h->recs.push_back({name, a, b, bytes});
+  }
+};
 
 magnus_status_t check_csr(const magnus_csr_t* X) {
   if (!X) return MAGNUS_ERR_INVALID_ARG;
@@ -182,6 +213,7 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   g.nch = nch;
   g.shift = P->shift;
   g.tile = P->tile;
+  g.hints = P->hints;
   int64_t* geo = (int64_t*)palloc(P, sizeof(int64_t) * (3 * nch + 4 * (nch + 1)));
   if (!geo) return MAGNUS_ERR_OOM;
   g.nb = geo;
@@ -205,9 +237,11 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   if (W <= 0) {
     int64_t budget = o.max_workspace_bytes;
     if (budget <= 0) {
+      // an eighth of the device memory: the same batches on every call,
+      // whatever the caching allocator currently holds
       size_t fr = 0, tot = 0;
       HIPCHK(hipMemGetInfo(&fr, &tot));
-      budget = (int64_t)(0.25 * (double)fr);
+      budget = (int64_t)(tot / 8);
     }
     W = budget / (2 + vs);
   }
@@ -301,8 +335,17 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
     return MAGNUS_ERR_OOM;
   HIPCHK(hipMemsetAsync(P->item_counts, 0, sizeof(int32_t) * 2 * nbat, P->st));
   HIPCHK(hipMemsetAsync(P->bin_nnz, 0, sizeof(int64_t) * nbins, P->st));
-  HIPCHK(launch_aoff(P->M, g.rows, nch, P->aoff, P->st));
+  P->ent = (int64_t*)palloc(P, sizeof(int64_t) * (4 * nch + 2));
+  if (!P->ent) return MAGNUS_ERR_OOM;
+  P->entBase = P->ent + nch;
+  P->nnzr = P->entBase + nch + 1;
+  P->nnzBase = P->nnzr + nch;
+  HIPCHK(launch_aoff(P->M, g.rows, nch, P->aoff, P->ent, P->st));
+  HIPCHK(scan_excl_i64(P->ent, P->entBase, nch, P->entBase + nch, nullptr, tmp, P->st));
   HIPCHK(launch_tiles(g.nt, g.tileBase, 0, nch, P->tile_row, P->st));
+  P->tile_e0 = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, ntiles));
+  if (!P->tile_e0) return MAGNUS_ERR_OOM;
+  HIPCHK(launch_tile_e0(P->M, g, P->tile_row, P->aoff, ntiles, P->tile_e0, P->st));
   P->info.n_batches = nbat;
   P->info.n_bins = nbins;
   return MAGNUS_OK;
@@ -313,8 +356,14 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
 magnus_status_t chunked_symbolic(magnus_plan_s* P) {
   magnus_handle_s* h = P->h;
   if (P->bitmap_symbolic) {
-    HIPCHK(launch_row_bitmap(P->M, P->g, P->aoff, P->max_nb, P->bin_nnz, P->bin_cnt, P->bin_row,
-                             P->crp, P->st));
+    {
+      const double ipc = (double)P->h_stats.ip_cat[2], ec = (double)P->h_stats.ent_cat[2];
+      ProfScope ps(h, P->st, "row_bitmap (symbolic, chunked rows)",
+                   ipc * P->s_col + ec * (P->s_col + 8 + P->s_rp) +
+                       (double)P->info.n_bins * 20 + (double)P->nch * 8);
+      HIPCHK(launch_row_bitmap(P->M, P->g, P->aoff, P->max_nb, P->bin_nnz, P->bin_cnt, P->bin_row,
+                               P->crp, P->st));
+    }
     for (size_t bi = 0; bi < P->batches.size(); ++bi) {
       const BatchArgs& b = P->batches[bi];
       HIPCHK(scan_excl_i64(P->bin_cnt + b.bin0, P->bin_start + b.bin0, b.nbins, nullptr, nullptr,
@@ -355,31 +404,60 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
     HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, nullptr, P->crp, P->bin_out, true,
                            P->st));
     HIPCHK(launch_fill_i64((int64_t*)P->bin_cursor + b.bin0, b.nbins, 0, P->st));
-    HIPCHK(launch_bin_scatter2(P->M, P->g, b, P->tile_row, P->aoff, P->bin_start, P->bin_cursor,
-                               P->ws_col, P->ws_val, P->max_nb, P->st));
+    {
+      // per product: B column and value read, chunk-local column and
+      // product written; per A entry: column, value, product offset, B row
+      ProfScope ps(h, P->st, "bin_scatter (numeric reorder)",
+                   (double)b.nip * (P->s_col + P->s_val + 2 + P->s_val) +
+                       (double)b.nent * (P->s_col + P->s_val + 8 + P->s_rp));
+      HIPCHK(launch_bin_scatter2(P->M, P->g, b, P->tile_row, P->aoff, P->tile_e0, P->bin_start,
+                                 P->bin_cursor, P->ws_col, P->ws_val, P->max_nb, P->st));
+    }
     unsigned int* wk = P->work_ctr + 4 * bi + 2;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
-    HIPCHK(launch_bin_accum(P->g, b, true, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
-                            P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
-                            P->bin_out, ccol, col64, cval, P->dense_block, wk,
-                            P->persistent_wgs, P->st));
+    {
+      // per product: chunk-local column and value read; per output: C write
+      ProfScope ps(h, P->st, "bin_accum (numeric, dense+sort chunks)",
+                   (double)b.nip * (2 + P->s_val) + (double)b.nnz_out * (P->s_col + P->s_val));
+      HIPCHK(launch_bin_accum(P->g, b, true, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
+                              P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
+                              P->bin_out, ccol, col64, cval, P->dense_block, wk,
+                              P->persistent_wgs, P->st));
+    }
   }
   return MAGNUS_OK;
 }
 
 magnus_status_t run_rows(magnus_plan_s* P, bool numeric, void* ccol, void* cval) {
   magnus_handle_s* h = P->h;
-  for (int c = 0; c < NSORT_CLS; ++c) {
-    const int64_t cnt = P->h_list_off[c + 1] - P->h_list_off[c];
-    if (cnt > 0)
-      HIPCHK(launch_sort_rows(P->M, c, numeric, P->list, P->h_list_off[c], cnt, P->minc,
-                              P->colbits, P->crp, P->crp, ccol, cval, P->stats, P->st));
+  const DevStats& S = P->h_stats;
+  const double cv = P->s_col + (numeric ? P->s_val : 0);
+  const double nzs = numeric ? (double)P->info.nnz_by_category[0] * (P->s_col + P->s_val) : 0;
+  const double nzd = numeric ? (double)P->info.nnz_by_category[1] * (P->s_col + P->s_val) : 0;
+  // per product: B column (and value); per A entry: column (value) and both
+  // B row pointers; per row: list entry, minc, row offset or count; per
+  // output (numeric): C column and value
+  {
+    ProfScope ps_sort(h, P->st, numeric ? "sort_rows (numeric)" : "sort_rows (symbolic)",
+                      (double)S.ip_cat[0] * cv + (double)S.ent_cat[0] * (cv + 2 * P->s_rp) +
+                          (double)S.rows_cat[0] * 20 + nzs);
+    for (int c = 0; c < NSORT_CLS; ++c) {
+      const int64_t cnt = P->h_list_off[c + 1] - P->h_list_off[c];
+      if (cnt > 0)
+        HIPCHK(launch_sort_rows(P->M, c, numeric, P->list, P->h_list_off[c], cnt, P->minc,
+                                P->colbits, P->crp, P->crp, ccol, cval, P->stats, P->st));
+    }
   }
   const int64_t nd = P->h_list_off[CLS_DENSE + 1] - P->h_list_off[CLS_DENSE];
-  if (nd > 0)
-    HIPCHK(launch_dense_rows(P->M, numeric, P->list, P->h_list_off[CLS_DENSE], nd, P->minc,
-                             P->maxc, P->shift, P->dense_block, P->crp, P->crp, ccol, cval,
-                             P->st));
+  {
+    ProfScope ps_dense(h, P->st, numeric ? "dense_rows (numeric)" : "dense_rows (symbolic)",
+                       (double)S.ip_cat[1] * cv + (double)S.ent_cat[1] * (cv + 2 * P->s_rp) +
+                           (double)S.rows_cat[1] * 28 + nzd);
+    if (nd > 0)
+      HIPCHK(launch_dense_rows(P->M, numeric, P->list, P->h_list_off[CLS_DENSE], nd, P->minc,
+                               P->maxc, P->shift, P->dense_block, P->crp, P->crp, ccol, cval,
+                               P->st));
+  }
   return MAGNUS_OK;
 }
 
@@ -559,6 +637,7 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   P->tile = o.tile_products > 0 ? o.tile_products : 2048;
   if (P->tile < 256 || P->tile > 16384 || (P->tile & (P->tile - 1))) P->tile = 2048;
   P->dense_block = (o.dense_block == 512 || o.dense_block == 1024) ? o.dense_block : 256;
+  P->hints = o.stream_hints & 7;
   {
     // dense accumulator workgroups resident per CU, from its LDS footprint
     const size_t dl = bin_dense_lds(M.f64, P->shift);
@@ -606,7 +685,15 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   cp.sort_max = P->sort_max;
   cp.dense_max = (int64_t)1 << P->shift;
   cp.force = (o.force_category >= 0 && o.force_category <= 2) ? o.force_category : -1;
-  PCHK(launch_rowinfo(M, A->nnz, cp, P->ip, P->minc, P->maxc, P->cls, P->stats, P->st));
+  P->s_rp = M.rp64 ? 8 : 4;
+  P->s_col = M.col64 ? 8 : 4;
+  P->s_val = M.f64 ? 8 : 4;
+  {
+    ProfScope ps(h, P->st, "rowinfo (setup)",
+                 (double)(n + 1) * P->s_rp + (double)A->nnz * (3 * P->s_col + 2 * P->s_rp) +
+                     (double)n * 28);
+    PCHK(launch_rowinfo(M, A->nnz, cp, P->ip, P->minc, P->maxc, P->cls, P->stats, P->st));
+  }
   PCHK(launch_classify(P->cls, n, P->list, P->list_off, P->temp, P->st));
   SCHK(readback(P, {{P->stats, sizeof(DevStats)}, {P->list_off, sizeof(int64_t) * (NCLS + 1)}},
                 {&P->h_stats, P->h_list_off}));
@@ -621,14 +708,35 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   PCHK(launch_fill_i64(P->crp, n + 1, 0, P->st));
   SCHK(run_rows(P, false, nullptr, nullptr));
   if (P->nch > 0) SCHK(chunked_symbolic(P));
+  PCHK(launch_cat_nnz(P->cls, P->crp, n, P->stats, P->st));
+  if (P->nch > 0) {
+    PCHK(launch_gather_rows(P->crp, P->g.rows, P->nch, P->nnzr, P->st));
+    PCHK(scan_excl_i64(P->nnzr, P->nnzBase, P->nch, P->nnzBase + P->nch, nullptr, P->temp, P->st));
+  }
   PCHK(scan_excl_i64(P->crp, P->crp, n + 1, nullptr, nullptr, P->temp, P->st));
   PCHK(hipEventRecord(ev1, P->st));
   int64_t nnzc = 0;
   DevStats st2{};
   std::vector<int32_t> icounts(2 * P->batches.size() + 2, 0);
-  SCHK(readback(P, {{P->crp + n, 8}, {P->stats, sizeof(DevStats)},
-                    {P->item_counts, sizeof(int32_t) * 2 * P->batches.size()}},
-                {&nnzc, &st2, icounts.data()}));
+  const size_t nb_ = P->batches.size();
+  std::vector<int64_t> bent(nb_ + 1, 0), bnnz(nb_ + 1, 0);
+  std::vector<std::pair<const void*, size_t>> src = {
+      {P->crp + n, 8}, {P->stats, sizeof(DevStats)}, {P->item_counts, sizeof(int32_t) * 2 * nb_}};
+  std::vector<void*> dst = {&nnzc, &st2, icounts.data()};
+  for (size_t b = 0; b <= nb_ && P->nch > 0; ++b) {
+    const int64_t kk = (b < nb_) ? P->batches[b].k0 : P->nch;
+    src.push_back({P->entBase + kk, 8});
+    dst.push_back(&bent[b]);
+    src.push_back({P->nnzBase + kk, 8});
+    dst.push_back(&bnnz[b]);
+  }
+  SCHK(readback(P, src, dst));
+  for (size_t b = 0; b < nb_; ++b) {
+    P->batches[b].nent = bent[b + 1] - bent[b];
+    P->batches[b].nnz_out = bnnz[b + 1] - bnnz[b];
+  }
+  for (int k = 0; k < 4; ++k) P->info.nnz_by_category[k] = (int64_t)st2.nnz_cat[k];
+  P->h_stats.nnz_cat[0] = st2.nnz_cat[0];
   for (size_t b = 0; b < P->batches.size(); ++b) {
     P->info.n_dense_chunks += icounts[2 * b];
     P->info.n_sort_groups += icounts[2 * b + 1];
@@ -737,6 +845,52 @@ magnus_status_t magnus_row_ip(magnus_handle_t h, const magnus_csr_t* A, const ma
   plan_free_all(&tmp);
   if (r == MAGNUS_OK && ip_total) *ip_total = (int64_t)hs.ip_total;
   return r;
+}
+
+magnus_status_t magnus_profile_enable(magnus_handle_t h, int on) {
+  if (!h) return MAGNUS_ERR_INVALID_ARG;
+  h->prof = on != 0;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_profile_read(magnus_handle_t h, magnus_kernel_stat_t* out, int max, int* n) {
+  if (!h || !n || (max > 0 && !out)) return MAGNUS_ERR_INVALID_ARG;
+  std::vector<magnus_kernel_stat_t> agg;
+  magnus_status_t r = MAGNUS_OK;
+  for (auto& rec : h->recs) {
+    float ms = 0;
+    if (hipEventSynchronize(rec.b) != hipSuccess ||
+        hipEventElapsedTime(&ms, rec.a, rec.b) != hipSuccess)
+      r = MAGNUS_ERR_HIP;
+    (void)hipEventDestroy(rec.a);
+    (void)hipEventDestroy(rec.b);
+    magnus_kernel_stat_t* s = nullptr;
+    for (auto& x : agg)
+      if (strncmp(x.name, rec.name, sizeof(x.name)) == 0) s = &x;
+    if (!s) {
+      magnus_kernel_stat_t z{};
+      strncpy(z.name, rec.name, sizeof(z.name) - 1);
+      agg.push_back(z);
+      s = &agg.back();
+    }
+    s->launches += 1;
+    s->ms += ms;
+    s->bytes += rec.bytes;
+  }
+  h->recs.clear();
+  *n = (int)agg.size();
+  for (int i = 0; i < (int)agg.size() && i < max; ++i) out[i] = agg[i];
+  if (r != MAGNUS_OK) h->err = "event timing failed";
+  return r;
+}
+
+magnus_status_t magnus_stream_copy(magnus_handle_t h, void* dst, const void* src, size_t bytes,
+                                   void* stream) {
+  if (!h || (bytes > 0 && (!dst || !src))) return MAGNUS_ERR_INVALID_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  ProfScope ps(h, (hipStream_t)stream, "stream_copy", 2.0 * (double)bytes);
+  HIPCHK(launch_stream_copy(dst, src, bytes, (hipStream_t)stream));
+  return MAGNUS_OK;
 }
 
 magnus_status_t magnus_exclusive_scan_i64(magnus_handle_t h, const int64_t* in, int64_t* out,
