@@ -225,6 +225,146 @@ def trace_summary(args):
     log(f"[bench] wrote {out}")
 
 
+def batch_main(args, opts):
+    """Batched products (512 independent C_b = A_b * A_b, A_b Erdos-Renyi with
+    n log-uniform in [1024, 65536] and 4..32 entries per row, f32 values,
+    int32 indices): one batch per step against the same products called one
+    at a time through the single-product calls, both timed with the whole
+    plan + execute; then the numeric phase alone, replayed from a kept plan
+    (captured graph vs the same launches issued eagerly vs per-call)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2501_07056_amd as mg
+    from paper_2501_07056_amd import autotune
+    import workloads as wl
+
+    t0 = time.time()
+    count = args.batch_count
+    pairs_host = wl.config4(count)
+    log(f"[bench] batch of {count} generated in {time.time() - t0:.1f} s, "
+        f"nnz(A) total {sum(A.nnz for A, _ in pairs_host)}")
+    pairs = []
+    for A, _ in pairs_host:
+        dA = mg.DeviceCSR.from_host(A)
+        pairs.append((dA, dA))
+    ctx = mg.Context(0, **opts)
+    torch.cuda.synchronize()
+
+    tuned = None
+    if not args.no_tune:
+        tuned = autotune.tune(ctx, pairs, cache_path=args.tune_cache, log=log)
+        ctx.set_options(dense_block=tuned["dense_block"])
+    sort_max = tuned["sort_max"] if tuned else None
+
+    def batched_step(graph=True):
+        bp = ctx.batch_plan(pairs, sort_max=sort_max)
+        outs = bp.execute(graph=graph)
+        info = bp.info.as_dict()
+        bp.destroy()
+        return outs, info
+
+    def per_call_step():
+        outs = []
+        for b, (dA, dB) in enumerate(pairs):
+            if sort_max is not None:
+                ctx.set_options(sort_max=sort_max[b])
+            p = ctx.plan(dA, dB)
+            outs.append(p.execute(rowptr_dtype=torch.int64))
+            p.destroy()
+        return outs
+
+    def timed(fn, steps, warmup):
+        res = None
+        for _ in range(warmup):
+            res = fn()
+            del res
+            torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            res = fn()
+            if i + 1 < steps:
+                del res
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps, res
+
+    ms_b, (outs, info) = timed(batched_step, args.steps, args.warmup)
+    ip = int(info["ip_total"])
+    log(f"[bench] batched: {ms_b:.2f} ms/step, {2 * ip / ms_b / 1e6:.1f} GFLOP/s")
+    del outs
+    ms_p, outs_p = timed(per_call_step, args.steps, args.warmup)
+    ctx.set_options(sort_max=0)
+    log(f"[bench] per-call: {ms_p:.2f} ms/step, {2 * ip / ms_p / 1e6:.1f} GFLOP/s")
+    del outs_p
+
+    # numeric phase only, replayed from a kept plan
+    bp = ctx.batch_plan(pairs, sort_max=sort_max)
+    outs = bp.alloc_outputs()
+    bp.execute(outs, graph=True)
+    torch.cuda.synchronize()
+    ms_graph, _ = timed(lambda: bp.execute(outs, graph=True), args.steps, 1)
+    ms_eager, _ = timed(lambda: bp.execute(outs, graph=False), args.steps, 1)
+    plans = []
+    for b, (dA, dB) in enumerate(pairs):
+        if sort_max is not None:
+            ctx.set_options(sort_max=sort_max[b])
+        plans.append(ctx.plan(dA, dB))
+    ctx.set_options(sort_max=0)
+    single_outs = [p.alloc_output() for p in plans]
+
+    def per_call_exec():
+        for p, C in zip(plans, single_outs):
+            p.execute(C)
+    ms_pexec, _ = timed(per_call_exec, args.steps, 1)
+    for p in plans:
+        p.destroy()
+    log(f"[bench] numeric only: graph {ms_graph:.2f} ms, eager {ms_eager:.2f} ms, "
+        f"per-call {ms_pexec:.2f} ms")
+
+    # sampled parity of the kept batch outputs against the oracle
+    rng = np.random.default_rng(11)
+    checked, worst, ok = 0, 0.0, True
+    for b in range(0, count, max(1, count // 16)):
+        A = pairs_host[b][0]
+        rows = np.sort(rng.choice(A.nrows, size=min(64, A.nrows), replace=False)).astype(np.int64)
+        ref = oracle.spgemm(A, A, rows)
+        rp, col, val = outs[b].to_host()
+        gl = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+        ok &= bool(np.array_equal(col[gl].astype(np.int64), ref.col) and
+                   np.array_equal(np.diff(ref.rowptr), rp[rows + 1] - rp[rows]))
+        err = np.abs(val[gl].astype(np.float64) - ref.ref) / np.maximum(ref.abssum, 1e-300)
+        worst = max(worst, float(err.max()) if len(err) else 0.0)
+        checked += len(rows)
+    bp.destroy()
+    parity = {"rows": checked, "structure_equal": ok, "max_err_over_abssum": worst,
+              "within_rtol": bool(ok and worst <= 1e-5), "rtol": 1e-5}
+    log(f"[bench] sampled parity {parity}")
+
+    gf = lambda ms: round(2 * ip / ms / 1e6, 2)  # noqa: E731
+    cfg = {"workload": f"{count} independent C = A*A, A Erdos-Renyi, n log-uniform in "
+                       f"[1024, 65536], 4..32 per row, f32, int32",
+           "products": count, "rows": int(sum(A.nrows for A, _ in pairs_host)),
+           "intermediate_products": ip, "nnz_C": int(info["nnz_c"]),
+           "categories_rows": info["rows_by_category"],
+           "autotuned": tuned is not None,
+           "dense_block": tuned["dense_block"] if tuned else None,
+           "sort_max_histogram": ({str(k): int(v) for k, v in
+                                   zip(*np.unique(sort_max, return_counts=True))} if tuned else None)}
+    out = {"metric": METRIC, "value": gf(ms_b), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": cfg,
+           "per_call": {"ms_per_step": round(ms_p, 3), "GFLOPs": gf(ms_p),
+                        "batched_speedup": round(ms_p / ms_b, 3)},
+           "numeric_only": {"graph_ms": round(ms_graph, 3), "eager_ms": round(ms_eager, 3),
+                            "per_call_ms": round(ms_pexec, 3), "graph_GFLOPs": gf(ms_graph),
+                            "per_call_GFLOPs": gf(ms_pexec)},
+           "sample_parity": parity, "src_sha": src_digest()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +384,11 @@ def main():
     ap.add_argument("--trace-summary", metavar="STATS_DIR",
                     help="turn a rocprofv3 --kernel-trace --stats CSV into profiles/kernels_<workload>.md")
     ap.add_argument("--trace-command", default="")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="products of the batch workload (--workload batch)")
+    ap.add_argument("--no-tune", action="store_true", help="batch workload: library defaults")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2501_07056_amd", "tuned",
+                                                         "batch_tuning.json"))
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args)
@@ -256,6 +401,14 @@ def main():
               f"(this build measures a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
+    opts = {}
+    for o in args.option:
+        k, v = o.split("=", 1)
+        opts[k] = int(v) if v.lstrip("-").isdigit() else v
+    if args.workload == "batch":
+        batch_main(args, opts)
+        return
+
     import numpy as np
     import torch
 
@@ -266,10 +419,6 @@ def main():
     log(f"[bench] {cfg['workload']}: generated in {time.time() - t0:.1f} s, nnz(A)={A.nnz}")
     dA = mg.DeviceCSR.from_host(A)
     dB = dA if B is A else mg.DeviceCSR.from_host(B)
-    opts = {}
-    for o in args.option:
-        k, v = o.split("=", 1)
-        opts[k] = int(v) if v.lstrip("-").isdigit() else v
     ctx = mg.Context(0, **opts)
     torch.cuda.synchronize()
     if args.copy_probe:

@@ -225,6 +225,49 @@ magnus_status_t magnus_stream_copy(magnus_handle_t h, void* dst, const void* src
 magnus_status_t magnus_exclusive_scan_i64(magnus_handle_t h, const int64_t* in, int64_t* out,
                                           int64_t n, int64_t* total, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent products C_b = A_b * B_b (b = 0 .. count-1).
+ *
+ * The rows of all products are numbered one after another and every phase
+ * of Sections 3.1 and 2.1 (setup, categorisation, precise symbolic count,
+ * prefix sum, numeric accumulation, row pointers of C) runs as one set of
+ * launches over the whole batch, with a per-row product index.  Products
+ * with CHUNKED rows (Algorithm 3) are planned and executed on their own
+ * inside the batch calls.  All products of a batch share the value type and
+ * the index types.
+ * ---------------------------------------------------------------------- */
+typedef struct magnus_batch_plan_s* magnus_batch_plan_t;
+
+/* Plans the batch.  A and B: host arrays of `count` descriptors (device
+ * pointers inside, as everywhere).  sort_max: host array of `count`
+ * per-product SORT thresholds (rows with ip < sort_max[b] are SORT rows;
+ * <= 1025), or NULL for the handle's option.  nnz_out: host int64[count]
+ * receiving nnz(C_b).  info (may be NULL) receives totals over the batch.
+ * Synchronises `stream` twice (sizes, then nnz per product) plus once per
+ * product planned on its own.  A_b and B_b must stay unchanged until the
+ * plan is destroyed. */
+magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus_csr_t* A,
+                                  const magnus_csr_t* B, const int32_t* sort_max, void* stream,
+                                  magnus_batch_plan_t* plan, int64_t* nnz_out,
+                                  magnus_plan_info_t* info);
+
+/* Execution modes of magnus_batch_execute. */
+#define MAGNUS_BATCH_GRAPH 0 /* numeric launches captured once into a HIP graph, then replayed */
+#define MAGNUS_BATCH_EAGER 1 /* the same launches issued one by one */
+
+/* Numeric phase of every product: writes C[b].rowptr/col/val (host array of
+ * `count` output descriptors; C[b].capacity >= nnz_out[b] of the plan).  The
+ * descriptors of A, B and C may point to other buffers of the same shapes on
+ * every call: a small table of pointers is copied to the device first and the
+ * captured graph reads it.  Does not synchronise the stream (it waits, on the
+ * host, for the previous call's table copy to finish).  Returns
+ * MAGNUS_ERR_CAPACITY (nothing launched) when any capacity is short. */
+magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t plan, int32_t count,
+                                     const magnus_csr_t* A, const magnus_csr_t* B,
+                                     const magnus_csr_out_t* C, int32_t mode, void* stream);
+
+magnus_status_t magnus_batch_plan_destroy(magnus_batch_plan_t plan);
+
 #ifdef __cplusplus
 }
 #endif

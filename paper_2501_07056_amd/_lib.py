@@ -59,6 +59,9 @@ class KernelStat(ctypes.Structure):
 ALLOC_FN = ctypes.CFUNCTYPE(c_vp, ctypes.c_size_t, c_vp, c_vp)
 FREE_FN = ctypes.CFUNCTYPE(None, c_vp, ctypes.c_size_t, c_vp, c_vp)
 
+BATCH_GRAPH = 0
+BATCH_EAGER = 1
+
 STATUS = {}
 _lib = None
 
@@ -107,6 +110,11 @@ def load(path: str = LIB_PATH):
     lib.magnus_profile_enable.argtypes = [c_vp, c_i32]
     lib.magnus_profile_read.argtypes = [c_vp, P(KernelStat), c_i32, P(c_i32)]
     lib.magnus_stream_copy.argtypes = [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
+    lib.magnus_batch_plan.argtypes = [c_vp, c_i32, P(CsrDesc), P(CsrDesc), P(c_i32), c_vp,
+                                      P(c_vp), P(c_i64), P(PlanInfo)]
+    lib.magnus_batch_execute.argtypes = [c_vp, c_vp, c_i32, P(CsrDesc), P(CsrDesc),
+                                         P(CsrOutDesc), c_i32, c_vp]
+    lib.magnus_batch_plan_destroy.argtypes = [c_vp]
     for fn in declared_symbols():
         f = getattr(lib, fn)
         if fn not in ("magnus_status_string", "magnus_last_error", "magnus_options_default"):

@@ -168,6 +168,24 @@ class Context:
                                           ctypes.c_void_p(src.data_ptr()), nbytes, s),
               "magnus_stream_copy", self.handle)
 
+    def batch_plan(self, pairs, sort_max=None, stream=None) -> "BatchPlan":
+        """Plan C_b = A_b * B_b for every (A_b, B_b) in pairs as one batch.
+        sort_max: optional per-product SORT thresholds."""
+        s, keep = _stream_ptr(stream)
+        n = len(pairs)
+        da = (CsrDesc * n)(*[a.desc() for a, _ in pairs])
+        db = (CsrDesc * n)(*[b.desc() for _, b in pairs])
+        sm = None
+        if sort_max is not None:
+            assert len(sort_max) == n
+            sm = (ctypes.c_int32 * n)(*[int(x) for x in sort_max])
+        nnz = (ctypes.c_int64 * n)()
+        p = ctypes.c_void_p()
+        info = PlanInfo()
+        check(self.lib.magnus_batch_plan(self.handle, n, da, db, sm, s, ctypes.byref(p), nnz,
+                                         ctypes.byref(info)), "magnus_batch_plan", self.handle)
+        return BatchPlan(self, p, info, list(pairs), [int(x) for x in nnz])
+
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, rowptr_dtype=torch.int64, stream=None):
         p = self.plan(A, B, stream)
         try:
@@ -196,14 +214,7 @@ class Plan:
         s, keep = _stream_ptr(stream)
         if C is None:
             C = self.alloc_output(rowptr_dtype)
-        d = CsrOutDesc()
-        d.nrows, d.ncols, d.capacity = C.nrows, C.ncols, C.col.numel()
-        d.rowptr_type = _ITYPE[C.rowptr.dtype]
-        d.col_type = _ITYPE[C.col.dtype]
-        d.val_type = _VTYPE[C.val.dtype]
-        d.rowptr = C.rowptr.data_ptr()
-        d.col = C.col.data_ptr() if C.col.numel() else None
-        d.val = C.val.data_ptr() if C.val.numel() else None
+        d = _out_desc(C)
         nnz = ctypes.c_int64()
         da, db = self.A.desc(), self.B.desc()
         check(self.ctx.lib.magnus_execute(self.ctx.handle, self.ptr, ctypes.byref(da),
@@ -214,6 +225,63 @@ class Plan:
     def destroy(self):
         if self.ptr:
             self.ctx.lib.magnus_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _out_desc(C: DeviceCSR) -> CsrOutDesc:
+    d = CsrOutDesc()
+    d.nrows, d.ncols, d.capacity = C.nrows, C.ncols, C.col.numel()
+    d.rowptr_type = _ITYPE[C.rowptr.dtype]
+    d.col_type = _ITYPE[C.col.dtype]
+    d.val_type = _VTYPE[C.val.dtype]
+    d.rowptr = C.rowptr.data_ptr()
+    d.col = C.col.data_ptr() if C.col.numel() else None
+    d.val = C.val.data_ptr() if C.val.numel() else None
+    return d
+
+
+class BatchPlan:
+    """A planned batch: nnz[b] is nnz(C_b); execute() runs the numeric phase
+    of every product (captured into a HIP graph on the first call, replayed
+    afterwards, unless graph=False)."""
+
+    def __init__(self, ctx: Context, ptr, info: PlanInfo, pairs, nnz):
+        self.ctx, self.ptr, self.info, self.pairs, self.nnz = ctx, ptr, info, pairs, nnz
+
+    def alloc_outputs(self, rowptr_dtype=torch.int64):
+        outs = []
+        for (A, B), nz in zip(self.pairs, self.nnz):
+            dev = A.rowptr.device
+            outs.append(DeviceCSR(A.nrows, B.ncols,
+                                  torch.empty(A.nrows + 1, dtype=rowptr_dtype, device=dev),
+                                  torch.empty(nz, dtype=B.col.dtype, device=dev),
+                                  torch.empty(nz, dtype=A.val.dtype, device=dev)))
+        return outs
+
+    def execute(self, outs=None, rowptr_dtype=torch.int64, graph: bool = True, stream=None,
+                pairs=None):
+        s, keep = _stream_ptr(stream)
+        pairs = self.pairs if pairs is None else pairs
+        if outs is None:
+            outs = self.alloc_outputs(rowptr_dtype)
+        n = len(pairs)
+        da = (CsrDesc * n)(*[a.desc() for a, _ in pairs])
+        db = (CsrDesc * n)(*[b.desc() for _, b in pairs])
+        dc = (CsrOutDesc * n)(*[_out_desc(C) for C in outs])
+        mode = _lib.BATCH_GRAPH if graph else _lib.BATCH_EAGER
+        check(self.ctx.lib.magnus_batch_execute(self.ctx.handle, self.ptr, n, da, db, dc, mode, s),
+              "magnus_batch_execute", self.ctx.handle)
+        return outs
+
+    def destroy(self):
+        if self.ptr:
+            self.ctx.lib.magnus_batch_plan_destroy(self.ptr)
             self.ptr = None
 
     def __del__(self):

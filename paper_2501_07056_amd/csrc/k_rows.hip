@@ -23,29 +23,41 @@ MG_INLINE void wave_sync() {
 // largest column over those B rows (B rows sorted); class of the row.
 // G lanes cooperate on one row.
 // ---------------------------------------------------------------------------
-template <typename RP, typename CI>
-__global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, const CI* __restrict__ acol,
-                                                 const RP* __restrict__ brp, const CI* __restrict__ bcol,
-                                                 int64_t n, int G, ClassParams cp, int64_t* ip,
-                                                 int64_t* minc, int64_t* maxc, int32_t* cls,
-                                                 DevStats* stats) {
+template <typename RP, typename CI, bool BATCH>
+__global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, ClassParams cp,
+                                                 int64_t* ip, int64_t* minc, int64_t* maxc,
+                                                 int32_t* cls, DevStats* stats, int32_t* flags) {
   // grid-stride over groups of G lanes per row; the statistics of all rows a
   // block visits are combined in LDS and added to the global totals once per
   // block (a global atomic per block on a handful of addresses would
   // serialise in L2 across hundreds of thousands of blocks)
-  __shared__ unsigned long long sh[18];
-  if (threadIdx.x < 18) sh[threadIdx.x] = 0;
+  __shared__ unsigned long long sh[21];
+  if (threadIdx.x < 21) sh[threadIdx.x] = 0;
   __syncthreads();
   const int64_t groups_per_block = blockDim.x / G;
   const int sub = (int)(threadIdx.x % G);
   unsigned long long l_ip = 0, l_max = 0, l_rng = 0, l_ipc[4] = {0, 0, 0, 0}, l_rc[4] = {0, 0, 0, 0};
-  unsigned long long l_ent[4] = {0, 0, 0, 0};
+  unsigned long long l_ent[4] = {0, 0, 0, 0}, l_rcat[3] = {0, 0, 0};
   for (int64_t rb = (int64_t)blockIdx.x * groups_per_block; rb < n;
        rb += (int64_t)gridDim.x * groups_per_block) {
     const int64_t row = rb + threadIdx.x / G;
     int64_t s = 0, mn = INT64_MAX, mx = -1, nent = 0;
+    int32_t b = 0;
+    int64_t sort_max = cp.sort_max, dense_max = cp.dense_max;
     if (row < n) {
-      const int64_t p0 = arp[row], p1 = arp[row + 1];
+      // a batch: the row's product from the per-row table
+      if (BATCH) b = src.mat_of_row[row];
+      const MatEnt& M = BATCH ? src.tab[b] : src.one;
+      const int64_t lrow = row - (BATCH ? M.row0 : 0);
+      if (BATCH) {
+        sort_max = M.sort_max;
+        dense_max = M.dense_max;
+      }
+      const RP* arp = (const RP*)M.arp;
+      const CI* acol = (const CI*)M.acol;
+      const RP* brp = (const RP*)M.brp;
+      const CI* bcol = (const CI*)M.bcol;
+      const int64_t p0 = arp[lrow], p1 = arp[lrow + 1];
       nent = p1 - p0;
       for (int64_t p = p0 + sub; p < p1; p += G) {
         const int64_t j = acol[p];
@@ -75,9 +87,10 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
         cat = 3;
       } else {
         int want = cp.force;
-        if (want < 0) want = (s < cp.sort_max) ? 0 : (range <= cp.dense_max ? 1 : 2);
-        if (want == 0 && s > SORT_CAP) want = (range <= cp.dense_max) ? 1 : 2;
-        if (want == 1 && range > cp.dense_max) want = 2;
+        if (want < 0) want = (s < sort_max) ? 0 : (range <= dense_max ? 1 : 2);
+        if (want == 0 && s > SORT_CAP) want = (range <= dense_max) ? 1 : 2;
+        if (want == 1 && range > dense_max) want = 2;
+        if (BATCH && want == 2 && flags[b] == 0) flags[b] = 1;  // idempotent store
         if (want == 0) {
           int lg = 0;
           while (((int64_t)1 << lg) < s) ++lg;
@@ -97,6 +110,7 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
       l_ipc[cat] += (unsigned long long)s;
       l_rc[cat] += 1;
       l_ent[cat] += (unsigned long long)nent;
+      if (cat < 3 && (unsigned long long)range > l_rcat[cat]) l_rcat[cat] = (unsigned long long)range;
     }
   }
   if (sub == 0) {
@@ -108,6 +122,8 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
       if (l_rc[k]) atomicAdd(&sh[10 + k], l_rc[k]);
       if (l_ent[k]) atomicAdd(&sh[14 + k], l_ent[k]);
     }
+    for (int k = 0; k < 3; ++k)
+      if (l_rcat[k]) atomicMax(&sh[18 + k], l_rcat[k]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -119,6 +135,8 @@ __global__ void __launch_bounds__(256) k_rowinfo(const RP* __restrict__ arp, con
       if (sh[10 + k]) atomicAdd(&stats->rows_cat[k], sh[10 + k]);
       if (sh[14 + k]) atomicAdd(&stats->ent_cat[k], sh[14 + k]);
     }
+    for (int k = 0; k < 3; ++k)
+      if (sh[18 + k]) atomicMax(&stats->range_cat[k], sh[18 + k]);
   }
 }
 
@@ -253,11 +271,9 @@ MG_INLINE int64_t block_excl_scan64(int64_t v, int64_t* sh_w, int64_t& total) {
 
 template <typename RP, typename CI, typename V, bool NUMERIC>
 __global__ void __launch_bounds__(1024)
-    k_dense_rows(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
-                 const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
-                 const int32_t* __restrict__ list, const int64_t* __restrict__ minc,
+    k_dense_rows(RowSrc src, const int32_t* __restrict__ list, const int64_t* __restrict__ minc,
                  const int64_t* __restrict__ maxc, int shift, int64_t* rownnz,
-                 const int64_t* __restrict__ crp, CI* ccol, V* cval) {
+                 const int64_t* __restrict__ crp) {
   extern __shared__ __align__(16) unsigned char dsm[];
   const int BS = blockDim.x;
   const int64_t L = (int64_t)1 << shift;
@@ -270,6 +286,14 @@ __global__ void __launch_bounds__(1024)
 
   const int t = threadIdx.x;
   const int32_t row = list[blockIdx.x];
+  const MatEnt& M = src.tab ? src.tab[src.mat_of_row[row]] : src.one;
+  const int64_t lrow = row - M.row0;
+  const RP* __restrict__ arp = (const RP*)M.arp;
+  const CI* __restrict__ acol = (const CI*)M.acol;
+  const V* __restrict__ aval = (const V*)M.aval;
+  const RP* __restrict__ brp = (const RP*)M.brp;
+  const CI* __restrict__ bcol = (const CI*)M.bcol;
+  const V* __restrict__ bval = (const V*)M.bval;
   const int64_t mn = minc[row];
   const int64_t range = maxc[row] - mn + 1;
   const int64_t nwords = (range + 31) / 32;
@@ -278,7 +302,7 @@ __global__ void __launch_bounds__(1024)
     for (int64_t q = t; q < range; q += BS) acc[q] = (V)0;
   __syncthreads();
 
-  const int64_t a0 = arp[row], a1 = arp[row + 1];
+  const int64_t a0 = arp[lrow], a1 = arp[lrow + 1];
   for (int64_t e0 = a0; e0 < a1; e0 += BS) {
     const int64_t e = e0 + t;
     int len = 0;
@@ -318,7 +342,9 @@ __global__ void __launch_bounds__(1024)
     if (t == 0) rownnz[row] = total;
     return;
   }
-  int64_t pos = crp[row] + base;
+  CI* ccol = (CI*)M.ccol;
+  V* cval = (V*)M.cval;
+  int64_t pos = crp[row] - (src.tab ? crp[M.row0] : 0) + base;
   for (int64_t q = w0; q < w1; ++q) {
     uint32_t b = bits[q];
     while (b) {
@@ -333,25 +359,18 @@ __global__ void __launch_bounds__(1024)
 }
 
 template <typename RP, typename CI, typename V>
-static hipError_t dense_rows_t(const Mats& M, bool numeric, const int32_t* list, int64_t count,
+static hipError_t dense_rows_t(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
                                const int64_t* minc, const int64_t* maxc, int shift, int block,
-                               int64_t* rownnz, const int64_t* crp, void* ccol, void* cval,
-                               hipStream_t st) {
+                               int64_t* rownnz, const int64_t* crp, hipStream_t st) {
   if (count == 0) return hipSuccess;
   const size_t lds = dense_rows_lds(sizeof(V) == 8, shift, block);
   auto kn = k_dense_rows<RP, CI, V, true>;
   auto kc = k_dense_rows<RP, CI, V, false>;
-  if (numeric) {
-    hipFuncSetAttribute((const void*)kn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kn, (unsigned)count, block, lds, st, (const RP*)M.arp, (const CI*)M.acol,
-                       (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol, (const V*)M.bval,
-                       list, minc, maxc, shift, rownnz, crp, (CI*)ccol, (V*)cval);
-  } else {
-    hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kc, (unsigned)count, block, lds, st, (const RP*)M.arp, (const CI*)M.acol,
-                       (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol, (const V*)M.bval,
-                       list, minc, maxc, shift, rownnz, crp, (CI*)ccol, (V*)cval);
-  }
+  auto k = numeric ? kn : kc;
+  hipError_t e =
+      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, (unsigned)count, block, lds, st, src, list, minc, maxc, shift, rownnz, crp);
   return hipGetLastError();
 }
 
@@ -447,23 +466,108 @@ hipError_t launch_write_rowptr(const int64_t* crp, int64_t n, void* out, int out
   return hipGetLastError();
 }
 
+static int rowinfo_lanes(int64_t n, int64_t a_nnz) {
+  // lanes per row: the power of two nearest the mean row length of A, 1..64
+  const int64_t avg = n ? (a_nnz + n - 1) / n : 1;
+  int G = 1;
+  while (G < 64 && G < avg) G <<= 1;
+  return G;
+}
+
 hipError_t launch_rowinfo(const Mats& M, int64_t a_nnz, const ClassParams& cp, int64_t* ip,
                           int64_t* minc, int64_t* maxc, int32_t* cls, DevStats* stats,
                           hipStream_t st) {
   if (M.n == 0) return hipSuccess;
-  // lanes per row: the power of two nearest the mean row length of A, 1..64
-  const int64_t avg = M.n ? (a_nnz + M.n - 1) / M.n : 1;
-  int G = 1;
-  while (G < 64 && G < avg) G <<= 1;
-  const int64_t threads = M.n * G;
-  const int64_t want = (threads + 255) / 256;
+  const int G = rowinfo_lanes(M.n, a_nnz);
+  const int64_t want = (M.n * G + 255) / 256;
   const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
-  MG_DISPATCH2(M, hipLaunchKernelGGL((k_rowinfo<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
-                                     (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, M.n,
-                                     G, cp, ip, minc, maxc, cls, stats));
+  const RowSrc src = single_src(M, nullptr, nullptr);
+  MG_DISPATCH2(M, hipLaunchKernelGGL((k_rowinfo<RP, CI, false>), grid, 256, 0, st, src, M.n, G,
+                                     cp, ip, minc, maxc, cls, stats, nullptr));
   return hipGetLastError();
 }
 
+hipError_t launch_rowinfo_batch(const Mats& T, const RowSrc& src, int64_t nrows, int64_t a_nnz,
+                                const ClassParams& cp, int64_t* ip, int64_t* minc, int64_t* maxc,
+                                int32_t* cls, DevStats* stats, int32_t* flags, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  const int G = rowinfo_lanes(nrows, a_nnz);
+  const int64_t want = (nrows * G + 255) / 256;
+  const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
+  MG_DISPATCH2(T, hipLaunchKernelGGL((k_rowinfo<RP, CI, true>), grid, 256, 0, st, src, nrows, G,
+                                     cp, ip, minc, maxc, cls, stats, flags));
+  return hipGetLastError();
+}
+
+__global__ void k_mat_of_row(const int64_t* row0, int64_t nmat, int64_t nrows, int32_t* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  // largest b with row0[b] <= r (row0 ascending, row0[0] = 0, row0[nmat] = nrows)
+  int64_t lo = 0, hi = nmat;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (row0[mid] <= r) lo = mid; else hi = mid;
+  }
+  out[r] = (int32_t)lo;
+}
+hipError_t launch_mat_of_row(const int64_t* row0, int64_t nmat, int64_t nrows, int32_t* mat_of_row,
+                             hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mat_of_row, (unsigned)((nrows + 255) / 256), 256, 0, st, row0, nmat, nrows,
+                     mat_of_row);
+  return hipGetLastError();
+}
+
+__global__ void k_drop_flagged(const int32_t* flags, const int32_t* mat_of_row, int64_t nrows,
+                               int32_t* cls) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrows && flags[mat_of_row[r]]) cls[r] = CLS_EMPTY;
+}
+hipError_t launch_drop_flagged(const int32_t* flags, const int32_t* mat_of_row, int64_t nrows,
+                               int32_t* cls, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_drop_flagged, (unsigned)((nrows + 255) / 256), 256, 0, st, flags,
+                     mat_of_row, nrows, cls);
+  return hipGetLastError();
+}
+
+// Row r of the batch is row r - row0 of its product; each product's last row
+// also writes the closing entry, and thread b < nmat writes the single entry
+// of a product without rows.  Products planned alone (flag set) are skipped:
+// their own execution writes their row pointers.
+__global__ void k_write_rowptr_batch(RowSrc src, const int64_t* __restrict__ crp, int64_t nrows,
+                                     int64_t nmat, const int32_t* __restrict__ flags) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nmat && src.tab[r].nrows == 0 && !flags[r]) {
+    const MatEnt& E = src.tab[r];
+    if (E.crp_out64) ((int64_t*)E.crp_out)[0] = 0;
+    else ((int32_t*)E.crp_out)[0] = 0;
+  }
+  if (r >= nrows) return;
+  const int32_t b = src.mat_of_row[r];
+  if (flags[b]) return;
+  const MatEnt& M = src.tab[b];
+  const int64_t base = crp[M.row0];
+  const int64_t lr = r - M.row0;
+  const bool last = (lr == M.nrows - 1);
+  if (M.crp_out64) {
+    int64_t* o = (int64_t*)M.crp_out;
+    o[lr] = crp[r] - base;
+    if (last) o[lr + 1] = crp[r + 1] - base;
+  } else {
+    int32_t* o = (int32_t*)M.crp_out;
+    o[lr] = (int32_t)(crp[r] - base);
+    if (last) o[lr + 1] = (int32_t)(crp[r + 1] - base);
+  }
+}
+hipError_t launch_write_rowptr_batch(const RowSrc& src, const int64_t* crp, int64_t nrows,
+                                     int64_t nmat, const int32_t* flags, hipStream_t st) {
+  const int64_t n = nrows > nmat ? nrows : nmat;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_write_rowptr_batch, (unsigned)((n + 255) / 256), 256, 0, st, src, crp,
+                     nrows, nmat, flags);
+  return hipGetLastError();
+}
 hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats* stats,
                            hipStream_t st) {
   // A: columns in [0, k), rows sorted not required; B: columns in [0, m), strictly ascending
@@ -478,13 +582,13 @@ hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats
   return hipGetLastError();
 }
 
-hipError_t launch_dense_rows(const Mats& M, bool numeric, const int32_t* list, int64_t begin,
-                             int64_t count, const int64_t* minc, const int64_t* maxc, int shift,
-                             int block, int64_t* rownnz, const int64_t* crp, void* ccol,
-                             void* cval, hipStream_t st) {
+hipError_t launch_dense_rows(const Mats& M, const RowSrc& src, bool numeric, const int32_t* list,
+                             int64_t begin, int64_t count, const int64_t* minc,
+                             const int64_t* maxc, int shift, int block, int64_t* rownnz,
+                             const int64_t* crp, hipStream_t st) {
   hipError_t e = hipSuccess;
-  MG_DISPATCH3(M, e = (dense_rows_t<RP, CI, V>(M, numeric, list + begin, count, minc, maxc, shift,
-                                                block, rownnz, crp, ccol, cval, st)));
+  MG_DISPATCH3(M, e = (dense_rows_t<RP, CI, V>(src, numeric, list + begin, count, minc, maxc,
+                                                shift, block, rownnz, crp, st)));
   return e;
 }
 

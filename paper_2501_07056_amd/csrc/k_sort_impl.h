@@ -28,22 +28,23 @@ MG_INLINE K key_max() { return (K)~(K)0; }
 
 template <typename RP, typename CI, typename V, int E, typename K, bool NUMERIC>
 __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
-    k_sort_rows(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
-                const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
-                const int32_t* __restrict__ list, int64_t count, int R, int colbits,
+    k_sort_rows(RowSrc src, const int32_t* __restrict__ list, int64_t count, int R, int colbits,
                 const int64_t* __restrict__ minc, int64_t* rownnz, const int64_t* __restrict__ crp,
-                CI* ccol, V* cval, DevStats* stats) {
+                DevStats* stats) {
   constexpr int CAP = MG_WAVE * E;
   __shared__ K s_key[SR_WAVES][CAP];
   __shared__ V s_val[SR_WAVES][NUMERIC ? CAP : 1];
   __shared__ int32_t s_pre[SR_WAVES][MG_WAVE + 1];
-  __shared__ int64_t s_b0[SR_WAVES][MG_WAVE];
+  __shared__ const CI* s_bcolp[SR_WAVES][MG_WAVE];
+  __shared__ const V* s_bvalp[SR_WAVES][NUMERIC ? MG_WAVE : 1];
   __shared__ V s_av[SR_WAVES][MG_WAVE];
   __shared__ int32_t s_wslot[SR_WAVES][MG_WAVE];
   __shared__ int64_t s_ent[SR_WAVES][MG_WAVE + 1];
   __shared__ int64_t s_apos[SR_WAVES][MG_WAVE];
   __shared__ int64_t s_minc[SR_WAVES][MG_WAVE];
   __shared__ int32_t s_row[SR_WAVES][MG_WAVE];
+  __shared__ int32_t s_mat[SR_WAVES][MG_WAVE];
+  __shared__ int64_t s_cb[SR_WAVES][NUMERIC ? MG_WAVE : 1];
   __shared__ int32_t s_aux[SR_WAVES][MG_WAVE];
 
   const int w = threadIdx.x / MG_WAVE;
@@ -56,11 +57,17 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
   int64_t ne = 0;
   if (l < nr) {
     const int32_t row = list[r0 + l];
-    const int64_t a0 = arp[row];
-    ne = (int64_t)arp[row + 1] - a0;
+    const int32_t b = src.tab ? src.mat_of_row[row] : 0;
+    const MatEnt& M = src.tab ? src.tab[b] : src.one;
+    const int64_t lrow = row - M.row0;
+    const RP* arp = (const RP*)M.arp;
+    const int64_t a0 = arp[lrow];
+    ne = (int64_t)arp[lrow + 1] - a0;
     s_row[w][l] = row;
+    s_mat[w][l] = b;
     s_apos[w][l] = a0;
     s_minc[w][l] = minc[row];
+    if (NUMERIC) s_cb[w][l] = src.tab ? crp[M.row0] : 0;
   }
   const int64_t einc = wave_incl_scan(ne);
   s_ent[w][l] = einc - ne;
@@ -74,20 +81,28 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
   for (int64_t f0 = 0; f0 < ntot; f0 += MG_WAVE) {
     const int64_t f = f0 + l;
     int len = 0, slot = 0;
-    int64_t b0 = 0;
+    const CI* bcp = nullptr;
+    const V* bvp = nullptr;
     V av = (V)0;
     if (f < ntot) {
       slot = upper_index(s_ent[w], 0, nr, f);
+      const MatEnt& M = src.tab ? src.tab[s_mat[w][slot]] : src.one;
       const int64_t p = s_apos[w][slot] + (f - s_ent[w][slot]);
-      const int64_t j = acol[p];
-      b0 = brp[j];
+      const int64_t j = ((const CI*)M.acol)[p];
+      const RP* brp = (const RP*)M.brp;
+      const int64_t b0 = brp[j];
       len = (int)((int64_t)brp[j + 1] - b0);
-      if (NUMERIC) av = aval[p];
+      bcp = (const CI*)M.bcol + b0;
+      if (NUMERIC) {
+        bvp = (const V*)M.bval + b0;
+        av = ((const V*)M.aval)[p];
+      }
     }
     const int inc = wave_incl_scan(len);
     const int tot = __shfl(inc, MG_WAVE - 1, MG_WAVE);
     s_pre[w][l] = inc - len;
-    s_b0[w][l] = b0;
+    s_bcolp[w][l] = bcp;
+    if (NUMERIC) s_bvalp[w][l] = bvp;
     s_av[w][l] = av;
     s_wslot[w][l] = slot;
     const int nvalid = (int)((ntot - f0) < MG_WAVE ? (ntot - f0) : MG_WAVE);
@@ -98,11 +113,11 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
     }
     for (int q = l; q < tot; q += MG_WAVE) {
       const int k = upper_index(s_pre[w], 0, nvalid, q);
-      const int64_t bi = s_b0[w][k] + (q - s_pre[w][k]);
-      const int64_t col = bcol[bi];
+      const int off = q - s_pre[w][k];
+      const int64_t col = s_bcolp[w][k][off];
       const int s = s_wslot[w][k];
       s_key[w][P + q] = ((K)s << colbits) | (K)(col - s_minc[w][s]);
-      if (NUMERIC) s_val[w][P + q] = s_av[w][k] * bval[bi];
+      if (NUMERIC) s_val[w][P + q] = s_av[w][k] * s_bvalp[w][k][off];
     }
     P += tot;
     wave_sync();
@@ -208,40 +223,36 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
       const bool tail = (x < P) && (x == P - 1 || nk != k[e]);
       if (tail) {
         const int sl = (int)(k[e] >> colbits);
-        const int64_t pos = crp[s_row[w][sl]] + (hr - 1 - s_aux[w][sl]);
-        st_stream<HINT_C_STORE>(&ccol[pos], (CI)(s_minc[w][sl] + (int64_t)(k[e] & kmask)));
-        st_stream<HINT_C_STORE>(&cval[pos], run);
+        const MatEnt& M = src.tab ? src.tab[s_mat[w][sl]] : src.one;
+        const int64_t pos = crp[s_row[w][sl]] - s_cb[w][sl] + (hr - 1 - s_aux[w][sl]);
+        st_stream<HINT_C_STORE>(&((CI*)M.ccol)[pos],
+                                (CI)(s_minc[w][sl] + (int64_t)(k[e] & kmask)));
+        st_stream<HINT_C_STORE>(&((V*)M.cval)[pos], run);
       }
     }
   }
 }
 
 template <typename RP, typename CI, typename V, int E, typename K>
-static hipError_t sort_rows_t(const Mats& M, bool numeric, const int32_t* list, int64_t count,
+static hipError_t sort_rows_t(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
                               int R, int colbits, const int64_t* minc, int64_t* rownnz,
-                              const int64_t* crp, void* ccol, void* cval, DevStats* stats,
-                              hipStream_t st) {
+                              const int64_t* crp, DevStats* stats, hipStream_t st) {
   const int64_t tiles = (count + R - 1) / R;
   const unsigned grid = (unsigned)((tiles + SR_WAVES - 1) / SR_WAVES);
   if (grid == 0) return hipSuccess;
   if (numeric)
-    hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, true>), grid, SR_WAVES * MG_WAVE, 0, st,
-                       (const RP*)M.arp, (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp,
-                       (const CI*)M.bcol, (const V*)M.bval, list, count, R, colbits, minc, rownnz,
-                       crp, (CI*)ccol, (V*)cval, stats);
+    hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, true>), grid, SR_WAVES * MG_WAVE, 0, st, src,
+                       list, count, R, colbits, minc, rownnz, crp, stats);
   else
-    hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, false>), grid, SR_WAVES * MG_WAVE, 0, st,
-                       (const RP*)M.arp, (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp,
-                       (const CI*)M.bcol, (const V*)M.bval, list, count, R, colbits, minc, rownnz,
-                       crp, (CI*)ccol, (V*)cval, stats);
+    hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, false>), grid, SR_WAVES * MG_WAVE, 0, st, src,
+                       list, count, R, colbits, minc, rownnz, crp, stats);
   return hipGetLastError();
 }
 
 template <typename RP, typename CI, typename V>
-hipError_t sort_rows_cls(const Mats& M, int cls, bool numeric, const int32_t* list,
-                                int64_t count, const int64_t* minc, int colbits, int64_t* rownnz,
-                                const int64_t* crp, void* ccol, void* cval, DevStats* stats,
-                                hipStream_t st) {
+hipError_t sort_rows_cls(const RowSrc& src, int cls, bool numeric, const int32_t* list,
+                         int64_t count, const int64_t* minc, int colbits, int64_t* rownnz,
+                         const int64_t* crp, DevStats* stats, hipStream_t st) {
   // class c holds rows with ip in (2^(c-1), 2^c]: E = max(1, 2^c / 64) per
   // lane, R = 64 * E / 2^c rows per wave
   const int E = (cls <= 6) ? 1 : (1 << (cls - 6));
@@ -256,25 +267,22 @@ hipError_t sort_rows_cls(const Mats& M, int cls, bool numeric, const int32_t* li
 #define MG_SR(EE)                                                                               \
   if (E == EE) {                                                                                \
     if (k64)                                                                                    \
-      return sort_rows_t<RP, CI, V, EE, uint64_t>(M, numeric, list, count, R, colbits, minc,    \
-                                                  rownnz, crp, ccol, cval, stats, st);          \
-    return sort_rows_t<RP, CI, V, EE, uint32_t>(M, numeric, list, count, R, colbits, minc,      \
-                                                rownnz, crp, ccol, cval, stats, st);            \
+      return sort_rows_t<RP, CI, V, EE, uint64_t>(src, numeric, list, count, R, colbits, minc,  \
+                                                  rownnz, crp, stats, st);                      \
+    return sort_rows_t<RP, CI, V, EE, uint32_t>(src, numeric, list, count, R, colbits, minc,    \
+                                                rownnz, crp, stats, st);                        \
   }
   MG_SR(1) MG_SR(2) MG_SR(4) MG_SR(8) MG_SR(16)
 #undef MG_SR
   return hipErrorInvalidValue;
 }
 
-
-#define MG_SORT_INSTANTIATE(RP, V)                                                               \
-  template hipError_t sort_rows_cls<RP, int32_t, V>(const Mats&, int, bool, const int32_t*,      \
-                                                     int64_t, const int64_t*, int, int64_t*,     \
-                                                     const int64_t*, void*, void*, DevStats*,    \
-                                                     hipStream_t);                               \
-  template hipError_t sort_rows_cls<RP, int64_t, V>(const Mats&, int, bool, const int32_t*,      \
-                                                     int64_t, const int64_t*, int, int64_t*,     \
-                                                     const int64_t*, void*, void*, DevStats*,    \
-                                                     hipStream_t);
+#define MG_SORT_INSTANTIATE(RP, V)                                                              \
+  template hipError_t sort_rows_cls<RP, int32_t, V>(const RowSrc&, int, bool, const int32_t*,   \
+                                                     int64_t, const int64_t*, int, int64_t*,    \
+                                                     const int64_t*, DevStats*, hipStream_t);   \
+  template hipError_t sort_rows_cls<RP, int64_t, V>(const RowSrc&, int, bool, const int32_t*,   \
+                                                     int64_t, const int64_t*, int, int64_t*,    \
+                                                     const int64_t*, DevStats*, hipStream_t);
 
 }  // namespace mg

@@ -25,6 +25,7 @@ struct DevStats {
   unsigned long long rows_cat[4];
   unsigned long long ent_cat[4];   // A entries of the rows of each category
   unsigned long long nnz_cat[4];   // nnz of C in the rows of each category
+  unsigned long long range_cat[3]; // widest column range among SORT, DENSE, CHUNKED rows
   unsigned int err;  // bit flags, see ERR_*
   unsigned int pad;
 };
@@ -38,6 +39,25 @@ struct Mats {
   const void *brp, *bcol, *bval;
   int64_t n, k, m;
   int rp64, col64, f64;
+};
+
+// One product C = A * B (device pointers).  In a batch, its rows are rows
+// row0 .. row0 + nrows - 1 of the batch's concatenated row numbering.
+struct MatEnt {
+  const void *arp, *acol, *aval;
+  const void *brp, *bcol, *bval;
+  void *ccol, *cval, *crp_out;
+  int64_t row0, nrows;
+  int64_t sort_max, dense_max;  // classification thresholds of this product
+  int32_t crp_out64;            // crp_out holds int64 (else int32)
+  int32_t pad;
+};
+
+// Batched row addressing: tab == nullptr means every row belongs to `one`.
+struct RowSrc {
+  MatEnt one;
+  const MatEnt* tab;
+  const int32_t* mat_of_row;
 };
 
 struct ClassParams {
@@ -63,15 +83,31 @@ size_t classify_temp_bytes(int64_t n);
 hipError_t launch_classify(const int32_t* cls, int64_t n, int32_t* list, int64_t* list_off,
                            void* temp, hipStream_t st);
 // SORT rows of class c (count mode writes rownnz; numeric writes C).
-hipError_t launch_sort_rows(const Mats& M, int cls, bool numeric, const int32_t* list,
-                            int64_t begin, int64_t count, const int64_t* minc, int colbits,
-                            int64_t* rownnz, const int64_t* crp, void* ccol, void* cval,
-                            DevStats* stats, hipStream_t st);
+hipError_t launch_sort_rows(const Mats& M, const RowSrc& src, int cls, bool numeric,
+                            const int32_t* list, int64_t begin, int64_t count, const int64_t* minc,
+                            int colbits, int64_t* rownnz, const int64_t* crp, DevStats* stats,
+                            hipStream_t st);
+// RowSrc for a single product
+RowSrc single_src(const Mats& M, void* ccol, void* cval);
 // DENSE rows: one workgroup per row, column range <= 2^shift.
-hipError_t launch_dense_rows(const Mats& M, bool numeric, const int32_t* list, int64_t begin,
-                             int64_t count, const int64_t* minc, const int64_t* maxc, int shift,
-                             int block, int64_t* rownnz, const int64_t* crp, void* ccol,
-                             void* cval, hipStream_t st);
+hipError_t launch_dense_rows(const Mats& M, const RowSrc& src, bool numeric, const int32_t* list,
+                             int64_t begin, int64_t count, const int64_t* minc,
+                             const int64_t* maxc, int shift, int block, int64_t* rownnz,
+                             const int64_t* crp, hipStream_t st);
+// --- batches of products (rows of all products concatenated) ---
+// mat_of_row[r] = b for row0[b] <= r < row0[b + 1]
+hipError_t launch_mat_of_row(const int64_t* row0, int64_t nmat, int64_t nrows, int32_t* mat_of_row,
+                             hipStream_t st);
+// setup over a batch; flags[b] is set to 1 when product b has CHUNKED rows
+hipError_t launch_rowinfo_batch(const Mats& T, const RowSrc& src, int64_t nrows, int64_t a_nnz,
+                                const ClassParams& cp, int64_t* ip, int64_t* minc, int64_t* maxc,
+                                int32_t* cls, DevStats* stats, int32_t* flags, hipStream_t st);
+// rows of products whose flag is set become EMPTY (they are planned alone)
+hipError_t launch_drop_flagged(const int32_t* flags, const int32_t* mat_of_row, int64_t nrows,
+                               int32_t* cls, hipStream_t st);
+// per-product row pointers of C from the batch's row offsets
+hipError_t launch_write_rowptr_batch(const RowSrc& src, const int64_t* crp, int64_t nrows,
+                                     int64_t nmat, const int32_t* flags, hipStream_t st);
 size_t dense_rows_lds(int f64, int shift, int block);
 
 // --- chunked rows (k_bins.hip) ---

@@ -1,0 +1,240 @@
+// Host-side state shared by the runtime's translation units: the handle, the
+// plan of one product, allocation, readback and profiling helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "magnus.h"
+
+using namespace mg;
+
+struct magnus_handle_s {
+  struct PRec {
+    const char* name;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof = false;
+  std::vector<PRec> recs;
+  int device = 0;
+  magnus_options_t opts{};
+  magnus_alloc_fn alloc_fn = nullptr;
+  magnus_free_fn free_fn = nullptr;
+  void* alloc_ctx = nullptr;
+  std::string err;
+  int lds_max = 65536;
+  int cus = 0;
+};
+
+namespace mgrt {
+
+struct Alloc {
+  void* p;
+  size_t n;
+};
+
+inline void* default_alloc(size_t n, void*, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, n ? n : 1) != hipSuccess) return nullptr;
+  return p;
+}
+inline void default_free(void* p, size_t, void*, void*) { (void)hipFree(p); }
+
+inline int bits_for(int64_t range) {
+  int b = 1;
+  while (b < 62 && ((int64_t)1 << b) < range) ++b;
+  return b;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace mgrt
+
+struct magnus_plan_s {
+  magnus_handle_s* h = nullptr;
+  hipStream_t st = nullptr;
+  std::vector<mgrt::Alloc> allocs;
+  Mats M{};
+  int64_t a_nnz = 0, b_nnz = 0, n = 0;
+  int vtype = 0, itype_rp = 0, itype_col = 0;
+  // per-row arrays
+  int64_t *ip = nullptr, *minc = nullptr, *maxc = nullptr, *crp = nullptr;
+  int32_t *cls = nullptr, *list = nullptr;
+  int64_t* list_off = nullptr;
+  DevStats* stats = nullptr;
+  void* temp = nullptr;
+  int64_t h_list_off[NCLS + 1]{};
+  DevStats h_stats{};
+  int shift = 13, colbits = 1, dense_block = 256, tile = 2048, lds_budget = 65536;
+  int dense_shift = 13;  // DENSE rows: accumulator length 2^dense_shift covers their widest range
+  int persistent_wgs = 512;
+  int hints = 0;
+  int64_t sort_max = 1025, dense_min = 1024, group_max = 1024;
+  // CHUNKED rows
+  int64_t nch = 0, max_nb = 1;
+  ChunkGeom g{};
+  int64_t *aoff = nullptr, *tab_off = nullptr, *tile_e0 = nullptr;
+  int32_t *tile_row = nullptr, *tab_cnt = nullptr, *bin_row = nullptr, *item_counts = nullptr;
+  int64_t *bin_start = nullptr, *bin_cnt = nullptr, *bin_nnz = nullptr, *bin_out = nullptr;
+  int64_t *dense_items = nullptr, *sort_items = nullptr;
+  unsigned long long* bin_cursor = nullptr;
+  unsigned int* work_ctr = nullptr;  // one counter per batch and phase
+  bool bitmap_symbolic = false;
+  uint16_t* ws_col = nullptr;
+  void* ws_val = nullptr;
+  void* tab_temp = nullptr;
+  int64_t ws_products = 0;
+  std::vector<BatchArgs> batches;
+  int64_t nnz_c = 0;
+  magnus_plan_info_t info{};
+  int64_t *ent = nullptr, *entBase = nullptr, *nnzr = nullptr, *nnzBase = nullptr;
+  double s_rp = 4, s_col = 4, s_val = 8;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+namespace mgrt {
+
+inline magnus_status_t fail_hip(magnus_handle_s* h, hipError_t e, const char* where) {
+  if (h) h->err = std::string(where) + ": " + hipGetErrorString(e);
+  return MAGNUS_ERR_HIP;
+}
+
+#define HIPCHK(expr)                                      \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return fail_hip(h, e_, #expr);  \
+  } while (0)
+
+inline void* palloc(magnus_plan_s* P, size_t bytes) {
+  magnus_handle_s* h = P->h;
+  bytes = align256(bytes ? bytes : 1);
+  void* p = h->alloc_fn ? h->alloc_fn(bytes, (void*)P->st, h->alloc_ctx)
+                        : default_alloc(bytes, nullptr, nullptr);
+  if (p) P->allocs.push_back({p, bytes});
+  return p;
+}
+
+inline void plan_free_all(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  for (auto& a : P->allocs) {
+    if (h && h->free_fn) h->free_fn(a.p, a.n, (void*)P->st, h->alloc_ctx);
+    else default_free(a.p, a.n, nullptr, nullptr);
+  }
+  P->allocs.clear();
+  if (P->pinned) (void)hipHostFree(P->pinned);
+  P->pinned = nullptr;
+}
+
+// Brackets one launch (or a group of launches) with events when profiling.
+struct ProfScope {
+  magnus_handle_s* h;
+  hipStream_t st;
+  const char* name;
+  double bytes;
+  hipEvent_t a{}, b{};
+  bool on;
+  ProfScope(magnus_handle_s* h_, hipStream_t st_, const char* name_, double bytes_)
+      : h(h_), st(st_), name(name_), bytes(bytes_), on(h_ && h_->prof) {
+    if (on) {
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+          hipEventRecord(a, st) != hipSuccess)
+        on = false;
+    }
+  }
+  ~ProfScope() {
+    if (on && hipEventRecord(b, st) == hipSuccess) h->recs.push_back({name, a, b, bytes});
+  }
+};
+
+inline magnus_status_t check_csr(const magnus_csr_t* X) {
+  if (!X) return MAGNUS_ERR_INVALID_ARG;
+  if (X->nrows < 0 || X->ncols < 0 || X->nnz < 0) return MAGNUS_ERR_INVALID_ARG;
+  if ((X->rowptr_type != MAGNUS_I32 && X->rowptr_type != MAGNUS_I64) ||
+      (X->col_type != MAGNUS_I32 && X->col_type != MAGNUS_I64) ||
+      (X->val_type != MAGNUS_F32 && X->val_type != MAGNUS_F64))
+    return MAGNUS_ERR_INVALID_ARG;
+  if (!X->rowptr) return MAGNUS_ERR_INVALID_ARG;
+  if (X->nnz > 0 && (!X->col || !X->val)) return MAGNUS_ERR_INVALID_ARG;
+  if (X->rowptr_type == MAGNUS_I32 && X->nnz > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  if (X->col_type == MAGNUS_I32 && X->ncols > (int64_t)INT32_MAX + 1) return MAGNUS_ERR_INDEX_OVERFLOW;
+  return MAGNUS_OK;
+}
+
+inline magnus_status_t readback(magnus_plan_s* P, const std::vector<std::pair<const void*, size_t>>& src,
+                         std::vector<void*> dst) {
+  magnus_handle_s* h = P->h;
+  size_t tot = 0;
+  for (auto& s : src) tot += align256(s.second);
+  if (tot > P->pinned_bytes) {
+    if (P->pinned) (void)hipHostFree(P->pinned);
+    P->pinned = nullptr;
+    HIPCHK(hipHostMalloc(&P->pinned, tot, hipHostMallocDefault));
+    P->pinned_bytes = tot;
+  }
+  size_t off = 0;
+  for (auto& s : src) {
+    if (s.second) HIPCHK(hipMemcpyAsync((char*)P->pinned + off, s.first, s.second,
+                                        hipMemcpyDeviceToHost, P->st));
+    off += align256(s.second);
+  }
+  HIPCHK(hipStreamSynchronize(P->st));
+  off = 0;
+  for (size_t i = 0; i < src.size(); ++i) {
+    if (src[i].second) memcpy(dst[i], (char*)P->pinned + off, src[i].second);
+    off += align256(src[i].second);
+  }
+  return MAGNUS_OK;
+}
+
+// Accumulator length of DENSE rows: the widest DENSE row's column range
+// rounded up to a power of two (at least one bitmap word), at most 2^shift.
+inline int dense_rows_shift(unsigned long long widest, int shift) {
+  int s = 5;
+  while (s < shift && ((unsigned long long)1 << s) < widest) ++s;
+  return s;
+}
+
+inline int default_shift(int f64, int lds_budget) {
+  // largest 2^s with s_val * 2^s + 2^s / 8 bytes <= half the LDS budget (two
+  // dense workgroups per CU), capped at 2^16 (16-bit chunk-local columns)
+  const double per = (f64 ? 8.0 : 4.0) + 0.125;
+  int s = 8;
+  while (s < 16 && per * (double)((int64_t)1 << (s + 1)) + 1024 <= lds_budget / 2.0) ++s;
+  return s;
+}
+
+inline magnus_status_t make_mats(const magnus_csr_t* A, const magnus_csr_t* B, Mats& M) {
+  magnus_status_t s = check_csr(A);
+  if (s != MAGNUS_OK) return s;
+  s = check_csr(B);
+  if (s != MAGNUS_OK) return s;
+  if (A->ncols != B->nrows) return MAGNUS_ERR_SHAPE;
+  if (A->rowptr_type != B->rowptr_type || A->col_type != B->col_type ||
+      A->val_type != B->val_type)
+    return MAGNUS_ERR_DTYPE;
+  if (A->nrows > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  M.arp = A->rowptr;
+  M.acol = A->col;
+  M.aval = A->val;
+  M.brp = B->rowptr;
+  M.bcol = B->col;
+  M.bval = B->val;
+  M.n = A->nrows;
+  M.k = A->ncols;
+  M.m = B->ncols;
+  M.rp64 = A->rowptr_type == MAGNUS_I64;
+  M.col64 = A->col_type == MAGNUS_I64;
+  M.f64 = A->val_type == MAGNUS_F64;
+  return MAGNUS_OK;
+}
+
+}  // namespace mgrt

@@ -93,3 +93,14 @@ def test_config5_stream():
     for r in reqs:
         if r.kind == "rmat":
             assert r.n & (r.n - 1) == 0
+
+
+def test_autotune_size_class_keys():
+    """Size classes group products by value type, rows and row lengths."""
+    import importlib
+    at = importlib.import_module("paper_2501_07056_amd.autotune")
+    A = wl.erdos_renyi(1000, 1000, 8, wl.seed(50), val_dtype=np.float32)
+    B = wl.erdos_renyi(1000, 1000, 30, wl.seed(51), val_dtype=np.float64)
+    assert at.size_class(A, A) == "f32/n10/da3/db3"
+    assert at.size_class(B, B) == "f64/n10/da5/db5"
+    assert at.size_class(A, B) == "f32/n10/da3/db5"
