@@ -365,6 +365,154 @@ def batch_main(args, opts):
     print(json.dumps(out), flush=True)
 
 
+def serve_main(args, opts):
+    """Serving: a Poisson stream of C = A*B requests (n log-uniform in
+    [1e3, 1e6]; half R-MAT with scale round(log2 n), half banded with
+    bandwidth 64 and 9 entries per row; f64 values, int32 indices) replayed
+    at a fixed rate against (1) the server (admission by memory bound,
+    batching, overlapped groups) and (2) one call at a time in arrival
+    order.  Latency is arrival to C complete on the device."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2501_07056_amd as mg
+    import workloads as wl
+
+    reqs = wl.config5_requests(args.serve_count, args.qps)
+    t0 = time.time()
+    host = {}
+
+    def operand(kind, n, which, seed_):
+        # R-MAT operands of one scale are shared (A and B differ); banded ones
+        # are the request's own
+        key = (kind, n, which) if kind == "rmat" else (kind, n, which, seed_)
+        if key not in host:
+            host[key] = wl.config5_operand(kind, n, seed_)
+        return key
+
+    keys = [(operand(r.kind, r.n, "A", r.a_seed), operand(r.kind, r.n, "B", r.b_seed)) for r in reqs]
+    log(f"[bench] {len(reqs)} requests over {reqs[-1].arrival_s:.1f} s, {len(host)} operands "
+        f"generated in {time.time() - t0:.1f} s")
+    dev = {k: mg.DeviceCSR.from_host(X) for k, X in host.items()}
+    torch.cuda.synchronize()
+    ctx = mg.Context(0, **opts)
+    # intermediate products of every request (for the GFLOP/s figures)
+    ips = []
+    for ka, kb in keys:
+        ip, _ = ctx.batch_bound([(dev[ka], dev[kb])])
+        ips.append(ip[0])
+    total_flop = 2.0 * sum(ips)
+
+    check_ids = [i for i, r in enumerate(reqs) if r.n <= 50000][:6]
+
+    def pct(v, q):
+        return float(np.percentile(np.array(v), q)) if v else None
+
+    # (1) served
+    srv = mg.Server(0, options=opts, max_batch=args.max_batch, streams=args.streams)
+    ids = {k: srv.register(X) for k, X in dev.items()}
+    lat, qms, bsz, states = {}, {}, {}, {}
+    parity = []
+    outstanding = {}
+    t_start = time.perf_counter()
+    i = 0
+    last_note, last_progress, n_done = 0.0, 0.0, 0
+    while i < len(reqs) or outstanding:
+        now = time.perf_counter() - t_start
+        if now - last_note >= 2.0:
+            log(f"[bench] served t={now:.1f} s: submitted {i}, finished {n_done}, "
+                f"outstanding {len(outstanding)}, reserved {srv.stats()['reserved_bytes'] / 1e9:.1f} GB")
+            last_note = now
+        if outstanding and now - last_progress > 90.0:
+            st = srv.stats()
+            states = {rid: srv.query(rid)["state"] for rid in list(outstanding)[:20]}
+            log(f"[bench] no request finished for 90 s; stats {st}; states {states}")
+            sys.stdout.flush()
+            os._exit(3)
+        while i < len(reqs) and reqs[i].arrival_s <= now:
+            ka, kb = keys[i]
+            outstanding[srv.submit(ids[ka], ids[kb])] = i
+            i += 1
+        for rid in list(outstanding):
+            if not srv.ready(rid):
+                continue
+            j = outstanding.pop(rid)
+            n_done += 1
+            last_progress = time.perf_counter() - t_start
+            info = srv.query(rid)
+            states[j] = info["state"]
+            if info["state"] == "done":
+                lat[j], qms[j], bsz[j] = info["latency_ms"], info["queue_ms"], info["batch_size"]
+                if j in check_ids:
+                    A, B = host[keys[j][0]], host[keys[j][1]]
+                    C = srv.result(rid)
+                    rp, col, val = (x.astype(np.float64) if k == 2 else x.astype(np.int64)
+                                    for k, x in enumerate(C.to_host()))
+                    rows = np.sort(np.random.default_rng(j).choice(A.nrows, min(200, A.nrows),
+                                                                   replace=False)).astype(np.int64)
+                    ref = oracle.spgemm(A, B, rows)
+                    gl = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+                    ok = bool(np.array_equal(col[gl], ref.col))
+                    err = np.abs(val[gl] - ref.ref) / np.maximum(ref.abssum, 1e-300)
+                    parity.append(ok and bool((err <= 1e-12).all()))
+            srv.release(rid)
+        time.sleep(0.0005)
+    served_s = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    log(f"[bench] served: {served_s:.2f} s, p50 {pct(list(lat.values()), 50):.1f} ms, "
+        f"p99 {pct(list(lat.values()), 99):.1f} ms, stats {st}")
+
+    # (2) one call at a time, arrival order
+    lat1 = {}
+    t_start = time.perf_counter()
+    last_note = 0.0
+    for j, r in enumerate(reqs):
+        if time.perf_counter() - t_start - last_note >= 2.0:
+            last_note = time.perf_counter() - t_start
+            log(f"[bench] serial t={last_note:.1f} s: request {j}")
+        while time.perf_counter() - t_start < r.arrival_s:
+            time.sleep(0.0002)
+        ka, kb = keys[j]
+        try:
+            C = ctx.spgemm(dev[ka], dev[kb])
+            torch.cuda.synchronize()
+            lat1[j] = 1e3 * (time.perf_counter() - t_start - r.arrival_s)
+            del C
+        except mg.MagnusError as e:
+            log(f"[bench] serial request {j} failed: {e}")
+    serial_s = time.perf_counter() - t_start
+    log(f"[bench] serial: {serial_s:.2f} s, p50 {pct(list(lat1.values()), 50):.1f} ms, "
+        f"p99 {pct(list(lat1.values()), 99):.1f} ms")
+
+    served_flop = 2.0 * sum(ips[j] for j in lat)
+    out = {"metric": METRIC, "value": round(served_flop / served_s / 1e9, 2), "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * served_s, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"{len(reqs)} Poisson requests at {args.qps} per second, "
+                                  "C = A*B, n log-uniform in [1e3, 1e6], half R-MAT (scale "
+                                  "round(log2 n)), half banded (w 64, 9 per row), f64, int32",
+                      "requests": len(reqs), "qps": args.qps, "operands": len(host),
+                      "intermediate_products": int(sum(ips)), "max_batch": args.max_batch,
+                      "streams": args.streams},
+           "served": {"seconds": round(served_s, 3), "GFLOPs": round(served_flop / served_s / 1e9, 2),
+                      "p50_ms": pct(list(lat.values()), 50), "p99_ms": pct(list(lat.values()), 99),
+                      "mean_queue_ms": float(np.mean(list(qms.values()))) if qms else None,
+                      "mean_batch": float(np.mean(list(bsz.values()))) if bsz else None,
+                      "completed": len(lat), "rejected": sum(v == "rejected" for v in states.values()),
+                      "failed": sum(v == "failed" for v in states.values()), "server_stats": st},
+           "serial_fifo": {"seconds": round(serial_s, 3),
+                           "GFLOPs": round(total_flop / serial_s / 1e9, 2),
+                           "p50_ms": pct(list(lat1.values()), 50),
+                           "p99_ms": pct(list(lat1.values()), 99), "completed": len(lat1)},
+           "sample_parity": {"requests": len(parity), "all_within_rtol": all(parity), "rtol": 1e-12},
+           "src_sha": src_digest()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +535,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512,
                     help="products of the batch workload (--workload batch)")
     ap.add_argument("--no-tune", action="store_true", help="batch workload: library defaults")
+    ap.add_argument("--serve-count", type=int, default=200, help="requests of --workload serve")
+    ap.add_argument("--qps", type=float, default=10.0, help="arrival rate of --workload serve")
+    ap.add_argument("--max-batch", type=int, default=32)
+    ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2501_07056_amd", "tuned",
                                                          "batch_tuning.json"))
     args = ap.parse_args()
@@ -407,6 +559,9 @@ def main():
         opts[k] = int(v) if v.lstrip("-").isdigit() else v
     if args.workload == "batch":
         batch_main(args, opts)
+        return
+    if args.workload == "serve":
+        serve_main(args, opts)
         return
 
     import numpy as np

@@ -268,6 +268,93 @@ magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t plan
 
 magnus_status_t magnus_batch_plan_destroy(magnus_batch_plan_t plan);
 
+/* Upper bound of nnz(C_b) for every product of a batch, from the setup
+ * phase's per-row count alone (Section 3.1): row i of C has at most
+ * min(ip_i, columns of C) entries.  ip_out and nnz_bound_out: host
+ * int64[count], receiving the intermediate products and the bound of each
+ * product.  One pass over A's entries and B's row pointers; synchronises the
+ * stream once.  Device scratch comes from the handle's allocator and is
+ * released before returning. */
+magnus_status_t magnus_batch_bound(magnus_handle_t h, int32_t count, const magnus_csr_t* A,
+                                   const magnus_csr_t* B, void* stream, int64_t* ip_out,
+                                   int64_t* nnz_bound_out);
+
+/* ------------------------------------------------------------------------
+ * Serving: products of registered, device-resident operands submitted as
+ * requests.  A scheduler thread owned by the server bounds each request's
+ * memory from the setup phase's per-row count (magnus_batch_bound: C bytes
+ * <= sum_i min(ip_i, columns) * (col + value bytes) + (n + 1) * 8, plus a
+ * workspace bound), admits requests in arrival order while the bound fits the
+ * unreserved budget and a slot is free (a request that does not fit may be
+ * passed by at most max_bypass later ones), runs each admitted group as one
+ * batch (magnus_batch_plan / magnus_batch_execute) on its own stream, so that
+ * a group is planned while earlier groups execute, and stamps completion from
+ * a host function enqueued behind the group.  A request whose bound alone
+ * exceeds the budget is planned exactly first and rejected
+ * (MAGNUS_ERR_REJECTED) only if its exact size does not fit either.  All
+ * operands of a server share value and index types.  The server's calls are
+ * thread safe; its results stay valid until released.
+ * ---------------------------------------------------------------------- */
+typedef struct magnus_server_s* magnus_server_t;
+
+typedef struct {
+  int64_t memory_budget_bytes; /* device memory for admitted requests' C and plans (0: half the free memory) */
+  int64_t workspace_cap_bytes; /* CHUNKED-row workspace of one request (0: budget / 16) */
+  int32_t max_inflight;        /* admitted, unfinished requests at most (0: 64) */
+  int32_t max_batch;           /* requests per group (0: 32) */
+  int32_t streams;             /* groups on the device at once (0: 2, at most 8) */
+  int32_t max_bypass;          /* see above (0: 8) */
+} magnus_server_config_t;
+
+typedef enum {
+  MAGNUS_REQ_QUEUED = 0,
+  MAGNUS_REQ_RUNNING = 1,
+  MAGNUS_REQ_DONE = 2,
+  MAGNUS_REQ_REJECTED = 3,
+  MAGNUS_REQ_FAILED = 4
+} magnus_req_state_t;
+
+typedef struct {
+  int32_t state;        /* magnus_req_state_t */
+  int32_t batch_size;   /* requests in the group it ran in */
+  int64_t nnz;          /* nnz(C), once running */
+  int64_t bound_bytes;  /* admission estimate */
+  int64_t exact_bytes;  /* bytes of C allocated */
+  double queue_ms;      /* submit -> admitted (-1 before) */
+  double latency_ms;    /* submit -> C complete on the device (-1 before) */
+  int32_t status;       /* magnus_status_t of a failed or rejected request */
+  int32_t _pad;
+} magnus_request_info_t;
+
+typedef struct {
+  int64_t submitted, completed, rejected, failed;
+  int64_t batches, batched_requests, exact_probes;
+  int64_t reserved_bytes, budget_bytes, queued, running;
+} magnus_server_stats_t;
+
+void magnus_server_config_default(magnus_server_config_t* cfg);
+/* Creates a server with its own handle on `device` (opts may be NULL) and
+ * starts its scheduler thread. */
+magnus_status_t magnus_server_create(int device, const magnus_options_t* opts,
+                                     const magnus_server_config_t* cfg, magnus_server_t* server);
+/* Drops queued requests, waits for running ones, frees every result. */
+magnus_status_t magnus_server_destroy(magnus_server_t server);
+/* Registers a device-resident CSR operand (the caller keeps its buffers
+ * unchanged and alive until the server is destroyed); *id is its handle. */
+magnus_status_t magnus_server_register(magnus_server_t server, const magnus_csr_t* X, int32_t* id);
+/* Queues C = X[a_id] * X[b_id]; returns at once with *request_id. */
+magnus_status_t magnus_server_submit(magnus_server_t server, int32_t a_id, int32_t b_id,
+                                     int64_t* request_id);
+magnus_status_t magnus_server_query(magnus_server_t server, int64_t request_id,
+                                    magnus_request_info_t* info);
+/* Device view of a finished request's C (int64 row pointers); NOT_READY
+ * before, REJECTED or the failure's status otherwise. */
+magnus_status_t magnus_server_result(magnus_server_t server, int64_t request_id,
+                                     magnus_csr_out_t* C);
+/* Frees a finished request's C and forgets the request. */
+magnus_status_t magnus_server_release(magnus_server_t server, int64_t request_id);
+magnus_status_t magnus_server_get_stats(magnus_server_t server, magnus_server_stats_t* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,6 @@
 row-wise method with the intermediate products of long rows reordered into
 LDS-sized column chunks (MAGNUS, ICS '25).  The computation runs in the HIP
 library libmagnus.so; this package only marshals arguments."""
-from .api import (CATEGORY, BatchPlan, Context, DeviceCSR, Plan, gpu_chunk_shift,  # noqa: F401
-                  paper_chunk_model)
+from .api import (CATEGORY, BatchPlan, Context, DeviceCSR, Plan, Server,  # noqa: F401
+                  gpu_chunk_shift, paper_chunk_model)
 from ._lib import MagnusError, declared_symbols, load  # noqa: F401

@@ -51,6 +51,24 @@ class PlanInfo(ctypes.Structure):
         return d
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget_bytes", c_i64), ("workspace_cap_bytes", c_i64),
+                ("max_inflight", c_i32), ("max_batch", c_i32), ("streams", c_i32),
+                ("max_bypass", c_i32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("state", c_i32), ("batch_size", c_i32), ("nnz", c_i64), ("bound_bytes", c_i64),
+                ("exact_bytes", c_i64), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("status", c_i32), ("_pad", c_i32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, c_i64) for n in ("submitted", "completed", "rejected", "failed", "batches",
+                                     "batched_requests", "exact_probes", "reserved_bytes",
+                                     "budget_bytes", "queued", "running")]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", c_i64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -115,9 +133,22 @@ def load(path: str = LIB_PATH):
     lib.magnus_batch_execute.argtypes = [c_vp, c_vp, c_i32, P(CsrDesc), P(CsrDesc),
                                          P(CsrOutDesc), c_i32, c_vp]
     lib.magnus_batch_plan_destroy.argtypes = [c_vp]
+    lib.magnus_batch_bound.argtypes = [c_vp, c_i32, P(CsrDesc), P(CsrDesc), c_vp, P(c_i64),
+                                       P(c_i64)]
+    lib.magnus_server_config_default.argtypes = [P(ServerConfig)]
+    lib.magnus_server_config_default.restype = None
+    lib.magnus_server_create.argtypes = [c_i32, P(Options), P(ServerConfig), P(c_vp)]
+    lib.magnus_server_destroy.argtypes = [c_vp]
+    lib.magnus_server_register.argtypes = [c_vp, P(CsrDesc), P(c_i32)]
+    lib.magnus_server_submit.argtypes = [c_vp, c_i32, c_i32, P(c_i64)]
+    lib.magnus_server_query.argtypes = [c_vp, c_i64, P(RequestInfo)]
+    lib.magnus_server_result.argtypes = [c_vp, c_i64, P(CsrOutDesc)]
+    lib.magnus_server_release.argtypes = [c_vp, c_i64]
+    lib.magnus_server_get_stats.argtypes = [c_vp, P(ServerStats)]
     for fn in declared_symbols():
         f = getattr(lib, fn)
-        if fn not in ("magnus_status_string", "magnus_last_error", "magnus_options_default"):
+        if fn not in ("magnus_status_string", "magnus_last_error", "magnus_options_default",
+                      "magnus_server_config_default"):
             f.restype = c_i32
     _parse_status()
     _lib = lib

@@ -9,7 +9,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import CsrDesc, CsrOutDesc, Options, PlanInfo, check
+from ._lib import (CsrDesc, CsrOutDesc, Options, PlanInfo, RequestInfo, ServerConfig, ServerStats,
+                   check)
 
 _ITYPE = {torch.int32: 0, torch.int64: 1}
 _VTYPE = {torch.float32: 0, torch.float64: 1}
@@ -186,6 +187,17 @@ class Context:
                                          ctypes.byref(info)), "magnus_batch_plan", self.handle)
         return BatchPlan(self, p, info, list(pairs), [int(x) for x in nnz])
 
+    def batch_bound(self, pairs, stream=None):
+        """(ip, nnz upper bound) of every product of the batch (host lists)."""
+        s, keep = _stream_ptr(stream)
+        n = len(pairs)
+        da = (CsrDesc * n)(*[a.desc() for a, _ in pairs])
+        db = (CsrDesc * n)(*[b.desc() for _, b in pairs])
+        ip, nb = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        check(self.lib.magnus_batch_bound(self.handle, n, da, db, s, ip, nb), "magnus_batch_bound",
+              self.handle)
+        return list(ip), list(nb)
+
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, rowptr_dtype=torch.int64, stream=None):
         p = self.plan(A, B, stream)
         try:
@@ -287,6 +299,107 @@ class BatchPlan:
     def __del__(self):
         try:
             self.destroy()
+        except Exception:
+            pass
+
+
+REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "rejected", 4: "failed"}
+
+
+class Server:
+    """Request loop over device-resident operands (see magnus_server_* in
+    include/magnus.h).  register() keeps a reference to each operand so its
+    device memory outlives the server."""
+
+    def __init__(self, device: int = 0, options=None, **config):
+        self.lib = _lib.load()
+        self.device = device
+        opts = Options()
+        self.lib.magnus_options_default(ctypes.byref(opts))
+        for k, v in (options or {}).items():
+            if k == "force_category" and isinstance(v, str):
+                v = CATEGORY[v]
+            setattr(opts, k, int(v))
+        cfg = ServerConfig()
+        self.lib.magnus_server_config_default(ctypes.byref(cfg))
+        for k, v in config.items():
+            if not hasattr(cfg, k):
+                raise TypeError(f"unknown server setting {k}")
+            setattr(cfg, k, int(v))
+        self.ptr = ctypes.c_void_p()
+        check(self.lib.magnus_server_create(device, ctypes.byref(opts), ctypes.byref(cfg),
+                                            ctypes.byref(self.ptr)), "magnus_server_create")
+        self.ops = []
+        self._copier = None
+
+    def register(self, X: DeviceCSR) -> int:
+        i = ctypes.c_int32()
+        d = X.desc()
+        check(self.lib.magnus_server_register(self.ptr, ctypes.byref(d), ctypes.byref(i)),
+              "magnus_server_register")
+        self.ops.append(X)
+        return i.value
+
+    def submit(self, a_id: int, b_id: int) -> int:
+        r = ctypes.c_int64()
+        check(self.lib.magnus_server_submit(self.ptr, a_id, b_id, ctypes.byref(r)),
+              "magnus_server_submit")
+        return r.value
+
+    def query(self, rid: int) -> dict:
+        info = RequestInfo()
+        check(self.lib.magnus_server_query(self.ptr, rid, ctypes.byref(info)), "magnus_server_query")
+        d = {n: getattr(info, n) for n, _ in info._fields_ if n != "_pad"}
+        d["state"] = REQ_STATE[d["state"]]
+        return d
+
+    def ready(self, rid: int) -> bool:
+        return self.query(rid)["state"] in ("done", "rejected", "failed")
+
+    def result(self, rid: int) -> DeviceCSR:
+        """C of a finished request, copied by the library's copy kernel into
+        tensors that torch owns (the server's memory is freed by release)."""
+        d = CsrOutDesc()
+        check(self.lib.magnus_server_result(self.ptr, rid, ctypes.byref(d)), "magnus_server_result")
+        if self._copier is None:
+            self._copier = Context(self.device)
+        dev = self.ops[0].rowptr.device
+        nnz = int(d.capacity)
+        ct = torch.int64 if d.col_type == 1 else torch.int32
+        vt = torch.float64 if d.val_type == 1 else torch.float32
+        out = DeviceCSR(int(d.nrows), int(d.ncols),
+                        torch.empty(int(d.nrows) + 1, dtype=torch.int64, device=dev),
+                        torch.empty(nnz, dtype=ct, device=dev), torch.empty(nnz, dtype=vt, device=dev))
+        lib, h = self._copier.lib, self._copier.handle
+        s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        for t, src in ((out.rowptr, d.rowptr), (out.col, d.col), (out.val, d.val)):
+            if t.numel():
+                check(lib.magnus_stream_copy(h, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(src),
+                                             t.numel() * t.element_size(), s), "magnus_stream_copy")
+        # the copies read the server's memory: finish them before a release
+        # can hand that memory to another request
+        torch.cuda.current_stream(dev).synchronize()
+        return out
+
+    def release(self, rid: int):
+        check(self.lib.magnus_server_release(self.ptr, rid), "magnus_server_release")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(self.lib.magnus_server_get_stats(self.ptr, ctypes.byref(st)), "magnus_server_get_stats")
+        return {n: getattr(st, n) for n, _ in st._fields_}
+
+    def close(self):
+        if self.ptr:
+            self.lib.magnus_server_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+        if self._copier is not None:
+            self._copier.close()
+            self._copier = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

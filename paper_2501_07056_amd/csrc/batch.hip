@@ -49,7 +49,7 @@ void batch_free(magnus_batch_plan_s* P) {
     (void)hipEventSynchronize(P->tab_ev);
     (void)hipEventDestroy(P->tab_ev);
   }
-  if (P->h_tab) (void)hipHostFree(P->h_tab);
+  if (P->h_tab) P->core.h->put_pinned(P->h_tab);
   plan_free_all(&P->core);
   delete P;
 }
@@ -144,7 +144,8 @@ magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus
   P->nnz.assign(count, 0);
   P->alone.assign(count, nullptr);
   P->h_flags.assign(count, 0);
-  BCHK(hipHostMalloc((void**)&P->h_tab, sizeof(MatEnt) * count, hipHostMallocDefault));
+  P->h_tab = (MatEnt*)h->get_pinned(sizeof(MatEnt) * count);
+  if (!P->h_tab) return cleanup(MAGNUS_ERR_OOM);
   std::vector<int32_t> row0_i32(count + 1);
   int64_t r0 = 0;
   for (int32_t b = 0; b < count; ++b) {
@@ -167,6 +168,7 @@ magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus
     E.nrows = A[b].nrows;
     E.sort_max = sort_max ? std::min<int64_t>(sort_max[b], SORT_CAP + 1) : C->sort_max;
     E.dense_max = (int64_t)1 << C->shift;
+    E.mcols = B[b].ncols;
     E.crp_out64 = 1;
     r0 += A[b].nrows;
   }
@@ -407,6 +409,95 @@ magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t P, i
   }
   (void)C;
   return MAGNUS_OK;
+}
+
+magnus_status_t magnus_batch_bound(magnus_handle_t h, int32_t count, const magnus_csr_t* A,
+                                   const magnus_csr_t* B, void* stream, int64_t* ip_out,
+                                   int64_t* nnz_bound_out) {
+  if (!h || count < 1 || !A || !B || !ip_out || !nnz_bound_out) return MAGNUS_ERR_INVALID_ARG;
+  Mats T{};
+  int64_t N = 0, annz = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    Mats M{};
+    magnus_status_t s = make_mats(&A[b], &B[b], M);
+    if (s != MAGNUS_OK) return s;
+    if (b == 0) T = M;
+    else if (M.rp64 != T.rp64 || M.col64 != T.col64 || M.f64 != T.f64) return MAGNUS_ERR_DTYPE;
+    N += A[b].nrows;
+    annz += A[b].nnz;
+    if (N > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  }
+  HIPCHK(hipSetDevice(h->device));
+  magnus_plan_s tmp;
+  tmp.h = h;
+  tmp.st = (hipStream_t)stream;
+  std::vector<MatEnt> tab(count);
+  std::vector<int64_t> row0(count + 1);
+  std::vector<int32_t> row0_i32(count + 1);
+  int64_t r0 = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    MatEnt& E = tab[b];
+    memset(&E, 0, sizeof(E));
+    E.arp = A[b].rowptr;
+    E.acol = A[b].col;
+    E.brp = B[b].rowptr;
+    E.bcol = B[b].col;
+    E.row0 = r0;
+    E.nrows = A[b].nrows;
+    E.mcols = B[b].ncols;
+    row0[b] = r0;
+    row0_i32[b] = (int32_t)r0;
+    r0 += A[b].nrows;
+  }
+  row0[count] = r0;
+  row0_i32[count] = (int32_t)r0;
+  MatEnt* d_tab = (MatEnt*)palloc(&tmp, sizeof(MatEnt) * count);
+  int64_t* d_row0 = (int64_t*)palloc(&tmp, sizeof(int64_t) * (count + 1));
+  int32_t* d_row0_i32 = (int32_t*)palloc(&tmp, sizeof(int32_t) * (count + 1));
+  int32_t* mor = (int32_t*)palloc(&tmp, sizeof(int32_t) * std::max<int64_t>(N, 1));
+  int64_t* vip = (int64_t*)palloc(&tmp, sizeof(int64_t) * (N + 1));
+  int64_t* vbd = (int64_t*)palloc(&tmp, sizeof(int64_t) * (N + 1));
+  int64_t* out = (int64_t*)palloc(&tmp, sizeof(int64_t) * 2 * (count + 1));
+  void* temp = palloc(&tmp, scan_temp_bytes(N + 1) + 1024);
+  magnus_status_t r = MAGNUS_OK;
+  if (!d_tab || !d_row0 || !d_row0_i32 || !mor || !vip || !vbd || !out || !temp) {
+    r = MAGNUS_ERR_OOM;
+  } else {
+    RowSrc src{};
+    src.tab = d_tab;
+    src.mat_of_row = mor;
+    hipError_t e = hipMemcpyAsync(d_tab, tab.data(), sizeof(MatEnt) * count,
+                                  hipMemcpyHostToDevice, tmp.st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_row0, row0.data(), sizeof(int64_t) * (count + 1),
+                         hipMemcpyHostToDevice, tmp.st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_row0_i32, row0_i32.data(), sizeof(int32_t) * (count + 1),
+                         hipMemcpyHostToDevice, tmp.st);
+    if (e == hipSuccess) e = launch_fill_i64(vip + N, 1, 0, tmp.st);
+    if (e == hipSuccess) e = launch_fill_i64(vbd + N, 1, 0, tmp.st);
+    if (e == hipSuccess) e = launch_mat_of_row(d_row0, count, N, mor, tmp.st);
+    if (e == hipSuccess) {
+      ProfScope ps(h, tmp.st, "batch row_bound", (double)annz * (T.col64 ? 8 : 4) * 3 +
+                                                     (double)N * 20);
+      e = launch_row_bound(T, src, N, annz, vip, vbd, tmp.st);
+    }
+    if (e == hipSuccess) e = scan_excl_i64(vip, vip, N + 1, nullptr, nullptr, temp, tmp.st);
+    if (e == hipSuccess) e = scan_excl_i64(vbd, vbd, N + 1, nullptr, nullptr, temp, tmp.st);
+    if (e == hipSuccess) e = launch_gather_rows(vip, d_row0_i32, count + 1, out, tmp.st);
+    if (e == hipSuccess) e = launch_gather_rows(vbd, d_row0_i32, count + 1, out + count + 1, tmp.st);
+    std::vector<int64_t> h_out(2 * (count + 1));
+    if (e != hipSuccess) r = fail_hip(h, e, "magnus_batch_bound");
+    else r = readback(&tmp, {{out, sizeof(int64_t) * 2 * (count + 1)}}, {h_out.data()});
+    if (r == MAGNUS_OK)
+      for (int32_t b = 0; b < count; ++b) {
+        ip_out[b] = h_out[b + 1] - h_out[b];
+        nnz_bound_out[b] = h_out[count + 1 + b + 1] - h_out[count + 1 + b];
+      }
+  }
+  if (r != MAGNUS_OK) (void)hipStreamSynchronize(tmp.st);
+  plan_free_all(&tmp);
+  return r;
 }
 
 magnus_status_t magnus_batch_plan_destroy(magnus_batch_plan_t P) {

@@ -499,6 +499,50 @@ hipError_t launch_rowinfo_batch(const Mats& T, const RowSrc& src, int64_t nrows,
   return hipGetLastError();
 }
 
+// Upper bound of a row's nnz in C: its intermediate-product count, and at
+// most the number of columns of C (the bound of the admission estimate).  G
+// lanes per row as in the setup kernel.
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(256) k_row_bound(RowSrc src, int64_t n, int G, int64_t* ip,
+                                                   int64_t* bound) {
+  const int64_t groups_per_block = blockDim.x / G;
+  const int sub = (int)(threadIdx.x % G);
+  for (int64_t rb = (int64_t)blockIdx.x * groups_per_block; rb < n;
+       rb += (int64_t)gridDim.x * groups_per_block) {
+    const int64_t row = rb + threadIdx.x / G;
+    int64_t s = 0, m = 0;
+    if (row < n) {
+      const MatEnt& M = src.tab[src.mat_of_row[row]];
+      const int64_t lrow = row - M.row0;
+      const RP* arp = (const RP*)M.arp;
+      const CI* acol = (const CI*)M.acol;
+      const RP* brp = (const RP*)M.brp;
+      m = M.mcols;
+      const int64_t p0 = arp[lrow], p1 = arp[lrow + 1];
+      for (int64_t p = p0 + sub; p < p1; p += G) {
+        const int64_t j = acol[p];
+        s += (int64_t)brp[j + 1] - (int64_t)brp[j];
+      }
+    }
+    for (int d = G >> 1; d >= 1; d >>= 1) s += __shfl_xor(s, d, G);
+    if (row < n && sub == 0) {
+      ip[row] = s;
+      bound[row] = s < m ? s : m;
+    }
+  }
+}
+
+hipError_t launch_row_bound(const Mats& T, const RowSrc& src, int64_t nrows, int64_t a_nnz,
+                            int64_t* ip, int64_t* bound, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  const int G = rowinfo_lanes(nrows, a_nnz);
+  const int64_t want = (nrows * G + 255) / 256;
+  const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
+  MG_DISPATCH2(T, hipLaunchKernelGGL((k_row_bound<RP, CI>), grid, 256, 0, st, src, nrows, G, ip,
+                                     bound));
+  return hipGetLastError();
+}
+
 __global__ void k_mat_of_row(const int64_t* row0, int64_t nmat, int64_t nrows, int32_t* out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;

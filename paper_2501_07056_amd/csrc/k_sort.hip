@@ -19,6 +19,7 @@ RowSrc single_src(const Mats& M, void* ccol, void* cval) {
   s.one.nrows = M.n;
   s.one.sort_max = 0;
   s.one.dense_max = 0;
+  s.one.mcols = M.m;
   s.one.crp_out64 = 1;
   s.one.pad = 0;
   s.tab = nullptr;

@@ -49,6 +49,7 @@ struct MatEnt {
   void *ccol, *cval, *crp_out;
   int64_t row0, nrows;
   int64_t sort_max, dense_max;  // classification thresholds of this product
+  int64_t mcols;                // columns of B (and C)
   int32_t crp_out64;            // crp_out holds int64 (else int32)
   int32_t pad;
 };
@@ -102,6 +103,9 @@ hipError_t launch_mat_of_row(const int64_t* row0, int64_t nmat, int64_t nrows, i
 hipError_t launch_rowinfo_batch(const Mats& T, const RowSrc& src, int64_t nrows, int64_t a_nnz,
                                 const ClassParams& cp, int64_t* ip, int64_t* minc, int64_t* maxc,
                                 int32_t* cls, DevStats* stats, int32_t* flags, hipStream_t st);
+// per row: ip_i and min(ip_i, columns of C) (the row's nnz bound)
+hipError_t launch_row_bound(const Mats& T, const RowSrc& src, int64_t nrows, int64_t a_nnz,
+                            int64_t* ip, int64_t* bound, hipStream_t st);
 // rows of products whose flag is set become EMPTY (they are planned alone)
 hipError_t launch_drop_flagged(const int32_t* flags, const int32_t* mat_of_row, int64_t nrows,
                                int32_t* cls, hipStream_t st);

@@ -32,6 +32,33 @@ struct magnus_handle_s {
   std::string err;
   int lds_max = 65536;
   int cus = 0;
+  // pinned host buffers, kept until the handle is destroyed: freeing pinned
+  // memory waits for the whole device, which would stall work on other
+  // streams (a serving loop plans on one stream while others execute)
+  struct Pinned {
+    void* p;
+    size_t n;
+    bool busy;
+  };
+  std::vector<Pinned> pinned;
+  void* get_pinned(size_t n) {
+    for (auto& b : pinned)
+      if (!b.busy && b.n >= n) {
+        b.busy = true;
+        return b.p;
+      }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) return nullptr;
+    pinned.push_back({p, n, true});
+    return p;
+  }
+  void put_pinned(void* p) {
+    for (auto& b : pinned)
+      if (b.p == p) b.busy = false;
+  }
+  ~magnus_handle_s() {
+    for (auto& b : pinned) (void)hipHostFree(b.p);
+  }
 };
 
 namespace mgrt {
@@ -97,8 +124,6 @@ struct magnus_plan_s {
   magnus_plan_info_t info{};
   int64_t *ent = nullptr, *entBase = nullptr, *nnzr = nullptr, *nnzBase = nullptr;
   double s_rp = 4, s_col = 4, s_val = 8;
-  void* pinned = nullptr;
-  size_t pinned_bytes = 0;
 };
 
 namespace mgrt {
@@ -130,8 +155,6 @@ inline void plan_free_all(magnus_plan_s* P) {
     else default_free(a.p, a.n, nullptr, nullptr);
   }
   P->allocs.clear();
-  if (P->pinned) (void)hipHostFree(P->pinned);
-  P->pinned = nullptr;
 }
 
 // Brackets one launch (or a group of launches) with events when profiling.
@@ -169,34 +192,39 @@ inline magnus_status_t check_csr(const magnus_csr_t* X) {
   return MAGNUS_OK;
 }
 
-inline magnus_status_t readback(magnus_plan_s* P, const std::vector<std::pair<const void*, size_t>>& src,
-                         std::vector<void*> dst) {
+inline magnus_status_t readback(magnus_plan_s* P,
+                                const std::vector<std::pair<const void*, size_t>>& src,
+                                std::vector<void*> dst) {
   magnus_handle_s* h = P->h;
   size_t tot = 0;
   for (auto& s : src) tot += align256(s.second);
-  if (tot > P->pinned_bytes) {
-    if (P->pinned) (void)hipHostFree(P->pinned);
-    P->pinned = nullptr;
-    HIPCHK(hipHostMalloc(&P->pinned, tot, hipHostMallocDefault));
-    P->pinned_bytes = tot;
+  char* buf = (char*)h->get_pinned(std::max<size_t>(tot, 4096));
+  if (!buf) {
+    h->err = "hipHostMalloc failed";
+    return MAGNUS_ERR_OOM;
   }
   size_t off = 0;
+  hipError_t e = hipSuccess;
   for (auto& s : src) {
-    if (s.second) HIPCHK(hipMemcpyAsync((char*)P->pinned + off, s.first, s.second,
-                                        hipMemcpyDeviceToHost, P->st));
+    if (s.second && e == hipSuccess)
+      e = hipMemcpyAsync(buf + off, s.first, s.second, hipMemcpyDeviceToHost, P->st);
     off += align256(s.second);
   }
-  HIPCHK(hipStreamSynchronize(P->st));
-  off = 0;
-  for (size_t i = 0; i < src.size(); ++i) {
-    if (src[i].second) memcpy(dst[i], (char*)P->pinned + off, src[i].second);
-    off += align256(src[i].second);
+  if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+  if (e == hipSuccess) {
+    off = 0;
+    for (size_t i = 0; i < src.size(); ++i) {
+      if (src[i].second) memcpy(dst[i], buf + off, src[i].second);
+      off += align256(src[i].second);
+    }
+  } else {
+    (void)hipStreamSynchronize(P->st);
   }
+  h->put_pinned(buf);
+  if (e != hipSuccess) return fail_hip(h, e, "readback");
   return MAGNUS_OK;
 }
 
-// Accumulator length of DENSE rows: the widest DENSE row's column range
-// rounded up to a power of two (at least one bitmap word), at most 2^shift.
 inline int dense_rows_shift(unsigned long long widest, int shift) {
   int s = 5;
   while (s < shift && ((unsigned long long)1 << s) < widest) ++s;

@@ -1,0 +1,686 @@
+// Serving loop: products C = A * B of registered, device-resident operands
+// are submitted as requests; a scheduler thread bounds each request's memory
+// from the setup phase's per-row count (Section 3.1: row i of C has at most
+// min(ip_i, columns) entries), admits requests while the bound fits the free
+// budget and a slot is free, groups admitted requests into one batched plan
+// and execution (the batch calls), and runs several such groups at once on
+// separate streams.  A request whose bound alone exceeds the budget is
+// planned exactly (precise symbolic phase, Section 2.1) and rejected only if
+// its exact size does not fit either.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "admission.h"
+#include "runtime_int.h"
+
+using namespace mgrt;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SrvReq {
+  int64_t id = 0;
+  int32_t a = 0, b = 0;
+  std::atomic<int> state{MAGNUS_REQ_QUEUED};
+  std::atomic<double> t_done{0.0};
+  double t_submit = 0, t_admit = 0;
+  int64_t bound_bytes = -1;  // admission estimate (C bound + workspace bound)
+  int64_t held = 0;          // bytes reserved against the budget
+  int64_t exact_bytes = 0, nnz = 0;
+  int32_t batch_size = 0, skipped = 0;
+  magnus_status_t status = MAGNUS_OK;
+  void* mem = nullptr;  // C: row pointers, columns, values in one allocation
+  hipStream_t mem_st = nullptr;
+  magnus_csr_out_t C{};
+  magnus_batch_plan_t pre = nullptr;  // exact plan of an oversized request
+  int64_t pre_nnz = 0, pre_plan_bytes = 0;
+};
+
+struct SrvBatch {
+  magnus_batch_plan_t bp = nullptr;
+  std::vector<SrvReq*> reqs;
+  int stream = 0;
+  int64_t plan_bytes = 0;
+  std::atomic<int> done{0};
+};
+
+// Host function enqueued after a group's launches: stamps completion.  It
+// runs on a runtime thread and calls no HIP API.
+void done_cb(void* p) {
+  SrvBatch* B = (SrvBatch*)p;
+  const double t = now_s();
+  for (SrvReq* r : B->reqs) {
+    r->t_done.store(t);
+    r->state.store(MAGNUS_REQ_DONE);
+  }
+  B->done.store(1);
+}
+
+// Device memory of the server: a caching allocator over hipMalloc.  Large
+// blocks (C of a big request, CHUNKED workspaces) are recycled instead of
+// being returned to the driver, which would clear fresh pages again on the
+// next allocation.  A freed block records an event on the stream that last
+// used it; a later allocation on another stream waits for that event on the
+// device (no host wait).  Blocks go back to the driver only when hipMalloc
+// fails, and when the server is destroyed.
+struct DevCache {
+  struct Blk {
+    void* p;
+    size_t n;
+    hipEvent_t ev;
+  };
+  std::mutex mu;
+  std::multimap<size_t, Blk> free_;
+  std::unordered_map<void*, size_t> live;
+
+  static size_t round(size_t n) {
+    const size_t g = n < ((size_t)1 << 24) ? 256 : ((size_t)2 << 20);
+    return (n + g - 1) / g * g;
+  }
+  void drop_free_locked() {
+    for (auto& kv : free_) {
+      if (kv.second.ev) {
+        (void)hipEventSynchronize(kv.second.ev);
+        (void)hipEventDestroy(kv.second.ev);
+      }
+      (void)hipFree(kv.second.p);
+    }
+    free_.clear();
+  }
+  void* alloc(size_t n, hipStream_t st) {
+    n = round(n ? n : 1);
+    std::lock_guard<std::mutex> lk(mu);
+    // best fit, without spending a block more than twice the size (or
+    // 64 MiB above it) on a smaller request
+    auto it = free_.lower_bound(n);
+    if (it != free_.end() && it->first <= std::max(2 * n, n + ((size_t)64 << 20))) {
+      Blk b = it->second;
+      free_.erase(it);
+      if (b.ev) {
+        if (hipEventQuery(b.ev) != hipSuccess) (void)hipStreamWaitEvent(st, b.ev, 0);
+        (void)hipEventDestroy(b.ev);
+      }
+      live[b.p] = b.n;
+      return b.p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      drop_free_locked();
+      if (hipMalloc(&p, n) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    live[p] = n;
+    return p;
+  }
+  void release(void* p, hipStream_t st) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(ev, st) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      ev = nullptr;
+      (void)hipStreamSynchronize(st);
+    }
+    free_.emplace(it->second, Blk{p, it->second, ev});
+    live.erase(it);
+  }
+  ~DevCache() {
+    std::lock_guard<std::mutex> lk(mu);
+    drop_free_locked();
+    for (auto& kv : live) (void)hipFree(kv.first);
+  }
+};
+
+void* srv_alloc(size_t n, void* stream, void* ctx) {
+  return ((DevCache*)ctx)->alloc(n, (hipStream_t)stream);
+}
+void srv_free(void* p, size_t, void* stream, void* ctx) {
+  ((DevCache*)ctx)->release(p, (hipStream_t)stream);
+}
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct magnus_server_s {
+  DevCache mem;  // destroyed last
+  magnus_handle_t h = nullptr;
+  magnus_server_config_t cfg{};
+  int64_t budget = 0;
+  std::vector<magnus_csr_t> ops;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<SrvReq*> pending;
+  std::unordered_map<int64_t, std::unique_ptr<SrvReq>> reqs;
+  std::vector<std::unique_ptr<SrvBatch>> inflight;
+  std::vector<hipStream_t> streams;
+  std::vector<char> stream_busy;
+  hipStream_t ctl = nullptr;
+  int64_t reserved = 0;
+  int running = 0;
+  int64_t next_id = 1;
+  bool stop = false;
+  std::thread thr;
+  magnus_server_stats_t stats{};
+};
+
+namespace {
+
+int64_t val_bytes(const magnus_csr_t& X) { return X.val_type == MAGNUS_F64 ? 8 : 4; }
+int64_t col_bytes(const magnus_csr_t& X) { return X.col_type == MAGNUS_I64 ? 8 : 4; }
+
+int64_t c_bytes(const magnus_csr_t& A, const magnus_csr_t& B, int64_t nnz) {
+  return (int64_t)(a256((size_t)(A.nrows + 1) * 8) + a256((size_t)nnz * col_bytes(B)) +
+                   a256((size_t)nnz * val_bytes(A)));
+}
+
+// Fail the requests of a group that never reached the device.
+void fail_group(magnus_server_s* S, std::vector<SrvReq*>& g, int sidx, magnus_status_t st) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (SrvReq* r : g) {
+    if (r->mem) S->mem.release(r->mem, r->mem_st);
+    r->mem = nullptr;
+    S->reserved -= r->held;
+    r->held = 0;
+    r->status = st;
+    r->state.store(MAGNUS_REQ_FAILED);
+    S->stats.failed++;
+  }
+  S->running -= (int)g.size();
+  if (sidx >= 0) S->stream_busy[sidx] = 0;
+}
+
+// Bounds of queued requests (one batched pass on the control stream).
+void compute_bounds(magnus_server_s* S, std::vector<SrvReq*>& need) {
+  const int n = (int)need.size();
+  std::vector<magnus_csr_t> A(n), B(n);
+  for (int i = 0; i < n; ++i) {
+    A[i] = S->ops[need[i]->a];
+    B[i] = S->ops[need[i]->b];
+  }
+  std::vector<int64_t> ip(n), nb(n);
+  magnus_status_t s = magnus_batch_bound(S->h, n, A.data(), B.data(), S->ctl, ip.data(), nb.data());
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (int i = 0; i < n; ++i) {
+    SrvReq* r = need[i];
+    if (s != MAGNUS_OK) {
+      r->status = s;
+      r->state.store(MAGNUS_REQ_FAILED);
+      S->stats.failed++;
+      continue;
+    }
+    const int64_t vs = val_bytes(A[i]);
+    const int64_t ws = 192 * (A[i].nrows + 1) +
+                       std::min<int64_t>(S->cfg.workspace_cap_bytes, (2 + vs) * ip[i]) + (1 << 20);
+    r->bound_bytes = c_bytes(A[i], B[i], nb[i]) + ws;
+  }
+  if (s != MAGNUS_OK) {
+    for (auto it = S->pending.begin(); it != S->pending.end();)
+      if ((*it)->state.load() == MAGNUS_REQ_FAILED) it = S->pending.erase(it);
+      else ++it;
+  }
+}
+
+// Exact size of a request whose bound alone exceeds the budget: it is
+// planned on its own, and keeps that plan if it fits.
+void probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
+  const magnus_csr_t& A = S->ops[r->a];
+  const magnus_csr_t& B = S->ops[r->b];
+  magnus_batch_plan_t bp = nullptr;
+  int64_t nnz = 0;
+  magnus_plan_info_t info{};
+  magnus_status_t s = magnus_batch_plan(S->h, 1, &A, &B, nullptr, S->streams[sidx], &bp, &nnz, &info);
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->stream_busy[sidx] = 0;
+  const int64_t total = (s == MAGNUS_OK) ? c_bytes(A, B, nnz) + info.plan_bytes : 0;
+  if (s != MAGNUS_OK || total > S->budget) {
+    if (bp) magnus_batch_plan_destroy(bp);
+    r->status = s != MAGNUS_OK ? s : MAGNUS_ERR_REJECTED;
+    r->state.store(s != MAGNUS_OK ? MAGNUS_REQ_FAILED : MAGNUS_REQ_REJECTED);
+    if (s != MAGNUS_OK) S->stats.failed++;
+    else S->stats.rejected++;
+    for (auto it = S->pending.begin(); it != S->pending.end(); ++it)
+      if (*it == r) {
+        S->pending.erase(it);
+        break;
+      }
+    return;
+  }
+  // the plan's memory is held from now on
+  r->pre = bp;
+  r->pre_nnz = nnz;
+  r->pre_plan_bytes = info.plan_bytes;
+  S->reserved += info.plan_bytes;
+  r->bound_bytes = c_bytes(A, B, nnz);
+  S->stats.exact_probes++;
+}
+
+void launch_group(magnus_server_s* S, std::vector<SrvReq*> g, int sidx) {
+  hipStream_t st = S->streams[sidx];
+  const int n = (int)g.size();
+  std::vector<magnus_csr_t> A(n), B(n);
+  std::vector<magnus_csr_out_t> C(n);
+  for (int i = 0; i < n; ++i) {
+    A[i] = S->ops[g[i]->a];
+    B[i] = S->ops[g[i]->b];
+  }
+  magnus_batch_plan_t bp = nullptr;
+  std::vector<int64_t> nnz(n, 0);
+  int64_t plan_bytes = 0;
+  bool pre = (n == 1 && g[0]->pre);
+  if (pre) {
+    bp = g[0]->pre;
+    g[0]->pre = nullptr;
+    nnz[0] = g[0]->pre_nnz;
+    plan_bytes = g[0]->pre_plan_bytes;  // reserved when it was planned
+  } else {
+    magnus_plan_info_t info{};
+    magnus_status_t s =
+        magnus_batch_plan(S->h, n, A.data(), B.data(), nullptr, st, &bp, nnz.data(), &info);
+    if (s != MAGNUS_OK) {
+      fail_group(S, g, sidx, s);
+      return;
+    }
+    plan_bytes = info.plan_bytes;
+  }
+  for (int i = 0; i < n; ++i) {
+    SrvReq* r = g[i];
+    const int64_t bytes = c_bytes(A[i], B[i], nnz[i]);
+    void* p = nullptr;
+    p = S->mem.alloc((size_t)bytes, st);
+    if (!p) {
+      magnus_batch_plan_destroy(bp);
+      if (pre) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->reserved -= plan_bytes;
+      }
+      fail_group(S, g, sidx, MAGNUS_ERR_OOM);
+      return;
+    }
+    r->mem = p;
+    r->mem_st = st;
+    magnus_csr_out_t& O = C[i];
+    O.nrows = A[i].nrows;
+    O.ncols = B[i].ncols;
+    O.capacity = nnz[i];
+    O.rowptr_type = MAGNUS_I64;
+    O.col_type = B[i].col_type;
+    O.val_type = A[i].val_type;
+    char* base = (char*)p;
+    O.rowptr = base;
+    O.col = base + a256((size_t)(A[i].nrows + 1) * 8);
+    O.val = base + a256((size_t)(A[i].nrows + 1) * 8) + a256((size_t)nnz[i] * col_bytes(B[i]));
+  }
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!pre) S->reserved += plan_bytes;
+    for (int i = 0; i < n; ++i) {
+      SrvReq* r = g[i];
+      const int64_t exact = c_bytes(A[i], B[i], nnz[i]);
+      S->reserved += exact - r->held;
+      r->held = exact;
+      r->exact_bytes = exact;
+      r->nnz = nnz[i];
+      r->batch_size = n;
+      r->C = C[i];
+    }
+  }
+  magnus_status_t s =
+      magnus_batch_execute(S->h, bp, n, A.data(), B.data(), C.data(), MAGNUS_BATCH_EAGER, st);
+  if (s != MAGNUS_OK) {
+    (void)hipStreamSynchronize(st);
+    magnus_batch_plan_destroy(bp);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->reserved -= plan_bytes;
+    }
+    fail_group(S, g, sidx, s);
+    return;
+  }
+  auto B_ = std::make_unique<SrvBatch>();
+  B_->bp = bp;
+  B_->reqs = g;
+  B_->stream = sidx;
+  B_->plan_bytes = plan_bytes;
+  SrvBatch* raw = B_.get();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->inflight.push_back(std::move(B_));
+    S->stats.batches++;
+    S->stats.batched_requests += n;
+  }
+  if (hipLaunchHostFunc(st, done_cb, raw) != hipSuccess) {
+    // no completion callback: wait here and stamp it directly
+    (void)hipStreamSynchronize(st);
+    done_cb(raw);
+  }
+}
+
+void sched_loop(magnus_server_s* S) {
+  const int window = std::max(4 * S->cfg.max_batch, 64);
+  for (;;) {
+    bool worked = false;
+    // 1. finished groups: release their plans and streams
+    std::vector<std::unique_ptr<SrvBatch>> fin;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto it = S->inflight.begin(); it != S->inflight.end();) {
+        if ((*it)->done.load()) {
+          fin.push_back(std::move(*it));
+          it = S->inflight.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      for (auto& B : fin) {
+        S->stream_busy[B->stream] = 0;
+        S->running -= (int)B->reqs.size();
+        S->reserved -= B->plan_bytes;
+        S->stats.completed += (int64_t)B->reqs.size();
+      }
+      if (S->stop && S->pending.empty() && S->inflight.empty()) break;
+    }
+    for (auto& B : fin) magnus_batch_plan_destroy(B->bp);
+    worked |= !fin.empty();
+
+    // 2. bounds of queued requests that have none yet
+    std::vector<SrvReq*> need;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (SrvReq* r : S->pending) {
+        if ((int)need.size() >= window) break;
+        if (r->bound_bytes < 0) need.push_back(r);
+      }
+    }
+    if (!need.empty()) {
+      compute_bounds(S, need);
+      worked = true;
+    }
+
+    // 3. admission into one group on an idle stream
+    std::vector<SrvReq*> group;
+    SrvReq* probe = nullptr;
+    int sidx = -1;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (int i = 0; i < (int)S->streams.size(); ++i)
+        if (!S->stream_busy[i]) {
+          sidx = i;
+          break;
+        }
+      if (sidx >= 0) {
+        // the admission rules live in admission.h (tested on the host)
+        std::vector<mgsrv::QItem> q;
+        std::vector<SrvReq*> qr;
+        for (SrvReq* r : S->pending) {
+          if ((int)q.size() >= window) break;
+          q.push_back({r->bound_bytes, r->pre != nullptr, r->skipped});
+          qr.push_back(r);
+        }
+        mgsrv::Decision d = mgsrv::admit_pass(q, S->reserved, S->budget,
+                                              S->cfg.max_inflight - S->running,
+                                              S->cfg.max_batch, S->cfg.max_bypass);
+        for (size_t i = 0; i < q.size(); ++i) qr[i]->skipped = q[i].skipped;
+        if (d.probe >= 0) probe = qr[(size_t)d.probe];
+        for (size_t i : d.admit) {
+          SrvReq* r = qr[i];
+          r->held = r->bound_bytes;
+          S->reserved += r->bound_bytes;
+          r->t_admit = now_s();
+          r->state.store(MAGNUS_REQ_RUNNING);
+          group.push_back(r);
+        }
+        if (!group.empty()) {
+          // admitted requests leave the queue (positions are ascending)
+          size_t k = 0;
+          std::deque<SrvReq*> rest;
+          size_t pos = 0;
+          for (SrvReq* r : S->pending) {
+            if (k < d.admit.size() && d.admit[k] == pos) ++k;
+            else rest.push_back(r);
+            ++pos;
+          }
+          S->pending.swap(rest);
+        }
+        if (!group.empty() || probe) {
+          S->stream_busy[sidx] = 1;
+          S->running += (int)group.size();
+        }
+      }
+    }
+    if (probe) {
+      probe_exact(S, probe, sidx);
+      worked = true;
+    } else if (!group.empty()) {
+      launch_group(S, group, sidx);
+      worked = true;
+    }
+    if (!worked) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait_for(lk, std::chrono::microseconds(100));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void magnus_server_config_default(magnus_server_config_t* c) {
+  if (!c) return;
+  memset(c, 0, sizeof(*c));
+}
+
+magnus_status_t magnus_server_create(int device, const magnus_options_t* opts,
+                                     const magnus_server_config_t* cfg, magnus_server_t* out) {
+  if (!out) return MAGNUS_ERR_INVALID_ARG;
+  *out = nullptr;
+  magnus_server_config_t c{};
+  if (cfg) c = *cfg;
+  if (c.memory_budget_bytes < 0 || c.workspace_cap_bytes < 0 || c.max_inflight < 0 ||
+      c.max_batch < 0 || c.streams < 0 || c.max_bypass < 0)
+    return MAGNUS_ERR_INVALID_ARG;
+  magnus_handle_t h = nullptr;
+  magnus_status_t s = magnus_create(&h, device, opts);
+  if (s != MAGNUS_OK) return s;
+  if (hipSetDevice(device) != hipSuccess) {
+    magnus_destroy(h);
+    return MAGNUS_ERR_HIP;
+  }
+  if (c.memory_budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      magnus_destroy(h);
+      return MAGNUS_ERR_HIP;
+    }
+    c.memory_budget_bytes = (int64_t)(fr / 2);
+  }
+  if (c.workspace_cap_bytes == 0) c.workspace_cap_bytes = c.memory_budget_bytes / 16;
+  if (c.max_inflight == 0) c.max_inflight = 64;
+  if (c.max_batch == 0) c.max_batch = 32;
+  if (c.streams == 0) c.streams = 2;
+  if (c.max_bypass == 0) c.max_bypass = 8;
+  c.streams = std::min(c.streams, 8);
+  // the CHUNKED workspace of any one plan stays within the per-request cap
+  magnus_options_t o;
+  magnus_options_default(&o);
+  if (opts) o = *opts;
+  if (o.max_workspace_bytes <= 0 || o.max_workspace_bytes > c.workspace_cap_bytes)
+    o.max_workspace_bytes = c.workspace_cap_bytes;
+  magnus_set_options(h, &o);
+  magnus_server_s* S = new magnus_server_s();
+  magnus_set_allocator(h, srv_alloc, srv_free, &S->mem);
+  S->h = h;
+  S->cfg = c;
+  S->budget = c.memory_budget_bytes;
+  S->streams.resize(c.streams, nullptr);
+  S->stream_busy.assign(c.streams, 0);
+  hipError_t e = hipStreamCreateWithFlags(&S->ctl, hipStreamNonBlocking);
+  for (int i = 0; i < c.streams && e == hipSuccess; ++i)
+    e = hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    for (auto st : S->streams)
+      if (st) (void)hipStreamDestroy(st);
+    if (S->ctl) (void)hipStreamDestroy(S->ctl);
+    magnus_destroy(h);
+    delete S;
+    return MAGNUS_ERR_HIP;
+  }
+  S->thr = std::thread([S, device] {
+    (void)hipSetDevice(device);
+    sched_loop(S);
+  });
+  *out = S;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_destroy(magnus_server_t S) {
+  if (!S) return MAGNUS_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    // queued requests are dropped; running ones finish
+    for (SrvReq* r : S->pending) {
+      r->status = MAGNUS_ERR_REJECTED;
+      r->state.store(MAGNUS_REQ_REJECTED);
+    }
+    S->pending.clear();
+  }
+  S->cv.notify_all();
+  if (S->thr.joinable()) S->thr.join();
+  for (auto& kv : S->reqs) {
+    SrvReq* r = kv.second.get();
+    if (r->mem) S->mem.release(r->mem, r->mem_st);
+    if (r->pre) magnus_batch_plan_destroy(r->pre);
+  }
+  for (auto st : S->streams) (void)hipStreamSynchronize(st);
+  (void)hipStreamSynchronize(S->ctl);
+  for (auto st : S->streams) (void)hipStreamDestroy(st);
+  (void)hipStreamDestroy(S->ctl);
+  magnus_destroy(S->h);
+  delete S;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_register(magnus_server_t S, const magnus_csr_t* X, int32_t* id) {
+  if (!S || !X || !id) return MAGNUS_ERR_INVALID_ARG;
+  magnus_status_t s = check_csr(X);
+  if (s != MAGNUS_OK) return s;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (!S->ops.empty()) {
+    const magnus_csr_t& F = S->ops[0];
+    if (X->rowptr_type != F.rowptr_type || X->col_type != F.col_type || X->val_type != F.val_type)
+      return MAGNUS_ERR_DTYPE;
+  }
+  if (X->nrows > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  *id = (int32_t)S->ops.size();
+  S->ops.push_back(*X);
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_submit(magnus_server_t S, int32_t a_id, int32_t b_id,
+                                     int64_t* request_id) {
+  if (!S || !request_id) return MAGNUS_ERR_INVALID_ARG;
+  const double t = now_s();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return MAGNUS_ERR_INVALID_ARG;
+    if (a_id < 0 || b_id < 0 || a_id >= (int32_t)S->ops.size() || b_id >= (int32_t)S->ops.size())
+      return MAGNUS_ERR_INVALID_ARG;
+    if (S->ops[a_id].ncols != S->ops[b_id].nrows) return MAGNUS_ERR_SHAPE;
+    auto r = std::make_unique<SrvReq>();
+    r->id = S->next_id++;
+    r->a = a_id;
+    r->b = b_id;
+    r->t_submit = t;
+    *request_id = r->id;
+    S->pending.push_back(r.get());
+    S->reqs.emplace(r->id, std::move(r));
+    S->stats.submitted++;
+  }
+  S->cv.notify_one();
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_query(magnus_server_t S, int64_t request_id,
+                                    magnus_request_info_t* info) {
+  if (!S || !info) return MAGNUS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(request_id);
+  if (it == S->reqs.end()) return MAGNUS_ERR_INVALID_ARG;
+  SrvReq* r = it->second.get();
+  memset(info, 0, sizeof(*info));
+  info->state = r->state.load();
+  info->batch_size = r->batch_size;
+  info->nnz = r->nnz;
+  info->bound_bytes = r->bound_bytes;
+  info->exact_bytes = r->exact_bytes;
+  info->queue_ms = r->t_admit > 0 ? 1e3 * (r->t_admit - r->t_submit) : -1.0;
+  info->latency_ms = info->state == MAGNUS_REQ_DONE ? 1e3 * (r->t_done.load() - r->t_submit) : -1.0;
+  info->status = r->status;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_result(magnus_server_t S, int64_t request_id, magnus_csr_out_t* C) {
+  if (!S || !C) return MAGNUS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(request_id);
+  if (it == S->reqs.end()) return MAGNUS_ERR_INVALID_ARG;
+  SrvReq* r = it->second.get();
+  const int st = r->state.load();
+  if (st == MAGNUS_REQ_REJECTED) return MAGNUS_ERR_REJECTED;
+  if (st == MAGNUS_REQ_FAILED) return r->status != MAGNUS_OK ? r->status : MAGNUS_ERR_INTERNAL;
+  if (st != MAGNUS_REQ_DONE) return MAGNUS_ERR_NOT_READY;
+  *C = r->C;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_release(magnus_server_t S, int64_t request_id) {
+  if (!S) return MAGNUS_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(request_id);
+    if (it == S->reqs.end()) return MAGNUS_ERR_INVALID_ARG;
+    SrvReq* r = it->second.get();
+    const int st = r->state.load();
+    if (st == MAGNUS_REQ_QUEUED || st == MAGNUS_REQ_RUNNING) return MAGNUS_ERR_NOT_READY;
+    // a finished request's group may still be in the in-flight list (its
+    // plan not yet released), but nothing of the group reads C any more
+    if (r->mem) S->mem.release(r->mem, r->mem_st);
+    r->mem = nullptr;
+    S->reserved -= r->held;
+    r->held = 0;
+    S->reqs.erase(it);
+  }
+  S->cv.notify_one();
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_get_stats(magnus_server_t S, magnus_server_stats_t* out) {
+  if (!S || !out) return MAGNUS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->stats;
+  out->reserved_bytes = S->reserved;
+  out->budget_bytes = S->budget;
+  out->queued = (int64_t)S->pending.size();
+  out->running = S->running;
+  return MAGNUS_OK;
+}
+
+}  // extern "C"

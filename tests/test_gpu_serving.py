@@ -1,0 +1,188 @@
+"""The serving loop (GPU): requests over registered operands are admitted by
+their memory bound, batched and overlapped; every result equals the oracle
+and the same product computed alone, whatever else ran beside it."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+from gpu_util import compare, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _wait(srv, rids, timeout=60.0):
+    t0 = time.time()
+    pending = set(rids)
+    while pending:
+        pending = {r for r in pending if not srv.ready(r)}
+        assert time.time() - t0 < timeout, f"requests {sorted(pending)[:5]} not finished"
+        time.sleep(0.001)
+
+
+def _host(C):
+    rp, col, val = C.to_host()
+    return rp.astype(np.int64), col.astype(np.int64), val.astype(np.float64)
+
+
+def _operands(kind_vals="int"):
+    """Mixed sizes: small R-MAT and banded operands (square, f64, int32)."""
+    ops = []
+    for sc in (8, 10, 11):
+        ops.append(wl.rmat(sc, wl.seed(300 + sc), val_kind=kind_vals, val_dtype=np.float64,
+                           rowptr_dtype=np.int32, col_dtype=np.int32))
+    for n in (700, 3000):
+        ops.append(wl.banded(n, 64, 8, wl.seed(400 + n), val_kind=kind_vals, val_dtype=np.float64,
+                             rowptr_dtype=np.int32, col_dtype=np.int32))
+    return ops
+
+
+def test_serving_same_alone_and_in_the_mix():
+    """Integer values (exact sums): each served result is bit-identical to
+    the oracle and to the product computed alone through the single calls."""
+    import torch
+
+    import paper_2501_07056_amd as mg
+    ops = _operands("int")
+    dev = [mg.DeviceCSR.from_host(X) for X in ops]
+    srv = mg.Server(0, max_batch=4, streams=2)
+    ctx = mg.Context(0)
+    try:
+        ids = [srv.register(X) for X in dev]
+        pairs = [(i, i) for i in range(len(ops))] + [(0, 0), (2, 2), (4, 4), (3, 3)]
+        log(f"serving {len(pairs)} requests")
+        rids = [srv.submit(a, b) for a, b in pairs]
+        _wait(srv, rids)
+        st = srv.stats()
+        assert st["completed"] == len(rids) and st["failed"] == 0 and st["rejected"] == 0, st
+        for rid, (a, b) in zip(rids, pairs):
+            info = srv.query(rid)
+            assert info["state"] == "done" and info["latency_ms"] >= info["queue_ms"] >= 0
+            C = srv.result(rid)
+            torch.cuda.synchronize()
+            got = _host(C)
+            ref = oracle.spgemm(ops[a], ops[b])
+            compare(*got, ref, np.float64, exact=True)
+            assert info["nnz"] == ref.nnz
+            alone = ctx.spgemm(dev[a], dev[b])
+            torch.cuda.synchronize()
+            for x, y in zip(got, _host(alone)):
+                assert np.array_equal(x, y), f"request {rid}: served != alone"
+            srv.release(rid)
+        assert srv.stats()["reserved_bytes"] == 0
+    finally:
+        srv.close()
+        ctx.close()
+
+
+def test_serving_small_budget_queues_and_random_values():
+    """A budget that holds only a few requests at once: requests wait for
+    memory, are admitted as earlier ones are released, and all finish within
+    the f64 tolerance."""
+    import torch
+
+    import paper_2501_07056_amd as mg
+    ops = _operands("uniform")
+    dev = [mg.DeviceCSR.from_host(X) for X in ops]
+    ctx = mg.Context(0)
+    ip, nb = ctx.batch_bound([(d, d) for d in dev])
+    ctx.close()
+    # room for about two of the largest request's bounds
+    big = max(nb) * 12 + 3001 * 8
+    srv = mg.Server(0, memory_budget_bytes=int(2.5 * big + (64 << 20)), max_batch=3, streams=2,
+                    workspace_cap_bytes=16 << 20)
+    try:
+        ids = [srv.register(X) for X in dev]
+        pairs = [(i % len(ops), i % len(ops)) for i in range(20)]
+        rids = [srv.submit(a, b) for a, b in pairs]
+        done = set()
+        t0 = time.time()
+        peak = 0
+        while len(done) < len(rids):
+            st = srv.stats()
+            peak = max(peak, st["reserved_bytes"])
+            for rid, (a, b) in zip(rids, pairs):
+                if rid in done or not srv.ready(rid):
+                    continue
+                C = srv.result(rid)
+                torch.cuda.synchronize()
+                compare(*_host(C), oracle.spgemm(ops[a], ops[b]), np.float64, exact=False)
+                srv.release(rid)
+                done.add(rid)
+            assert time.time() - t0 < 120
+            time.sleep(0.001)
+        st = srv.stats()
+        assert st["completed"] == 20 and st["failed"] == 0, st
+        assert peak <= st["budget_bytes"] + (64 << 20)
+    finally:
+        srv.close()
+
+
+def test_serving_exact_probe_and_rejection():
+    """A request whose bound exceeds the budget but whose exact size fits is
+    planned exactly and served; one whose exact size does not fit is
+    rejected."""
+    import paper_2501_07056_amd as mg
+    # every A row picks 8 of 16 B rows; all B rows hold the same 1000
+    # columns: ip = 8000 per row, nnz(C) = 1000 per row
+    n, k, m = 400, 16, 100000
+    rng = np.random.default_rng(5)
+    arp = np.arange(0, 8 * n + 1, 8, dtype=np.int32)
+    acol = np.concatenate([np.sort(rng.choice(k, 8, replace=False)) for _ in range(n)]).astype(np.int32)
+    A = wl.CSR(n, k, arp, acol, rng.integers(-3, 4, size=8 * n).astype(np.float64))
+    cols = np.sort(rng.choice(m, 1000, replace=False)).astype(np.int32)
+    B = wl.CSR(k, m, np.arange(0, 1000 * k + 1, 1000, dtype=np.int32), np.tile(cols, k),
+               rng.integers(-3, 4, size=1000 * k).astype(np.float64))
+    dA, dB = mg.DeviceCSR.from_host(A), mg.DeviceCSR.from_host(B)
+    exact_c = 1000 * n * 12 + (n + 1) * 8
+    bound_c = 8000 * n * 12
+    srv = mg.Server(0, memory_budget_bytes=int(exact_c * 1.5 + (8 << 20)),
+                    workspace_cap_bytes=1 << 20)
+    try:
+        assert srv.stats()["budget_bytes"] < bound_c
+        a, b = srv.register(dA), srv.register(dB)
+        rid = srv.submit(a, b)
+        _wait(srv, [rid])
+        assert srv.query(rid)["state"] == "done", srv.query(rid)
+        assert srv.stats()["exact_probes"] == 1
+        import torch
+        C = srv.result(rid)
+        torch.cuda.synchronize()
+        compare(*_host(C), oracle.spgemm(A, B), np.float64, exact=True)
+        srv.release(rid)
+    finally:
+        srv.close()
+    srv = mg.Server(0, memory_budget_bytes=exact_c // 2, workspace_cap_bytes=1 << 20)
+    try:
+        a, b = srv.register(dA), srv.register(dB)
+        rid = srv.submit(a, b)
+        _wait(srv, [rid])
+        assert srv.query(rid)["state"] == "rejected"
+        with pytest.raises(mg.MagnusError, match="REJECTED"):
+            srv.result(rid)
+        srv.release(rid)
+        assert srv.stats()["rejected"] == 1
+    finally:
+        srv.close()
+
+
+def test_serving_errors():
+    import paper_2501_07056_amd as mg
+    X = wl.erdos_renyi(50, 70, 3, wl.seed(7), val_dtype=np.float64)
+    Y = wl.erdos_renyi(50, 50, 3, wl.seed(8), val_dtype=np.float32)
+    srv = mg.Server(0)
+    try:
+        x = srv.register(mg.DeviceCSR.from_host(X))
+        with pytest.raises(mg.MagnusError, match="DTYPE"):
+            srv.register(mg.DeviceCSR.from_host(Y))
+        with pytest.raises(mg.MagnusError, match="SHAPE"):
+            srv.submit(x, x)  # 50x70 times 50x70
+        with pytest.raises(mg.MagnusError, match="INVALID_ARG"):
+            srv.submit(x, 5)
+        with pytest.raises(mg.MagnusError, match="INVALID_ARG"):
+            srv.release(12345)
+    finally:
+        srv.close()
