@@ -484,7 +484,20 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   P->max_nb = (int64_t)(P->h_stats.range_cat[2] >> P->shift) + 2;
   P->nch = P->h_list_off[CLS_CHUNKED + 1] - P->h_list_off[CLS_CHUNKED];
   if (P->max_nb > 65535 && P->nch > 0) return cleanup(MAGNUS_ERR_INVALID_ARG);
-  if (P->nch > 0) SCHK(setup_chunked(P));
+  if (P->nch > 0) {
+    // the reorder kernels keep per-chunk counters of a row in LDS: shrink the
+    // tile if they and the staged tile do not fit
+    auto fits = [&](int tile) {
+      return bin_scatter2_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max &&
+             bin_scatter_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max;
+    };
+    while (P->tile > 256 && !fits(P->tile)) P->tile /= 2;
+    if (!fits(P->tile)) {
+      h->err = "too many chunks per row for the LDS: raise chunk_shift";
+      return cleanup(MAGNUS_ERR_INVALID_ARG);
+    }
+    SCHK(setup_chunked(P));
+  }
 
   // precise symbolic phase: exact nnz per row, then the row offsets of C
   PCHK(launch_fill_i64(P->crp, n + 1, 0, P->st));
