@@ -518,42 +518,63 @@ __global__ void k_bin_stats(ChunkGeom g, BatchArgs b, const int64_t* tab_off, in
 }
 
 // per row: dense chunks become single items; runs of small consecutive chunks
-// (<= 64 chunks, <= group_max products) become packed sort items
-__global__ void k_bin_group(ChunkGeom g, BatchArgs b, const int64_t* bin_cnt, int64_t dense_min,
-                            int64_t group_max, int64_t* dense_items, int64_t* sort_items,
-                            int32_t* item_counts, int64_t item_base) {
-  const int64_t k = b.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= b.k1) return;
-  const int64_t nbk = g.nb[k], bb = g.binBase[k];
+// (<= 64 chunks, <= group_max products) become packed sort items.  Each
+// thread walks its row's chunks twice: once to count its items, then (after
+// one reservation per wave on each item counter) to write them; per-item
+// atomics on the two counters would serialise across the whole grid.
+template <typename Emit>
+MG_INLINE void group_row(const int64_t* bin_cnt, int64_t bb, int64_t nbk, int64_t dense_min,
+                         int64_t group_max, Emit&& emit) {
   int64_t gs = -1, gn = 0, gc = 0;
   for (int64_t q = 0; q < nbk; ++q) {
     const int64_t cnt = bin_cnt[bb + q];
     if (cnt >= dense_min) {
       if (gs >= 0) {
-        const int idx = atomicAdd(&item_counts[1], 1);
-        sort_items[2 * (item_base + idx)] = gs;
-        sort_items[2 * (item_base + idx) + 1] = gn;
+        emit(1, gs, gn);
         gs = -1; gn = 0; gc = 0;
       }
-      const int idx = atomicAdd(&item_counts[0], 1);
-      dense_items[item_base + idx] = bb + q;
+      emit(0, bb + q, 1);
       continue;
     }
     if (gs >= 0 && (gc + cnt > group_max || gn >= 64)) {
-      const int idx = atomicAdd(&item_counts[1], 1);
-      sort_items[2 * (item_base + idx)] = gs;
-      sort_items[2 * (item_base + idx) + 1] = gn;
+      emit(1, gs, gn);
       gs = -1; gn = 0; gc = 0;
     }
     if (gs < 0) gs = bb + q;
     ++gn;
     gc += cnt;
   }
-  if (gs >= 0) {
-    const int idx = atomicAdd(&item_counts[1], 1);
-    sort_items[2 * (item_base + idx)] = gs;
-    sort_items[2 * (item_base + idx) + 1] = gn;
+  if (gs >= 0) emit(1, gs, gn);
+}
+
+__global__ void k_bin_group(ChunkGeom g, BatchArgs b, const int64_t* bin_cnt, int64_t dense_min,
+                            int64_t group_max, int64_t* dense_items, int64_t* sort_items,
+                            int32_t* item_counts, int64_t item_base) {
+  const int64_t k = b.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = k < b.k1;
+  const int64_t nbk = live ? g.nb[k] : 0, bb = live ? g.binBase[k] : 0;
+  int n[2] = {0, 0};
+  if (live)
+    group_row(bin_cnt, bb, nbk, dense_min, group_max,
+              [&](int kind, int64_t, int64_t) { ++n[kind]; });
+  int base[2];
+  for (int kind = 0; kind < 2; ++kind) {
+    const int inc = wave_incl_scan(n[kind]);
+    const int tot = __shfl(inc, MG_WAVE - 1, MG_WAVE);
+    int wb = 0;
+    if (lane() == 0 && tot > 0) wb = atomicAdd(&item_counts[kind], tot);
+    base[kind] = __shfl(wb, 0, MG_WAVE) + inc - n[kind];
   }
+  if (!live) return;
+  group_row(bin_cnt, bb, nbk, dense_min, group_max, [&](int kind, int64_t first, int64_t cnt) {
+    const int64_t idx = item_base + base[kind]++;
+    if (kind == 0) {
+      dense_items[idx] = first;
+    } else {
+      sort_items[2 * idx] = first;
+      sort_items[2 * idx + 1] = cnt;
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------

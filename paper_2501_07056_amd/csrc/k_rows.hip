@@ -21,12 +21,36 @@ MG_INLINE void wave_sync() {
 // ---------------------------------------------------------------------------
 // Setup: ip_i = sum over entries (i,j) of nnz(B_j); minc/maxc = smallest /
 // largest column over those B rows (B rows sorted); class of the row.
-// G lanes cooperate on one row.
+// G lanes cooperate on one row; rows with more than HEAVY_ENTRIES entries of
+// A are listed and set up by a workgroup each (k_rowinfo_heavy), so a few
+// very long rows do not hold the whole grid.
 // ---------------------------------------------------------------------------
+constexpr int64_t HEAVY_ENTRIES = 1024;
+
+// Category (Section 3.1) and class of a row from its products and range.
+MG_INLINE int row_class(int64_t s, int64_t range, int force, int64_t sort_max, int64_t dense_max,
+                        int& cat) {
+  if (s == 0) {
+    cat = 3;
+    return CLS_EMPTY;
+  }
+  int want = force;
+  if (want < 0) want = (s < sort_max) ? 0 : (range <= dense_max ? 1 : 2);
+  if (want == 0 && s > SORT_CAP) want = (range <= dense_max) ? 1 : 2;
+  if (want == 1 && range > dense_max) want = 2;
+  cat = want;
+  if (want == 0) {
+    int lg = 0;
+    while (((int64_t)1 << lg) < s) ++lg;
+    return lg;
+  }
+  return (want == 1) ? CLS_DENSE : CLS_CHUNKED;
+}
 template <typename RP, typename CI, bool BATCH>
 __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, ClassParams cp,
                                                  int64_t* ip, int64_t* minc, int64_t* maxc,
-                                                 int32_t* cls, DevStats* stats, int32_t* flags) {
+                                                 int32_t* cls, DevStats* stats, int32_t* flags,
+                                                 int32_t* heavy) {
   // grid-stride over groups of G lanes per row; the statistics of all rows a
   // block visits are combined in LDS and added to the global totals once per
   // block (a global atomic per block on a handful of addresses would
@@ -59,6 +83,11 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
       const CI* bcol = (const CI*)M.bcol;
       const int64_t p0 = arp[lrow], p1 = arp[lrow + 1];
       nent = p1 - p0;
+      if (!BATCH && nent > HEAVY_ENTRIES) {
+        // the whole group skips this row; one lane lists it
+        if (sub == 0) heavy[atomicAdd(&stats->heavy, 1ull)] = (int32_t)row;
+        continue;
+      }
       for (int64_t p = p0 + sub; p < p1; p += G) {
         const int64_t j = acol[p];
         const int64_t b0 = brp[j], b1 = brp[j + 1];
@@ -78,28 +107,14 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
       mx = b > mx ? b : mx;
     }
     if (row < n && sub == 0) {
-      int c, cat;
+      int cat;
       const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
+      const int c = row_class(s, range, cp.force, sort_max, dense_max, cat);
       if (s == 0) {
-        c = CLS_EMPTY;
         mn = 0;
         mx = -1;
-        cat = 3;
-      } else {
-        int want = cp.force;
-        if (want < 0) want = (s < sort_max) ? 0 : (range <= dense_max ? 1 : 2);
-        if (want == 0 && s > SORT_CAP) want = (range <= dense_max) ? 1 : 2;
-        if (want == 1 && range > dense_max) want = 2;
-        if (BATCH && want == 2 && flags[b] == 0) flags[b] = 1;  // idempotent store
-        if (want == 0) {
-          int lg = 0;
-          while (((int64_t)1 << lg) < s) ++lg;
-          c = lg;
-        } else {
-          c = (want == 1) ? CLS_DENSE : CLS_CHUNKED;
-        }
-        cat = want;
       }
+      if (BATCH && cat == 2 && flags[b] == 0) flags[b] = 1;  // idempotent store
       ip[row] = s;
       minc[row] = mn;
       maxc[row] = mx;
@@ -137,6 +152,72 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
     }
     for (int k = 0; k < 3; ++k)
       if (sh[18 + k]) atomicMax(&stats->range_cat[k], sh[18 + k]);
+  }
+}
+
+// Setup of the listed long rows: one workgroup per row (grid-stride over the
+// list, whose length the first kernel left in stats->heavy).
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(256) k_rowinfo_heavy(RowSrc src, ClassParams cp,
+                                                       const int32_t* __restrict__ heavy,
+                                                       int64_t* ip, int64_t* minc, int64_t* maxc,
+                                                       int32_t* cls, DevStats* stats) {
+  __shared__ int64_t sh_s[4], sh_mn[4], sh_mx[4];
+  const unsigned long long nh = stats->heavy;
+  const RP* arp = (const RP*)src.one.arp;
+  const CI* acol = (const CI*)src.one.acol;
+  const RP* brp = (const RP*)src.one.brp;
+  const CI* bcol = (const CI*)src.one.bcol;
+  const int w = threadIdx.x / MG_WAVE;
+  for (unsigned long long h = blockIdx.x; h < nh; h += gridDim.x) {
+    const int32_t row = heavy[h];
+    const int64_t p0 = arp[row], p1 = arp[row + 1];
+    int64_t s = 0, mn = INT64_MAX, mx = -1;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      const int64_t j = acol[p];
+      const int64_t b0 = brp[j], b1 = brp[j + 1];
+      if (b1 > b0) {
+        s += b1 - b0;
+        const int64_t f = bcol[b0], l = bcol[b1 - 1];
+        mn = f < mn ? f : mn;
+        mx = l > mx ? l : mx;
+      }
+    }
+    s = wave_sum(s);
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane() == 0) {
+      sh_s[w] = s;
+      sh_mn[w] = mn;
+      sh_mx[w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int v = 1; v < (int)(blockDim.x / MG_WAVE); ++v) {
+        s += sh_s[v];
+        mn = sh_mn[v] < mn ? sh_mn[v] : mn;
+        mx = sh_mx[v] > mx ? sh_mx[v] : mx;
+      }
+      int cat;
+      const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
+      const int c = row_class(s, range, cp.force, cp.sort_max, cp.dense_max, cat);
+      if (s == 0) {
+        mn = 0;
+        mx = -1;
+      }
+      ip[row] = s;
+      minc[row] = mn;
+      maxc[row] = mx;
+      cls[row] = c;
+      atomicAdd(&stats->ip_total, (unsigned long long)s);
+      atomicMax(&stats->max_ip, (unsigned long long)s);
+      atomicMax(&stats->max_range, (unsigned long long)range);
+      atomicAdd(&stats->ip_cat[cat], (unsigned long long)s);
+      atomicAdd(&stats->rows_cat[cat], 1ull);
+      atomicAdd(&stats->ent_cat[cat], (unsigned long long)(p1 - p0));
+      if (cat < 3) atomicMax(&stats->range_cat[cat], (unsigned long long)range);
+    }
+    __syncthreads();
   }
 }
 
@@ -476,14 +557,18 @@ static int rowinfo_lanes(int64_t n, int64_t a_nnz) {
 
 hipError_t launch_rowinfo(const Mats& M, int64_t a_nnz, const ClassParams& cp, int64_t* ip,
                           int64_t* minc, int64_t* maxc, int32_t* cls, DevStats* stats,
-                          hipStream_t st) {
+                          int32_t* heavy, hipStream_t st) {
   if (M.n == 0) return hipSuccess;
   const int G = rowinfo_lanes(M.n, a_nnz);
   const int64_t want = (M.n * G + 255) / 256;
   const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
   const RowSrc src = single_src(M, nullptr, nullptr);
-  MG_DISPATCH2(M, hipLaunchKernelGGL((k_rowinfo<RP, CI, false>), grid, 256, 0, st, src, M.n, G,
-                                     cp, ip, minc, maxc, cls, stats, nullptr));
+  MG_DISPATCH2(M, {
+    hipLaunchKernelGGL((k_rowinfo<RP, CI, false>), grid, 256, 0, st, src, M.n, G, cp, ip, minc,
+                       maxc, cls, stats, nullptr, heavy);
+    hipLaunchKernelGGL((k_rowinfo_heavy<RP, CI>), 1024, 256, 0, st, src, cp, heavy, ip, minc,
+                       maxc, cls, stats);
+  });
   return hipGetLastError();
 }
 
@@ -495,7 +580,7 @@ hipError_t launch_rowinfo_batch(const Mats& T, const RowSrc& src, int64_t nrows,
   const int64_t want = (nrows * G + 255) / 256;
   const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
   MG_DISPATCH2(T, hipLaunchKernelGGL((k_rowinfo<RP, CI, true>), grid, 256, 0, st, src, nrows, G,
-                                     cp, ip, minc, maxc, cls, stats, flags));
+                                     cp, ip, minc, maxc, cls, stats, flags, nullptr));
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct DevStats {
   unsigned long long ent_cat[4];   // A entries of the rows of each category
   unsigned long long nnz_cat[4];   // nnz of C in the rows of each category
   unsigned long long range_cat[3]; // widest column range among SORT, DENSE, CHUNKED rows
+  unsigned long long heavy;        // rows deferred to the long-row setup kernel
   unsigned int err;  // bit flags, see ERR_*
   unsigned int pad;
 };
@@ -74,9 +75,11 @@ hipError_t scan_excl_i32(const int32_t* in, int64_t* out, int64_t n, int64_t* to
                          const int64_t* carry, void* temp, hipStream_t st);
 
 // --- row level (k_rows.hip) ---
+// heavy: scratch of M.n int32 (rows with many A entries are listed there and
+// set up by a workgroup each)
 hipError_t launch_rowinfo(const Mats& M, int64_t a_nnz, const ClassParams& cp, int64_t* ip,
                           int64_t* minc, int64_t* maxc, int32_t* cls, DevStats* stats,
-                          hipStream_t st);
+                          int32_t* heavy, hipStream_t st);
 hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats* stats,
                            hipStream_t st);
 // Stable partition of rows by class: list (int32 row ids) and list_off[NCLS+1].

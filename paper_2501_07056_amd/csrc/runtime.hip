@@ -415,8 +415,8 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   P->group_max = o.sort_group_max > 0 ? std::min<int64_t>(o.sort_group_max, SORT_CAP) : SORT_CAP;
   P->dense_min = o.bin_dense_min > 0 ? o.bin_dense_min : P->group_max;
   if (P->dense_min > P->group_max + 1) P->dense_min = P->group_max + 1;
-  P->tile = o.tile_products > 0 ? o.tile_products : 2048;
-  if (P->tile < 256 || P->tile > 16384 || (P->tile & (P->tile - 1))) P->tile = 2048;
+  P->tile = o.tile_products > 0 ? o.tile_products : 1024;
+  if (P->tile < 256 || P->tile > 16384 || (P->tile & (P->tile - 1))) P->tile = 1024;
   P->dense_block = (o.dense_block == 512 || o.dense_block == 1024) ? o.dense_block : 256;
   P->hints = o.stream_hints & 7;
   {
@@ -473,7 +473,8 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     ProfScope ps(h, P->st, "rowinfo (setup)",
                  (double)(n + 1) * P->s_rp + (double)A->nnz * (3 * P->s_col + 2 * P->s_rp) +
                      (double)n * 28);
-    PCHK(launch_rowinfo(M, A->nnz, cp, P->ip, P->minc, P->maxc, P->cls, P->stats, P->st));
+    PCHK(launch_rowinfo(M, A->nnz, cp, P->ip, P->minc, P->maxc, P->cls, P->stats, P->list,
+                        P->st));
   }
   PCHK(launch_classify(P->cls, n, P->list, P->list_off, P->temp, P->st));
   SCHK(readback(P, {{P->stats, sizeof(DevStats)}, {P->list_off, sizeof(int64_t) * (NCLS + 1)}},
@@ -625,14 +626,16 @@ magnus_status_t magnus_row_ip(magnus_handle_t h, const magnus_csr_t* A, const ma
   int64_t* minc = (int64_t*)palloc(&tmp, sizeof(int64_t) * std::max<int64_t>(n, 1));
   int64_t* maxc = (int64_t*)palloc(&tmp, sizeof(int64_t) * std::max<int64_t>(n, 1));
   int32_t* cls = (int32_t*)palloc(&tmp, sizeof(int32_t) * std::max<int64_t>(n, 1));
+  int32_t* heavy = (int32_t*)palloc(&tmp, sizeof(int32_t) * std::max<int64_t>(n, 1));
   DevStats* stats = (DevStats*)palloc(&tmp, sizeof(DevStats));
-  if (!minc || !maxc || !cls || !stats) {
+  if (!minc || !maxc || !cls || !heavy || !stats) {
     plan_free_all(&tmp);
     return MAGNUS_ERR_OOM;
   }
   ClassParams cp{SORT_CAP + 1, 1 << 13, -1};
   hipError_t e = hipMemsetAsync(stats, 0, sizeof(DevStats), tmp.st);
-  if (e == hipSuccess) e = launch_rowinfo(M, A->nnz, cp, ip_out, minc, maxc, cls, stats, tmp.st);
+  if (e == hipSuccess)
+    e = launch_rowinfo(M, A->nnz, cp, ip_out, minc, maxc, cls, stats, heavy, tmp.st);
   DevStats hs{};
   magnus_status_t r = MAGNUS_OK;
   if (e != hipSuccess) r = fail_hip(h, e, "launch_rowinfo");
