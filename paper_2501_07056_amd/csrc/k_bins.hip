@@ -11,6 +11,7 @@
 // tile) gives every tile a private, contiguous destination inside every chunk,
 // so the reorder needs no global atomics and is deterministic.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -181,68 +182,93 @@ __global__ void k_tile_e0(const RP* __restrict__ arp, ChunkGeom g, const int32_t
 // column and prod = a_ij * b_jk (only when WANT_VAL).  The A entries
 // overlapping the range are staged in LDS in windows of BS entries (their
 // product offsets relative to p0, B row starts, A values); threads take
-// products striped by BS, so the B loads of a wave are contiguous, and each
-// thread advances its owning entry incrementally (one LDS read per product
-// while it stays inside the same B row, a binary search when it jumps).  Four
-// products per thread are gathered before any is used.
+// products striped by BS, so the B loads of a wave are contiguous.  The
+// window's products are taken in super-chunks of 16*BS: first the A entry
+// holding the first product of every group of 64 products is recorded
+// (each entry marks the group starts inside its own product range), then a
+// product's entry is found by a binary search between the entries of its
+// group's start and the next group's start (0 steps inside long B rows, a
+// few for short ones).  Four products per thread are gathered before any is
+// used.  Offsets into B are 32-bit when B's row pointers are.
 template <int BS, typename RP, typename CI, typename V, bool WANT_VAL, typename F>
 MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
                                const CI* __restrict__ acol, const V* __restrict__ aval,
                                const RP* __restrict__ brp, const CI* __restrict__ bcol,
                                const V* __restrict__ bval, const int64_t* __restrict__ aoff,
                                int32_t* w_pre, int64_t* w_b0, V* w_av, F&& f) {
-  // offsets relative to p0 fit 32 bits: the range spans < 2^31 products and a
-  // B row holds < 2^31 entries
+  using OFF = typename std::conditional<sizeof(RP) == 4, int32_t, int64_t>::type;
+  constexpr int SC = 16 * BS;            // products per super-chunk
+  constexpr int NG = SC / MG_WAVE;       // groups of 64 products per super-chunk
+  __shared__ int32_t s_grp[NG + 1];
+  OFF* w_off = (OFF*)w_b0;
   const int t = threadIdx.x;
+  // offsets relative to p0 fit 32 bits: the range spans < 2^31 products
   const int32_t span = (int32_t)(p1 - p0);
   for (int64_t eb = e0; eb < a1; eb += BS) {
     const int64_t e = eb + t;
     int64_t pre = INT32_MAX;
-    int64_t b0 = 0;
+    OFF b0 = 0;
     V av = (V)0;
     if (e < a1) {
       pre = aoff[e] - p0;
       if (pre > INT32_MAX) pre = INT32_MAX;
       const int64_t j = acol[e];
-      b0 = brp[j];
+      b0 = (OFF)brp[j];
       if (WANT_VAL) av = aval[e];
     }
     w_pre[t] = (int32_t)pre;
-    w_b0[t] = b0;
+    w_off[t] = b0;
     if (WANT_VAL) w_av[t] = av;
     const int nvalid = (int)((a1 - eb) < BS ? (a1 - eb) : BS);
     __syncthreads();
     const int32_t wstart = w_pre[0] > 0 ? w_pre[0] : 0;
-    int64_t we = (eb + BS < a1) ? (aoff[eb + BS] - p0) : (int64_t)span;
+    const int64_t we = (eb + BS < a1) ? (aoff[eb + BS] - p0) : (int64_t)span;
     const int32_t wend = (int32_t)(we < span ? we : span);
-    int k = -1;
-    for (int32_t qb = wstart + t; qb < wend; qb += 4 * BS) {
-      int64_t bi[4];
+    for (int32_t s0 = wstart; s0 < wend; s0 += SC) {
+      const int32_t s1 = (wend - s0 < SC) ? wend : s0 + SC;
+      // the entry holding each group start s0 + 64 G (entries partition the
+      // products; empty entries hold none)
+      if (t < nvalid) {
+        int32_t lo = w_pre[t] > s0 ? w_pre[t] : s0;
+        int32_t hi = (t + 1 < nvalid) ? w_pre[t + 1] : wend;
+        hi = hi < s1 ? hi : s1;
+        for (int32_t G = (lo - s0 + MG_WAVE - 1) / MG_WAVE; s0 + G * MG_WAVE < hi; ++G)
+          s_grp[G] = t;
+      }
+      if (t == 0) s_grp[NG] = nvalid - 1;
+      __syncthreads();
+      const int32_t ngr = (s1 - s0 + MG_WAVE - 1) / MG_WAVE;
+      for (int32_t qb = s0 + t; qb < s1; qb += 4 * BS) {
+      OFF bi[4];
       V a4[4];
       bool ok[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int32_t q = qb + u * BS;
-        ok[u] = q < wend;
+        ok[u] = q < s1;
         bi[u] = 0;
         a4[u] = (V)0;
         if (ok[u]) {
-          if (k < 0 || (k + 1 < nvalid && w_pre[k + 1] <= q))
-            k = upper_index(w_pre, k < 0 ? 0 : k + 1, nvalid, q);
-          bi[u] = w_b0[k] + (int64_t)(q - w_pre[k]);
+          const int G = (q - s0) / MG_WAVE;
+          const int klo = s_grp[G];
+          const int khi = (G + 1 < ngr) ? s_grp[G + 1] : s_grp[NG];
+          const int k = (khi > klo) ? upper_index(w_pre, klo, khi + 1, q) : klo;
+          bi[u] = w_off[k] + (OFF)(q - w_pre[k]);
           if (WANT_VAL) a4[u] = w_av[k];
         }
       }
-      int64_t c4[4];
+      CI c4[4];
       V v4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        c4[u] = ok[u] ? (int64_t)bcol[bi[u]] : 0;
+        c4[u] = ok[u] ? bcol[bi[u]] : (CI)0;
         if (WANT_VAL) v4[u] = ok[u] ? a4[u] * bval[bi[u]] : (V)0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (ok[u]) f(qb + u * BS, c4[u], WANT_VAL ? v4[u] : (V)0);
+      }
+      __syncthreads();
     }
     __syncthreads();
     if (wend >= span) break;
@@ -268,8 +294,8 @@ __global__ void __launch_bounds__(BIN_BS)
   __syncthreads();
   expand_products<BIN_BS, RP, CI, float, false>(
       c.p0, c.p1, c.e0, c.a1, acol, (const float*)nullptr, brp, bcol, (const float*)nullptr, aoff,
-      w_pre, w_b0, (float*)nullptr, [&](int32_t, int64_t col, float) {
-        const uint32_t bin = (uint32_t)((col >> g.shift) - c.base_bin);
+      w_pre, w_b0, (float*)nullptr, [&](int32_t, CI col, float) {
+        const uint32_t bin = (uint32_t)(col >> g.shift) - (uint32_t)c.base_bin;
         int hl, len;
         wave_run(bin, hl, len);
         if (lane() == hl) atomicAdd(&hist[bin], len);
@@ -340,10 +366,10 @@ __global__ void __launch_bounds__(BIN_BS)
   const int64_t lmask = ((int64_t)1 << g.shift) - 1;
   expand_products<BIN_BS, RP, CI, V, NUMERIC>(
       c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
-      [&](int32_t, int64_t col, V pv) {
-        const int bin = (int)((col >> g.shift) - c.base_bin);
+      [&](int32_t, CI col, V pv) {
+        const int bin = (int)((uint32_t)(col >> g.shift) - (uint32_t)c.base_bin);
         const int pos = loc[bin] + atomicAdd(&cur[bin], 1);
-        st_col[pos] = (uint16_t)(col & lmask);
+        st_col[pos] = (uint16_t)((uint32_t)col & (uint32_t)lmask);
         st_bin[pos] = (uint16_t)bin;
         if (NUMERIC) st_val[pos] = pv;
       });
@@ -373,7 +399,8 @@ constexpr int RB_BS = 1024;
 
 size_t row_bitmap_lds(int shift, int64_t max_nb) {
   const size_t words = ((size_t)max_nb << shift) / 32;
-  return words * 4 + (size_t)max_nb * 4 + RB_BS * 16 + 64;
+  // + static LDS of the expansion (group owners) and the row total
+  return words * 4 + (size_t)max_nb * 4 + RB_BS * 16 + 64 + 1024;
 }
 
 template <typename RP, typename CI>
@@ -400,8 +427,8 @@ __global__ void __launch_bounds__(RB_BS)
   const int64_t a0 = arp[row], a1 = arp[row + 1];
   expand_products<RB_BS, RP, CI, float, false>(
       0, g.ip[row], a0, a1, acol, (const float*)nullptr, brp, bcol, (const float*)nullptr, aoff,
-      w_pre, w_b0, (float*)nullptr, [&](int32_t, int64_t col, float) {
-        const uint32_t lc = (uint32_t)(col - base);
+      w_pre, w_b0, (float*)nullptr, [&](int32_t, CI col, float) {
+        const uint32_t lc = (uint32_t)col - (uint32_t)base;
         atomicOr(&bits[lc >> 5], 1u << (lc & 31));
         const uint32_t bin = lc >> sh;
         int hl, len;
@@ -467,14 +494,14 @@ __global__ void __launch_bounds__(BIN_BS)
   // this tile's run of that chunk
   expand_products<BIN_BS, RP, CI, V, true>(
       c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
-      [&](int32_t q, int64_t col, V pv) {
-        const uint32_t bin = (uint32_t)((col >> g.shift) - c.base_bin);
+      [&](int32_t q, CI col, V pv) {
+        const uint32_t bin = (uint32_t)(col >> g.shift) - (uint32_t)c.base_bin;
         int hl, len;
         wave_run(bin, hl, len);
         int r = 0;
         if (lane() == hl) r = atomicAdd(&hist[bin], len);
         r = __shfl(r, hl, MG_WAVE);
-        u_word[q] = (bin << 16) | (uint32_t)(col & lmask);
+        u_word[q] = (bin << 16) | ((uint32_t)col & (uint32_t)lmask);
         u_rank[q] = (uint32_t)(r + (lane() - hl));
         u_val[q] = pv;
       });
