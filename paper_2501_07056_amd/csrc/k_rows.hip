@@ -65,23 +65,25 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
   for (int64_t rb = (int64_t)blockIdx.x * groups_per_block; rb < n;
        rb += (int64_t)gridDim.x * groups_per_block) {
     const int64_t row = rb + threadIdx.x / G;
-    int64_t s = 0, mn = INT64_MAX, mx = -1, nent = 0;
+    int64_t s = 0, mn = INT64_MAX, mx = -1, nent = 0, p0 = 0, p1 = 0, mcols = 0;
     int32_t b = 0;
     int64_t sort_max = cp.sort_max, dense_max = cp.dense_max;
+    const MatEnt* Mp = &src.one;
     if (row < n) {
       // a batch: the row's product from the per-row table
-      if (BATCH) b = src.mat_of_row[row];
-      const MatEnt& M = BATCH ? src.tab[b] : src.one;
-      const int64_t lrow = row - (BATCH ? M.row0 : 0);
       if (BATCH) {
-        sort_max = M.sort_max;
-        dense_max = M.dense_max;
+        b = src.mat_of_row[row];
+        Mp = &src.tab[b];
+        sort_max = Mp->sort_max;
+        dense_max = Mp->dense_max;
       }
-      const RP* arp = (const RP*)M.arp;
-      const CI* acol = (const CI*)M.acol;
-      const RP* brp = (const RP*)M.brp;
-      const CI* bcol = (const CI*)M.bcol;
-      const int64_t p0 = arp[lrow], p1 = arp[lrow + 1];
+      const int64_t lrow = row - (BATCH ? Mp->row0 : 0);
+      const RP* arp = (const RP*)Mp->arp;
+      const CI* acol = (const CI*)Mp->acol;
+      const RP* brp = (const RP*)Mp->brp;
+      mcols = Mp->mcols;
+      p0 = arp[lrow];
+      p1 = arp[lrow + 1];
       nent = p1 - p0;
       if (!BATCH && nent > HEAVY_ENTRIES) {
         // the whole group skips this row; one lane lists it
@@ -90,9 +92,22 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
       }
       for (int64_t p = p0 + sub; p < p1; p += G) {
         const int64_t j = acol[p];
+        s += (int64_t)brp[j + 1] - (int64_t)brp[j];
+      }
+    }
+    for (int d = G >> 1; d >= 1; d >>= 1) s += __shfl_xor(s, d, G);
+    // the column range (first and last column of every B row: two more
+    // gathers per entry) only where the category depends on it; SORT rows
+    // key their products on the full column (range = the columns of C)
+    const bool need = row < n && s > 0 && (cp.force > 0 || s >= sort_max || s > SORT_CAP);
+    if (need) {
+      const CI* acol = (const CI*)Mp->acol;
+      const RP* brp = (const RP*)Mp->brp;
+      const CI* bcol = (const CI*)Mp->bcol;
+      for (int64_t p = p0 + sub; p < p1; p += G) {
+        const int64_t j = acol[p];
         const int64_t b0 = brp[j], b1 = brp[j + 1];
         if (b1 > b0) {
-          s += b1 - b0;
           const int64_t f = bcol[b0], l = bcol[b1 - 1];
           mn = f < mn ? f : mn;
           mx = l > mx ? l : mx;
@@ -100,11 +115,14 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
       }
     }
     for (int d = G >> 1; d >= 1; d >>= 1) {
-      s += __shfl_xor(s, d, G);
       const int64_t a = __shfl_xor(mn, d, G);
-      const int64_t b = __shfl_xor(mx, d, G);
+      const int64_t c2 = __shfl_xor(mx, d, G);
       mn = a < mn ? a : mn;
-      mx = b > mx ? b : mx;
+      mx = c2 > mx ? c2 : mx;
+    }
+    if (!need && s > 0) {
+      mn = 0;
+      mx = mcols - 1;
     }
     if (row < n && sub == 0) {
       int cat;
