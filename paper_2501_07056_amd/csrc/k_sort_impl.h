@@ -111,13 +111,47 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
       if (l == 0) atomicOr(&stats->err, ERR_STAGE_OVERFLOW);
       return;
     }
-    for (int q = l; q < tot; q += MG_WAVE) {
-      const int k = upper_index(s_pre[w], 0, nvalid, q);
-      const int off = q - s_pre[w][k];
-      const int64_t col = s_bcolp[w][k][off];
-      const int s = s_wslot[w][k];
-      s_key[w][P + q] = ((K)s << colbits) | (K)(col - s_minc[w][s]);
-      if (NUMERIC) s_val[w][P + q] = s_av[w][k] * s_bvalp[w][k][off];
+    // four products per lane are located, then loaded, then staged, so
+    // their loads are in flight together
+    for (int qb = l; qb < tot; qb += 4 * MG_WAVE) {
+      const CI* cp4[4];
+      const V* vp4[4];
+      V a4[4];
+      int s4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = qb + u * MG_WAVE;
+        cp4[u] = nullptr;
+        vp4[u] = nullptr;
+        a4[u] = (V)0;
+        s4[u] = 0;
+        if (q < tot) {
+          const int k = upper_index(s_pre[w], 0, nvalid, q);
+          const int off = q - s_pre[w][k];
+          cp4[u] = s_bcolp[w][k] + off;
+          if (NUMERIC) {
+            vp4[u] = s_bvalp[w][k] + off;
+            a4[u] = s_av[w][k];
+          }
+          s4[u] = s_wslot[w][k];
+        }
+      }
+      CI c4[4];
+      V v4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = qb + u * MG_WAVE < tot;
+        c4[u] = ok ? *cp4[u] : (CI)0;
+        if (NUMERIC) v4[u] = ok ? *vp4[u] : (V)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = qb + u * MG_WAVE;
+        if (q < tot) {
+          s_key[w][P + q] = ((K)s4[u] << colbits) | (K)((int64_t)c4[u] - s_minc[w][s4[u]]);
+          if (NUMERIC) s_val[w][P + q] = a4[u] * v4[u];
+        }
+      }
     }
     P += tot;
     wave_sync();
