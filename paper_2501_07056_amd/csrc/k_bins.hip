@@ -29,7 +29,7 @@ MG_INLINE void wave_sync2() {
 // ---------------------------------------------------------------------------
 __global__ void k_chunk_geom(const int32_t* rows, const int64_t* ip, const int64_t* minc,
                              const int64_t* maxc, int64_t nch, int shift, int tile, int64_t* nb,
-                             int64_t* nt, int64_t* tabsz, int64_t* ipr) {
+                             int64_t* nt, int64_t* ipr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch) return;
   const int32_t r = rows[k];
@@ -37,7 +37,6 @@ __global__ void k_chunk_geom(const int32_t* rows, const int64_t* ip, const int64
   const int64_t t = (ip[r] + tile - 1) / tile;
   nb[k] = b;
   nt[k] = t;
-  tabsz[k] = b * t;
   ipr[k] = ip[r];
 }
 
@@ -45,24 +44,23 @@ hipError_t launch_chunk_geom(const ChunkGeom& g, hipStream_t st) {
   // ipBase doubles as the per-row ip input of its own scan (in place)
   if (g.nch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_chunk_geom, (unsigned)((g.nch + 255) / 256), 256, 0, st, g.rows, g.ip,
-                     g.minc, g.maxc, g.nch, g.shift, g.tile, g.nb, g.nt, g.tabsz, g.ipBase);
+                     g.minc, g.maxc, g.nch, g.shift, g.tile, g.nb, g.nt, g.ipBase);
   return hipGetLastError();
 }
 
 // first_of[s] = first CHUNKED row whose product range starts in [s*W, (s+1)*W)
-// bases[s*4 + {0,1,2,3}] = ipBase, tileBase, tabBase, binBase at that row
+// bases[s*3 + {0,1,2}] = ipBase, tileBase, binBase at that row
 __global__ void k_batch_bounds(const int64_t* ipBase, const int64_t* tileBase,
-                               const int64_t* tabBase, const int64_t* binBase, int64_t nch,
-                               int64_t W, int32_t* first_of, int64_t* bases) {
+                               const int64_t* binBase, int64_t nch, int64_t W, int32_t* first_of,
+                               int64_t* bases) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch) return;
   const int64_t s = ipBase[k] / W;
   if (k == 0 || ipBase[k - 1] / W != s) {
     first_of[s] = (int32_t)k;
-    bases[s * 4 + 0] = ipBase[k];
-    bases[s * 4 + 1] = tileBase[k];
-    bases[s * 4 + 2] = tabBase[k];
-    bases[s * 4 + 3] = binBase[k];
+    bases[s * 3 + 0] = ipBase[k];
+    bases[s * 3 + 1] = tileBase[k];
+    bases[s * 3 + 2] = binBase[k];
   }
 }
 
@@ -70,7 +68,7 @@ hipError_t launch_batch_bounds(const ChunkGeom& g, int64_t W, int32_t* first_of,
                                 hipStream_t st) {
   if (g.nch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_bounds, (unsigned)((g.nch + 255) / 256), 256, 0, st, g.ipBase,
-                     g.tileBase, g.tabBase, g.binBase, g.nch, W, first_of, bases);
+                     g.tileBase, g.binBase, g.nch, W, first_of, bases);
   return hipGetLastError();
 }
 
@@ -125,7 +123,7 @@ hipError_t launch_tiles(const int64_t* nt, const int64_t* tileBase, int64_t k0, 
 constexpr int BIN_BS = 256;
 
 struct TileCtx {
-  int64_t row, k, ti, p0, p1, a0, a1, e0, base_bin, nbk, ntk, tabk;
+  int64_t row, k, ti, p0, p1, a0, a1, e0, base_bin, nbk, ntk;
 };
 
 template <typename RP>
@@ -144,7 +142,6 @@ MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t*
   c.base_bin = g.minc[c.row] >> g.shift;
   c.nbk = g.nb[c.k];
   c.ntk = g.nt[c.k];
-  c.tabk = g.tabBase[c.k];
   if (tile_e0) {
     c.e0 = tile_e0[tg];
     return;
@@ -276,20 +273,23 @@ MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
 }
 
 // ---------------------------------------------------------------------------
-// Histogram pass: per tile, products per chunk.
+// Histogram pass: per tile, products per chunk, added into the chunk's total
+// (one global atomic per non-empty chunk of the tile); the first tile of a
+// row also records the row of each of its chunks.
 // ---------------------------------------------------------------------------
 template <typename RP, typename CI>
 __global__ void __launch_bounds__(BIN_BS)
     k_bin_hist(const RP* __restrict__ arp, const CI* __restrict__ acol, const RP* __restrict__ brp,
                const CI* __restrict__ bcol, ChunkGeom g, BatchArgs b,
                const int32_t* __restrict__ tile_row, const int64_t* __restrict__ aoff,
-               int32_t* tab_cnt) {
+               const int64_t* __restrict__ tile_e0, unsigned long long* bin_cnt,
+               int32_t* bin_row) {
   extern __shared__ __align__(16) unsigned char dsm[];
   int32_t* w_pre = (int32_t*)dsm;                        // BIN_BS
   int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);            // BIN_BS
   int32_t* hist = (int32_t*)(w_b0 + BIN_BS);               // nb
   TileCtx c;
-  tile_setup<RP>(g, b, tile_row, arp, aoff, c);
+  tile_setup<RP>(g, b, tile_row, arp, aoff, c, tile_e0);
   for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) hist[q] = 0;
   __syncthreads();
   expand_products<BIN_BS, RP, CI, float, false>(
@@ -301,90 +301,11 @@ __global__ void __launch_bounds__(BIN_BS)
         if (lane() == hl) atomicAdd(&hist[bin], len);
       });
   __syncthreads();
-  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS)
-    tab_cnt[c.tabk + q * c.ntk + c.ti] = hist[q];
-}
-
-// ---------------------------------------------------------------------------
-// Reorder pass: stage the tile's products in LDS grouped by chunk (counting
-// sort with the tile's own histogram), then copy each chunk's run to the
-// tile's slot of that chunk: contiguous, coalesced stores.
-// ---------------------------------------------------------------------------
-size_t bin_scatter_lds(int f64, int tile, int64_t max_nb) {
-  const size_t vs = f64 ? 8 : 4;
-  return BIN_BS * 8 * 3 + (size_t)max_nb * 8 + 16 + (size_t)tile * (2 + 2) + 16 +
-         (size_t)tile * vs + 16 + (size_t)max_nb * 8 + 64;
-}
-
-template <typename RP, typename CI, typename V, bool NUMERIC>
-__global__ void __launch_bounds__(BIN_BS)
-    k_bin_scatter(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
-                  const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
-                  ChunkGeom g, BatchArgs b, const int32_t* __restrict__ tile_row,
-                  const int64_t* __restrict__ aoff, const int32_t* __restrict__ tab_cnt,
-                  const int64_t* __restrict__ tab_off, uint16_t* ws_col, V* ws_val,
-                  DevStats* stats) {
-  extern __shared__ __align__(16) unsigned char dsm[];
-  int32_t* w_pre = (int32_t*)dsm;                     // BIN_BS
-  int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);       // BIN_BS
-  V* w_av = (V*)(w_b0 + BIN_BS);                      // BIN_BS
-  int32_t* loc = (int32_t*)((char*)w_av + BIN_BS * 8);  // nb (w_av padded to 8 B entries)
-  TileCtx c;
-  tile_setup<RP>(g, b, tile_row, arp, aoff, c);
-  int32_t* cur = loc + c.nbk;                          // nb
-  uint16_t* st_col = (uint16_t*)(((uintptr_t)(cur + c.nbk) + 15) & ~(uintptr_t)15);
-  uint16_t* st_bin = st_col + g.tile;
-  V* st_val = (V*)(((uintptr_t)(st_bin + g.tile) + 15) & ~(uintptr_t)15);
-  __shared__ int64_t sh_w[4];
-  __shared__ int64_t sh_tot;
-
-  // local chunk offsets = exclusive scan of this tile's counts
-  {
-    const int64_t per = (c.nbk + BIN_BS - 1) / BIN_BS;
-    const int64_t q0 = threadIdx.x * per;
-    int64_t s = 0;
-    for (int64_t q = q0; q < q0 + per && q < c.nbk; ++q) s += tab_cnt[c.tabk + q * c.ntk + c.ti];
-    const int64_t inc = wave_incl_scan(s);
-    const int wv = threadIdx.x / MG_WAVE;
-    if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
-    __syncthreads();
-    int64_t before = 0;
-    for (int v = 0; v < wv; ++v) before += sh_w[v];
-    if (threadIdx.x == BIN_BS - 1) sh_tot = before + inc;
-    int64_t run = before + inc - s;
-    for (int64_t q = q0; q < q0 + per && q < c.nbk; ++q) {
-      loc[q] = (int32_t)run;
-      cur[q] = 0;
-      run += tab_cnt[c.tabk + q * c.ntk + c.ti];
-    }
-  }
-  __syncthreads();
-  if (sh_tot != c.p1 - c.p0) {
-    if (threadIdx.x == 0) atomicOr(&stats->err, ERR_BIN_OVERFLOW);
-    return;
-  }
-  const int64_t lmask = ((int64_t)1 << g.shift) - 1;
-  expand_products<BIN_BS, RP, CI, V, NUMERIC>(
-      c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
-      [&](int32_t, CI col, V pv) {
-        const int bin = (int)((uint32_t)(col >> g.shift) - (uint32_t)c.base_bin);
-        const int pos = loc[bin] + atomicAdd(&cur[bin], 1);
-        st_col[pos] = (uint16_t)((uint32_t)col & (uint32_t)lmask);
-        st_bin[pos] = (uint16_t)bin;
-        if (NUMERIC) st_val[pos] = pv;
-      });
-  __syncthreads();
-  // cur[] is free now: reuse it (as int64 pairs would not fit) for the
-  // destination of each chunk relative to the staging index
-  int64_t* dst = (int64_t*)(((uintptr_t)(st_val + g.tile) + 15) & ~(uintptr_t)15);
-  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS)
-    dst[q] = tab_off[c.tabk + q * c.ntk + c.ti] - loc[q];
-  __syncthreads();
-  const int64_t nloc = c.p1 - c.p0;
-  for (int64_t s = threadIdx.x; s < nloc; s += BIN_BS) {
-    const int64_t d = dst[st_bin[s]] + s;
-    st_stream<HINT_WS_STORE>(&ws_col[d], st_col[s]);
-    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], st_val[s]);
+  const int64_t gb = g.binBase[c.k];
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) {
+    const int h = hist[q];
+    if (h > 0) atomicAdd(&bin_cnt[gb + q], (unsigned long long)h);
+    if (c.ti == 0) bin_row[gb + q] = (int32_t)c.k;
   }
 }
 
@@ -467,7 +388,7 @@ size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb) {
          (size_t)tile * vs + 64;
 }
 
-template <typename RP, typename CI, typename V>
+template <typename RP, typename CI, typename V, bool NUMERIC>
 __global__ void __launch_bounds__(BIN_BS)
     k_bin_scatter2(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
                    const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
@@ -492,7 +413,7 @@ __global__ void __launch_bounds__(BIN_BS)
   const int64_t lmask = ((int64_t)1 << g.shift) - 1;
   // gather once; the chunk counter's old value is the product's rank inside
   // this tile's run of that chunk
-  expand_products<BIN_BS, RP, CI, V, true>(
+  expand_products<BIN_BS, RP, CI, V, NUMERIC>(
       c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
       [&](int32_t q, CI col, V pv) {
         const uint32_t bin = (uint32_t)(col >> g.shift) - (uint32_t)c.base_bin;
@@ -503,7 +424,7 @@ __global__ void __launch_bounds__(BIN_BS)
         r = __shfl(r, hl, MG_WAVE);
         u_word[q] = (bin << 16) | ((uint32_t)col & (uint32_t)lmask);
         u_rank[q] = (uint32_t)(r + (lane() - hl));
-        u_val[q] = pv;
+        if (NUMERIC) u_val[q] = pv;
       });
   __syncthreads();
   // reserve each chunk's run inside its bin with one atomic add
@@ -521,29 +442,13 @@ __global__ void __launch_bounds__(BIN_BS)
     const uint32_t w = u_word[q];
     const int64_t d = dst[w >> 16] + u_rank[q];
     st_stream<HINT_WS_STORE>(&ws_col[d], (uint16_t)(w & 0xFFFFu));
-    st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
+    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Chunk start / size and work items
 // ---------------------------------------------------------------------------
-__global__ void k_bin_stats(ChunkGeom g, BatchArgs b, const int64_t* tab_off, int64_t* bin_start,
-                            int64_t* bin_cnt, int32_t* bin_row) {
-  const int64_t k = b.k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= b.k1) return;
-  const int64_t nbk = g.nb[k], ntk = g.nt[k], tb = g.tabBase[k], bb = g.binBase[k];
-  for (int64_t q = 0; q < nbk; ++q) {
-    const int64_t e = tb + q * ntk;
-    const int64_t e1 = e + ntk;
-    const int64_t s = tab_off[e];
-    const int64_t en = (e1 < b.tab0 + b.ntab) ? tab_off[e1] : b.nip;
-    bin_start[bb + q] = s;
-    bin_cnt[bb + q] = en - s;
-    bin_row[bb + q] = (int32_t)k;
-  }
-}
-
 // per row: dense chunks become single items; runs of small consecutive chunks
 // (<= 64 chunks, <= group_max products) become packed sort items.  Each
 // thread walks its row's chunks twice: once to count its items, then (after
@@ -877,8 +782,8 @@ hipError_t launch_aoff(const Mats& M, const int32_t* rows, int64_t nrows, int64_
 }
 
 hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
-                            const int32_t* tile_row, const int64_t* aoff, int32_t* tab_cnt,
-                            int64_t max_nb, hipStream_t st) {
+                            const int32_t* tile_row, const int64_t* aoff, const int64_t* tile_e0,
+                            int64_t* bin_cnt, int32_t* bin_row, int64_t max_nb, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
   const size_t lds = BIN_BS * 8 * 2 + (size_t)max_nb * 4 + 64;
   MG_DISPATCH2(M, {
@@ -886,44 +791,10 @@ hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,
                        (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, b, tile_row,
-                       aoff, tab_cnt);
+                       aoff, tile_e0, (unsigned long long*)bin_cnt, bin_row);
   });
   return hipGetLastError();
 }
-
-hipError_t launch_bin_scatter(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
-                               const int32_t* tile_row, const int64_t* aoff,
-                               const int32_t* tab_cnt, const int64_t* tab_off, uint16_t* ws_col,
-                               void* ws_val, int64_t max_nb, DevStats* stats, hipStream_t st) {
-  if (b.ntiles <= 0) return hipSuccess;
-  const size_t lds = bin_scatter_lds(M.f64, g.tile, max_nb);
-#define MG_SC(V)                                                                                   \
-  MG_DISPATCH2(M, {                                                                               \
-    auto kf = numeric ? k_bin_scatter<RP, CI, V, true> : k_bin_scatter<RP, CI, V, false>;          \
-    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
-    hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                  \
-                       (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,   \
-                       (const V*)M.bval, g, b, tile_row, aoff, tab_cnt, tab_off, ws_col,           \
-                       (V*)ws_val, stats);                                                         \
-  });
-  if (M.f64) { MG_SC(double) } else { MG_SC(float) }
-#undef MG_SC
-  return hipGetLastError();
-}
-
-hipError_t launch_bin_items(const ChunkGeom& g, const BatchArgs& b, const int64_t* tab_off,
-                             int64_t* bin_start, int64_t* bin_cnt, int32_t* bin_row,
-                             int64_t dense_min, int64_t group_max, int64_t* dense_items,
-                             int64_t* sort_items, int32_t* item_counts, hipStream_t st) {
-  const int64_t nr = b.k1 - b.k0;
-  if (nr <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((nr + 255) / 256);
-  hipLaunchKernelGGL(k_bin_stats, grid, 256, 0, st, g, b, tab_off, bin_start, bin_cnt, bin_row);
-  hipLaunchKernelGGL(k_bin_group, grid, 256, 0, st, g, b, (const int64_t*)bin_cnt, dense_min,
-                     group_max, dense_items, sort_items, item_counts, b.bin0);
-  return hipGetLastError();
-}
-
 hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric, int f64,
                              const int64_t* bin_start, const int64_t* bin_cnt,
                              const int32_t* bin_row, const int64_t* dense_items,
@@ -981,7 +852,7 @@ hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile
   return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
                                const int32_t* tile_row, const int64_t* aoff,
                                const int64_t* tile_e0, const int64_t* bin_start,
                                unsigned long long* bin_cursor, uint16_t* ws_col, void* ws_val,
@@ -990,7 +861,7 @@ hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArg
   const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb);
 #define MG_SC2(V)                                                                                 \
   MG_DISPATCH2(M, {                                                                               \
-    auto kf = k_bin_scatter2<RP, CI, V>;                                                          \
+    auto kf = numeric ? k_bin_scatter2<RP, CI, V, true> : k_bin_scatter2<RP, CI, V, false>;      \
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                 \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \

@@ -126,10 +126,8 @@ struct ChunkGeom {
   const int64_t* maxc;   // per-row max column (by row id)
   int64_t* nb;           // bins per row                      [nch]
   int64_t* nt;           // tiles per row                     [nch]
-  int64_t* tabsz;        // nb*nt                             [nch]
   int64_t* binBase;      // exclusive scan of nb              [nch+1]
   int64_t* tileBase;     // exclusive scan of nt              [nch+1]
-  int64_t* tabBase;      // exclusive scan of tabsz           [nch+1]
   int64_t* ipBase;       // exclusive scan of ip              [nch+1]
   int64_t nch;
   int shift;             // chunk length 2^shift
@@ -137,7 +135,7 @@ struct ChunkGeom {
   int hints;             // HINT_* bits: non-temporal access classes
 };
 hipError_t launch_chunk_geom(const ChunkGeom& g, hipStream_t st);
-// first_of[s] (int32, pre-filled with -1) and bases[4*s] for batch slots of W products
+// first_of[s] (int32, pre-filled with -1) and bases[3*s] for batch slots of W products
 hipError_t launch_batch_bounds(const ChunkGeom& g, int64_t W, int32_t* first_of, int64_t* bases,
                                hipStream_t st);
 // aoff of every A entry of the CHUNKED rows; ent[k] = A entries of row k
@@ -156,24 +154,15 @@ hipError_t launch_tiles(const int64_t* nt, const int64_t* tileBase, int64_t k0, 
 struct BatchArgs {
   int64_t k0, k1;          // CHUNKED list range of the batch
   int64_t tile0, ntiles;   // global tile range
-  int64_t tab0, ntab;      // global table range
   int64_t bin0, nbins;     // global bin range
   int64_t ip0, nip;        // global product range (batch workspace offset = ip - ip0)
   int64_t nent, nnz_out;   // A entries of the batch's rows; nnz of C they produce
 };
+// per-chunk product totals of a batch (bin_cnt zeroed before), and each
+// chunk's row
 hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
-                           const int32_t* tile_row, const int64_t* aoff, int32_t* tab_cnt,
-                           int64_t max_nb, hipStream_t st);
-hipError_t launch_bin_scatter(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
-                              const int32_t* tile_row, const int64_t* aoff, const int32_t* tab_cnt,
-                              const int64_t* tab_off, uint16_t* ws_col, void* ws_val,
-                              int64_t max_nb, DevStats* stats, hipStream_t st);
-size_t bin_scatter_lds(int f64, int tile, int64_t max_nb);
-// chunk start / size / row from the table; items: dense chunks and packed sort groups
-hipError_t launch_bin_items(const ChunkGeom& g, const BatchArgs& b, const int64_t* tab_off,
-                            int64_t* bin_start, int64_t* bin_cnt, int32_t* bin_row,
-                            int64_t dense_min, int64_t group_max, int64_t* dense_items,
-                            int64_t* sort_items, int32_t* item_counts, hipStream_t st);
+                            const int32_t* tile_row, const int64_t* aoff, const int64_t* tile_e0,
+                            int64_t* bin_cnt, int32_t* bin_row, int64_t max_nb, hipStream_t st);
 hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric, int f64,
                             const int64_t* bin_start, const int64_t* bin_cnt,
                             const int32_t* bin_row, const int64_t* dense_items,
@@ -192,7 +181,7 @@ hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* a
                              int64_t* rownnz, hipStream_t st);
 // numeric reorder with chunk ranges reserved by atomic adds on bin cursors
 size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb);
-hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
                                const int32_t* tile_row, const int64_t* aoff,
                                const int64_t* tile_e0, const int64_t* bin_start,
                                unsigned long long* bin_cursor, uint16_t* ws_col, void* ws_val,

@@ -19,21 +19,18 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   g.shift = P->shift;
   g.tile = P->tile;
   g.hints = P->hints;
-  int64_t* geo = (int64_t*)palloc(P, sizeof(int64_t) * (3 * nch + 4 * (nch + 1)));
+  int64_t* geo = (int64_t*)palloc(P, sizeof(int64_t) * (2 * nch + 3 * (nch + 1)));
   if (!geo) return MAGNUS_ERR_OOM;
   g.nb = geo;
   g.nt = geo + nch;
-  g.tabsz = geo + 2 * nch;
-  g.binBase = geo + 3 * nch;
+  g.binBase = geo + 2 * nch;
   g.tileBase = g.binBase + (nch + 1);
-  g.tabBase = g.tileBase + (nch + 1);
-  g.ipBase = g.tabBase + (nch + 1);
+  g.ipBase = g.tileBase + (nch + 1);
   void* tmp = palloc(P, scan_temp_bytes(nch + 1));
   if (!tmp) return MAGNUS_ERR_OOM;
   HIPCHK(launch_chunk_geom(g, P->st));
   HIPCHK(scan_excl_i64(g.nb, g.binBase, nch, g.binBase + nch, nullptr, tmp, P->st));
   HIPCHK(scan_excl_i64(g.nt, g.tileBase, nch, g.tileBase + nch, nullptr, tmp, P->st));
-  HIPCHK(scan_excl_i64(g.tabsz, g.tabBase, nch, g.tabBase + nch, nullptr, tmp, P->st));
   HIPCHK(scan_excl_i64(g.ipBase, g.ipBase, nch, g.ipBase + nch, nullptr, tmp, P->st));
 
   // products per batch
@@ -55,22 +52,21 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   if (W < 1) W = 1;
   const int64_t nslots = ipch / W + 1;
   int32_t* first_of = (int32_t*)palloc(P, sizeof(int32_t) * nslots);
-  int64_t* bases = (int64_t*)palloc(P, sizeof(int64_t) * 4 * nslots);
+  int64_t* bases = (int64_t*)palloc(P, sizeof(int64_t) * 3 * nslots);
   if (!first_of || !bases) return MAGNUS_ERR_OOM;
   HIPCHK(hipMemsetAsync(first_of, 0xFF, sizeof(int32_t) * nslots, P->st));
   HIPCHK(launch_batch_bounds(g, W, first_of, bases, P->st));
   std::vector<int32_t> h_first(nslots);
-  std::vector<int64_t> h_bases(4 * nslots);
-  int64_t tots[4];
+  std::vector<int64_t> h_bases(3 * nslots);
+  int64_t tots[3];
   magnus_status_t s = readback(
       P,
       {{first_of, sizeof(int32_t) * nslots},
-       {bases, sizeof(int64_t) * 4 * nslots},
+       {bases, sizeof(int64_t) * 3 * nslots},
        {g.ipBase + nch, 8},
        {g.tileBase + nch, 8},
-       {g.tabBase + nch, 8},
        {g.binBase + nch, 8}},
-      {h_first.data(), h_bases.data(), &tots[0], &tots[1], &tots[2], &tots[3]});
+      {h_first.data(), h_bases.data(), &tots[0], &tots[1], &tots[2]});
   if (s != MAGNUS_OK) return s;
   // batches in slot order
   std::vector<int64_t> starts;
@@ -78,49 +74,38 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
     if (h_first[q] >= 0) starts.push_back(q);
   P->batches.clear();
   P->ws_products = 0;
-  int64_t max_ntab = 0, max_tiles = 0;
+  int64_t max_tiles = 0;
   for (size_t b = 0; b < starts.size(); ++b) {
     const int64_t q = starts[b];
     BatchArgs ba{};
     ba.k0 = h_first[q];
-    ba.ip0 = h_bases[4 * q + 0];
-    ba.tile0 = h_bases[4 * q + 1];
-    ba.tab0 = h_bases[4 * q + 2];
-    ba.bin0 = h_bases[4 * q + 3];
+    ba.ip0 = h_bases[3 * q + 0];
+    ba.tile0 = h_bases[3 * q + 1];
+    ba.bin0 = h_bases[3 * q + 2];
     if (b + 1 < starts.size()) {
       const int64_t q2 = starts[b + 1];
       ba.k1 = h_first[q2];
-      ba.nip = h_bases[4 * q2 + 0] - ba.ip0;
-      ba.ntiles = h_bases[4 * q2 + 1] - ba.tile0;
-      ba.ntab = h_bases[4 * q2 + 2] - ba.tab0;
-      ba.nbins = h_bases[4 * q2 + 3] - ba.bin0;
+      ba.nip = h_bases[3 * q2 + 0] - ba.ip0;
+      ba.ntiles = h_bases[3 * q2 + 1] - ba.tile0;
+      ba.nbins = h_bases[3 * q2 + 2] - ba.bin0;
     } else {
       ba.k1 = nch;
       ba.nip = tots[0] - ba.ip0;
       ba.ntiles = tots[1] - ba.tile0;
-      ba.ntab = tots[2] - ba.tab0;
-      ba.nbins = tots[3] - ba.bin0;
+      ba.nbins = tots[2] - ba.bin0;
     }
     P->ws_products = std::max(P->ws_products, ba.nip);
-    max_ntab = std::max(max_ntab, ba.ntab);
     max_tiles = std::max(max_tiles, ba.ntiles);
     P->batches.push_back(ba);
   }
   if (max_tiles > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
-  const int64_t ntiles = tots[1], ntab = tots[2], nbins = tots[3];
+  const int64_t ntiles = tots[1], nbins = tots[2];
   const int64_t nbat = (int64_t)P->batches.size();
   P->bitmap_symbolic = row_bitmap_lds(P->shift, P->max_nb) <= (size_t)P->lds_budget;
   P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
   P->tile_row = (int32_t*)palloc(P, sizeof(int32_t) * ntiles);
-  if (!P->bitmap_symbolic) {
-    P->tab_cnt = (int32_t*)palloc(P, sizeof(int32_t) * ntab);
-    P->tab_off = (int64_t*)palloc(P, sizeof(int64_t) * ntab);
-    P->tab_temp = palloc(P, scan_temp_bytes(max_ntab));
-    if (!P->tab_cnt || !P->tab_off || !P->tab_temp) return MAGNUS_ERR_OOM;
-  } else {
-    P->tab_temp = palloc(P, scan_temp_bytes(nbins));
-    if (!P->tab_temp) return MAGNUS_ERR_OOM;
-  }
+  P->scan_temp = palloc(P, scan_temp_bytes(nbins));
+  if (!P->scan_temp) return MAGNUS_ERR_OOM;
   P->bin_cursor = (unsigned long long*)palloc(P, sizeof(unsigned long long) * nbins);
   P->work_ctr = (unsigned int*)palloc(P, sizeof(int64_t) * 2 * nbat);
   if (!P->work_ctr) return MAGNUS_ERR_OOM;
@@ -172,22 +157,29 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
     for (size_t bi = 0; bi < P->batches.size(); ++bi) {
       const BatchArgs& b = P->batches[bi];
       HIPCHK(scan_excl_i64(P->bin_cnt + b.bin0, P->bin_start + b.bin0, b.nbins, nullptr, nullptr,
-                           P->tab_temp, P->st));
+                           P->scan_temp, P->st));
       HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
                               P->sort_items, P->item_counts + 2 * bi, P->st));
     }
     return MAGNUS_OK;
   }
+  // the row bitmap does not fit the LDS: per batch, per-chunk product totals
+  // (tile histograms added atomically), their scan, a reorder of the
+  // chunk-local columns, and a count of the distinct columns of every chunk
   for (size_t bi = 0; bi < P->batches.size(); ++bi) {
     const BatchArgs& b = P->batches[bi];
     int32_t* ic = P->item_counts + 2 * bi;
-    HIPCHK(launch_bin_hist(P->M, P->g, b, P->tile_row, P->aoff, P->tab_cnt, P->max_nb, P->st));
-    HIPCHK(scan_excl_i32(P->tab_cnt + b.tab0, P->tab_off + b.tab0, b.ntab, nullptr, nullptr,
-                         P->tab_temp, P->st));
-    HIPCHK(launch_bin_scatter(P->M, P->g, b, false, P->tile_row, P->aoff, P->tab_cnt, P->tab_off,
-                              P->ws_col, P->ws_val, P->max_nb, P->stats, P->st));
-    HIPCHK(launch_bin_items(P->g, b, P->tab_off, P->bin_start, P->bin_cnt, P->bin_row,
-                            P->dense_min, P->group_max, P->dense_items, P->sort_items, ic, P->st));
+    HIPCHK(launch_fill_i64(P->bin_cnt + b.bin0, b.nbins, 0, P->st));
+    HIPCHK(launch_bin_hist(P->M, P->g, b, P->tile_row, P->aoff, P->tile_e0, P->bin_cnt,
+                           P->bin_row, P->max_nb, P->st));
+    HIPCHK(scan_excl_i64(P->bin_cnt + b.bin0, P->bin_start + b.bin0, b.nbins, nullptr, nullptr,
+                         P->scan_temp, P->st));
+    HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
+                            P->sort_items, ic, P->st));
+    HIPCHK(launch_fill_i64((int64_t*)P->bin_cursor + b.bin0, b.nbins, 0, P->st));
+    HIPCHK(launch_bin_scatter2(P->M, P->g, b, false, P->tile_row, P->aoff, P->tile_e0,
+                               P->bin_start, P->bin_cursor, P->ws_col, P->ws_val, P->max_nb,
+                               P->st));
     unsigned int* wk = P->work_ctr + 4 * bi;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
     HIPCHK(launch_bin_accum(P->g, b, false, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
@@ -215,8 +207,9 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
       ProfScope ps(h, P->st, "bin_scatter (numeric reorder)",
                    (double)b.nip * (P->s_col + P->s_val + 2 + P->s_val) +
                        (double)b.nent * (P->s_col + P->s_val + 8 + P->s_rp));
-      HIPCHK(launch_bin_scatter2(P->M, P->g, b, P->tile_row, P->aoff, P->tile_e0, P->bin_start,
-                                 P->bin_cursor, P->ws_col, P->ws_val, P->max_nb, P->st));
+      HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, P->tile_row, P->aoff, P->tile_e0,
+                                 P->bin_start, P->bin_cursor, P->ws_col, P->ws_val, P->max_nb,
+                                 P->st));
     }
     unsigned int* wk = P->work_ctr + 4 * bi + 2;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
@@ -489,8 +482,7 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     // the reorder kernels keep per-chunk counters of a row in LDS: shrink the
     // tile if they and the staged tile do not fit
     auto fits = [&](int tile) {
-      return bin_scatter2_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max &&
-             bin_scatter_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max;
+      return bin_scatter2_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max;
     };
     while (P->tile > 256 && !fits(P->tile)) P->tile /= 2;
     if (!fits(P->tile)) {

@@ -108,8 +108,8 @@ struct magnus_plan_s {
   // CHUNKED rows
   int64_t nch = 0, max_nb = 1;
   ChunkGeom g{};
-  int64_t *aoff = nullptr, *tab_off = nullptr, *tile_e0 = nullptr;
-  int32_t *tile_row = nullptr, *tab_cnt = nullptr, *bin_row = nullptr, *item_counts = nullptr;
+  int64_t *aoff = nullptr, *tile_e0 = nullptr;
+  int32_t *tile_row = nullptr, *bin_row = nullptr, *item_counts = nullptr;
   int64_t *bin_start = nullptr, *bin_cnt = nullptr, *bin_nnz = nullptr, *bin_out = nullptr;
   int64_t *dense_items = nullptr, *sort_items = nullptr;
   unsigned long long* bin_cursor = nullptr;
@@ -117,7 +117,7 @@ struct magnus_plan_s {
   bool bitmap_symbolic = false;
   uint16_t* ws_col = nullptr;
   void* ws_val = nullptr;
-  void* tab_temp = nullptr;
+  void* scan_temp = nullptr;
   int64_t ws_products = 0;
   std::vector<BatchArgs> batches;
   int64_t nnz_c = 0;
