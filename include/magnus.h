@@ -115,7 +115,11 @@ typedef struct {
   int32_t lds_bytes;      /* LDS budget per workgroup (0: device maximum) */
   int32_t sort_group_max; /* products per packed sort group of small chunks (<= 1024) */
   int32_t stream_hints;   /* non-temporal accesses: 1 workspace stores, 2 workspace loads, 4 C stores */
-  int32_t _reserved[4];
+  int32_t coarse_chunks;  /* chunks per coarse chunk (power of two, Section 3.3): CHUNKED rows
+                           * wider than one coarse chunk are reordered into coarse chunks first.
+                           * 0: the widest coarse chunk whose symbolic bitmap fits the LDS
+                           * budget; < 0: no coarse level */
+  int32_t _reserved[3];
 } magnus_options_t;
 
 /* Sizes the plan reports (host struct). */
@@ -137,6 +141,11 @@ typedef struct {
   int32_t bin_dense_min;
   int32_t tile_products;
   double symbolic_ms;      /* device time of the symbolic phase (events) */
+  int64_t coarse_rows;     /* CHUNKED rows taken through the coarse level */
+  int64_t coarse_chunks;   /* their coarse chunks (2^coarse_shift columns each) */
+  int64_t coarse_fine_chunks; /* chunks of 2^chunk_shift columns inside the coarse chunks */
+  int32_t coarse_shift;
+  int32_t _pad1;
 } magnus_plan_info_t;
 
 typedef struct magnus_handle_s* magnus_handle_t;

@@ -31,7 +31,7 @@ class Options(ctypes.Structure):
                 ("bin_dense_min", c_i32), ("tile_products", c_i32), ("dense_block", c_i32),
                 ("batch_products", c_i64), ("max_workspace_bytes", c_i64), ("validate", c_i32),
                 ("lds_bytes", c_i32), ("sort_group_max", c_i32), ("stream_hints", c_i32),
-                ("_reserved", c_i32 * 4)]
+                ("coarse_chunks", c_i32), ("_reserved", c_i32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -41,7 +41,9 @@ class PlanInfo(ctypes.Structure):
                 ("n_batches", c_i64), ("n_bins", c_i64), ("n_dense_chunks", c_i64),
                 ("n_sort_groups", c_i64), ("plan_bytes", c_i64),
                 ("chunk_shift", c_i32), ("sort_max", c_i32), ("bin_dense_min", c_i32),
-                ("tile_products", c_i32), ("symbolic_ms", ctypes.c_double)]
+                ("tile_products", c_i32), ("symbolic_ms", ctypes.c_double),
+                ("coarse_rows", c_i64), ("coarse_chunks", c_i64), ("coarse_fine_chunks", c_i64),
+                ("coarse_shift", c_i32), ("_pad1", c_i32)]
 
     def as_dict(self):
         d = {}

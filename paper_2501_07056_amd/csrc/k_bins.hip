@@ -382,20 +382,52 @@ __global__ void __launch_bounds__(RB_BS)
 // add on that bin's cursor, the products are ranked within their chunk, and
 // every chunk's run is copied out contiguously.
 // ---------------------------------------------------------------------------
-size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb) {
-  const size_t vs = f64 ? 8 : 4;
-  return BIN_BS * (8 + 8 + 8) + (size_t)max_nb * (4 + 8) + 16 + (size_t)tile * (4 + 4) + 16 +
-         (size_t)tile * vs + 64;
+// Exclusive scan of a[0, n) into out[0, n) (both LDS) by a workgroup of BS
+// threads; tmp holds BS / 64 ints.  Ends with a barrier.
+template <int BS>
+MG_INLINE void block_excl_scan(const int32_t* a, int32_t* out, int64_t n, int32_t* tmp) {
+  const int t = threadIdx.x;
+  const int64_t per = (n + BS - 1) / BS;
+  const int64_t i0 = t * per, i1 = (i0 + per < n) ? (i0 + per) : n;
+  int32_t s = 0;
+  for (int64_t i = i0; i < i1; ++i) s += a[i];
+  const int32_t inc = wave_incl_scan(s);
+  const int w = t / MG_WAVE;
+  if (lane() == MG_WAVE - 1) tmp[w] = inc;
+  __syncthreads();
+  int32_t run = inc - s;
+  for (int v = 0; v < w; ++v) run += tmp[v];
+  for (int64_t i = i0; i < i1; ++i) {
+    out[i] = run;
+    run += a[i];
+  }
+  __syncthreads();
 }
 
-template <typename RP, typename CI, typename V, bool NUMERIC>
+// Chunk-local columns go out as 16-bit words (chunks of <= 2^16 columns) or,
+// for the coarse level's chunks, as 32-bit words.
+// With `sorted`, the staged tile is permuted into chunk order in LDS before
+// the write-out (as in the level-2 reorder below), so that a wave stores
+// consecutive addresses of one chunk's run even where the expansion order
+// interleaves many chunks.
+size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb, int lc32, int sorted) {
+  const size_t vs = f64 ? 8 : 4;
+  const size_t w = 4 + (lc32 ? 2 : 0);
+  size_t b = BIN_BS * (8 + 8 + 8) + (size_t)max_nb * (4 + 8) + 16 + (size_t)tile * (4 + w) + 16 +
+             (size_t)tile * vs + 64;
+  if (sorted) b += (size_t)max_nb * 4 + 16 + (size_t)tile * w + 16 + (size_t)tile * vs + 16;
+  return b;
+}
+
+template <typename RP, typename CI, typename V, typename LC, bool NUMERIC, bool SORTED>
 __global__ void __launch_bounds__(BIN_BS)
     k_bin_scatter2(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
                    const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
                    ChunkGeom g, BatchArgs b, const int32_t* __restrict__ tile_row,
                    const int64_t* __restrict__ aoff, const int64_t* __restrict__ tile_e0,
                    const int64_t* __restrict__ bin_start, unsigned long long* bin_cursor,
-                   uint16_t* ws_col, V* ws_val) {
+                   LC* ws_col, V* ws_val) {
+  constexpr bool W16 = sizeof(LC) == 2;
   extern __shared__ __align__(16) unsigned char dsm[];
   int32_t* w_pre = (int32_t*)dsm;
   int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);
@@ -406,7 +438,14 @@ __global__ void __launch_bounds__(BIN_BS)
   int64_t* dst = (int64_t*)(((uintptr_t)(hist + c.nbk) + 15) & ~(uintptr_t)15);
   uint32_t* u_word = (uint32_t*)(dst + c.nbk);
   uint32_t* u_rank = u_word + g.tile;
-  V* u_val = (V*)(((uintptr_t)(u_rank + g.tile) + 15) & ~(uintptr_t)15);
+  uint16_t* u_bin = (uint16_t*)(u_rank + g.tile);  // 32-bit columns: the chunk apart
+  V* u_val = (V*)(((uintptr_t)(u_bin + (W16 ? 0 : g.tile)) + 15) & ~(uintptr_t)15);
+  // chunk-ordered copy of the tile (SORTED)
+  int32_t* loff = (int32_t*)(u_val + g.tile);
+  uint32_t* s_word = (uint32_t*)(((uintptr_t)(loff + c.nbk) + 15) & ~(uintptr_t)15);
+  uint16_t* s_bin = (uint16_t*)(s_word + g.tile);
+  V* s_val = (V*)(((uintptr_t)(s_bin + (W16 ? 0 : g.tile)) + 15) & ~(uintptr_t)15);
+  __shared__ int32_t s_tmp[BIN_BS / MG_WAVE];
 
   for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) hist[q] = 0;
   __syncthreads();
@@ -422,11 +461,17 @@ __global__ void __launch_bounds__(BIN_BS)
         int r = 0;
         if (lane() == hl) r = atomicAdd(&hist[bin], len);
         r = __shfl(r, hl, MG_WAVE);
-        u_word[q] = (bin << 16) | ((uint32_t)col & (uint32_t)lmask);
+        if (W16) {
+          u_word[q] = (bin << 16) | ((uint32_t)col & (uint32_t)lmask);
+        } else {
+          u_word[q] = (uint32_t)((uint64_t)col & (uint64_t)lmask);
+          u_bin[q] = (uint16_t)bin;
+        }
         u_rank[q] = (uint32_t)(r + (lane() - hl));
         if (NUMERIC) u_val[q] = pv;
       });
   __syncthreads();
+  if (SORTED) block_excl_scan<BIN_BS>(hist, loff, c.nbk, s_tmp);
   // reserve each chunk's run inside its bin with one atomic add
   const int64_t gb = g.binBase[c.k];
   for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) {
@@ -436,14 +481,265 @@ __global__ void __launch_bounds__(BIN_BS)
       dst[q] = bin_start[gb + q] + (int64_t)r;
     }
   }
-  __syncthreads();
   const int32_t nloc = (int32_t)(c.p1 - c.p0);
+  if (SORTED) {
+    for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
+      const uint32_t w = u_word[q];
+      const uint32_t bin = W16 ? (w >> 16) : (uint32_t)u_bin[q];
+      const int32_t p = loff[bin] + (int32_t)u_rank[q];
+      s_word[p] = w;
+      if (!W16) s_bin[p] = (uint16_t)bin;
+      if (NUMERIC) s_val[p] = u_val[q];
+    }
+  }
+  __syncthreads();
+  if (SORTED) {
+    for (int32_t p = threadIdx.x; p < nloc; p += BIN_BS) {
+      const uint32_t w = s_word[p];
+      const uint32_t bin = W16 ? (w >> 16) : (uint32_t)s_bin[p];
+      const int64_t d = dst[bin] + (p - loff[bin]);
+      st_stream<HINT_WS_STORE>(&ws_col[d], W16 ? (LC)(w & 0xFFFFu) : (LC)w);
+      if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], s_val[p]);
+    }
+  } else {
+    for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
+      const uint32_t w = u_word[q];
+      const uint32_t bin = W16 ? (w >> 16) : (uint32_t)u_bin[q];
+      const int64_t d = dst[bin] + u_rank[q];
+      st_stream<HINT_WS_STORE>(&ws_col[d], W16 ? (LC)(w & 0xFFFFu) : (LC)w);
+      if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse level (Section 3.3).  Every chunk of 2^cshift columns that the first
+// reorder produced becomes a "virtual row" of a second chunk geometry: its
+// products sit contiguously in the first workspace with 32-bit columns local
+// to the chunk, and the chunks of 2^shift columns inside it are handled like
+// the chunks of an ordinary CHUNKED row.
+// ---------------------------------------------------------------------------
+// per coarse row k (one wave): the column base, last column and fine chunk
+// count of each of its coarse chunks
+__global__ void k_vrow_geom(ChunkGeom g1, int fshift, int64_t* minc2, int64_t* maxc2, int64_t* nb2,
+                            int32_t* ident) {
+  const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
+  if (k >= g1.nch) return;
+  const int32_t row = g1.rows[k];
+  const int cs = g1.shift;
+  const int64_t c0 = g1.minc[row] >> cs, mx = g1.maxc[row];
+  const int64_t bb = g1.binBase[k], nbk = g1.nb[k];
+  for (int64_t q = lane(); q < nbk; q += MG_WAVE) {
+    const int64_t base = (c0 + q) << cs;
+    const int64_t last = base + ((int64_t)1 << cs) - 1;
+    const int64_t hi = last < mx ? last : mx;
+    minc2[bb + q] = base;
+    maxc2[bb + q] = hi;
+    nb2[bb + q] = (hi >> fshift) - (base >> fshift) + 1;
+    ident[bb + q] = (int32_t)(bb + q);
+  }
+}
+
+// tiles of the level-2 reorder: nt2 = ceil(products / tile) per virtual row
+__global__ void k_vrow_tiles(const int64_t* cnt1, int64_t k0, int64_t k1, int tile, int64_t* nt2) {
+  const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
+  nt2[k] = (cnt1[k] + tile - 1) / tile;
+}
+
+// Symbolic phase of a coarse chunk: its column bitmap (2^cshift bits) in
+// LDS, one workgroup per virtual row; per fine chunk the distinct columns
+// and the products, and the virtual row's nnz.
+constexpr int VB_BS = 1024;
+
+size_t vrow_bitmap_lds(int cshift, int64_t max_nb2) {
+  return (((size_t)1 << cshift) >> 3) + (size_t)max_nb2 * 4 + 64;
+}
+
+__global__ void __launch_bounds__(VB_BS)
+    k_vrow_bitmap(ChunkGeom g2, int64_t k0, const int64_t* __restrict__ start1,
+                  const uint32_t* __restrict__ ws1_col, int64_t* bin_cnt2, int64_t* bin_nnz2,
+                  int32_t* bin_row2, int64_t* vnnz) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int64_t k = k0 + blockIdx.x;
+  const int64_t nbk = g2.nb[k], bb = g2.binBase[k];
+  const int sh = g2.shift;
+  const int64_t cnt = g2.ip[k], s0 = start1[k];
+  const int t = threadIdx.x;
+  if (cnt == 0) {
+    for (int64_t q = t; q < nbk; q += VB_BS) {
+      bin_cnt2[bb + q] = 0;
+      bin_nnz2[bb + q] = 0;
+      bin_row2[bb + q] = (int32_t)k;
+    }
+    if (t == 0) vnnz[k] = 0;
+    return;
+  }
+  const int64_t nwords = (nbk << sh) >> 5;
+  uint32_t* bits = (uint32_t*)dsm;
+  int32_t* cntf = (int32_t*)(bits + nwords);
+  __shared__ unsigned long long tot;
+  for (int64_t q = t; q < nwords; q += VB_BS) bits[q] = 0u;
+  for (int64_t q = t; q < nbk; q += VB_BS) cntf[q] = 0;
+  if (t == 0) tot = 0;
+  __syncthreads();
+  for (int64_t q = t; q < cnt; q += VB_BS) {
+    const uint32_t lc = ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + q]);
+    atomicOr(&bits[lc >> 5], 1u << (lc & 31));
+    const uint32_t f = lc >> sh;
+    int hl, len;
+    wave_run(f, hl, len);
+    if (lane() == hl) atomicAdd(&cntf[f], len);
+  }
+  __syncthreads();
+  const int w = t / MG_WAVE, nw = VB_BS / MG_WAVE;
+  const int64_t wpb = ((int64_t)1 << sh) >> 5;
+  for (int64_t f = w; f < nbk; f += nw) {
+    unsigned long long s = 0;
+    for (int64_t q = lane(); q < wpb; q += MG_WAVE) s += __popc(bits[f * wpb + q]);
+    s = wave_sum(s);
+    if (lane() == 0) {
+      bin_nnz2[bb + f] = (int64_t)s;
+      bin_cnt2[bb + f] = cntf[f];
+      bin_row2[bb + f] = (int32_t)k;
+      atomicAdd(&tot, s);
+    }
+  }
+  __syncthreads();
+  if (t == 0) vnnz[k] = (int64_t)tot;
+}
+
+// Level-2 reorder: a tile of a virtual row's products (first workspace) is
+// staged in LDS with its fine chunk and its rank inside that chunk, the
+// tile is permuted into chunk order in LDS (offsets from a scan of the
+// tile's chunk counts), each chunk's run is reserved in its bin with one
+// atomic add, and the permuted tile is written out, so that consecutive
+// lanes store consecutive addresses of one chunk's run (the staging order
+// interleaves the chunks: inside a coarse chunk, neighbouring products
+// seldom share a fine chunk).  16-bit chunk-local columns.
+size_t l2_scatter_lds(int f64, int tile, int64_t max_nb2) {
+  const size_t vs = f64 ? 8 : 4;
+  return (size_t)max_nb2 * (4 + 4 + 8) + 3 * 16 + (size_t)tile * (4 + 4 + vs) +
+         (size_t)tile * (4 + vs) + 16 + (BIN_BS / MG_WAVE) * 4 + 64;
+}
+
+template <typename V, bool NUMERIC>
+__global__ void __launch_bounds__(BIN_BS)
+    k_l2_scatter(ChunkGeom g2, BatchArgs b2, const int32_t* __restrict__ tile_row2,
+                 const int64_t* __restrict__ start1, const uint32_t* __restrict__ ws1_col,
+                 const V* __restrict__ ws1_val, const int64_t* __restrict__ bin_start2,
+                 unsigned long long* bin_cursor2, uint16_t* ws2_col, V* ws2_val) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ int32_t s_tmp[BIN_BS / MG_WAVE];
+  const int64_t tg = b2.tile0 + blockIdx.x;
+  const int64_t k = tile_row2[tg];
+  const int64_t ti = tg - g2.tileBase[k];
+  const int64_t cnt = g2.ip[k];
+  const int64_t p0 = ti * (int64_t)g2.tile;
+  const int32_t nloc = (int32_t)((cnt - p0 < g2.tile) ? (cnt - p0) : g2.tile);
+  const int64_t s0 = start1[k] + p0;
+  const int64_t nbk = g2.nb[k], gb = g2.binBase[k];
+  const int sh = g2.shift;
+  const uint32_t lmask = (1u << sh) - 1u;
+  auto al16 = [](void* p) { return (void*)(((uintptr_t)p + 15) & ~(uintptr_t)15); };
+  int32_t* hist = (int32_t*)dsm;
+  int32_t* loff = (int32_t*)al16(hist + nbk);
+  int64_t* dst = (int64_t*)al16(loff + nbk);
+  uint32_t* u_word = (uint32_t*)(dst + nbk);
+  uint32_t* u_rank = u_word + g2.tile;
+  V* u_val = (V*)al16(u_rank + g2.tile);
+  uint32_t* s_word = (uint32_t*)(u_val + g2.tile);
+  V* s_val = (V*)al16(s_word + g2.tile);
+  for (int64_t q = threadIdx.x; q < nbk; q += BIN_BS) hist[q] = 0;
+  __syncthreads();
+  for (int32_t qb = threadIdx.x; qb < nloc; qb += 4 * BIN_BS) {
+    uint32_t c4[4];
+    V v4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t q = qb + u * BIN_BS;
+      c4[u] = (q < nloc) ? ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + q]) : 0u;
+      v4[u] = (NUMERIC && q < nloc) ? ld_stream<HINT_WS_LOAD>(&ws1_val[s0 + q]) : (V)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t q = qb + u * BIN_BS;
+      if (q < nloc) {
+        const uint32_t f = c4[u] >> sh;
+        int hl, len;
+        wave_run(f, hl, len);
+        int r = 0;
+        if (lane() == hl) r = atomicAdd(&hist[f], len);
+        r = __shfl(r, hl, MG_WAVE);
+        u_word[q] = (f << 16) | (c4[u] & lmask);
+        u_rank[q] = (uint32_t)(r + (lane() - hl));
+        if (NUMERIC) u_val[q] = v4[u];
+      }
+    }
+  }
+  __syncthreads();
+  block_excl_scan<BIN_BS>(hist, loff, nbk, s_tmp);
+  for (int64_t q = threadIdx.x; q < nbk; q += BIN_BS) {
+    const int h = hist[q];
+    if (h > 0) {
+      const unsigned long long r = atomicAdd(&bin_cursor2[gb + q], (unsigned long long)h);
+      dst[q] = bin_start2[gb + q] + (int64_t)r;
+    }
+  }
   for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
     const uint32_t w = u_word[q];
-    const int64_t d = dst[w >> 16] + u_rank[q];
-    st_stream<HINT_WS_STORE>(&ws_col[d], (uint16_t)(w & 0xFFFFu));
-    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
+    const int32_t p = loff[w >> 16] + (int32_t)u_rank[q];
+    s_word[p] = w;
+    if (NUMERIC) s_val[p] = u_val[q];
   }
+  __syncthreads();
+  for (int32_t p = threadIdx.x; p < nloc; p += BIN_BS) {
+    const uint32_t w = s_word[p];
+    const uint32_t f = w >> 16;
+    const int64_t d = dst[f] + (p - loff[f]);
+    st_stream<HINT_WS_STORE>(&ws2_col[d], (uint16_t)(w & 0xFFFFu));
+    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws2_val[d], s_val[p]);
+  }
+}
+
+// Fine-chunk product counts of the level-2 tiles of b2 (cnt2 zeroed before):
+// per tile a histogram in LDS, added into the chunk totals.
+template <int BS>
+__global__ void __launch_bounds__(BS)
+    k_l2_hist(ChunkGeom g2, BatchArgs b2, const int32_t* __restrict__ tile_row2,
+              const int64_t* __restrict__ start1, const uint32_t* __restrict__ ws1_col,
+              unsigned long long* cnt2) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  int32_t* hist = (int32_t*)dsm;
+  const int64_t tg = b2.tile0 + blockIdx.x;
+  const int64_t k = tile_row2[tg];
+  const int64_t p0 = (tg - g2.tileBase[k]) * (int64_t)g2.tile;
+  const int64_t cnt = g2.ip[k];
+  const int32_t nloc = (int32_t)((cnt - p0 < g2.tile) ? (cnt - p0) : g2.tile);
+  const int64_t s0 = start1[k] + p0;
+  const int64_t nbk = g2.nb[k], gb = g2.binBase[k];
+  const int sh = g2.shift;
+  for (int64_t q = threadIdx.x; q < nbk; q += BS) hist[q] = 0;
+  __syncthreads();
+  for (int32_t q = threadIdx.x; q < nloc; q += BS) {
+    const uint32_t f = ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + q]) >> sh;
+    int hl, len;
+    wave_run(f, hl, len);
+    if (lane() == hl) atomicAdd(&hist[f], len);
+  }
+  __syncthreads();
+  for (int64_t q = threadIdx.x; q < nbk; q += BS) {
+    const int h = hist[q];
+    if (h > 0) atomicAdd(&cnt2[gb + q], (unsigned long long)h);
+  }
+}
+
+// the virtual row of every fine chunk (one wave per virtual row)
+__global__ void k_vrow_rows(ChunkGeom g2, int32_t* row2) {
+  const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
+  if (k >= g2.nch) return;
+  const int64_t bb = g2.binBase[k], nbk = g2.nb[k];
+  for (int64_t q = lane(); q < nbk; q += MG_WAVE) row2[bb + q] = (int32_t)k;
 }
 
 // ---------------------------------------------------------------------------
@@ -853,23 +1149,94 @@ hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile
 }
 
 hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
-                               const int32_t* tile_row, const int64_t* aoff,
+                               int lc32, int sorted, const int32_t* tile_row, const int64_t* aoff,
                                const int64_t* tile_e0, const int64_t* bin_start,
-                               unsigned long long* bin_cursor, uint16_t* ws_col, void* ws_val,
+                               unsigned long long* bin_cursor, void* ws_col, void* ws_val,
                                int64_t max_nb, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
-  const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb);
-#define MG_SC2(V)                                                                                 \
+  const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb, lc32, sorted);
+#define MG_SC2(V, LC)                                                                             \
   MG_DISPATCH2(M, {                                                                               \
-    auto kf = numeric ? k_bin_scatter2<RP, CI, V, true> : k_bin_scatter2<RP, CI, V, false>;      \
+    auto kf = numeric ? (sorted ? k_bin_scatter2<RP, CI, V, LC, true, true>                        \
+                                : k_bin_scatter2<RP, CI, V, LC, true, false>)                      \
+                      : (sorted ? k_bin_scatter2<RP, CI, V, LC, false, true>                       \
+                                : k_bin_scatter2<RP, CI, V, LC, false, false>);                    \
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                 \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
                        (const V*)M.bval, g, b, tile_row, aoff, tile_e0, bin_start, bin_cursor,    \
-                       ws_col, (V*)ws_val);                                                       \
+                       (LC*)ws_col, (V*)ws_val);                                                  \
   });
-  if (M.f64) { MG_SC2(double) } else { MG_SC2(float) }
+  if (lc32) {
+    if (M.f64) { MG_SC2(double, uint32_t) } else { MG_SC2(float, uint32_t) }
+  } else {
+    if (M.f64) { MG_SC2(double, uint16_t) } else { MG_SC2(float, uint16_t) }
+  }
 #undef MG_SC2
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_hist(const ChunkGeom& g2, const BatchArgs& b2, const int32_t* tile_row2,
+                          const int64_t* start1, const uint32_t* ws1_col, int64_t* cnt2,
+                          int64_t max_nb2, hipStream_t st) {
+  if (b2.ntiles <= 0) return hipSuccess;
+  const size_t lds = (size_t)max_nb2 * 4 + 64;
+  hipLaunchKernelGGL(k_l2_hist<512>, (unsigned)b2.ntiles, 512, lds, st, g2, b2, tile_row2, start1,
+                     ws1_col, (unsigned long long*)cnt2);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_rows(const ChunkGeom& g2, int32_t* row2, hipStream_t st) {
+  if (g2.nch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vrow_rows, (unsigned)((g2.nch + 3) / 4), 256, 0, st, g2, row2);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_geom(const ChunkGeom& g1, int fshift, int64_t* minc2, int64_t* maxc2,
+                            int64_t* nb2, int32_t* ident, hipStream_t st) {
+  if (g1.nch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vrow_geom, (unsigned)((g1.nch + 3) / 4), 256, 0, st, g1, fshift, minc2,
+                     maxc2, nb2, ident);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_tiles(const int64_t* cnt1, int64_t k0, int64_t k1, int tile, int64_t* nt2,
+                             hipStream_t st) {
+  if (k1 <= k0) return hipSuccess;
+  hipLaunchKernelGGL(k_vrow_tiles, (unsigned)((k1 - k0 + 255) / 256), 256, 0, st, cnt1, k0, k1,
+                     tile, nt2);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_bitmap(const ChunkGeom& g2, int cshift, int64_t k0, int64_t k1,
+                              int64_t max_nb2, const int64_t* start1, const uint32_t* ws1_col,
+                              int64_t* bin_cnt2, int64_t* bin_nnz2, int32_t* bin_row2,
+                              int64_t* vnnz, hipStream_t st) {
+  if (k1 <= k0) return hipSuccess;
+  const size_t lds = vrow_bitmap_lds(cshift, max_nb2);
+  hipFuncSetAttribute((const void*)k_vrow_bitmap, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL(k_vrow_bitmap, (unsigned)(k1 - k0), VB_BS, lds, st, g2, k0, start1, ws1_col,
+                     bin_cnt2, bin_nnz2, bin_row2, vnnz);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool numeric, int f64,
+                             const int32_t* tile_row2, const int64_t* start1,
+                             const uint32_t* ws1_col, const void* ws1_val,
+                             const int64_t* bin_start2, unsigned long long* bin_cursor2,
+                             uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, hipStream_t st) {
+  if (b2.ntiles <= 0) return hipSuccess;
+  const size_t lds = l2_scatter_lds(f64, g2.tile, max_nb2);
+#define MG_L2(V)                                                                                  \
+  {                                                                                               \
+    auto kf = numeric ? k_l2_scatter<V, true> : k_l2_scatter<V, false>;                           \
+    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    hipLaunchKernelGGL(kf, (unsigned)b2.ntiles, BIN_BS, lds, st, g2, b2, tile_row2, start1,       \
+                       ws1_col, (const V*)ws1_val, bin_start2, bin_cursor2, ws2_col, (V*)ws2_val); \
+  }
+  if (f64) MG_L2(double) else MG_L2(float)
+#undef MG_L2
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ constexpr int64_t HEAVY_ENTRIES = 1024;
 
 // Category (Section 3.1) and class of a row from its products and range.
 MG_INLINE int row_class(int64_t s, int64_t range, int force, int64_t sort_max, int64_t dense_max,
-                        int& cat) {
+                        int64_t coarse_range, int& cat) {
   if (s == 0) {
     cat = 3;
     return CLS_EMPTY;
@@ -44,7 +44,8 @@ MG_INLINE int row_class(int64_t s, int64_t range, int force, int64_t sort_max, i
     while (((int64_t)1 << lg) < s) ++lg;
     return lg;
   }
-  return (want == 1) ? CLS_DENSE : CLS_CHUNKED;
+  if (want == 1) return CLS_DENSE;
+  return (coarse_range > 0 && range > coarse_range) ? CLS_COARSE : CLS_CHUNKED;
 }
 template <typename RP, typename CI, bool BATCH>
 __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, ClassParams cp,
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(256) k_rowinfo(RowSrc src, int64_t n, int G, C
     if (row < n && sub == 0) {
       int cat;
       const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
-      const int c = row_class(s, range, cp.force, sort_max, dense_max, cat);
+      const int c = row_class(s, range, cp.force, sort_max, dense_max, cp.coarse_range, cat);
       if (s == 0) {
         mn = 0;
         mx = -1;
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(256) k_rowinfo_heavy(RowSrc src, ClassParams c
       }
       int cat;
       const int64_t range = (s > 0) ? (mx - mn + 1) : 0;
-      const int c = row_class(s, range, cp.force, cp.sort_max, cp.dense_max, cat);
+      const int c = row_class(s, range, cp.force, cp.sort_max, cp.dense_max, cp.coarse_range, cat);
       if (s == 0) {
         mn = 0;
         mx = -1;
@@ -485,7 +486,8 @@ __global__ void __launch_bounds__(256) k_cat_nnz(const int32_t* cls, const int64
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int c = cls[i];
-    const int cat = c < CLS_DENSE ? 0 : (c == CLS_DENSE ? 1 : (c == CLS_CHUNKED ? 2 : 3));
+    const int cat =
+        c < CLS_DENSE ? 0 : (c == CLS_DENSE ? 1 : ((c == CLS_CHUNKED || c == CLS_COARSE) ? 2 : 3));
     loc[cat] += (unsigned long long)rownnz[i];
   }
   for (int k = 0; k < 4; ++k) {

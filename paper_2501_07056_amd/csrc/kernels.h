@@ -13,6 +13,7 @@ constexpr int NSORT_CLS = 11;
 constexpr int CLS_DENSE = 11;
 constexpr int CLS_CHUNKED = 12;
 constexpr int CLS_EMPTY = 13;
+constexpr int CLS_COARSE = 14;  // CHUNKED rows taken through the coarse level first
 constexpr int NCLS = 16;
 constexpr int SORT_CAP = 1024;  // products one wave sorts (64 lanes x 16)
 
@@ -66,6 +67,7 @@ struct ClassParams {
   int64_t sort_max;   // SORT iff ip < sort_max (<= SORT_CAP)
   int64_t dense_max;  // DENSE iff column range <= dense_max
   int force;          // -1 auto, else category
+  int64_t coarse_range;  // CHUNKED rows wider than this take the coarse level (<= 0: never)
 };
 
 size_t scan_temp_bytes(int64_t n);
@@ -179,13 +181,45 @@ size_t row_bitmap_lds(int shift, int64_t max_nb);
 hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
                              int64_t max_nb, int64_t* bin_nnz, int64_t* bin_cnt, int32_t* bin_row,
                              int64_t* rownnz, hipStream_t st);
-// numeric reorder with chunk ranges reserved by atomic adds on bin cursors
-size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb);
+// reorder with chunk ranges reserved by atomic adds on bin cursors (count
+// mode: columns only); ws_col holds uint16 (lc32 = 0) or uint32 (lc32 = 1)
+// chunk-local columns
+// chunk-local columns; sorted = 1 permutes each tile into chunk order in LDS
+// before the write-out
+size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb, int lc32, int sorted);
 hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
-                               const int32_t* tile_row, const int64_t* aoff,
+                               int lc32, int sorted, const int32_t* tile_row, const int64_t* aoff,
                                const int64_t* tile_e0, const int64_t* bin_start,
-                               unsigned long long* bin_cursor, uint16_t* ws_col, void* ws_val,
+                               unsigned long long* bin_cursor, void* ws_col, void* ws_val,
                                int64_t max_nb, hipStream_t st);
+// --- coarse level: coarse chunks as virtual rows of a second geometry ---
+// per coarse chunk (global index over the coarse rows' chunks): column base,
+// last column, fine chunk count and its own index (identity row list)
+hipError_t launch_vrow_geom(const ChunkGeom& g1, int fshift, int64_t* minc2, int64_t* maxc2,
+                            int64_t* nb2, int32_t* ident, hipStream_t st);
+// fine-chunk product counts of the level-2 tiles of b2 (cnt2 zeroed before)
+hipError_t launch_l2_hist(const ChunkGeom& g2, const BatchArgs& b2, const int32_t* tile_row2,
+                          const int64_t* start1, const uint32_t* ws1_col, int64_t* cnt2,
+                          int64_t max_nb2, hipStream_t st);
+// row2[fine chunk] = its virtual row
+hipError_t launch_vrow_rows(const ChunkGeom& g2, int32_t* row2, hipStream_t st);
+hipError_t launch_vrow_tiles(const int64_t* cnt1, int64_t k0, int64_t k1, int tile, int64_t* nt2,
+                             hipStream_t st);
+// symbolic phase of virtual rows [k0, k1): fine chunk products, nnz, row;
+// virtual row nnz
+size_t vrow_bitmap_lds(int cshift, int64_t max_nb2);
+hipError_t launch_vrow_bitmap(const ChunkGeom& g2, int cshift, int64_t k0, int64_t k1,
+                              int64_t max_nb2, const int64_t* start1, const uint32_t* ws1_col,
+                              int64_t* bin_cnt2, int64_t* bin_nnz2, int32_t* bin_row2,
+                              int64_t* vnnz, hipStream_t st);
+// level-2 reorder of the tiles of b2 (first workspace -> second; count
+// mode: columns only)
+size_t l2_scatter_lds(int f64, int tile, int64_t max_nb2);
+hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool numeric, int f64,
+                             const int32_t* tile_row2, const int64_t* start1,
+                             const uint32_t* ws1_col, const void* ws1_val,
+                             const int64_t* bin_start2, unsigned long long* bin_cursor2,
+                             uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, hipStream_t st);
 // first A entry of every tile
 hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile_row,
                           const int64_t* aoff, int64_t ntiles, int64_t* tile_e0, hipStream_t st);

@@ -6,19 +6,37 @@ using namespace mgrt;
 
 namespace {
 
-magnus_status_t setup_chunked(magnus_plan_s* P) {
+// Products per row batch: the batch_products option, else the workspace cap
+// (max_workspace_bytes, else an eighth of the device memory, the same batches
+// on every call whatever the caching allocator holds) over the workspace
+// bytes per product; a batch always holds the longest row.
+magnus_status_t batch_width(magnus_plan_s* P, int64_t bytes_per_product, int64_t& W) {
   magnus_handle_s* h = P->h;
   const magnus_options_t& o = h->opts;
-  const int64_t nch = P->nch;
-  ChunkGeom& g = P->g;
-  g.rows = P->list + P->h_list_off[CLS_CHUNKED];
-  g.ip = P->ip;
-  g.minc = P->minc;
-  g.maxc = P->maxc;
-  g.nch = nch;
-  g.shift = P->shift;
-  g.tile = P->tile;
-  g.hints = P->hints;
+  W = o.batch_products;
+  if (W <= 0) {
+    int64_t budget = o.max_workspace_bytes;
+    if (budget <= 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      budget = (int64_t)(tot / 8);
+    }
+    W = budget / bytes_per_product;
+  }
+  if (W < (int64_t)P->h_stats.max_ip) W = (int64_t)P->h_stats.max_ip;
+  if (W < 1) W = 1;
+  return MAGNUS_OK;
+}
+
+// Geometry of the rows of g (g.rows, g.ip, g.minc, g.maxc, g.nch, g.shift,
+// g.tile set): chunks, tiles and products per row and their exclusive scans,
+// then the row batches of at most W products each (whole rows).  tots =
+// products, tiles, chunks over all rows.
+magnus_status_t geometry_and_batches(magnus_plan_s* P, ChunkGeom& g, int64_t W,
+                                     std::vector<BatchArgs>& batches, int64_t& ws_products,
+                                     int64_t tots[3]) {
+  magnus_handle_s* h = P->h;
+  const int64_t nch = g.nch;
   int64_t* geo = (int64_t*)palloc(P, sizeof(int64_t) * (2 * nch + 3 * (nch + 1)));
   if (!geo) return MAGNUS_ERR_OOM;
   g.nb = geo;
@@ -26,30 +44,12 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   g.binBase = geo + 2 * nch;
   g.tileBase = g.binBase + (nch + 1);
   g.ipBase = g.tileBase + (nch + 1);
-  void* tmp = palloc(P, scan_temp_bytes(nch + 1));
-  if (!tmp) return MAGNUS_ERR_OOM;
+  void* tmp = P->temp;  // sized for a scan of n + 1 >= nch + 1 entries
   HIPCHK(launch_chunk_geom(g, P->st));
   HIPCHK(scan_excl_i64(g.nb, g.binBase, nch, g.binBase + nch, nullptr, tmp, P->st));
   HIPCHK(scan_excl_i64(g.nt, g.tileBase, nch, g.tileBase + nch, nullptr, tmp, P->st));
   HIPCHK(scan_excl_i64(g.ipBase, g.ipBase, nch, g.ipBase + nch, nullptr, tmp, P->st));
-
-  // products per batch
-  const int64_t vs = P->M.f64 ? 8 : 4;
-  int64_t W = o.batch_products;
-  if (W <= 0) {
-    int64_t budget = o.max_workspace_bytes;
-    if (budget <= 0) {
-      // an eighth of the device memory: the same batches on every call,
-      // whatever the caching allocator currently holds
-      size_t fr = 0, tot = 0;
-      HIPCHK(hipMemGetInfo(&fr, &tot));
-      budget = (int64_t)(tot / 8);
-    }
-    W = budget / (2 + vs);
-  }
   const int64_t ipch = (int64_t)P->h_stats.ip_cat[2];
-  if (W < (int64_t)P->h_stats.max_ip) W = (int64_t)P->h_stats.max_ip;
-  if (W < 1) W = 1;
   const int64_t nslots = ipch / W + 1;
   int32_t* first_of = (int32_t*)palloc(P, sizeof(int32_t) * nslots);
   int64_t* bases = (int64_t*)palloc(P, sizeof(int64_t) * 3 * nslots);
@@ -58,7 +58,6 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   HIPCHK(launch_batch_bounds(g, W, first_of, bases, P->st));
   std::vector<int32_t> h_first(nslots);
   std::vector<int64_t> h_bases(3 * nslots);
-  int64_t tots[3];
   magnus_status_t s = readback(
       P,
       {{first_of, sizeof(int32_t) * nslots},
@@ -72,8 +71,8 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   std::vector<int64_t> starts;
   for (int64_t q = 0; q < nslots; ++q)
     if (h_first[q] >= 0) starts.push_back(q);
-  P->batches.clear();
-  P->ws_products = 0;
+  batches.clear();
+  ws_products = 0;
   int64_t max_tiles = 0;
   for (size_t b = 0; b < starts.size(); ++b) {
     const int64_t q = starts[b];
@@ -94,15 +93,37 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
       ba.ntiles = tots[1] - ba.tile0;
       ba.nbins = tots[2] - ba.bin0;
     }
-    P->ws_products = std::max(P->ws_products, ba.nip);
+    ws_products = std::max(ws_products, ba.nip);
     max_tiles = std::max(max_tiles, ba.ntiles);
-    P->batches.push_back(ba);
+    batches.push_back(ba);
   }
   if (max_tiles > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  return MAGNUS_OK;
+}
+
+magnus_status_t setup_chunked(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  const int64_t nch = P->nch;
+  ChunkGeom& g = P->g;
+  g.rows = P->list + P->h_list_off[CLS_CHUNKED];
+  g.ip = P->ip;
+  g.minc = P->minc;
+  g.maxc = P->maxc;
+  g.nch = nch;
+  g.shift = P->shift;
+  g.tile = P->tile;
+  g.hints = P->hints;
+  void* tmp = P->temp;
+  const int64_t vs = P->M.f64 ? 8 : 4;
+  int64_t W = 0, tots[3];
+  magnus_status_t s = batch_width(P, 2 + vs, W);
+  if (s != MAGNUS_OK) return s;
+  s = geometry_and_batches(P, g, W, P->batches, P->ws_products, tots);
+  if (s != MAGNUS_OK) return s;
   const int64_t ntiles = tots[1], nbins = tots[2];
   const int64_t nbat = (int64_t)P->batches.size();
   P->bitmap_symbolic = row_bitmap_lds(P->shift, P->max_nb) <= (size_t)P->lds_budget;
-  P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
+  if (!P->aoff) P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
   P->tile_row = (int32_t*)palloc(P, sizeof(int32_t) * ntiles);
   P->scan_temp = palloc(P, scan_temp_bytes(nbins));
   if (!P->scan_temp) return MAGNUS_ERR_OOM;
@@ -177,9 +198,9 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
     HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
                             P->sort_items, ic, P->st));
     HIPCHK(launch_fill_i64((int64_t*)P->bin_cursor + b.bin0, b.nbins, 0, P->st));
-    HIPCHK(launch_bin_scatter2(P->M, P->g, b, false, P->tile_row, P->aoff, P->tile_e0,
-                               P->bin_start, P->bin_cursor, P->ws_col, P->ws_val, P->max_nb,
-                               P->st));
+    HIPCHK(launch_bin_scatter2(P->M, P->g, b, false, 0, P->sorted_out, P->tile_row, P->aoff,
+                               P->tile_e0, P->bin_start, P->bin_cursor, P->ws_col, P->ws_val,
+                               P->max_nb, P->st));
     unsigned int* wk = P->work_ctr + 4 * bi;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
     HIPCHK(launch_bin_accum(P->g, b, false, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
@@ -207,9 +228,9 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
       ProfScope ps(h, P->st, "bin_scatter (numeric reorder)",
                    (double)b.nip * (P->s_col + P->s_val + 2 + P->s_val) +
                        (double)b.nent * (P->s_col + P->s_val + 8 + P->s_rp));
-      HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, P->tile_row, P->aoff, P->tile_e0,
-                                 P->bin_start, P->bin_cursor, P->ws_col, P->ws_val, P->max_nb,
-                                 P->st));
+      HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, 0, P->sorted_out, P->tile_row, P->aoff,
+                                 P->tile_e0, P->bin_start, P->bin_cursor, P->ws_col, P->ws_val,
+                                 P->max_nb, P->st));
     }
     unsigned int* wk = P->work_ctr + 4 * bi + 2;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
@@ -221,6 +242,259 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
                               P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
                               P->bin_out, ccol, col64, cval, P->dense_block, wk,
                               P->persistent_wgs, P->st));
+    }
+  }
+  return MAGNUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-level rows (Section 3.3, Algorithm 4)
+// ---------------------------------------------------------------------------
+magnus_status_t setup_coarse(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  auto& C = P->co;
+  const int64_t n1 = C.nrows;
+  ChunkGeom& g1 = C.g1;
+  g1.rows = P->list + P->h_list_off[CLS_COARSE];
+  g1.ip = P->ip;
+  g1.minc = P->minc;
+  g1.maxc = P->maxc;
+  g1.nch = n1;
+  g1.shift = C.cshift;
+  g1.tile = C.tile1;
+  g1.hints = P->hints;
+  const int64_t vs = P->M.f64 ? 8 : 4;
+  int64_t W = 0, tots[3];
+  // per product: the first workspace (32-bit column, value) and the second
+  // (16-bit column, value)
+  magnus_status_t s = batch_width(P, (4 + vs) + (2 + vs), W);
+  if (s != MAGNUS_OK) return s;
+  s = geometry_and_batches(P, g1, W, C.b1, C.ws_products, tots);
+  if (s != MAGNUS_OK) return s;
+  const int64_t ntiles1 = tots[1], nv = tots[2];
+  const int64_t nbat = (int64_t)C.b1.size();
+  C.nv = nv;
+  if (nv > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  if (!P->aoff) P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
+  C.tile_row1 = (int32_t*)palloc(P, sizeof(int32_t) * std::max<int64_t>(1, ntiles1));
+  C.tile_e0 = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, ntiles1));
+  C.ent = (int64_t*)palloc(P, sizeof(int64_t) * (2 * n1 + 1));
+  if (!P->aoff || !C.tile_row1 || !C.tile_e0 || !C.ent) return MAGNUS_ERR_OOM;
+  C.entBase = C.ent + n1;
+  HIPCHK(launch_aoff(P->M, g1.rows, n1, P->aoff, C.ent, P->st));
+  HIPCHK(scan_excl_i64(C.ent, C.entBase, n1, C.entBase + n1, nullptr, P->temp, P->st));
+  HIPCHK(launch_tiles(g1.nt, g1.tileBase, 0, n1, C.tile_row1, P->st));
+  HIPCHK(launch_tile_e0(P->M, g1, C.tile_row1, P->aoff, ntiles1, C.tile_e0, P->st));
+
+  // per coarse chunk, and the coarse chunks as virtual rows of g2
+  C.cnt1 = (int64_t*)palloc(P, sizeof(int64_t) * nv);
+  C.start1 = (int64_t*)palloc(P, sizeof(int64_t) * nv);
+  C.nnz1 = (int64_t*)palloc(P, sizeof(int64_t) * nv);
+  C.out1 = (int64_t*)palloc(P, sizeof(int64_t) * (nv + 1));
+  C.row1 = (int32_t*)palloc(P, sizeof(int32_t) * nv);
+  C.cur1 = (unsigned long long*)palloc(P, sizeof(unsigned long long) * nv);
+  int64_t* vgeo = (int64_t*)palloc(P, sizeof(int64_t) * (4 * nv + 2 * (nv + 1)));
+  int32_t* ident = (int32_t*)palloc(P, sizeof(int32_t) * nv);
+  C.scan_temp = palloc(P, scan_temp_bytes(nv + 1));
+  if (!C.cnt1 || !C.start1 || !C.nnz1 || !C.out1 || !C.row1 || !C.cur1 || !vgeo || !ident ||
+      !C.scan_temp)
+    return MAGNUS_ERR_OOM;
+  ChunkGeom& g2 = C.g2;
+  g2.rows = ident;
+  g2.ip = C.cnt1;
+  g2.minc = vgeo;
+  g2.maxc = vgeo + nv;
+  g2.nb = vgeo + 2 * nv;
+  g2.nt = vgeo + 3 * nv;
+  g2.binBase = vgeo + 4 * nv;
+  g2.tileBase = g2.binBase + (nv + 1);
+  g2.ipBase = nullptr;
+  g2.nch = nv;
+  g2.shift = P->shift;
+  g2.tile = C.tile2;
+  g2.hints = P->hints;
+  HIPCHK(launch_vrow_geom(g1, P->shift, (int64_t*)g2.minc, (int64_t*)g2.maxc, g2.nb, ident,
+                          P->st));
+  HIPCHK(scan_excl_i64(g2.nb, g2.binBase, nv, g2.binBase + nv, nullptr, C.scan_temp, P->st));
+  // fine chunks of every batch's virtual rows
+  std::vector<int64_t> fb(nbat + 1, 0);
+  {
+    std::vector<std::pair<const void*, size_t>> src;
+    std::vector<void*> dst;
+    for (int64_t b = 0; b <= nbat; ++b) {
+      const int64_t kk = (b < nbat) ? C.b1[b].bin0 : nv;
+      src.push_back({g2.binBase + kk, 8});
+      dst.push_back(&fb[b]);
+    }
+    s = readback(P, src, dst);
+    if (s != MAGNUS_OK) return s;
+  }
+  C.nbins2 = fb[nbat];
+  C.b2.assign(nbat, BatchArgs{});
+  int64_t max_fine = 1;
+  for (int64_t b = 0; b < nbat; ++b) {
+    BatchArgs& b2 = C.b2[b];
+    b2.k0 = C.b1[b].bin0;
+    b2.k1 = C.b1[b].bin0 + C.b1[b].nbins;
+    b2.bin0 = fb[b];
+    b2.nbins = fb[b + 1] - fb[b];
+    b2.ip0 = C.b1[b].ip0;
+    b2.nip = C.b1[b].nip;
+    max_fine = std::max(max_fine, b2.nbins);
+  }
+  const int64_t nb2 = C.nbins2;
+  C.cnt2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
+  C.start2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
+  C.nnz2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
+  C.out2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
+  C.dense2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
+  C.sort2 = (int64_t*)palloc(P, sizeof(int64_t) * 2 * nb2);
+  C.row2 = (int32_t*)palloc(P, sizeof(int32_t) * nb2);
+  C.cur2 = (unsigned long long*)palloc(P, sizeof(unsigned long long) * nb2);
+  void* t2 = palloc(P, scan_temp_bytes(max_fine));
+  C.item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2 * nbat);
+  C.btiles = (int64_t*)palloc(P, sizeof(int64_t) * (nbat + 1));
+  C.work = (unsigned int*)palloc(P, sizeof(int64_t) * 2 * nbat);
+  // level-2 tiles: at most products / tile + one per virtual row
+  C.tile_row2 = (int32_t*)palloc(P, sizeof(int32_t) * (tots[0] / C.tile2 + nv + 1));
+  C.ws1_col = (uint32_t*)palloc(P, sizeof(uint32_t) * C.ws_products);
+  C.ws1_val = palloc(P, (size_t)vs * C.ws_products);
+  C.ws2_col = (uint16_t*)palloc(P, sizeof(uint16_t) * C.ws_products);
+  C.ws2_val = palloc(P, (size_t)vs * C.ws_products);
+  if (!C.cnt2 || !C.start2 || !C.nnz2 || !C.out2 || !C.dense2 || !C.sort2 || !C.row2 || !C.cur2 ||
+      !t2 || !C.item_counts || !C.btiles || !C.work || !C.tile_row2 || !C.ws1_col ||
+      !C.ws1_val || !C.ws2_col || !C.ws2_val)
+    return MAGNUS_ERR_OOM;
+  if (scan_temp_bytes(max_fine) > scan_temp_bytes(nv + 1)) C.scan_temp = t2;
+  HIPCHK(hipMemsetAsync(C.item_counts, 0, sizeof(int32_t) * 2 * nbat, P->st));
+  HIPCHK(hipMemsetAsync(C.btiles, 0, sizeof(int64_t) * (nbat + 1), P->st));
+  HIPCHK(launch_vrow_rows(g2, C.row2, P->st));
+  // the bitmap of a coarse chunk (2^cshift bits) pays when its products are
+  // dense enough
+  const int64_t per_chunk = tots[0] / std::max<int64_t>(1, nv);
+  C.bitmap_sym = per_chunk * MG_BITMAP_DENSITY >= ((int64_t)1 << C.cshift);
+  return MAGNUS_OK;
+}
+
+// Symbolic phase of coarse-level rows: per batch, the coarse chunks' product
+// counts and the first reorder (columns only), the level-2 tiles, then per
+// fine chunk its products and nnz, either from a bitmap of every coarse
+// chunk (dense coarse chunks) or from the level-2 reorder of the columns and
+// the accumulators in count mode (sparse ones, where clearing and scanning a
+// bitmap would cost more than the products); row nnz; fine chunk starts
+// and work items.
+magnus_status_t coarse_symbolic(magnus_plan_s* P) {
+  magnus_handle_s* h = P->h;
+  auto& C = P->co;
+  ChunkGeom& g1 = C.g1;
+  ChunkGeom& g2 = C.g2;
+  for (size_t bi = 0; bi < C.b1.size(); ++bi) {
+    const BatchArgs& b = C.b1[bi];
+    BatchArgs& b2 = C.b2[bi];
+    int32_t* ic = C.item_counts + 2 * bi;
+    {
+      // per product: B column read, 32-bit column written; per A entry:
+      // column, product offset, B row pointer (twice: histogram and reorder)
+      ProfScope ps(h, P->st, "coarse_reorder (symbolic, level 1)",
+                   (double)b.nip * (2 * P->s_col + 4) +
+                       2.0 * (double)b.nip / std::max<int64_t>(1, g1.tile) * 64);
+      HIPCHK(launch_fill_i64(C.cnt1 + b.bin0, b.nbins, 0, P->st));
+      HIPCHK(launch_bin_hist(P->M, g1, b, C.tile_row1, P->aoff, C.tile_e0, C.cnt1, C.row1,
+                             C.max_nb1, P->st));
+      HIPCHK(scan_excl_i64(C.cnt1 + b.bin0, C.start1 + b.bin0, b.nbins, nullptr, nullptr,
+                           C.scan_temp, P->st));
+      HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
+      HIPCHK(launch_bin_scatter2(P->M, g1, b, false, 1, C.sorted1, C.tile_row1, P->aoff,
+                                 C.tile_e0, C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1,
+                                 P->st));
+    }
+    // level-2 tiles of the batch's virtual rows (running total in btiles)
+    HIPCHK(launch_vrow_tiles(C.cnt1, b2.k0, b2.k1, C.tile2, g2.nt, P->st));
+    HIPCHK(scan_excl_i64(g2.nt + b2.k0, g2.tileBase + b2.k0, b2.k1 - b2.k0, C.btiles + bi + 1,
+                         C.btiles + bi, C.scan_temp, P->st));
+    HIPCHK(launch_tiles(g2.nt, g2.tileBase, b2.k0, b2.k1, C.tile_row2, P->st));
+    int64_t tb[2] = {0, 0};
+    magnus_status_t s = readback(P, {{C.btiles + bi, 16}}, {tb});
+    if (s != MAGNUS_OK) return s;
+    b2.tile0 = tb[0];
+    b2.ntiles = tb[1] - tb[0];
+    if (b2.ntiles > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+    if (C.bitmap_sym) {
+      // per product: 32-bit column read; per fine chunk: three words out
+      ProfScope ps(h, P->st, "coarse_bitmap (symbolic, level 2)",
+                   (double)b.nip * 4 + (double)b2.nbins * 20);
+      HIPCHK(launch_vrow_bitmap(g2, C.cshift, b2.k0, b2.k1, C.max_nb2, C.start1, C.ws1_col,
+                                C.cnt2, C.nnz2, C.row2, C.nnz1, P->st));
+      HIPCHK(scan_excl_i64(C.cnt2 + b2.bin0, C.start2 + b2.bin0, b2.nbins, nullptr, nullptr,
+                           C.scan_temp, P->st));
+      HIPCHK(launch_bin_group(g2, b2, C.cnt2, P->dense_min, P->group_max, C.dense2, C.sort2, ic,
+                              P->st));
+    } else {
+      // per product: 32-bit column read twice (histogram, reorder), 16-bit
+      // column written and read; per fine chunk: count, start, nnz
+      ProfScope ps(h, P->st, "coarse_count (symbolic, level 2)",
+                   (double)b.nip * (4 + 4 + 2 + 2) + (double)b2.nbins * 24);
+      HIPCHK(launch_fill_i64(C.cnt2 + b2.bin0, b2.nbins, 0, P->st));
+      HIPCHK(launch_l2_hist(g2, b2, C.tile_row2, C.start1, C.ws1_col, C.cnt2, C.max_nb2, P->st));
+      HIPCHK(scan_excl_i64(C.cnt2 + b2.bin0, C.start2 + b2.bin0, b2.nbins, nullptr, nullptr,
+                           C.scan_temp, P->st));
+      HIPCHK(launch_bin_group(g2, b2, C.cnt2, P->dense_min, P->group_max, C.dense2, C.sort2, ic,
+                              P->st));
+      HIPCHK(launch_fill_i64((int64_t*)C.cur2 + b2.bin0, b2.nbins, 0, P->st));
+      HIPCHK(launch_l2_scatter(g2, b2, false, P->M.f64, C.tile_row2, C.start1, C.ws1_col,
+                               C.ws1_val, C.start2, C.cur2, C.ws2_col, C.ws2_val, C.max_nb2,
+                               P->st));
+      unsigned int* wk = C.work + 4 * bi + 2;
+      HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+      HIPCHK(launch_bin_accum(g2, b2, false, P->M.f64, C.start2, C.cnt2, C.row2, C.dense2,
+                              C.sort2, ic, C.ws2_col, C.ws2_val, C.nnz2, C.out2, nullptr, 0,
+                              nullptr, P->dense_block, wk, P->persistent_wgs, P->st));
+      HIPCHK(launch_bin_rows(g2, b2.k0, b2.k1, C.nnz2, C.nnz1, nullptr, nullptr, false, P->st));
+    }
+    HIPCHK(launch_bin_rows(g1, b.k0, b.k1, C.nnz1, P->crp, nullptr, nullptr, false, P->st));
+  }
+  return MAGNUS_OK;
+}
+
+// Numeric phase of coarse-level rows, batch by batch: output offsets of the
+// coarse and fine chunks, the two reorders, accumulation of every fine chunk
+// into C.
+magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cval) {
+  magnus_handle_s* h = P->h;
+  auto& C = P->co;
+  const double vs = P->s_val;
+  for (size_t bi = 0; bi < C.b1.size(); ++bi) {
+    const BatchArgs& b = C.b1[bi];
+    const BatchArgs& b2 = C.b2[bi];
+    HIPCHK(launch_bin_rows(C.g1, b.k0, b.k1, C.nnz1, nullptr, P->crp, C.out1, true, P->st));
+    HIPCHK(launch_bin_rows(C.g2, b2.k0, b2.k1, C.nnz2, nullptr, C.out1, C.out2, true, P->st));
+    HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
+    {
+      // per product: B column and value read, 32-bit column and product
+      // written; per A entry: column, value, product offset, B row
+      ProfScope ps(h, P->st, "coarse_scatter (numeric, level 1)",
+                   (double)b.nip * (P->s_col + vs + 4 + vs) +
+                       (double)b.nent * (P->s_col + vs + 8 + P->s_rp));
+      HIPCHK(launch_bin_scatter2(P->M, C.g1, b, true, 1, C.sorted1, C.tile_row1, P->aoff, C.tile_e0,
+                                 C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1, P->st));
+    }
+    HIPCHK(launch_fill_i64((int64_t*)C.cur2 + b2.bin0, b2.nbins, 0, P->st));
+    {
+      // per product: 32-bit column and value read, 16-bit column and value
+      // written
+      ProfScope ps(h, P->st, "fine_scatter (numeric, level 2)", (double)b.nip * (4 + vs + 2 + vs));
+      HIPCHK(launch_l2_scatter(C.g2, b2, true, P->M.f64, C.tile_row2, C.start1, C.ws1_col, C.ws1_val,
+                               C.start2, C.cur2, C.ws2_col, C.ws2_val, C.max_nb2, P->st));
+    }
+    unsigned int* wk = C.work + 4 * bi;
+    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    {
+      ProfScope ps(h, P->st, "bin_accum (numeric, coarse rows)",
+                   (double)b.nip * (2 + vs) + (double)b.nnz_out * (P->s_col + vs));
+      HIPCHK(launch_bin_accum(C.g2, b2, true, P->M.f64, C.start2, C.cnt2, C.row2, C.dense2,
+                              C.sort2, C.item_counts + 2 * bi, C.ws2_col, C.ws2_val, C.nnz2,
+                              C.out2, ccol, col64, cval, P->dense_block, wk, P->persistent_wgs,
+                              P->st));
     }
   }
   return MAGNUS_OK;
@@ -459,6 +733,28 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   cp.sort_max = P->sort_max;
   cp.dense_max = (int64_t)1 << P->shift;
   cp.force = (o.force_category >= 0 && o.force_category <= 2) ? o.force_category : -1;
+  {
+    // coarse level (the paper's m_CmaxL2 with the LDS for the L2 cache):
+    // chunks of 2^cshift columns, the widest whose bitmap (the symbolic
+    // phase's accumulator, one bit per column) and chunk counts fit the LDS
+    // budget, at most 2^12 chunks each, or coarse_chunks chunks; CHUNKED rows
+    // wider than one coarse chunk take it
+    auto& Co = P->co;
+    const int sh = P->shift;
+    auto fits = [&](int c) {
+      return vrow_bitmap_lds(c, ((int64_t)1 << (c - sh)) + 1) + 1024 <= (size_t)lds;
+    };
+    int cs = sh + 1;
+    while (cs < sh + 12 && fits(cs + 1)) ++cs;
+    if (o.coarse_chunks > 0) {
+      int lg = 1;
+      while (lg < 12 && ((int64_t)2 << lg) <= o.coarse_chunks) ++lg;
+      cs = std::min(cs, sh + lg);
+    }
+    Co.cshift = cs;
+    Co.coarse_range = (o.coarse_chunks >= 0 && fits(cs)) ? ((int64_t)1 << cs) : 0;
+    cp.coarse_range = Co.coarse_range;
+  }
   P->s_rp = M.rp64 ? 8 : 4;
   P->s_col = M.col64 ? 8 : 4;
   P->s_val = M.f64 ? 8 : 4;
@@ -482,7 +778,7 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     // the reorder kernels keep per-chunk counters of a row in LDS: shrink the
     // tile if they and the staged tile do not fit
     auto fits = [&](int tile) {
-      return bin_scatter2_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max;
+      return bin_scatter2_lds(M.f64, tile, P->max_nb, 0, P->sorted_out) <= (size_t)h->lds_max;
     };
     while (P->tile > 256 && !fits(P->tile)) P->tile /= 2;
     if (!fits(P->tile)) {
@@ -491,11 +787,45 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     }
     SCHK(setup_chunked(P));
   }
+  P->co.nrows = P->h_list_off[CLS_COARSE + 1] - P->h_list_off[CLS_COARSE];
+  if (P->co.nrows > 0) {
+    auto& Co = P->co;
+    Co.max_nb1 = (int64_t)(P->h_stats.range_cat[2] >> Co.cshift) + 2;
+    Co.max_nb2 = ((int64_t)1 << (Co.cshift - P->shift)) + 1;
+    if (Co.max_nb1 > 65535) {
+      h->err = "too many coarse chunks per row";
+      return cleanup(MAGNUS_ERR_INVALID_ARG);
+    }
+    // expansion-order write-out with short tiles while the rows span few
+    // coarse chunks (long runs per chunk); chunk-ordered with long tiles
+    // beyond
+    Co.sorted1 = Co.max_nb1 > MG_COARSE_SORTED_MIN ? 1 : 0;
+    Co.tile1 = Co.sorted1 ? 4096 : 1024;
+    if (o.tile_products > 0) Co.tile1 = P->tile;
+    while (Co.tile1 > 256 &&
+           bin_scatter2_lds(M.f64, Co.tile1, Co.max_nb1, 1, Co.sorted1) > (size_t)h->lds_max)
+      Co.tile1 /= 2;
+    while (Co.tile2 > 256 && l2_scatter_lds(M.f64, Co.tile2, Co.max_nb2) > (size_t)h->lds_max)
+      Co.tile2 /= 2;
+    if (bin_scatter2_lds(M.f64, Co.tile1, Co.max_nb1, 1, Co.sorted1) > (size_t)h->lds_max ||
+        l2_scatter_lds(M.f64, Co.tile2, Co.max_nb2) > (size_t)h->lds_max) {
+      h->err = "too many coarse chunks per row for the LDS";
+      return cleanup(MAGNUS_ERR_INVALID_ARG);
+    }
+    SCHK(setup_coarse(P));
+  }
 
   // precise symbolic phase: exact nnz per row, then the row offsets of C
   PCHK(launch_fill_i64(P->crp, n + 1, 0, P->st));
   SCHK(run_rows(P, false, nullptr, nullptr));
   if (P->nch > 0) SCHK(chunked_symbolic(P));
+  if (P->co.nrows > 0) {
+    SCHK(coarse_symbolic(P));
+    // nnz of C per coarse-level batch (profiling bytes): scan of the coarse
+    // chunks' nnz, overwritten by their output offsets in the numeric phase
+    PCHK(scan_excl_i64(P->co.nnz1, P->co.out1, P->co.nv, P->co.out1 + P->co.nv, nullptr,
+                       P->co.scan_temp, P->st));
+  }
   PCHK(launch_cat_nnz(P->cls, P->crp, n, P->stats, P->st));
   if (P->nch > 0) {
     PCHK(launch_gather_rows(P->crp, P->g.rows, P->nch, P->nnzr, P->st));
@@ -518,10 +848,30 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     src.push_back({P->nnzBase + kk, 8});
     dst.push_back(&bnnz[b]);
   }
+  const size_t nbc = P->co.b1.size();
+  std::vector<int64_t> cent(nbc + 1, 0), cnnz(nbc + 1, 0);
+  std::vector<int32_t> cicounts(2 * nbc + 2, 0);
+  if (P->co.nrows > 0) {
+    auto& Co = P->co;
+    src.push_back({Co.item_counts, sizeof(int32_t) * 2 * nbc});
+    dst.push_back(cicounts.data());
+    for (size_t b = 0; b <= nbc; ++b) {
+      src.push_back({Co.entBase + ((b < nbc) ? Co.b1[b].k0 : Co.nrows), 8});
+      dst.push_back(&cent[b]);
+      src.push_back({Co.out1 + ((b < nbc) ? Co.b1[b].bin0 : Co.nv), 8});
+      dst.push_back(&cnnz[b]);
+    }
+  }
   SCHK(readback(P, src, dst));
   for (size_t b = 0; b < nb_; ++b) {
     P->batches[b].nent = bent[b + 1] - bent[b];
     P->batches[b].nnz_out = bnnz[b + 1] - bnnz[b];
+  }
+  for (size_t b = 0; b < nbc; ++b) {
+    P->co.b1[b].nent = cent[b + 1] - cent[b];
+    P->co.b1[b].nnz_out = cnnz[b + 1] - cnnz[b];
+    P->info.n_dense_chunks += cicounts[2 * b];
+    P->info.n_sort_groups += cicounts[2 * b + 1];
   }
   for (int k = 0; k < 4; ++k) P->info.nnz_by_category[k] = (int64_t)st2.nnz_cat[k];
   P->h_stats.nnz_cat[0] = st2.nnz_cat[0];
@@ -556,6 +906,10 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   I.bin_dense_min = (int32_t)P->dense_min;
   I.tile_products = P->tile;
   I.symbolic_ms = ms;
+  I.coarse_rows = P->co.nrows;
+  I.coarse_chunks = P->co.nv;
+  I.coarse_fine_chunks = P->co.nbins2;
+  I.coarse_shift = P->co.nrows > 0 ? P->co.cshift : 0;
   if (info) *info = I;
   *out = P;
   return MAGNUS_OK;
@@ -591,6 +945,10 @@ magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t P, const magnus_
   if (r != MAGNUS_OK) return r;
   if (P->nch > 0) {
     r = chunked_numeric(P, C->col, C->col_type == MAGNUS_I64, C->val);
+    if (r != MAGNUS_OK) return r;
+  }
+  if (P->co.nrows > 0) {
+    r = coarse_numeric(P, C->col, C->col_type == MAGNUS_I64, C->val);
     if (r != MAGNUS_OK) return r;
   }
   HIPCHK(launch_write_rowptr(P->crp, P->n, C->rowptr, C->rowptr_type == MAGNUS_I64, P->st));

@@ -14,6 +14,26 @@
 #include "kernels.h"
 #include "magnus.h"
 
+// default write-out order of the one-level CHUNKED reorder (1: chunk order)
+#ifndef MG_SORTED_OUT
+#define MG_SORTED_OUT 0
+#endif
+// the coarse level's first reorder writes in chunk order when rows span more
+// coarse chunks than this (short runs per chunk in the expansion order)
+#ifndef MG_COARSE_SORTED_MIN
+#define MG_COARSE_SORTED_MIN 256
+#endif
+#ifndef MG_L2_TILE
+#define MG_L2_TILE 2048
+#endif
+// coarse chunks with at least 2^cshift / MG_BITMAP_DENSITY products (on
+// average) are counted with a bitmap in the symbolic phase (measured on
+// uniform rows: the bitmap is faster at 1/128, the count-mode accumulators
+// at 1/1024)
+#ifndef MG_BITMAP_DENSITY
+#define MG_BITMAP_DENSITY 512
+#endif
+
 using namespace mg;
 
 struct magnus_handle_s {
@@ -115,6 +135,7 @@ struct magnus_plan_s {
   unsigned long long* bin_cursor = nullptr;
   unsigned int* work_ctr = nullptr;  // one counter per batch and phase
   bool bitmap_symbolic = false;
+  int sorted_out = MG_SORTED_OUT;  // CHUNKED reorder writes each tile out in chunk order
   uint16_t* ws_col = nullptr;
   void* ws_val = nullptr;
   void* scan_temp = nullptr;
@@ -124,6 +145,38 @@ struct magnus_plan_s {
   magnus_plan_info_t info{};
   int64_t *ent = nullptr, *entBase = nullptr, *nnzr = nullptr, *nnzBase = nullptr;
   double s_rp = 4, s_col = 4, s_val = 8;
+  // Coarse-level rows (CHUNKED rows wider than coarse_range): a first reorder
+  // into coarse chunks of 2^cshift columns (geometry g1, 32-bit chunk-local
+  // columns in ws1), then every coarse chunk is a virtual row of a second
+  // geometry g2 whose chunks of 2^shift columns are reordered into ws2 and
+  // accumulated like the chunks of CHUNKED rows.
+  struct Coarse {
+    int64_t nrows = 0, coarse_range = 0, max_nb1 = 1, max_nb2 = 1, nv = 0, nbins2 = 0;
+    int cshift = 20, tile1 = 4096, tile2 = MG_L2_TILE, sorted1 = 1;
+    bool bitmap_sym = true;
+    ChunkGeom g1{}, g2{};
+    std::vector<BatchArgs> b1, b2;  // level-1 batches; the level-2 range of each
+    int64_t *tile_e0 = nullptr, *ent = nullptr, *entBase = nullptr;
+    int32_t *tile_row1 = nullptr, *tile_row2 = nullptr;
+    // per coarse chunk (= virtual row)
+    int64_t *cnt1 = nullptr, *start1 = nullptr, *nnz1 = nullptr, *out1 = nullptr;
+    int32_t* row1 = nullptr;
+    unsigned long long* cur1 = nullptr;
+    // per fine chunk
+    int64_t *cnt2 = nullptr, *start2 = nullptr, *nnz2 = nullptr, *out2 = nullptr;
+    int64_t *dense2 = nullptr, *sort2 = nullptr;
+    int32_t* row2 = nullptr;
+    unsigned long long* cur2 = nullptr;
+    int32_t* item_counts = nullptr;  // per batch: dense items, sort items
+    int64_t* btiles = nullptr;       // level-2 tiles before each batch
+    unsigned int* work = nullptr;    // per batch: persistent-kernel counter
+    uint32_t* ws1_col = nullptr;
+    void* ws1_val = nullptr;
+    uint16_t* ws2_col = nullptr;
+    void* ws2_val = nullptr;
+    int64_t ws_products = 0;
+    void* scan_temp = nullptr;
+  } co;
 };
 
 namespace mgrt {

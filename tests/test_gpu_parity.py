@@ -80,6 +80,55 @@ def test_rmat_table_symbolic(ctx):
                     force_category="auto")
 
 
+@pytest.mark.parametrize("vt", [np.float64, np.float32])
+def test_coarse_level_er(ctx, vt):
+    """Rows wider than one coarse chunk take the coarse level (Section 3.3):
+    small coarse chunks (4 chunks of 2^9 columns under a 16 KiB LDS budget)
+    put every CHUNKED row through both reorders; the ablation without the
+    coarse level gives the same product."""
+    A = wl.erdos_renyi(3000, 5000, 12, wl.seed(88), val_dtype=vt)
+    B = wl.erdos_renyi(5000, 1 << 18, 100, wl.seed(89), val_dtype=vt)
+    ref = oracle.spgemm(A, B)
+    log(f"coarse er vt={vt.__name__}")
+    for cc in (4, 64, -1):
+        rp, col, val, info = gpu_product(ctx, A, B, force_category="chunked", lds_bytes=16384,
+                                         coarse_chunks=cc, batch_products=400000)
+        if cc > 0:
+            assert info["coarse_rows"] == A.nrows and info["coarse_chunks"] > A.nrows
+            assert info["rows_by_category"][2] == A.nrows and info["n_batches"] == 0
+        else:
+            assert info["coarse_rows"] == 0
+        compare(rp, col, val, ref, vt, exact=False)
+    ctx.set_options(force_category="auto", lds_bytes=0, coarse_chunks=0, batch_products=0)
+
+
+def test_coarse_level_rmat(ctx):
+    """Power-law rows through the coarse level: chunks of 2^6 columns, coarse
+    chunks of 4 of them, so heavy rows span many coarse chunks (some empty)
+    and some fine chunks are dense; several batches."""
+    A, _ = wl.config2(12)
+    log("coarse rmat12")
+    rp, col, val, info = gpu_product(ctx, A, A, force_category="chunked", chunk_shift=6,
+                                     coarse_chunks=4, batch_products=300000)
+    assert info["coarse_rows"] > 0 and info["coarse_shift"] == 8
+    compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
+    ctx.set_options(force_category="auto", chunk_shift=0, coarse_chunks=0, batch_products=0)
+
+
+@pytest.mark.parametrize("cit", [np.int32, np.int64])
+def test_coarse_level_int_values(ctx, cit):
+    """Integer-valued products through the coarse level are bit-exact, with
+    32- and 64-bit column indices."""
+    A = wl.erdos_renyi(700, 900, 9, wl.seed(90), val_kind="int", col_dtype=cit)
+    B = wl.erdos_renyi(900, 1 << 17, 60, wl.seed(91), val_kind="int", col_dtype=cit)
+    log(f"coarse int col={cit.__name__}")
+    rp, col, val, info = gpu_product(ctx, A, B, force_category="chunked", chunk_shift=8,
+                                     coarse_chunks=16)
+    assert info["coarse_rows"] > 0
+    compare(rp, col, val, oracle.spgemm(A, B), np.float64, exact=True)
+    ctx.set_options(force_category="auto", chunk_shift=0, coarse_chunks=0)
+
+
 @pytest.mark.parametrize("rpt", [np.int32, np.int64])
 @pytest.mark.parametrize("cit", [np.int32, np.int64])
 @pytest.mark.parametrize("vt", [np.float32, np.float64])

@@ -1,5 +1,6 @@
 """The seeded generators: determinism, exact structure and distribution."""
 import numpy as np
+import pytest
 
 import workloads as wl
 
@@ -28,6 +29,44 @@ def test_er_uniform_columns():
     h = np.bincount(A.col, minlength=64)
     exp = A.nnz / 64
     assert np.abs(h - exp).max() < 6 * np.sqrt(exp)
+
+
+def test_er_wide_rows_mask_and_threads():
+    """Wide rows: exactly d distinct sorted columns in [0, m) in the rows the
+    mask names, empty rows elsewhere, the same for any thread count, and
+    uniform columns (also where m is only 2d and duplicates are common)."""
+    n, m, d = 3000, 1 << 12, 300
+    mask = (np.arange(n) % 3 != 1).astype(np.uint8)
+    A = wl.erdos_renyi_wide(n, m, d, wl.seed(55), rows_mask=mask)
+    rp = A.rowptr.astype(np.int64)
+    assert (np.diff(rp) == d * mask.astype(np.int64)).all()
+    for i in range(0, n, 7):
+        c = A.col[rp[i]:rp[i + 1]]
+        assert (np.diff(c) > 0).all() and (len(c) == 0 or (c.min() >= 0 and c.max() < m))
+    rp1 = np.empty(n + 1, dtype=np.int64)
+    col1 = np.empty(A.nnz, dtype=np.int32)
+    assert wl._load().wl_er_wide(n, m, d, wl.seed(55), wl._ptr(mask), wl._ptr(rp1),
+                                 wl._ptr(col1), 4, 1) == A.nnz
+    assert (col1 == A.col).all() and (rp1 == rp).all()
+    h = np.bincount(A.col, minlength=m)
+    exp = A.nnz / m
+    assert np.abs(h - exp).max() < 6 * np.sqrt(exp)
+    B = wl.erdos_renyi_wide(500, 2 * 400, 400, wl.seed(56))
+    rb = B.rowptr.astype(np.int64)
+    assert all(len(np.unique(B.col[rb[i]:rb[i + 1]])) == 400 for i in range(500))
+    with pytest.raises(ValueError):
+        wl.erdos_renyi_wide(10, 100, 60, wl.seed(57))
+
+
+def test_massive_er_shape():
+    A, B = wl.massive_er(20, d=32, nrows=64)
+    assert A.nrows == 64 and A.ncols == 64 * 32 == B.nrows and B.ncols == 1 << 20
+    assert (np.diff(A.rowptr) == 32).all()
+    ref = np.zeros(B.nrows, bool)
+    ref[A.col] = True
+    assert np.array_equal(np.diff(B.rowptr) > 0, ref)
+    assert (np.diff(B.rowptr)[ref] == 32).all()
+    assert A.val.dtype == np.float32 and B.col.dtype == np.int32
 
 
 def test_banded_constraint():

@@ -55,6 +55,8 @@ def _load():
         lib.wl_draw.restype = u64
         lib.wl_er.argtypes = [i64, i64, i32, u64, P, P, i32, i32]
         lib.wl_er.restype = i32
+        lib.wl_er_wide.argtypes = [i64, i64, i32, u64, P, P, P, i32, i32]
+        lib.wl_er_wide.restype = i64
         lib.wl_banded.argtypes = [i64, i64, i32, u64, P, P, i32, i32]
         lib.wl_banded.restype = i64
         lib.wl_rmat.argtypes = [i32, i64, dbl, dbl, dbl, u64, i32, P, P, i32, i32]
@@ -124,6 +126,29 @@ def erdos_renyi(n: int, m: int, d: int, seed_: int, *, val_kind="uniform", val_d
                    {"kind": "er", "d": d, "seed": seed_})
 
 
+def erdos_renyi_wide(n: int, m: int, d: int, seed_: int, *, rows_mask=None, val_kind="uniform",
+                     val_dtype=np.float32, rowptr_dtype=np.int64, col_dtype=np.int32) -> CSR:
+    """n x m with d distinct uniform columns in each row that rows_mask names
+    (every row if None), the other rows empty; for m >= 2d, fast for large d."""
+    col_dtype = np.dtype(col_dtype)
+    if m > np.iinfo(col_dtype).max + 1:
+        raise ValueError("column type too narrow for m")
+    rowptr = np.empty(n + 1, dtype=np.int64)
+    if rows_mask is not None:
+        rows_mask = np.ascontiguousarray(rows_mask, dtype=np.uint8)
+        assert rows_mask.shape == (n,)
+        nr = int(rows_mask.sum())
+    else:
+        nr = n
+    col = np.empty(nr * d, dtype=col_dtype)
+    nnz = _load().wl_er_wide(n, m, d, seed_, None if rows_mask is None else _ptr(rows_mask),
+                             _ptr(rowptr), _ptr(col), col_dtype.itemsize, 0)
+    if nnz < 0:
+        raise ValueError("wl_er_wide failed")
+    return _finish(n, m, rowptr, col, seed_ + 7919, val_kind, val_dtype, rowptr_dtype,
+                   {"kind": "er_wide", "d": d, "seed": seed_})
+
+
 def banded(n: int, w: int, k: int, seed_: int, *, val_kind="uniform", val_dtype=np.float64,
            rowptr_dtype=np.int64, col_dtype=np.int32) -> CSR:
     """n x n: diagonal plus k distinct uniform columns within |i-j| <= w."""
@@ -185,6 +210,28 @@ def config3(logn: int = 24, d: int = 16):
                     rowptr_dtype=np.int64, col_dtype=np.int32)
     B = erdos_renyi(n, n, d, seed(33), val_kind="uniform", val_dtype=np.float32,
                     rowptr_dtype=np.int64, col_dtype=np.int32)
+    return A, B
+
+
+def massive_er(log_mc: int, d: int = 1024, nrows: int = 4096):
+    """The uniform random test set of Section 4.3 (Fig. 9): C has `nrows` rows
+    and 2^log_mc columns; every row of A has d distinct uniform columns and
+    every row of B that A references has d distinct uniform columns in
+    [0, 2^log_mc); the rows of B that no entry of A references are empty.
+
+    A's column space (the rows of B) is nrows * d wide instead of 2^log_mc:
+    only referenced rows of B exist either way, so the product has the same
+    statistics, and B's row pointers stay small.  f32 values uniform in
+    [-1, 1); int64 row pointers; int32 columns up to 2^31 columns, int64
+    beyond."""
+    mc = 1 << log_mc
+    k = nrows * d
+    A = erdos_renyi_wide(nrows, k, d, seed(6), val_dtype=np.float32,
+                         col_dtype=np.int32 if k <= (1 << 31) else np.int64)
+    mask = np.zeros(k, dtype=np.uint8)
+    mask[A.col] = 1
+    B = erdos_renyi_wide(k, mc, d, seed(66), rows_mask=mask, val_dtype=np.float32,
+                         col_dtype=np.int32 if mc <= (1 << 31) else np.int64)
     return A, B
 
 

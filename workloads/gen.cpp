@@ -11,6 +11,8 @@
 // Patterns:
 //   * Erdos-Renyi with exactly d distinct uniform columns per row (Floyd's
 //     sampling without replacement, then sorted);
+//   * the same for wide rows with many entries (d draws, sorted, duplicates
+//     replaced by further draws), optionally only for the rows a mask names;
 //   * R-MAT (Chakrabarti, Zhan, Faloutsos 2004) with quadrant probabilities
 //     (a, b, c, d); the first choice sets the most significant bit; duplicate
 //     edges merged; no noise and no vertex permutation;
@@ -79,7 +81,24 @@ inline void floyd_sorted(uint64_t key, uint64_t ctr0, int64_t m, int d, int64_t*
   std::sort(out, out + d);
 }
 
-enum { STREAM_ER = 1, STREAM_RMAT = 2, STREAM_BAND = 3, STREAM_VAL = 4 };
+enum { STREAM_ER = 1, STREAM_RMAT = 2, STREAM_BAND = 3, STREAM_VAL = 4, STREAM_ERW = 5 };
+
+// d distinct uniform values in [0, m) (m >= 2d), sorted: draw d, sort, drop
+// duplicates, top up with the next draws of the row's counter range (at most
+// `budget` draws); false if the range runs out.
+inline bool draw_sorted_distinct(uint64_t key, uint64_t ctr0, uint64_t budget, int64_t m, int d,
+                                 std::vector<int64_t>& out) {
+  out.clear();
+  uint64_t used = 0;
+  while ((int)out.size() < d) {
+    const int need = d - (int)out.size();
+    if (used + (uint64_t)need > budget) return false;
+    for (int q = 0; q < need; ++q) out.push_back((int64_t)below(draw(key, ctr0 + used++), (uint64_t)m));
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+  }
+  return true;
+}
 
 }  // namespace
 
@@ -104,6 +123,33 @@ int wl_er(int64_t n, int64_t m, int d, uint64_t seed, int64_t* rowptr, void* col
     }
   });
   return 0;
+}
+
+// Wide Erdos-Renyi: rows i with mask[i] != 0 (every row when mask is null)
+// hold d distinct uniform columns in [0, m), the other rows are empty; needs
+// m >= 2d.  Row i draws from counters [8di, 8d(i+1)).  Returns nnz (rowptr
+// int64[n+1]; col capacity = d * rows named), or -1.
+int64_t wl_er_wide(int64_t n, int64_t m, int d, uint64_t seed, const uint8_t* mask,
+                   int64_t* rowptr, void* col, int col_width, int nthreads) {
+  if (d < 0 || m < 2 * (int64_t)d) return -1;
+  const uint64_t key = stream_key(seed, STREAM_ERW);
+  rowptr[0] = 0;
+  for (int64_t i = 0; i < n; ++i) rowptr[i + 1] = rowptr[i] + ((!mask || mask[i]) ? d : 0);
+  std::atomic<int> bad{0};
+  parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+    std::vector<int64_t> buf;
+    buf.reserve(2 * (size_t)d + 1);
+    for (int64_t i = lo; i < hi; ++i) {
+      if (mask && !mask[i]) continue;
+      const uint64_t budget = 8 * (uint64_t)d;
+      if (!draw_sorted_distinct(key, (uint64_t)i * budget, budget, m, d, buf)) {
+        bad = 1;
+        return;
+      }
+      for (int q = 0; q < d; ++q) put_idx(col, col_width, rowptr[i] + q, buf[q]);
+    }
+  });
+  return bad ? -1 : rowptr[n];
 }
 
 // Banded: n x n, each row holds the diagonal plus k distinct uniform columns j
