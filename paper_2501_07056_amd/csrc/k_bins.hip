@@ -841,12 +841,16 @@ __global__ void __launch_bounds__(1024)
   const int64_t wpt = (nwords + BS - 1) / BS;
   const int64_t w0 = t * wpt, w1 = (w0 + wpt < nwords) ? (w0 + wpt) : nwords;
   const int wv = t / MG_WAVE, nw = BS / MG_WAVE;
+  // the next item's index is fetched while the current one is processed
+  unsigned int nxt = 0;
+  if (t == 0) nxt = atomicAdd(work, 1u);
   for (;;) {
     __syncthreads();
-    if (t == 0) sh_item = atomicAdd(work, 1u);
+    if (t == 0) sh_item = nxt;
     __syncthreads();
     const int64_t it = sh_item;
     if (it >= nitems) break;
+    if (t == 0) nxt = atomicAdd(work, 1u);
     const int64_t gb = items[item_base + it];
     const int64_t s0 = bin_start[gb], cnt = bin_cnt[gb];
     int64_t q = t;
