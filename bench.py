@@ -166,7 +166,6 @@ KERNEL_SYMBOLS = {
     "rowinfo (setup)": [("k_rowinfo<",)],
     "coarse_scatter (numeric, level 1)": [("k_bin_scatter2<", "unsigned int, true")],
     "fine_scatter (numeric, level 2)": [("k_l2_scatter<", "true>")],
-    "bin_accum (numeric, coarse rows)": [("k_accum_dense<", "true>"), ("k_accum_sort<", "true>")],
     "coarse_reorder (symbolic, level 1)": [("k_bin_hist<",),
                                            ("k_bin_scatter2<", "unsigned int, false")],
     "coarse_bitmap (symbolic, level 2)": [("k_vrow_bitmap",)],

@@ -11,6 +11,10 @@ imports it.
 * ``chunk_model`` -- the chunk-count model, Eqs. 2-7 of Section 3.5, as printed.
 * ``reorder``     -- the fine-level histogram / prefix-sum / reorder steps of
                      Section 3.2 (Algorithm 3) on one row's products.
+* ``coarse``      -- the coarse level of Section 3.3 (Algorithm 4): coarseRowsB,
+                     the CSC form of the coarse rows, the outer-product
+                     histogram and reorder into coarse chunks, and the fine
+                     level inside each coarse chunk.
 * ``ideal_volume``-- the ideal data volume of Section 4.3 (read and write
                      volumes, Eqs. 8-9).
 """
@@ -27,6 +31,7 @@ from .chunk_model import (paper_fine_nchunks, paper_mcmax, paper_model, pow2_flo
                           pow2_nearest, pow2_ceil)
 from .volume import ideal_volume  # noqa: F401
 from .reorder import reorder_row  # noqa: F401
+from . import coarse  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")

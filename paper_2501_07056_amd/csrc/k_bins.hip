@@ -174,6 +174,11 @@ __global__ void k_tile_e0(const RP* __restrict__ arp, ChunkGeom g, const int32_t
   tile_e0[t] = lo;
 }
 
+// products gathered per lane before any is used (count-only expansions)
+#ifndef MG_EXPAND_UNROLL
+#define MG_EXPAND_UNROLL 4
+#endif
+
 // Calls f(q, col, prod) for every product q in [0, p1 - p0) of a row's
 // product range [p0, p1) (the order of Eq. 1), where col is the product's
 // column and prod = a_ij * b_jk (only when WANT_VAL).  The A entries
@@ -187,7 +192,8 @@ __global__ void k_tile_e0(const RP* __restrict__ arp, ChunkGeom g, const int32_t
 // group's start and the next group's start (0 steps inside long B rows, a
 // few for short ones).  Four products per thread are gathered before any is
 // used.  Offsets into B are 32-bit when B's row pointers are.
-template <int BS, typename RP, typename CI, typename V, bool WANT_VAL, typename F>
+template <int BS, typename RP, typename CI, typename V, bool WANT_VAL, typename F,
+          int U = MG_EXPAND_UNROLL>
 MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
                                const CI* __restrict__ acol, const V* __restrict__ aval,
                                const RP* __restrict__ brp, const CI* __restrict__ bcol,
@@ -235,12 +241,12 @@ MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
       if (t == 0) s_grp[NG] = nvalid - 1;
       __syncthreads();
       const int32_t ngr = (s1 - s0 + MG_WAVE - 1) / MG_WAVE;
-      for (int32_t qb = s0 + t; qb < s1; qb += 4 * BS) {
-      OFF bi[4];
-      V a4[4];
-      bool ok[4];
+      for (int32_t qb = s0 + t; qb < s1; qb += U * BS) {
+      OFF bi[U];
+      V a4[U];
+      bool ok[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int32_t q = qb + u * BS;
         ok[u] = q < s1;
         bi[u] = 0;
@@ -254,15 +260,15 @@ MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
           if (WANT_VAL) a4[u] = w_av[k];
         }
       }
-      CI c4[4];
-      V v4[4];
+      CI c4[U];
+      V v4[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         c4[u] = ok[u] ? bcol[bi[u]] : (CI)0;
         if (WANT_VAL) v4[u] = ok[u] ? a4[u] * bval[bi[u]] : (V)0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < U; ++u)
         if (ok[u]) f(qb + u * BS, c4[u], WANT_VAL ? v4[u] : (V)0);
       }
       __syncthreads();

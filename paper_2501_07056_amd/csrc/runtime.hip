@@ -489,7 +489,8 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
     unsigned int* wk = C.work + 4 * bi;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
     {
-      ProfScope ps(h, P->st, "bin_accum (numeric, coarse rows)",
+      // the kernels of the CHUNKED rows' accumulation, under the same name
+      ProfScope ps(h, P->st, "bin_accum (numeric, dense+sort chunks)",
                    (double)b.nip * (2 + vs) + (double)b.nnz_out * (P->s_col + vs));
       HIPCHK(launch_bin_accum(C.g2, b2, true, P->M.f64, C.start2, C.cnt2, C.row2, C.dense2,
                               C.sort2, C.item_counts + 2 * bi, C.ws2_col, C.ws2_val, C.nnz2,
