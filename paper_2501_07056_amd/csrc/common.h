@@ -10,6 +10,12 @@
 
 namespace mg {
 
+// A dispatch counts its work-items (grid x block) in 32 bits: a launch of
+// 2^32 or more work-items runs a truncated grid and reports no error.
+// Launches whose grid grows with the data are cut into pieces of at most
+// max_grid(block) blocks.
+inline int64_t max_grid(int block) { return (int64_t)(0xFFFFFFFFull / (unsigned)block); }
+
 // -------------------------------------------------------------------------
 // Index widths: A and B share a row pointer type RP and a column type CI.
 // -------------------------------------------------------------------------

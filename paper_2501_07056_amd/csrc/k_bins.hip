@@ -334,9 +334,10 @@ template <typename RP, typename CI>
 __global__ void __launch_bounds__(RB_BS)
     k_row_bitmap(const RP* __restrict__ arp, const CI* __restrict__ acol, const RP* __restrict__ brp,
                  const CI* __restrict__ bcol, ChunkGeom g, const int64_t* __restrict__ aoff,
-                 int64_t* bin_nnz, int64_t* bin_cnt, int32_t* bin_row, int64_t* rownnz) {
+                 int64_t* bin_nnz, int64_t* bin_cnt, int32_t* bin_row, int64_t* rownnz,
+                 int64_t k0) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  const int64_t k = blockIdx.x;
+  const int64_t k = k0 + blockIdx.x;
   const int32_t row = g.rows[k];
   const int64_t nbk = g.nb[k], bb = g.binBase[k];
   const int sh = g.shift;
@@ -528,8 +529,8 @@ __global__ void __launch_bounds__(BIN_BS)
 // per coarse row k (one wave): the column base, last column and fine chunk
 // count of each of its coarse chunks
 __global__ void k_vrow_geom(ChunkGeom g1, int fshift, int64_t* minc2, int64_t* maxc2, int64_t* nb2,
-                            int32_t* ident) {
-  const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
+                            int32_t* ident, int64_t k0) {
+  const int64_t k = k0 + (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
   if (k >= g1.nch) return;
   const int32_t row = g1.rows[k];
   const int cs = g1.shift;
@@ -741,8 +742,8 @@ __global__ void __launch_bounds__(BS)
 }
 
 // the virtual row of every fine chunk (one wave per virtual row)
-__global__ void k_vrow_rows(ChunkGeom g2, int32_t* row2) {
-  const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
+__global__ void k_vrow_rows(ChunkGeom g2, int32_t* row2, int64_t k0) {
+  const int64_t k = k0 + (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
   if (k >= g2.nch) return;
   const int64_t bb = g2.binBase[k], nbk = g2.nb[k];
   for (int64_t q = lane(); q < nbk; q += MG_WAVE) row2[bb + q] = (int32_t)k;
@@ -1033,12 +1034,12 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
                  const int64_t* __restrict__ bin_cnt, const int32_t* __restrict__ bin_row,
                  const uint16_t* __restrict__ ws_col, const V* __restrict__ ws_val,
                  int64_t* bin_nnz, const int64_t* __restrict__ bin_out, void* ccol_, int col64,
-                 V* cval) {
+                 V* cval, int64_t it0) {
   __shared__ int64_t s_bs[AS_WAVES][MG_WAVE];
   __shared__ int32_t s_cnt[AS_WAVES][MG_WAVE];
   __shared__ V s_v[AS_WAVES][NUMERIC ? SORT_CAP : 1];
   const int w = threadIdx.x / MG_WAVE;
-  const int64_t it = (int64_t)blockIdx.x * AS_WAVES + w;
+  const int64_t it = it0 + (int64_t)blockIdx.x * AS_WAVES + w;
   if (it >= item_counts[1]) return;
   const int64_t g0 = items[2 * (item_base + it)];
   const int nbg = (int)items[2 * (item_base + it) + 1];
@@ -1080,10 +1081,14 @@ __global__ void k_bin_rows(ChunkGeom g, int64_t k0, int64_t k1, const int64_t* b
 // ---------------------------------------------------------------------------
 hipError_t launch_aoff(const Mats& M, const int32_t* rows, int64_t nrows, int64_t* aoff,
                        int64_t* ent, hipStream_t st) {
-  if (nrows <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((nrows + 3) / 4);
-  MG_DISPATCH2(M, hipLaunchKernelGGL((k_aoff<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
-                                      (const CI*)M.acol, (const RP*)M.brp, rows, nrows, aoff, ent));
+  const int64_t cap = max_grid(256) * 4;  // one wave per row, four per block
+  for (int64_t o = 0; o < nrows; o += cap) {
+    const int64_t n = std::min(cap, nrows - o);
+    const unsigned grid = (unsigned)((n + 3) / 4);
+    MG_DISPATCH2(M, hipLaunchKernelGGL((k_aoff<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
+                                        (const CI*)M.acol, (const RP*)M.brp, rows + o, n, aoff,
+                                        ent + o));
+  }
   return hipGetLastError();
 }
 
@@ -1092,13 +1097,19 @@ hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b
                             int64_t* bin_cnt, int32_t* bin_row, int64_t max_nb, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
   const size_t lds = BIN_BS * 8 * 2 + (size_t)max_nb * 4 + 64;
-  MG_DISPATCH2(M, {
-    auto kf = k_bin_hist<RP, CI>;
-    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,
-                       (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, b, tile_row,
-                       aoff, tile_e0, (unsigned long long*)bin_cnt, bin_row);
-  });
+  const int64_t cap = max_grid(BIN_BS);
+  for (int64_t o = 0; o < b.ntiles; o += cap) {
+    BatchArgs bp = b;
+    bp.tile0 = b.tile0 + o;
+    bp.ntiles = std::min(cap, b.ntiles - o);
+    MG_DISPATCH2(M, {
+      auto kf = k_bin_hist<RP, CI>;
+      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, (const RP*)M.arp,
+                         (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, bp, tile_row,
+                         aoff, tile_e0, (unsigned long long*)bin_cnt, bin_row);
+    });
+  }
   return hipGetLastError();
 }
 hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric, int f64,
@@ -1112,7 +1123,9 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
   if (b.nbins <= 0) return hipSuccess;
   const size_t lds = bin_dense_lds(f64, g.shift);
   const unsigned gd = (unsigned)std::min<int64_t>(b.nbins, persistent_wgs);
-  const unsigned gs = (unsigned)((b.nbins + AS_WAVES - 1) / AS_WAVES);
+  // sort items: at most one per chunk; the grid is cut below 2^32 work-items
+  const int64_t gs_all = (b.nbins + AS_WAVES - 1) / AS_WAVES;
+  const int64_t gcap = max_grid(AS_WAVES * MG_WAVE);
 #define MG_AC(V)                                                                                  \
   {                                                                                               \
     auto kd = numeric ? k_accum_dense<V, true> : k_accum_dense<V, false>;                         \
@@ -1121,9 +1134,11 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
                        bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
                        ccol, col64, (V*)cval, work);                                              \
     auto ks = numeric ? k_accum_sort<V, true> : k_accum_sort<V, false>;                           \
-    hipLaunchKernelGGL(ks, gs, AS_WAVES * MG_WAVE, 0, st, g, sort_items, item_counts, b.bin0,     \
-                       bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
-                       ccol, col64, (V*)cval);                                                    \
+    for (int64_t o = 0; o < gs_all; o += gcap)                                                    \
+      hipLaunchKernelGGL(ks, (unsigned)std::min(gcap, gs_all - o), AS_WAVES * MG_WAVE, 0, st, g,  \
+                         sort_items, item_counts, b.bin0, bin_start, bin_cnt, bin_row, ws_col,    \
+                         (const V*)ws_val, bin_nnz, bin_out, ccol, col64, (V*)cval,               \
+                         o * AS_WAVES);                                                           \
   }
   if (f64) MG_AC(double) else MG_AC(float)
 #undef MG_AC
@@ -1135,13 +1150,16 @@ hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* a
                              int64_t* rownnz, hipStream_t st) {
   if (g.nch <= 0) return hipSuccess;
   const size_t lds = row_bitmap_lds(g.shift, max_nb);
-  MG_DISPATCH2(M, {
-    auto kf = k_row_bitmap<RP, CI>;
-    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kf, (unsigned)g.nch, RB_BS, lds, st, (const RP*)M.arp, (const CI*)M.acol,
-                       (const RP*)M.brp, (const CI*)M.bcol, g, aoff, bin_nnz, bin_cnt, bin_row,
-                       rownnz);
-  });
+  const int64_t cap = max_grid(RB_BS);
+  for (int64_t o = 0; o < g.nch; o += cap) {
+    MG_DISPATCH2(M, {
+      auto kf = k_row_bitmap<RP, CI>;
+      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(kf, (unsigned)std::min(cap, g.nch - o), RB_BS, lds, st, (const RP*)M.arp,
+                         (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, aoff, bin_nnz,
+                         bin_cnt, bin_row, rownnz, o);
+    });
+  }
   return hipGetLastError();
 }
 
@@ -1165,6 +1183,11 @@ hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArg
                                int64_t max_nb, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
   const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb, lc32, sorted);
+  const int64_t cap = max_grid(BIN_BS);
+  for (int64_t o = 0; o < b.ntiles; o += cap) {
+    BatchArgs bp = b;
+    bp.tile0 = b.tile0 + o;
+    bp.ntiles = std::min(cap, b.ntiles - o);
 #define MG_SC2(V, LC)                                                                             \
   MG_DISPATCH2(M, {                                                                               \
     auto kf = numeric ? (sorted ? k_bin_scatter2<RP, CI, V, LC, true, true>                        \
@@ -1172,17 +1195,18 @@ hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArg
                       : (sorted ? k_bin_scatter2<RP, CI, V, LC, false, true>                       \
                                 : k_bin_scatter2<RP, CI, V, LC, false, false>);                    \
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-    hipLaunchKernelGGL(kf, (unsigned)b.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                 \
+    hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
-                       (const V*)M.bval, g, b, tile_row, aoff, tile_e0, bin_start, bin_cursor,    \
+                       (const V*)M.bval, g, bp, tile_row, aoff, tile_e0, bin_start, bin_cursor,   \
                        (LC*)ws_col, (V*)ws_val);                                                  \
   });
-  if (lc32) {
-    if (M.f64) { MG_SC2(double, uint32_t) } else { MG_SC2(float, uint32_t) }
-  } else {
-    if (M.f64) { MG_SC2(double, uint16_t) } else { MG_SC2(float, uint16_t) }
-  }
+    if (lc32) {
+      if (M.f64) { MG_SC2(double, uint32_t) } else { MG_SC2(float, uint32_t) }
+    } else {
+      if (M.f64) { MG_SC2(double, uint16_t) } else { MG_SC2(float, uint16_t) }
+    }
 #undef MG_SC2
+  }
   return hipGetLastError();
 }
 
@@ -1191,22 +1215,31 @@ hipError_t launch_l2_hist(const ChunkGeom& g2, const BatchArgs& b2, const int32_
                           int64_t max_nb2, hipStream_t st) {
   if (b2.ntiles <= 0) return hipSuccess;
   const size_t lds = (size_t)max_nb2 * 4 + 64;
-  hipLaunchKernelGGL(k_l2_hist<512>, (unsigned)b2.ntiles, 512, lds, st, g2, b2, tile_row2, start1,
-                     ws1_col, (unsigned long long*)cnt2);
+  const int64_t cap = max_grid(512);
+  for (int64_t o = 0; o < b2.ntiles; o += cap) {
+    BatchArgs bp = b2;
+    bp.tile0 = b2.tile0 + o;
+    bp.ntiles = std::min(cap, b2.ntiles - o);
+    hipLaunchKernelGGL(k_l2_hist<512>, (unsigned)bp.ntiles, 512, lds, st, g2, bp, tile_row2,
+                       start1, ws1_col, (unsigned long long*)cnt2);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_vrow_rows(const ChunkGeom& g2, int32_t* row2, hipStream_t st) {
-  if (g2.nch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vrow_rows, (unsigned)((g2.nch + 3) / 4), 256, 0, st, g2, row2);
+  const int64_t cap = max_grid(256) * 4;  // one wave per virtual row
+  for (int64_t o = 0; o < g2.nch; o += cap)
+    hipLaunchKernelGGL(k_vrow_rows, (unsigned)((std::min(cap, g2.nch - o) + 3) / 4), 256, 0, st,
+                       g2, row2, o);
   return hipGetLastError();
 }
 
 hipError_t launch_vrow_geom(const ChunkGeom& g1, int fshift, int64_t* minc2, int64_t* maxc2,
                             int64_t* nb2, int32_t* ident, hipStream_t st) {
-  if (g1.nch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vrow_geom, (unsigned)((g1.nch + 3) / 4), 256, 0, st, g1, fshift, minc2,
-                     maxc2, nb2, ident);
+  const int64_t cap = max_grid(256) * 4;  // one wave per coarse row
+  for (int64_t o = 0; o < g1.nch; o += cap)
+    hipLaunchKernelGGL(k_vrow_geom, (unsigned)((std::min(cap, g1.nch - o) + 3) / 4), 256, 0, st,
+                       g1, fshift, minc2, maxc2, nb2, ident, o);
   return hipGetLastError();
 }
 
@@ -1226,8 +1259,10 @@ hipError_t launch_vrow_bitmap(const ChunkGeom& g2, int cshift, int64_t k0, int64
   const size_t lds = vrow_bitmap_lds(cshift, max_nb2);
   hipFuncSetAttribute((const void*)k_vrow_bitmap, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
-  hipLaunchKernelGGL(k_vrow_bitmap, (unsigned)(k1 - k0), VB_BS, lds, st, g2, k0, start1, ws1_col,
-                     bin_cnt2, bin_nnz2, bin_row2, vnnz);
+  const int64_t cap = max_grid(VB_BS);
+  for (int64_t o = k0; o < k1; o += cap)
+    hipLaunchKernelGGL(k_vrow_bitmap, (unsigned)std::min(cap, k1 - o), VB_BS, lds, st, g2, o,
+                       start1, ws1_col, bin_cnt2, bin_nnz2, bin_row2, vnnz);
   return hipGetLastError();
 }
 
@@ -1238,12 +1273,19 @@ hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool nume
                              uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, hipStream_t st) {
   if (b2.ntiles <= 0) return hipSuccess;
   const size_t lds = l2_scatter_lds(f64, g2.tile, max_nb2);
+  const int64_t cap = max_grid(BIN_BS);
 #define MG_L2(V)                                                                                  \
   {                                                                                               \
     auto kf = numeric ? k_l2_scatter<V, true> : k_l2_scatter<V, false>;                           \
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-    hipLaunchKernelGGL(kf, (unsigned)b2.ntiles, BIN_BS, lds, st, g2, b2, tile_row2, start1,       \
-                       ws1_col, (const V*)ws1_val, bin_start2, bin_cursor2, ws2_col, (V*)ws2_val); \
+    for (int64_t o = 0; o < b2.ntiles; o += cap) {                                                \
+      BatchArgs bp = b2;                                                                          \
+      bp.tile0 = b2.tile0 + o;                                                                    \
+      bp.ntiles = std::min(cap, b2.ntiles - o);                                                   \
+      hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, g2, bp, tile_row2, start1,     \
+                         ws1_col, (const V*)ws1_val, bin_start2, bin_cursor2, ws2_col,            \
+                         (V*)ws2_val);                                                            \
+    }                                                                                             \
   }
   if (f64) MG_L2(double) else MG_L2(float)
 #undef MG_L2

@@ -470,7 +470,10 @@ static hipError_t dense_rows_t(const RowSrc& src, bool numeric, const int32_t* l
   hipError_t e =
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, (unsigned)count, block, lds, st, src, list, minc, maxc, shift, rownnz, crp);
+  const int64_t cap = max_grid(block);  // one workgroup per row
+  for (int64_t o = 0; o < count; o += cap)
+    hipLaunchKernelGGL(k, (unsigned)std::min(cap, count - o), block, lds, st, src, list + o, minc,
+                       maxc, shift, rownnz, crp);
   return hipGetLastError();
 }
 
@@ -548,8 +551,11 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
   if (i < n) p[i] = v;
 }
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i64, (unsigned)((n + 255) / 256), 256, 0, st, p, n, v);
+  const int64_t cap = max_grid(256) * 256;
+  for (int64_t o = 0; o < n; o += cap) {
+    const int64_t m = std::min(cap, n - o);
+    hipLaunchKernelGGL(k_fill_i64, (unsigned)((m + 255) / 256), 256, 0, st, p + o, m, v);
+  }
   return hipGetLastError();
 }
 

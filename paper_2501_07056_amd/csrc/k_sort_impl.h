@@ -268,20 +268,34 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
 }
 
 template <typename RP, typename CI, typename V, int E, typename K>
-static hipError_t sort_rows_t(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
-                              int R, int colbits, const int64_t* minc, int64_t* rownnz,
-                              const int64_t* crp, DevStats* stats, hipStream_t st) {
-  const int64_t tiles = (count + R - 1) / R;
-  const unsigned grid = (unsigned)((tiles + SR_WAVES - 1) / SR_WAVES);
-  if (grid == 0) return hipSuccess;
+static void sort_rows_launch(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
+                             int R, int colbits, const int64_t* minc, int64_t* rownnz,
+                             const int64_t* crp, DevStats* stats, unsigned grid, hipStream_t st) {
+  if (grid == 0) return;
   if (numeric)
     hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, true>), grid, SR_WAVES * MG_WAVE, 0, st, src,
                        list, count, R, colbits, minc, rownnz, crp, stats);
   else
     hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, false>), grid, SR_WAVES * MG_WAVE, 0, st, src,
                        list, count, R, colbits, minc, rownnz, crp, stats);
+}
+
+template <typename RP, typename CI, typename V, int E, typename K>
+static hipError_t sort_rows_t(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
+                              int R, int colbits, const int64_t* minc, int64_t* rownnz,
+                              const int64_t* crp, DevStats* stats, hipStream_t st) {
+  // a wave takes R rows; pieces of at most max_grid blocks of SR_WAVES waves
+  const int64_t rows_cap = max_grid(SR_WAVES * MG_WAVE) * SR_WAVES * R;
+  for (int64_t o = 0; o < count; o += rows_cap) {
+    const int64_t n = std::min(rows_cap, count - o);
+    const int64_t tiles = (n + R - 1) / R;
+    const unsigned grid = (unsigned)((tiles + SR_WAVES - 1) / SR_WAVES);
+    sort_rows_launch<RP, CI, V, E, K>(src, numeric, list + o, n, R, colbits, minc, rownnz, crp,
+                                      stats, grid, st);
+  }
   return hipGetLastError();
 }
+
 
 template <typename RP, typename CI, typename V>
 hipError_t sort_rows_cls(const RowSrc& src, int cls, bool numeric, const int32_t* list,
