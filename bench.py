@@ -534,6 +534,104 @@ def serve_main(args, opts):
     print(json.dumps(out), flush=True)
 
 
+def micro_main(args, opts):
+    """Building blocks on one stream of products (the microbenchmarks of
+    Section 4.1, Figs. 5-6): L products with columns uniform in [0, m) and
+    f32 values, cut into m / 2^s chunks by histogram, prefix sum and reorder,
+    then each chunk counted and summed; every stage is event-timed.  The
+    reference is the streaming time of the paper: a plain copy of the
+    stream's bytes (columns and values read and written once) with the
+    library's copy kernel."""
+    import torch
+
+    import paper_2501_07056_amd as mg
+    ctx = mg.Context(0, **opts)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2501070560)
+    rows = []
+    for lg_l in (22, 24, 26):
+        L = 1 << lg_l
+        vals = torch.rand(L, generator=g, device="cuda", dtype=torch.float32) * 2 - 1
+        src = torch.zeros(2 * L, dtype=torch.float32, device="cuda")
+        dst = torch.zeros_like(src)
+        for _ in range(2):
+            ctx.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(3):
+            ctx.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        ck = ctx.profile_read()[0]
+        ctx.profile(False)
+        t_stream = ck["ms"] / ck["launches"]
+        del src, dst
+        for lg_m in (16, 20, 24, 26):
+            m = 1 << lg_m
+            cols = torch.randint(0, m, (L,), generator=g, device="cuda", dtype=torch.int32)
+            for s in (10, 12, 14):
+                if (m >> s) > 8191 or (m >> s) < 1:
+                    continue
+                best = None
+                for _ in range(3):
+                    _, _, t = ctx.stream_chunks(cols, vals, m, s)
+                    tot = (t["histogram_ms"] + t["scan_ms"] + t["reorder_ms"] + t["group_ms"] +
+                           t["count_ms"] + t["accumulate_ms"])
+                    if best is None or tot < best[0]:
+                        best = (tot, t)
+                tot, t = best
+                gb = L * 8 / 1e9  # the stream: 32-bit column and f32 value
+                row = {"L": L, "m": m, "chunk_shift": s, "chunks": t["chunks"],
+                       "products_per_chunk": L / t["chunks"], "dense_chunks": t["dense_chunks"],
+                       "sort_groups": t["sort_groups"], "total_ms": round(tot, 3),
+                       "streaming_ms": round(t_stream, 3),
+                       "multiple_of_streaming": round(tot / t_stream, 2),
+                       "histogram_GBps": round(L * 4 / 1e9 / (t["histogram_ms"] / 1e3), 1),
+                       "reorder_GBps": round(L * (8 + 6) / 1e9 / (t["reorder_ms"] / 1e3), 1),
+                       "count_GBps": round(L * 2 / 1e9 / (t["count_ms"] / 1e3), 1),
+                       "accumulate_GBps": round(L * 6 / 1e9 / (t["accumulate_ms"] / 1e3), 1),
+                       "stage_ms": {k: round(t[k], 3) for k in ("histogram_ms", "scan_ms",
+                                                                  "reorder_ms", "group_ms",
+                                                                  "count_ms", "accumulate_ms")}}
+                rows.append(row)
+                log(f"[bench] L=2^{lg_l} m=2^{lg_m} chunks={t['chunks']}: {tot:.2f} ms "
+                    f"= {tot / t_stream:.2f}x streaming ({gb:.2f} GB stream)")
+            del cols
+    # accumulators against the products per chunk (Fig. 4): 4096 chunks of
+    # 2^13 columns, every chunk dense (dense_min = 1) or sorted wherever it
+    # holds at most 1024 products (dense_min = 1025)
+    acc = []
+    m = 1 << 25
+    for lg_l in (19, 20, 21, 22):
+        L = 1 << lg_l
+        cols = torch.randint(0, m, (L,), generator=g, device="cuda", dtype=torch.int32)
+        vals = torch.rand(L, generator=g, device="cuda", dtype=torch.float32)
+        for dmin, kind in ((1, "dense"), (1025, "sort")):
+            best = None
+            for _ in range(3):
+                _, _, t = ctx.stream_chunks(cols, vals, m, 13, dmin)
+                tt = t["count_ms"] + t["accumulate_ms"]
+                if best is None or tt < best[0]:
+                    best = (tt, t)
+            tt, t = best
+            acc.append({"products_per_chunk": L / 4096, "accumulator": kind,
+                        "dense_chunks": t["dense_chunks"], "sort_groups": t["sort_groups"],
+                        "count_ms": round(t["count_ms"], 4),
+                        "accumulate_ms": round(t["accumulate_ms"], 4),
+                        "Gproducts_per_s": round(L / (t["accumulate_ms"] / 1e3) / 1e9, 1)})
+            log(f"[bench] {L // 4096} products per chunk, {kind}: count {t['count_ms']:.3f} ms, "
+                f"sum {t['accumulate_ms']:.3f} ms")
+        del cols, vals
+    ctx.close()
+    best = min(rows, key=lambda r: r["multiple_of_streaming"])
+    out = {"metric": "building blocks on one stream: time as a multiple of the streaming time",
+           "value": best["multiple_of_streaming"], "unit": "x streaming", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "one stream of L products, columns uniform in [0, m), "
+                                  "chunks of 2^s columns", "options": opts},
+           "sweep": rows, "accumulators": acc, "src_sha": src_digest()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,7 +639,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat20",
                     help="rmat<scale> | er<log n> | cfg1 | mer<log m_C> (massive uniform random, "
-                         "Section 4.3) | batch | serve")
+                         "Section 4.3) | batch | serve | micro (building blocks, Section 4.1)")
     ap.add_argument("--mer-d", type=int, default=1024,
                     help="entries per row of A and of B for --workload mer<log m_C>")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -587,6 +685,9 @@ def main():
         return
     if args.workload == "serve":
         serve_main(args, opts)
+        return
+    if args.workload == "micro":
+        micro_main(args, opts)
         return
 
     import numpy as np

@@ -234,6 +234,37 @@ magnus_status_t magnus_stream_copy(magnus_handle_t h, void* dst, const void* src
 magnus_status_t magnus_exclusive_scan_i64(magnus_handle_t h, const int64_t* in, int64_t* out,
                                           int64_t n, int64_t* total, void* stream);
 
+/* Building blocks on one stream of intermediate products (the reordering
+ * and accumulation microbenchmarks of Section 4.1, Figs. 4-6): the n
+ * products (cols[i], vals[i]) of one row are cut into chunks of
+ * 2^chunk_shift columns by a histogram, a prefix sum and a reorder
+ * (Algorithm 3); each chunk is then accumulated, by the dense accumulator
+ * (Algorithm 1) when it holds at least dense_min products and otherwise by
+ * sorting (Algorithm 2, consecutive small chunks packed into one sort),
+ * first counting its distinct columns (the precise symbolic phase) and then
+ * summing.  The same kernels run for CHUNKED rows.
+ *   cols: device uint32[n], each < m; vals: device, n values of val_type
+ *     (read only).
+ *   m: columns (m < 2^31; m >> chunk_shift chunks, at most 8191).
+ *   chunk_shift: log2 of the chunk length, 1..16, and its dense accumulator
+ *     must fit the LDS (magnus_gpu_chunk_shift gives the largest).
+ *   dense_min: 1..1025 (1025: every chunk of <= 1024 products is sorted; a
+ *     bigger one is always dense); 0: the library default.
+ *   out_cols (device int32[n]), out_vals (device, n values): the distinct
+ *     columns in ascending order with their sums; *nnz (host) receives how
+ *     many.  Workspace comes from the handle's allocator.
+ *   times (host, may be NULL): event milliseconds of each block.
+ * Synchronises the stream.  Errors: MAGNUS_ERR_INVALID_ARG for sizes out of
+ * range, MAGNUS_ERR_OOM. */
+typedef struct {
+  double histogram_ms, scan_ms, reorder_ms, group_ms, count_ms, accumulate_ms;
+  int64_t chunks, dense_chunks, sort_groups;
+} magnus_stream_times_t;
+magnus_status_t magnus_stream_chunks(magnus_handle_t h, const uint32_t* cols, const void* vals,
+                                     int32_t val_type, int64_t n, int64_t m, int32_t chunk_shift,
+                                     int32_t dense_min, int32_t* out_cols, void* out_vals,
+                                     int64_t* nnz, void* stream, magnus_stream_times_t* times);
+
 /* ------------------------------------------------------------------------
  * Batches of independent products C_b = A_b * B_b (b = 0 .. count-1).
  *

@@ -71,6 +71,16 @@ class ServerStats(ctypes.Structure):
                                      "budget_bytes", "queued", "running")]
 
 
+class StreamTimes(ctypes.Structure):
+    _fields_ = [("histogram_ms", ctypes.c_double), ("scan_ms", ctypes.c_double),
+                ("reorder_ms", ctypes.c_double), ("group_ms", ctypes.c_double),
+                ("count_ms", ctypes.c_double), ("accumulate_ms", ctypes.c_double),
+                ("chunks", c_i64), ("dense_chunks", c_i64), ("sort_groups", c_i64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", c_i64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -130,6 +140,8 @@ def load(path: str = LIB_PATH):
     lib.magnus_profile_enable.argtypes = [c_vp, c_i32]
     lib.magnus_profile_read.argtypes = [c_vp, P(KernelStat), c_i32, P(c_i32)]
     lib.magnus_stream_copy.argtypes = [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
+    lib.magnus_stream_chunks.argtypes = [c_vp, c_vp, c_vp, c_i32, c_i64, c_i64, c_i32, c_i32,
+                                         c_vp, c_vp, P(c_i64), c_vp, P(StreamTimes)]
     lib.magnus_batch_plan.argtypes = [c_vp, c_i32, P(CsrDesc), P(CsrDesc), P(c_i32), c_vp,
                                       P(c_vp), P(c_i64), P(PlanInfo)]
     lib.magnus_batch_execute.argtypes = [c_vp, c_vp, c_i32, P(CsrDesc), P(CsrDesc),

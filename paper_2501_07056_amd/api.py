@@ -169,6 +169,28 @@ class Context:
                                           ctypes.c_void_p(src.data_ptr()), nbytes, s),
               "magnus_stream_copy", self.handle)
 
+    def stream_chunks(self, cols: torch.Tensor, vals: torch.Tensor, m: int, chunk_shift: int,
+                      dense_min: int = 0, stream=None):
+        """The chunk building blocks on one stream of products (Section 4.1):
+        cols (device int32, each in [0, m)) and vals (device f32/f64).
+        Returns the distinct columns (ascending), their sums and the per-stage
+        event times."""
+        s, keep = _stream_ptr(stream)
+        assert cols.dtype == torch.int32 and cols.is_contiguous() and vals.is_contiguous()
+        assert vals.dtype in (torch.float32, torch.float64) and vals.numel() == cols.numel()
+        n = cols.numel()
+        out_c = torch.empty(max(n, 1), dtype=torch.int32, device=cols.device)
+        out_v = torch.empty(max(n, 1), dtype=vals.dtype, device=cols.device)
+        nnz = ctypes.c_int64()
+        t = _lib.StreamTimes()
+        vt = 1 if vals.dtype == torch.float64 else 0
+        check(self.lib.magnus_stream_chunks(
+            self.handle, ctypes.c_void_p(cols.data_ptr()) if n else None,
+            ctypes.c_void_p(vals.data_ptr()) if n else None, vt, n, int(m), int(chunk_shift),
+            int(dense_min), ctypes.c_void_p(out_c.data_ptr()), ctypes.c_void_p(out_v.data_ptr()),
+            ctypes.byref(nnz), s, ctypes.byref(t)), "magnus_stream_chunks", self.handle)
+        return out_c[:nnz.value], out_v[:nnz.value], t.as_dict()
+
     def batch_plan(self, pairs, sort_max=None, stream=None) -> "BatchPlan":
         """Plan C_b = A_b * B_b for every (A_b, B_b) in pairs as one batch.
         sort_max: optional per-product SORT thresholds."""

@@ -728,11 +728,22 @@ __global__ void __launch_bounds__(BS)
   const int sh = g2.shift;
   for (int64_t q = threadIdx.x; q < nbk; q += BS) hist[q] = 0;
   __syncthreads();
-  for (int32_t q = threadIdx.x; q < nloc; q += BS) {
-    const uint32_t f = ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + q]) >> sh;
-    int hl, len;
-    wave_run(f, hl, len);
-    if (lane() == hl) atomicAdd(&hist[f], len);
+  for (int32_t qb = threadIdx.x; qb < nloc; qb += 4 * BS) {
+    uint32_t c4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t q = qb + u * BS;
+      c4[u] = (q < nloc) ? ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + q]) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (qb + u * BS < nloc) {
+        const uint32_t f = c4[u] >> sh;
+        int hl, len;
+        wave_run(f, hl, len);
+        if (lane() == hl) atomicAdd(&hist[f], len);
+      }
+    }
   }
   __syncthreads();
   for (int64_t q = threadIdx.x; q < nbk; q += BS) {

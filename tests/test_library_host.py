@@ -48,6 +48,8 @@ def test_null_arguments_rejected_before_any_device_call():
     assert lib.magnus_server_create(0, None, None, None) == INVALID
     assert lib.magnus_server_submit(None, 0, 0, None) == INVALID
     assert lib.magnus_server_release(None, 1) == INVALID
+    assert lib.magnus_stream_chunks(None, None, None, 0, 0, 1, 4, 0, None, None, None, None,
+                                    None) == INVALID
     assert lib.magnus_plan_destroy(None) == 0
     assert lib.magnus_batch_plan_destroy(None) == 0
     assert lib.magnus_server_destroy(None) == 0
