@@ -547,11 +547,35 @@ __global__ void k_vrow_geom(ChunkGeom g1, int fshift, int64_t* minc2, int64_t* m
   }
 }
 
-// tiles of the level-2 reorder: nt2 = ceil(products / tile) per virtual row
-__global__ void k_vrow_tiles(const int64_t* cnt1, int64_t k0, int64_t k1, int tile, int64_t* nt2) {
+// tiles of the level-2 reorder: nt = ceil(products / tile) per listed virtual row
+__global__ void k_vrow_tiles(ChunkGeom g2, int64_t k0, int64_t k1) {
   const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= k1) return;
-  nt2[k] = (cnt1[k] + tile - 1) / tile;
+  g2.nt[k] = (g2.ip[g2.rows[k]] + g2.tile - 1) / g2.tile;
+}
+
+// Coarse chunks of a batch split by size: those with more than SORT_CAP
+// products go through the fine level (`big`), the others are sorted
+// directly (`small`); pos = exclusive scan of the big flags.
+__global__ void k_vrow_flags(const int64_t* cnt1, int64_t k0, int64_t n, int64_t* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = cnt1[k0 + i] > SORT_CAP ? 1 : 0;
+}
+__global__ void k_vrow_split(const int64_t* cnt1, int64_t k0, int64_t n, const int64_t* pos,
+                             int32_t* big, int32_t* small) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = k0 + i;
+  if (cnt1[v] > SORT_CAP) big[pos[i]] = (int32_t)v;
+  else small[i - pos[i]] = (int32_t)v;
+}
+// per listed virtual row: fine chunks, products
+__global__ void k_vrow_gather(const int32_t* rows, int64_t n, const int64_t* vnb,
+                              const int64_t* cnt1, int64_t* nb, int64_t* cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  nb[k] = vnb[rows[k]];
+  cnt[k] = cnt1[rows[k]];
 }
 
 // Symbolic phase of a coarse chunk: its column bitmap (2^cshift bits) in
@@ -571,7 +595,8 @@ __global__ void __launch_bounds__(VB_BS)
   const int64_t k = k0 + blockIdx.x;
   const int64_t nbk = g2.nb[k], bb = g2.binBase[k];
   const int sh = g2.shift;
-  const int64_t cnt = g2.ip[k], s0 = start1[k];
+  const int64_t v = g2.rows[k];
+  const int64_t cnt = g2.ip[v], s0 = start1[v];
   const int t = threadIdx.x;
   if (cnt == 0) {
     for (int64_t q = t; q < nbk; q += VB_BS) {
@@ -579,7 +604,7 @@ __global__ void __launch_bounds__(VB_BS)
       bin_nnz2[bb + q] = 0;
       bin_row2[bb + q] = (int32_t)k;
     }
-    if (t == 0) vnnz[k] = 0;
+    if (t == 0) vnnz[v] = 0;
     return;
   }
   const int64_t nwords = (nbk << sh) >> 5;
@@ -613,7 +638,7 @@ __global__ void __launch_bounds__(VB_BS)
     }
   }
   __syncthreads();
-  if (t == 0) vnnz[k] = (int64_t)tot;
+  if (t == 0) vnnz[v] = (int64_t)tot;
 }
 
 // Level-2 reorder: a tile of a virtual row's products (first workspace) is
@@ -641,10 +666,11 @@ __global__ void __launch_bounds__(BIN_BS)
   const int64_t tg = b2.tile0 + blockIdx.x;
   const int64_t k = tile_row2[tg];
   const int64_t ti = tg - g2.tileBase[k];
-  const int64_t cnt = g2.ip[k];
+  const int64_t v = g2.rows[k];
+  const int64_t cnt = g2.ip[v];
   const int64_t p0 = ti * (int64_t)g2.tile;
   const int32_t nloc = (int32_t)((cnt - p0 < g2.tile) ? (cnt - p0) : g2.tile);
-  const int64_t s0 = start1[k] + p0;
+  const int64_t s0 = start1[v] + p0;
   const int64_t nbk = g2.nb[k], gb = g2.binBase[k];
   const int sh = g2.shift;
   const uint32_t lmask = (1u << sh) - 1u;
@@ -721,9 +747,10 @@ __global__ void __launch_bounds__(BS)
   const int64_t tg = b2.tile0 + blockIdx.x;
   const int64_t k = tile_row2[tg];
   const int64_t p0 = (tg - g2.tileBase[k]) * (int64_t)g2.tile;
-  const int64_t cnt = g2.ip[k];
+  const int64_t v = g2.rows[k];
+  const int64_t cnt = g2.ip[v];
   const int32_t nloc = (int32_t)((cnt - p0 < g2.tile) ? (cnt - p0) : g2.tile);
-  const int64_t s0 = start1[k] + p0;
+  const int64_t s0 = start1[v] + p0;
   const int64_t nbk = g2.nb[k], gb = g2.binBase[k];
   const int sh = g2.shift;
   for (int64_t q = threadIdx.x; q < nbk; q += BS) hist[q] = 0;
@@ -1072,6 +1099,129 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
                                     bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
 }
 
+// ---------------------------------------------------------------------------
+// Coarse chunks of at most SORT_CAP products, sorted straight from the first
+// workspace (no fine level): one wave per coarse chunk; key = the column
+// local to the coarse chunk (< 2^cshift <= 2^22), numeric keys carry the
+// element index below it; count mode writes the distinct columns, numeric
+// mode the sums of each run at the chunk's offset in C.
+// ---------------------------------------------------------------------------
+template <typename V, int E, bool NUMERIC>
+MG_INLINE void vrow_sort_item(int64_t s0, int P, int64_t colbase,
+                              const uint32_t* __restrict__ ws1_col, const V* __restrict__ ws1_val,
+                              int64_t* nnz_out, int64_t obase, void* ccol_, int col64, V* cval,
+                              V* s_v) {
+  constexpr int CAP = MG_WAVE * E;
+  constexpr int IDXB = NUMERIC ? ilog2c(CAP) : 0;
+  const int l = lane();
+  uint32_t k[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = e * MG_WAVE + l;
+    if (x < P) {
+      const uint32_t key = ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + x]);
+      k[e] = NUMERIC ? ((key << IDXB) | (uint32_t)x) : key;
+      if (NUMERIC) s_v[x] = ld_stream<HINT_WS_LOAD>(&ws1_val[s0 + x]);
+    } else {
+      k[e] = 0xFFFFFFFFu;
+    }
+  }
+  bitonic_sort_keys<E>(k);
+  wave_sync2();
+  const uint32_t prevk = __shfl_up(k[E - 1], 1, MG_WAVE) >> IDXB;
+  bool head[E];
+  int hc = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = l * E + e;
+    const uint32_t pk = (e == 0) ? prevk : (k[e - 1] >> IDXB);
+    head[e] = (x < P) && (x == 0 || (k[e] >> IDXB) != pk);
+    hc += head[e] ? 1 : 0;
+  }
+  if (!NUMERIC) {
+    const int tot = wave_sum(hc);
+    if (l == 0) *nnz_out = tot;
+    return;
+  } else {
+    V v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      v[e] = (x < P) ? s_v[k[e] & (CAP - 1)] : (V)0;
+    }
+    const int hinc = wave_incl_scan(hc);
+    const int hbase = hinc - hc;
+    V t = (V)0;
+    bool anyh = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (head[e]) { t = (V)0 + v[e]; anyh = true; }
+      else t = t + v[e];
+    }
+    V s = t;
+    bool f = anyh;
+#pragma unroll
+    for (int d = 1; d < MG_WAVE; d <<= 1) {
+      const V ps = __shfl_up(s, d, MG_WAVE);
+      const int pf = __shfl_up((int)f, d, MG_WAVE);
+      if (l >= d && !f) { s = ps + s; f = pf != 0; }
+    }
+    V carry = __shfl_up(s, 1, MG_WAVE);
+    if (l == 0) carry = (V)0;
+    const uint32_t nextk = __shfl_down(k[0], 1, MG_WAVE) >> IDXB;
+    V run = carry;
+    int hr = hbase;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = l * E + e;
+      if (head[e]) { run = (V)0 + v[e]; ++hr; }
+      else run = run + v[e];
+      const uint32_t key = k[e] >> IDXB;
+      const uint32_t nk = (e == E - 1) ? nextk : (k[e + 1] >> IDXB);
+      const bool tail = (x < P) && (x == P - 1 || nk != key);
+      if (tail) {
+        const int64_t pos = obase + hr - 1;
+        const int64_t col = colbase + (int64_t)key;
+        if (col64) st_stream<HINT_C_STORE>(&((int64_t*)ccol_)[pos], (int64_t)col);
+        else st_stream<HINT_C_STORE>(&((int32_t*)ccol_)[pos], (int32_t)col);
+        st_stream<HINT_C_STORE>(&cval[pos], run);
+      }
+    }
+  }
+}
+
+template <typename V, bool NUMERIC>
+__global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
+    k_vrow_sort(const int32_t* __restrict__ small, int64_t nsmall, const int64_t* __restrict__ cnt1,
+                const int64_t* __restrict__ start1, const int64_t* __restrict__ minc2,
+                const uint32_t* __restrict__ ws1_col, const V* __restrict__ ws1_val,
+                int64_t* nnz1, const int64_t* __restrict__ out1, void* ccol_, int col64, V* cval,
+                int64_t i0) {
+  __shared__ V s_v[AS_WAVES][NUMERIC ? SORT_CAP : 1];
+  const int w = threadIdx.x / MG_WAVE;
+  const int64_t i = i0 + (int64_t)blockIdx.x * AS_WAVES + w;
+  if (i >= nsmall) return;
+  const int64_t v = small[i];
+  const int P = (int)cnt1[v];
+  if (P == 0) {
+    if (!NUMERIC && lane() == 0) nnz1[v] = 0;
+    return;
+  }
+  const int64_t s0 = start1[v], cb = minc2[v], ob = NUMERIC ? out1[v] : 0;
+  int64_t* no = nnz1 + v;
+  if (P <= 64)
+    vrow_sort_item<V, 1, NUMERIC>(s0, P, cb, ws1_col, ws1_val, no, ob, ccol_, col64, cval, s_v[w]);
+  else if (P <= 128)
+    vrow_sort_item<V, 2, NUMERIC>(s0, P, cb, ws1_col, ws1_val, no, ob, ccol_, col64, cval, s_v[w]);
+  else if (P <= 256)
+    vrow_sort_item<V, 4, NUMERIC>(s0, P, cb, ws1_col, ws1_val, no, ob, ccol_, col64, cval, s_v[w]);
+  else if (P <= 512)
+    vrow_sort_item<V, 8, NUMERIC>(s0, P, cb, ws1_col, ws1_val, no, ob, ccol_, col64, cval, s_v[w]);
+  else
+    vrow_sort_item<V, 16, NUMERIC>(s0, P, cb, ws1_col, ws1_val, no, ob, ccol_, col64, cval,
+                                   s_v[w]);
+}
+
 // rownnz of CHUNKED rows (count) / output offset of every chunk (numeric)
 __global__ void k_bin_rows(ChunkGeom g, int64_t k0, int64_t k1, const int64_t* bin_nnz,
                            int64_t* rownnz, const int64_t* crp, int64_t* bin_out, int to_out) {
@@ -1254,11 +1404,50 @@ hipError_t launch_vrow_geom(const ChunkGeom& g1, int fshift, int64_t* minc2, int
   return hipGetLastError();
 }
 
-hipError_t launch_vrow_tiles(const int64_t* cnt1, int64_t k0, int64_t k1, int tile, int64_t* nt2,
-                             hipStream_t st) {
+hipError_t launch_vrow_tiles(const ChunkGeom& g2, int64_t k0, int64_t k1, hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
-  hipLaunchKernelGGL(k_vrow_tiles, (unsigned)((k1 - k0 + 255) / 256), 256, 0, st, cnt1, k0, k1,
-                     tile, nt2);
+  hipLaunchKernelGGL(k_vrow_tiles, (unsigned)((k1 - k0 + 255) / 256), 256, 0, st, g2, k0, k1);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_split(const int64_t* cnt1, int64_t k0, int64_t n, int64_t* flags,
+                             int64_t* pos, int64_t* nbig, void* scan_temp, int32_t* big,
+                             int32_t* small, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_vrow_flags, g, 256, 0, st, cnt1, k0, n, flags);
+  hipError_t e = scan_excl_i64(flags, pos, n, nbig, nullptr, scan_temp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vrow_split, g, 256, 0, st, cnt1, k0, n, (const int64_t*)pos, big, small);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_gather(const int32_t* rows, int64_t n, const int64_t* vnb,
+                              const int64_t* cnt1, int64_t* nb, int64_t* cnt, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vrow_gather, (unsigned)((n + 255) / 256), 256, 0, st, rows, n, vnb, cnt1,
+                     nb, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrow_sort(bool numeric, int f64, const int32_t* small, int64_t nsmall,
+                            const int64_t* cnt1, const int64_t* start1, const int64_t* minc2,
+                            const uint32_t* ws1_col, const void* ws1_val, int64_t* nnz1,
+                            const int64_t* out1, void* ccol, int col64, void* cval,
+                            hipStream_t st) {
+  if (nsmall <= 0) return hipSuccess;
+  const int64_t gall = (nsmall + AS_WAVES - 1) / AS_WAVES;
+  const int64_t gcap = max_grid(AS_WAVES * MG_WAVE);
+#define MG_VS(V)                                                                                  \
+  {                                                                                               \
+    auto kf = numeric ? k_vrow_sort<V, true> : k_vrow_sort<V, false>;                             \
+    for (int64_t o = 0; o < gall; o += gcap)                                                      \
+      hipLaunchKernelGGL(kf, (unsigned)std::min(gcap, gall - o), AS_WAVES * MG_WAVE, 0, st,       \
+                         small, nsmall, cnt1, start1, minc2, ws1_col, (const V*)ws1_val, nnz1,    \
+                         out1, ccol, col64, (V*)cval, o * AS_WAVES);                               \
+  }
+  if (f64) MG_VS(double) else MG_VS(float)
+#undef MG_VS
   return hipGetLastError();
 }
 

@@ -203,8 +203,24 @@ hipError_t launch_l2_hist(const ChunkGeom& g2, const BatchArgs& b2, const int32_
                           int64_t max_nb2, hipStream_t st);
 // row2[fine chunk] = its virtual row
 hipError_t launch_vrow_rows(const ChunkGeom& g2, int32_t* row2, hipStream_t st);
-hipError_t launch_vrow_tiles(const int64_t* cnt1, int64_t k0, int64_t k1, int tile, int64_t* nt2,
-                             hipStream_t st);
+// g2.nt[k] = ceil(products / g2.tile) of listed virtual rows k in [k0, k1)
+hipError_t launch_vrow_tiles(const ChunkGeom& g2, int64_t k0, int64_t k1, hipStream_t st);
+// the coarse chunks [k0, k0 + n) split into those with more than SORT_CAP
+// products (big, ascending) and the others (small, ascending); *nbig
+// (device) receives the big count; flags, pos: n entries of scratch
+hipError_t launch_vrow_split(const int64_t* cnt1, int64_t k0, int64_t n, int64_t* flags,
+                             int64_t* pos, int64_t* nbig, void* scan_temp, int32_t* big,
+                             int32_t* small, hipStream_t st);
+// nb[k] = vnb[rows[k]], cnt[k] = cnt1[rows[k]]
+hipError_t launch_vrow_gather(const int32_t* rows, int64_t n, const int64_t* vnb,
+                              const int64_t* cnt1, int64_t* nb, int64_t* cnt, hipStream_t st);
+// small coarse chunks sorted from the first workspace: nnz1 (count mode) or
+// C at out1 (numeric); columns = minc2 + local column
+hipError_t launch_vrow_sort(bool numeric, int f64, const int32_t* small, int64_t nsmall,
+                            const int64_t* cnt1, const int64_t* start1, const int64_t* minc2,
+                            const uint32_t* ws1_col, const void* ws1_val, int64_t* nnz1,
+                            const int64_t* out1, void* ccol, int col64, void* cval,
+                            hipStream_t st);
 // symbolic phase of virtual rows [k0, k1): fine chunk products, nnz, row;
 // virtual row nnz
 size_t vrow_bitmap_lds(int cshift, int64_t max_nb2);

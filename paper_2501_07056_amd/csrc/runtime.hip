@@ -286,111 +286,128 @@ magnus_status_t setup_coarse(magnus_plan_s* P) {
   HIPCHK(launch_tiles(g1.nt, g1.tileBase, 0, n1, C.tile_row1, P->st));
   HIPCHK(launch_tile_e0(P->M, g1, C.tile_row1, P->aoff, ntiles1, C.tile_e0, P->st));
 
-  // per coarse chunk, and the coarse chunks as virtual rows of g2
+  // per coarse chunk: counts, starts, nnz, output offsets, column range and
+  // fine chunk count; the size split's lists and scratch
+  int64_t max_nb1b = 1;
+  for (auto& b : C.b1) max_nb1b = std::max(max_nb1b, b.nbins);
   C.cnt1 = (int64_t*)palloc(P, sizeof(int64_t) * nv);
   C.start1 = (int64_t*)palloc(P, sizeof(int64_t) * nv);
   C.nnz1 = (int64_t*)palloc(P, sizeof(int64_t) * nv);
   C.out1 = (int64_t*)palloc(P, sizeof(int64_t) * (nv + 1));
   C.row1 = (int32_t*)palloc(P, sizeof(int32_t) * nv);
   C.cur1 = (unsigned long long*)palloc(P, sizeof(unsigned long long) * nv);
-  int64_t* vgeo = (int64_t*)palloc(P, sizeof(int64_t) * (4 * nv + 2 * (nv + 1)));
-  int32_t* ident = (int32_t*)palloc(P, sizeof(int32_t) * nv);
+  C.minc2 = (int64_t*)palloc(P, sizeof(int64_t) * 3 * nv);
+  C.big_all = (int32_t*)palloc(P, sizeof(int32_t) * nv);
+  C.small_all = (int32_t*)palloc(P, sizeof(int32_t) * nv);
+  C.ident = (int32_t*)palloc(P, sizeof(int32_t) * nv);
+  C.flags = (int64_t*)palloc(P, sizeof(int64_t) * 2 * max_nb1b);
+  C.nbig_dev = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, nbat));
   C.scan_temp = palloc(P, scan_temp_bytes(nv + 1));
-  if (!C.cnt1 || !C.start1 || !C.nnz1 || !C.out1 || !C.row1 || !C.cur1 || !vgeo || !ident ||
-      !C.scan_temp)
-    return MAGNUS_ERR_OOM;
-  ChunkGeom& g2 = C.g2;
-  g2.rows = ident;
-  g2.ip = C.cnt1;
-  g2.minc = vgeo;
-  g2.maxc = vgeo + nv;
-  g2.nb = vgeo + 2 * nv;
-  g2.nt = vgeo + 3 * nv;
-  g2.binBase = vgeo + 4 * nv;
-  g2.tileBase = g2.binBase + (nv + 1);
-  g2.ipBase = nullptr;
-  g2.nch = nv;
-  g2.shift = P->shift;
-  g2.tile = C.tile2;
-  g2.hints = P->hints;
-  HIPCHK(launch_vrow_geom(g1, P->shift, (int64_t*)g2.minc, (int64_t*)g2.maxc, g2.nb, ident,
-                          P->st));
-  HIPCHK(scan_excl_i64(g2.nb, g2.binBase, nv, g2.binBase + nv, nullptr, C.scan_temp, P->st));
-  // fine chunks of every batch's virtual rows
-  std::vector<int64_t> fb(nbat + 1, 0);
-  {
-    std::vector<std::pair<const void*, size_t>> src;
-    std::vector<void*> dst;
-    for (int64_t b = 0; b <= nbat; ++b) {
-      const int64_t kk = (b < nbat) ? C.b1[b].bin0 : nv;
-      src.push_back({g2.binBase + kk, 8});
-      dst.push_back(&fb[b]);
-    }
-    s = readback(P, src, dst);
-    if (s != MAGNUS_OK) return s;
-  }
-  C.nbins2 = fb[nbat];
-  C.b2.assign(nbat, BatchArgs{});
-  int64_t max_fine = 1;
-  for (int64_t b = 0; b < nbat; ++b) {
-    BatchArgs& b2 = C.b2[b];
-    b2.k0 = C.b1[b].bin0;
-    b2.k1 = C.b1[b].bin0 + C.b1[b].nbins;
-    b2.bin0 = fb[b];
-    b2.nbins = fb[b + 1] - fb[b];
-    b2.ip0 = C.b1[b].ip0;
-    b2.nip = C.b1[b].nip;
-    max_fine = std::max(max_fine, b2.nbins);
-  }
-  const int64_t nb2 = C.nbins2;
-  C.cnt2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
-  C.start2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
-  C.nnz2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
-  C.out2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
-  C.dense2 = (int64_t*)palloc(P, sizeof(int64_t) * nb2);
-  C.sort2 = (int64_t*)palloc(P, sizeof(int64_t) * 2 * nb2);
-  C.row2 = (int32_t*)palloc(P, sizeof(int32_t) * nb2);
-  C.cur2 = (unsigned long long*)palloc(P, sizeof(unsigned long long) * nb2);
-  void* t2 = palloc(P, scan_temp_bytes(max_fine));
-  C.item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2 * nbat);
-  C.btiles = (int64_t*)palloc(P, sizeof(int64_t) * (nbat + 1));
-  C.work = (unsigned int*)palloc(P, sizeof(int64_t) * 2 * nbat);
-  // level-2 tiles: at most products / tile + one per virtual row
-  C.tile_row2 = (int32_t*)palloc(P, sizeof(int32_t) * (tots[0] / C.tile2 + nv + 1));
+  C.item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2 * std::max<int64_t>(1, nbat));
+  C.work = (unsigned int*)palloc(P, sizeof(int64_t) * 2 * std::max<int64_t>(1, nbat));
   C.ws1_col = (uint32_t*)palloc(P, sizeof(uint32_t) * C.ws_products);
   C.ws1_val = palloc(P, (size_t)vs * C.ws_products);
   C.ws2_col = (uint16_t*)palloc(P, sizeof(uint16_t) * C.ws_products);
   C.ws2_val = palloc(P, (size_t)vs * C.ws_products);
-  if (!C.cnt2 || !C.start2 || !C.nnz2 || !C.out2 || !C.dense2 || !C.sort2 || !C.row2 || !C.cur2 ||
-      !t2 || !C.item_counts || !C.btiles || !C.work || !C.tile_row2 || !C.ws1_col ||
-      !C.ws1_val || !C.ws2_col || !C.ws2_val)
+  if (!C.cnt1 || !C.start1 || !C.nnz1 || !C.out1 || !C.row1 || !C.cur1 || !C.minc2 ||
+      !C.big_all || !C.small_all || !C.ident || !C.flags || !C.nbig_dev || !C.scan_temp ||
+      !C.item_counts || !C.work || !C.ws1_col || !C.ws1_val || !C.ws2_col || !C.ws2_val)
     return MAGNUS_ERR_OOM;
-  if (scan_temp_bytes(max_fine) > scan_temp_bytes(nv + 1)) C.scan_temp = t2;
-  HIPCHK(hipMemsetAsync(C.item_counts, 0, sizeof(int32_t) * 2 * nbat, P->st));
-  HIPCHK(hipMemsetAsync(C.btiles, 0, sizeof(int64_t) * (nbat + 1), P->st));
-  HIPCHK(launch_vrow_rows(g2, C.row2, P->st));
+  C.maxc2 = C.minc2 + nv;
+  C.vnb = C.minc2 + 2 * nv;
+  C.pos = C.flags + max_nb1b;
+  HIPCHK(launch_vrow_geom(g1, P->shift, C.minc2, C.maxc2, C.vnb, C.ident, P->st));
+  HIPCHK(hipMemsetAsync(C.item_counts, 0, sizeof(int32_t) * 2 * std::max<int64_t>(1, nbat),
+                        P->st));
+  C.cb.assign(nbat, magnus_plan_s::CBatch{});
+  return MAGNUS_OK;
+}
+
+// Level-2 geometry of a batch's big coarse chunks (known after the first
+// reorder has counted them): their fine chunks and tiles, and the per fine
+// chunk arrays, allocated for this batch.
+magnus_status_t coarse_fine_setup(magnus_plan_s* P, size_t bi) {
+  magnus_handle_s* h = P->h;
+  auto& C = P->co;
+  magnus_plan_s::CBatch& cb = C.cb[bi];
+  const int64_t nb = cb.nbig;
+  int64_t* geo = (int64_t*)palloc(P, sizeof(int64_t) * (3 * nb + 2 * (nb + 1) + 1));
+  if (!geo) return MAGNUS_ERR_OOM;
+  ChunkGeom& g2 = cb.g2;
+  g2.rows = cb.big;
+  g2.ip = C.cnt1;
+  g2.minc = C.minc2;
+  g2.maxc = C.maxc2;
+  g2.nb = geo;
+  g2.nt = geo + nb;
+  int64_t* cntL = geo + 2 * nb;
+  g2.binBase = geo + 3 * nb;
+  g2.tileBase = g2.binBase + (nb + 1);
+  int64_t* ptot = g2.tileBase + (nb + 1);
+  g2.ipBase = nullptr;
+  g2.nch = nb;
+  g2.shift = P->shift;
+  g2.tile = C.tile2;
+  g2.hints = P->hints;
+  HIPCHK(launch_vrow_gather(cb.big, nb, C.vnb, C.cnt1, g2.nb, cntL, P->st));
+  HIPCHK(launch_vrow_tiles(g2, 0, nb, P->st));
+  HIPCHK(scan_excl_i64(g2.nb, g2.binBase, nb, g2.binBase + nb, nullptr, C.scan_temp, P->st));
+  HIPCHK(scan_excl_i64(g2.nt, g2.tileBase, nb, g2.tileBase + nb, nullptr, C.scan_temp, P->st));
+  HIPCHK(scan_excl_i64(cntL, cntL, nb, ptot, nullptr, C.scan_temp, P->st));
+  int64_t tot[3] = {0, 0, 0};
+  magnus_status_t s = readback(P, {{g2.binBase + nb, 8}, {g2.tileBase + nb, 8}, {ptot, 8}},
+                               {&tot[0], &tot[1], &tot[2]});
+  if (s != MAGNUS_OK) return s;
+  const int64_t F = tot[0], T = tot[1];
+  if (T > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  cb.nbins2 = F;
+  cb.nip2 = tot[2];
+  C.nbins2 += F;
+  cb.cnt2 = (int64_t*)palloc(P, sizeof(int64_t) * F);
+  cb.start2 = (int64_t*)palloc(P, sizeof(int64_t) * F);
+  cb.nnz2 = (int64_t*)palloc(P, sizeof(int64_t) * F);
+  cb.out2 = (int64_t*)palloc(P, sizeof(int64_t) * F);
+  cb.dense2 = (int64_t*)palloc(P, sizeof(int64_t) * F);
+  cb.sort2 = (int64_t*)palloc(P, sizeof(int64_t) * 2 * F);
+  cb.row2 = (int32_t*)palloc(P, sizeof(int32_t) * F);
+  cb.cur2 = (unsigned long long*)palloc(P, sizeof(unsigned long long) * F);
+  cb.tile_row2 = (int32_t*)palloc(P, sizeof(int32_t) * std::max<int64_t>(1, T));
+  cb.scan_temp = palloc(P, scan_temp_bytes(F + 1));
+  if (!cb.cnt2 || !cb.start2 || !cb.nnz2 || !cb.out2 || !cb.dense2 || !cb.sort2 || !cb.row2 ||
+      !cb.cur2 || !cb.tile_row2 || !cb.scan_temp)
+    return MAGNUS_ERR_OOM;
+  HIPCHK(launch_tiles(g2.nt, g2.tileBase, 0, nb, cb.tile_row2, P->st));
+  HIPCHK(launch_vrow_rows(g2, cb.row2, P->st));
+  BatchArgs& b2 = cb.b2;
+  b2 = BatchArgs{};
+  b2.k0 = 0;
+  b2.k1 = nb;
+  b2.tile0 = 0;
+  b2.ntiles = T;
+  b2.bin0 = 0;
+  b2.nbins = F;
+  b2.nip = tot[2];
   // the bitmap of a coarse chunk (2^cshift bits) pays when its products are
   // dense enough
-  const int64_t per_chunk = tots[0] / std::max<int64_t>(1, nv);
-  C.bitmap_sym = per_chunk * MG_BITMAP_DENSITY >= ((int64_t)1 << C.cshift);
+  cb.bitmap_sym = (tot[2] / std::max<int64_t>(1, nb)) * MG_BITMAP_DENSITY >=
+                  ((int64_t)1 << C.cshift);
   return MAGNUS_OK;
 }
 
 // Symbolic phase of coarse-level rows: per batch, the coarse chunks' product
-// counts and the first reorder (columns only), the level-2 tiles, then per
-// fine chunk its products and nnz, either from a bitmap of every coarse
-// chunk (dense coarse chunks) or from the level-2 reorder of the columns and
-// the accumulators in count mode (sparse ones, where clearing and scanning a
-// bitmap would cost more than the products); row nnz; fine chunk starts
-// and work items.
+// counts and the first reorder (columns only), the split of the coarse
+// chunks by size; small ones counted by sorting; for big ones each fine
+// chunk's products and nnz, either from a bitmap of the coarse chunk (dense
+// coarse chunks) or from the level-2 reorder of the columns and the
+// accumulators in count mode (sparse ones, where clearing and scanning a
+// bitmap would cost more than the products); row nnz.
 magnus_status_t coarse_symbolic(magnus_plan_s* P) {
   magnus_handle_s* h = P->h;
   auto& C = P->co;
   ChunkGeom& g1 = C.g1;
-  ChunkGeom& g2 = C.g2;
   for (size_t bi = 0; bi < C.b1.size(); ++bi) {
     const BatchArgs& b = C.b1[bi];
-    BatchArgs& b2 = C.b2[bi];
+    magnus_plan_s::CBatch& cb = C.cb[bi];
     int32_t* ic = C.item_counts + 2 * bi;
     {
       // per product: B column read, 32-bit column written; per A entry:
@@ -408,48 +425,60 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
                                  C.tile_e0, C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1,
                                  P->st));
     }
-    // level-2 tiles of the batch's virtual rows (running total in btiles)
-    HIPCHK(launch_vrow_tiles(C.cnt1, b2.k0, b2.k1, C.tile2, g2.nt, P->st));
-    HIPCHK(scan_excl_i64(g2.nt + b2.k0, g2.tileBase + b2.k0, b2.k1 - b2.k0, C.btiles + bi + 1,
-                         C.btiles + bi, C.scan_temp, P->st));
-    HIPCHK(launch_tiles(g2.nt, g2.tileBase, b2.k0, b2.k1, C.tile_row2, P->st));
-    int64_t tb[2] = {0, 0};
-    magnus_status_t s = readback(P, {{C.btiles + bi, 16}}, {tb});
+    cb.big = C.big_all + b.bin0;
+    cb.small = C.small_all + b.bin0;
+    HIPCHK(launch_vrow_split(C.cnt1, b.bin0, b.nbins, C.flags, C.pos, C.nbig_dev + bi,
+                             C.scan_temp, cb.big, cb.small, P->st));
+    magnus_status_t s = readback(P, {{C.nbig_dev + bi, 8}}, {&cb.nbig});
     if (s != MAGNUS_OK) return s;
-    b2.tile0 = tb[0];
-    b2.ntiles = tb[1] - tb[0];
-    if (b2.ntiles > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
-    if (C.bitmap_sym) {
-      // per product: 32-bit column read; per fine chunk: three words out
-      ProfScope ps(h, P->st, "coarse_bitmap (symbolic, level 2)",
-                   (double)b.nip * 4 + (double)b2.nbins * 20);
-      HIPCHK(launch_vrow_bitmap(g2, C.cshift, b2.k0, b2.k1, C.max_nb2, C.start1, C.ws1_col,
-                                C.cnt2, C.nnz2, C.row2, C.nnz1, P->st));
-      HIPCHK(scan_excl_i64(C.cnt2 + b2.bin0, C.start2 + b2.bin0, b2.nbins, nullptr, nullptr,
-                           C.scan_temp, P->st));
-      HIPCHK(launch_bin_group(g2, b2, C.cnt2, P->dense_min, P->group_max, C.dense2, C.sort2, ic,
+    cb.nsmall = b.nbins - cb.nbig;
+    {
+      // per product of a small coarse chunk: 32-bit column read
+      ProfScope ps(h, P->st, "coarse_sort (symbolic, small coarse chunks)",
+                   (double)(b.nip) * 4);
+      HIPCHK(launch_vrow_sort(false, P->M.f64, cb.small, cb.nsmall, C.cnt1, C.start1, C.minc2,
+                              C.ws1_col, C.ws1_val, C.nnz1, nullptr, nullptr, 0, nullptr,
                               P->st));
-    } else {
-      // per product: 32-bit column read twice (histogram, reorder), 16-bit
-      // column written and read; per fine chunk: count, start, nnz
-      ProfScope ps(h, P->st, "coarse_count (symbolic, level 2)",
-                   (double)b.nip * (4 + 4 + 2 + 2) + (double)b2.nbins * 24);
-      HIPCHK(launch_fill_i64(C.cnt2 + b2.bin0, b2.nbins, 0, P->st));
-      HIPCHK(launch_l2_hist(g2, b2, C.tile_row2, C.start1, C.ws1_col, C.cnt2, C.max_nb2, P->st));
-      HIPCHK(scan_excl_i64(C.cnt2 + b2.bin0, C.start2 + b2.bin0, b2.nbins, nullptr, nullptr,
-                           C.scan_temp, P->st));
-      HIPCHK(launch_bin_group(g2, b2, C.cnt2, P->dense_min, P->group_max, C.dense2, C.sort2, ic,
+    }
+    if (cb.nbig > 0) {
+      s = coarse_fine_setup(P, bi);
+      if (s != MAGNUS_OK) return s;
+      ChunkGeom& g2 = cb.g2;
+      const BatchArgs& b2 = cb.b2;
+      if (cb.bitmap_sym) {
+        // per product: 32-bit column read; per fine chunk: three words out
+        ProfScope ps(h, P->st, "coarse_bitmap (symbolic, level 2)",
+                     (double)b2.nip * 4 + (double)b2.nbins * 20);
+        HIPCHK(launch_vrow_bitmap(g2, C.cshift, 0, cb.nbig, C.max_nb2, C.start1, C.ws1_col,
+                                  cb.cnt2, cb.nnz2, cb.row2, C.nnz1, P->st));
+        HIPCHK(scan_excl_i64(cb.cnt2, cb.start2, b2.nbins, nullptr, nullptr, cb.scan_temp,
+                             P->st));
+        HIPCHK(launch_bin_group(g2, b2, cb.cnt2, P->dense_min, P->group_max, cb.dense2,
+                                cb.sort2, ic, P->st));
+      } else {
+        // per product: 32-bit column read twice (histogram, reorder), 16-bit
+        // column written and read; per fine chunk: count, start, nnz
+        ProfScope ps(h, P->st, "coarse_count (symbolic, level 2)",
+                     (double)b2.nip * (4 + 4 + 2 + 2) + (double)b2.nbins * 24);
+        HIPCHK(launch_fill_i64(cb.cnt2, b2.nbins, 0, P->st));
+        HIPCHK(launch_l2_hist(g2, b2, cb.tile_row2, C.start1, C.ws1_col, cb.cnt2, C.max_nb2,
                               P->st));
-      HIPCHK(launch_fill_i64((int64_t*)C.cur2 + b2.bin0, b2.nbins, 0, P->st));
-      HIPCHK(launch_l2_scatter(g2, b2, false, P->M.f64, C.tile_row2, C.start1, C.ws1_col,
-                               C.ws1_val, C.start2, C.cur2, C.ws2_col, C.ws2_val, C.max_nb2,
+        HIPCHK(scan_excl_i64(cb.cnt2, cb.start2, b2.nbins, nullptr, nullptr, cb.scan_temp,
+                             P->st));
+        HIPCHK(launch_bin_group(g2, b2, cb.cnt2, P->dense_min, P->group_max, cb.dense2,
+                                cb.sort2, ic, P->st));
+        HIPCHK(launch_fill_i64((int64_t*)cb.cur2, b2.nbins, 0, P->st));
+        HIPCHK(launch_l2_scatter(g2, b2, false, P->M.f64, cb.tile_row2, C.start1, C.ws1_col,
+                                 C.ws1_val, cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2,
+                                 P->st));
+        unsigned int* wk = C.work + 4 * bi + 2;
+        HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+        HIPCHK(launch_bin_accum(g2, b2, false, P->M.f64, cb.start2, cb.cnt2, cb.row2, cb.dense2,
+                                cb.sort2, ic, C.ws2_col, C.ws2_val, cb.nnz2, cb.out2, nullptr, 0,
+                                nullptr, P->dense_block, wk, P->persistent_wgs, P->st));
+        HIPCHK(launch_bin_rows(g2, 0, cb.nbig, cb.nnz2, C.nnz1, nullptr, nullptr, false,
                                P->st));
-      unsigned int* wk = C.work + 4 * bi + 2;
-      HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
-      HIPCHK(launch_bin_accum(g2, b2, false, P->M.f64, C.start2, C.cnt2, C.row2, C.dense2,
-                              C.sort2, ic, C.ws2_col, C.ws2_val, C.nnz2, C.out2, nullptr, 0,
-                              nullptr, P->dense_block, wk, P->persistent_wgs, P->st));
-      HIPCHK(launch_bin_rows(g2, b2.k0, b2.k1, C.nnz2, C.nnz1, nullptr, nullptr, false, P->st));
+      }
     }
     HIPCHK(launch_bin_rows(g1, b.k0, b.k1, C.nnz1, P->crp, nullptr, nullptr, false, P->st));
   }
@@ -457,17 +486,17 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
 }
 
 // Numeric phase of coarse-level rows, batch by batch: output offsets of the
-// coarse and fine chunks, the two reorders, accumulation of every fine chunk
-// into C.
+// coarse and fine chunks, the first reorder, the sorts of the small coarse
+// chunks, the second reorder and the accumulation of the big ones' fine
+// chunks into C.
 magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cval) {
   magnus_handle_s* h = P->h;
   auto& C = P->co;
   const double vs = P->s_val;
   for (size_t bi = 0; bi < C.b1.size(); ++bi) {
     const BatchArgs& b = C.b1[bi];
-    const BatchArgs& b2 = C.b2[bi];
+    magnus_plan_s::CBatch& cb = C.cb[bi];
     HIPCHK(launch_bin_rows(C.g1, b.k0, b.k1, C.nnz1, nullptr, P->crp, C.out1, true, P->st));
-    HIPCHK(launch_bin_rows(C.g2, b2.k0, b2.k1, C.nnz2, nullptr, C.out1, C.out2, true, P->st));
     HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
     {
       // per product: B column and value read, 32-bit column and product
@@ -475,26 +504,40 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
       ProfScope ps(h, P->st, "coarse_scatter (numeric, level 1)",
                    (double)b.nip * (P->s_col + vs + 4 + vs) +
                        (double)b.nent * (P->s_col + vs + 8 + P->s_rp));
-      HIPCHK(launch_bin_scatter2(P->M, C.g1, b, true, 1, C.sorted1, C.tile_row1, P->aoff, C.tile_e0,
-                                 C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1, P->st));
+      HIPCHK(launch_bin_scatter2(P->M, C.g1, b, true, 1, C.sorted1, C.tile_row1, P->aoff,
+                                 C.tile_e0, C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1,
+                                 P->st));
     }
-    HIPCHK(launch_fill_i64((int64_t*)C.cur2 + b2.bin0, b2.nbins, 0, P->st));
+    {
+      // per product of a small coarse chunk: column and value read; per
+      // output: C column and value
+      ProfScope ps(h, P->st, "coarse_sort (numeric, small coarse chunks)",
+                   (double)(b.nip - cb.nip2) * (4 + vs));
+      HIPCHK(launch_vrow_sort(true, P->M.f64, cb.small, cb.nsmall, C.cnt1, C.start1, C.minc2,
+                              C.ws1_col, C.ws1_val, C.nnz1, C.out1, ccol, col64, cval, P->st));
+    }
+    if (cb.nbig == 0) continue;
+    const BatchArgs& b2 = cb.b2;
+    HIPCHK(launch_bin_rows(cb.g2, 0, cb.nbig, cb.nnz2, nullptr, C.out1, cb.out2, true, P->st));
+    HIPCHK(launch_fill_i64((int64_t*)cb.cur2, b2.nbins, 0, P->st));
     {
       // per product: 32-bit column and value read, 16-bit column and value
       // written
-      ProfScope ps(h, P->st, "fine_scatter (numeric, level 2)", (double)b.nip * (4 + vs + 2 + vs));
-      HIPCHK(launch_l2_scatter(C.g2, b2, true, P->M.f64, C.tile_row2, C.start1, C.ws1_col, C.ws1_val,
-                               C.start2, C.cur2, C.ws2_col, C.ws2_val, C.max_nb2, P->st));
+      ProfScope ps(h, P->st, "fine_scatter (numeric, level 2)",
+                   (double)b2.nip * (4 + vs + 2 + vs));
+      HIPCHK(launch_l2_scatter(cb.g2, b2, true, P->M.f64, cb.tile_row2, C.start1, C.ws1_col,
+                               C.ws1_val, cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2,
+                               P->st));
     }
     unsigned int* wk = C.work + 4 * bi;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
     {
       // the kernels of the CHUNKED rows' accumulation, under the same name
       ProfScope ps(h, P->st, "bin_accum (numeric, dense+sort chunks)",
-                   (double)b.nip * (2 + vs) + (double)b.nnz_out * (P->s_col + vs));
-      HIPCHK(launch_bin_accum(C.g2, b2, true, P->M.f64, C.start2, C.cnt2, C.row2, C.dense2,
-                              C.sort2, C.item_counts + 2 * bi, C.ws2_col, C.ws2_val, C.nnz2,
-                              C.out2, ccol, col64, cval, P->dense_block, wk, P->persistent_wgs,
+                   (double)b2.nip * (2 + vs) + (double)b.nnz_out * (P->s_col + vs));
+      HIPCHK(launch_bin_accum(cb.g2, b2, true, P->M.f64, cb.start2, cb.cnt2, cb.row2, cb.dense2,
+                              cb.sort2, C.item_counts + 2 * bi, C.ws2_col, C.ws2_val, cb.nnz2,
+                              cb.out2, ccol, col64, cval, P->dense_block, wk, P->persistent_wgs,
                               P->st));
     }
   }

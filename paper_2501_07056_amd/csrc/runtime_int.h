@@ -147,35 +147,44 @@ struct magnus_plan_s {
   double s_rp = 4, s_col = 4, s_val = 8;
   // Coarse-level rows (CHUNKED rows wider than coarse_range): a first reorder
   // into coarse chunks of 2^cshift columns (geometry g1, 32-bit chunk-local
-  // columns in ws1), then every coarse chunk is a virtual row of a second
-  // geometry g2 whose chunks of 2^shift columns are reordered into ws2 and
-  // accumulated like the chunks of CHUNKED rows.
+  // columns in ws1).  Per batch the coarse chunks split by size: those with
+  // at most SORT_CAP products are sorted straight from ws1; the others are
+  // the rows of a second geometry whose chunks of 2^shift columns are
+  // reordered into ws2 and accumulated like the chunks of CHUNKED rows.
+  struct CBatch {
+    int64_t nbig = 0, nsmall = 0, nbins2 = 0, nip2 = 0;
+    int32_t *big = nullptr, *small = nullptr;  // coarse chunk ids (slices of big_all/small_all)
+    ChunkGeom g2{};
+    BatchArgs b2{};
+    int64_t *cnt2 = nullptr, *start2 = nullptr, *nnz2 = nullptr, *out2 = nullptr;
+    int64_t *dense2 = nullptr, *sort2 = nullptr;
+    int32_t *row2 = nullptr, *tile_row2 = nullptr;
+    unsigned long long* cur2 = nullptr;
+    void* scan_temp = nullptr;
+    bool bitmap_sym = true;
+  };
   struct Coarse {
     int64_t nrows = 0, coarse_range = 0, max_nb1 = 1, max_nb2 = 1, nv = 0, nbins2 = 0;
     int cshift = 20, tile1 = 4096, tile2 = MG_L2_TILE, sorted1 = 1;
-    bool bitmap_sym = true;
-    ChunkGeom g1{}, g2{};
-    std::vector<BatchArgs> b1, b2;  // level-1 batches; the level-2 range of each
+    ChunkGeom g1{};
+    std::vector<BatchArgs> b1;  // level-1 batches
+    std::vector<CBatch> cb;     // their level-2 parts
     int64_t *tile_e0 = nullptr, *ent = nullptr, *entBase = nullptr;
-    int32_t *tile_row1 = nullptr, *tile_row2 = nullptr;
-    // per coarse chunk (= virtual row)
+    int32_t* tile_row1 = nullptr;
+    // per coarse chunk
     int64_t *cnt1 = nullptr, *start1 = nullptr, *nnz1 = nullptr, *out1 = nullptr;
-    int32_t* row1 = nullptr;
+    int64_t *minc2 = nullptr, *maxc2 = nullptr, *vnb = nullptr;
+    int32_t *row1 = nullptr, *big_all = nullptr, *small_all = nullptr, *ident = nullptr;
     unsigned long long* cur1 = nullptr;
-    // per fine chunk
-    int64_t *cnt2 = nullptr, *start2 = nullptr, *nnz2 = nullptr, *out2 = nullptr;
-    int64_t *dense2 = nullptr, *sort2 = nullptr;
-    int32_t* row2 = nullptr;
-    unsigned long long* cur2 = nullptr;
+    int64_t *flags = nullptr, *pos = nullptr, *nbig_dev = nullptr;  // split scratch
     int32_t* item_counts = nullptr;  // per batch: dense items, sort items
-    int64_t* btiles = nullptr;       // level-2 tiles before each batch
-    unsigned int* work = nullptr;    // per batch: persistent-kernel counter
+    unsigned int* work = nullptr;    // per batch: persistent-kernel counters
     uint32_t* ws1_col = nullptr;
     void* ws1_val = nullptr;
     uint16_t* ws2_col = nullptr;
     void* ws2_val = nullptr;
     int64_t ws_products = 0;
-    void* scan_temp = nullptr;
+    void* scan_temp = nullptr;  // scans of up to nv + 1 entries
   } co;
 };
 

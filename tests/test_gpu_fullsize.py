@@ -61,10 +61,11 @@ def test_config2_rmat20_sampled():
         ctx.close()
 
 
-# CHUNKED forced on the 2^24 product needs per-chunk tables of rows x chunks
-# (2^24 x 1025 chunks): beyond device memory; it is checked at 2^22, where
-# they fit (the default category of these rows is SORT)
-@pytest.mark.parametrize("cat,logn", [("auto", 24), ("chunked", 22)])
+# forced to CHUNKED, the rows span 2^24 columns and take the coarse level;
+# their coarse chunks hold about 16 products each and are sorted directly,
+# so no per-chunk arrays of rows x chunks are built (the default category of
+# these rows is SORT)
+@pytest.mark.parametrize("cat,logn", [("auto", 24), ("chunked", 22), ("chunked", 24)])
 def test_config3_er_sampled(cat, logn):
     import torch
 

@@ -15,7 +15,7 @@ from test_gpu_fullsize import _check_rows
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("log_mc,coarse", [(18, 0), (22, 0), (27, 0), (27, -1), (31, 0)])
+@pytest.mark.parametrize("log_mc,coarse", [(18, 0), (22, 0), (27, 0), (27, -1), (28, 0), (31, 0)])
 def test_massive_er_sampled(log_mc, coarse):
     import torch
 
@@ -31,8 +31,14 @@ def test_massive_er_sampled(log_mc, coarse):
         torch.cuda.synchronize()
         p.destroy()
         assert info["ip_total"] == 1024 * 512 * 512
-        # one coarse chunk spans 2^20 columns under the full LDS budget
+        # one coarse chunk spans 2^20 columns under the full LDS budget;
+        # coarse chunks of <= 1024 products skip the fine level (2^31: about
+        # 128 products each)
         assert (info["coarse_rows"] > 0) == (coarse == 0 and log_mc > 20)
+        if log_mc == 31:
+            assert info["coarse_fine_chunks"] == 0
+        if log_mc in (22, 27) and coarse == 0:
+            assert info["coarse_fine_chunks"] > 0
         rng = np.random.default_rng(log_mc)
         rows = np.concatenate([[0, A.nrows - 1], rng.choice(A.nrows, 40, replace=False)])
         _check_rows(C, A, B, rows, np.float32)

@@ -96,6 +96,9 @@ def test_coarse_level_er(ctx, vt):
         if cc > 0:
             assert info["coarse_rows"] == A.nrows and info["coarse_chunks"] > A.nrows
             assert info["rows_by_category"][2] == A.nrows and info["n_batches"] == 0
+            # every coarse chunk holds at most 1024 products: all are sorted
+            # directly, none goes through the fine level
+            assert info["coarse_fine_chunks"] == 0
         else:
             assert info["coarse_rows"] == 0
         compare(rp, col, val, ref, vt, exact=False)
@@ -111,6 +114,9 @@ def test_coarse_level_rmat(ctx):
     rp, col, val, info = gpu_product(ctx, A, A, force_category="chunked", chunk_shift=6,
                                      coarse_chunks=4, batch_products=300000)
     assert info["coarse_rows"] > 0 and info["coarse_shift"] == 8
+    # heavy rows' first coarse chunks exceed 1024 products (fine level), the
+    # others are sorted directly
+    assert 0 < info["coarse_fine_chunks"] < 4 * info["coarse_chunks"]
     compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
     ctx.set_options(force_category="auto", chunk_shift=0, coarse_chunks=0, batch_products=0)
 
