@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(BIN_BS)
 // per coarse row k (one wave): the column base, last column and fine chunk
 // count of each of its coarse chunks
 __global__ void k_vrow_geom(ChunkGeom g1, int fshift, int64_t* minc2, int64_t* maxc2, int64_t* nb2,
-                            int32_t* ident, int64_t k0) {
+                            int64_t k0) {
   const int64_t k = k0 + (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
   if (k >= g1.nch) return;
   const int32_t row = g1.rows[k];
@@ -543,7 +543,6 @@ __global__ void k_vrow_geom(ChunkGeom g1, int fshift, int64_t* minc2, int64_t* m
     minc2[bb + q] = base;
     maxc2[bb + q] = hi;
     nb2[bb + q] = (hi >> fshift) - (base >> fshift) + 1;
-    ident[bb + q] = (int32_t)(bb + q);
   }
 }
 
@@ -1396,11 +1395,11 @@ hipError_t launch_vrow_rows(const ChunkGeom& g2, int32_t* row2, hipStream_t st) 
 }
 
 hipError_t launch_vrow_geom(const ChunkGeom& g1, int fshift, int64_t* minc2, int64_t* maxc2,
-                            int64_t* nb2, int32_t* ident, hipStream_t st) {
+                            int64_t* nb2, hipStream_t st) {
   const int64_t cap = max_grid(256) * 4;  // one wave per coarse row
   for (int64_t o = 0; o < g1.nch; o += cap)
     hipLaunchKernelGGL(k_vrow_geom, (unsigned)((std::min(cap, g1.nch - o) + 3) / 4), 256, 0, st,
-                       g1, fshift, minc2, maxc2, nb2, ident, o);
+                       g1, fshift, minc2, maxc2, nb2, o);
   return hipGetLastError();
 }
 

@@ -194,9 +194,9 @@ hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArg
                                int64_t max_nb, hipStream_t st);
 // --- coarse level: coarse chunks as virtual rows of a second geometry ---
 // per coarse chunk (global index over the coarse rows' chunks): column base,
-// last column, fine chunk count and its own index (identity row list)
+// last column, fine chunk count
 hipError_t launch_vrow_geom(const ChunkGeom& g1, int fshift, int64_t* minc2, int64_t* maxc2,
-                            int64_t* nb2, int32_t* ident, hipStream_t st);
+                            int64_t* nb2, hipStream_t st);
 // fine-chunk product counts of the level-2 tiles of b2 (cnt2 zeroed before)
 hipError_t launch_l2_hist(const ChunkGeom& g2, const BatchArgs& b2, const int32_t* tile_row2,
                           const int64_t* start1, const uint32_t* ws1_col, int64_t* cnt2,

@@ -299,7 +299,6 @@ magnus_status_t setup_coarse(magnus_plan_s* P) {
   C.minc2 = (int64_t*)palloc(P, sizeof(int64_t) * 3 * nv);
   C.big_all = (int32_t*)palloc(P, sizeof(int32_t) * nv);
   C.small_all = (int32_t*)palloc(P, sizeof(int32_t) * nv);
-  C.ident = (int32_t*)palloc(P, sizeof(int32_t) * nv);
   C.flags = (int64_t*)palloc(P, sizeof(int64_t) * 2 * max_nb1b);
   C.nbig_dev = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, nbat));
   C.scan_temp = palloc(P, scan_temp_bytes(nv + 1));
@@ -310,13 +309,13 @@ magnus_status_t setup_coarse(magnus_plan_s* P) {
   C.ws2_col = (uint16_t*)palloc(P, sizeof(uint16_t) * C.ws_products);
   C.ws2_val = palloc(P, (size_t)vs * C.ws_products);
   if (!C.cnt1 || !C.start1 || !C.nnz1 || !C.out1 || !C.row1 || !C.cur1 || !C.minc2 ||
-      !C.big_all || !C.small_all || !C.ident || !C.flags || !C.nbig_dev || !C.scan_temp ||
+      !C.big_all || !C.small_all || !C.flags || !C.nbig_dev || !C.scan_temp ||
       !C.item_counts || !C.work || !C.ws1_col || !C.ws1_val || !C.ws2_col || !C.ws2_val)
     return MAGNUS_ERR_OOM;
   C.maxc2 = C.minc2 + nv;
   C.vnb = C.minc2 + 2 * nv;
   C.pos = C.flags + max_nb1b;
-  HIPCHK(launch_vrow_geom(g1, P->shift, C.minc2, C.maxc2, C.vnb, C.ident, P->st));
+  HIPCHK(launch_vrow_geom(g1, P->shift, C.minc2, C.maxc2, C.vnb, P->st));
   HIPCHK(hipMemsetAsync(C.item_counts, 0, sizeof(int32_t) * 2 * std::max<int64_t>(1, nbat),
                         P->st));
   C.cb.assign(nbat, magnus_plan_s::CBatch{});
@@ -421,7 +420,7 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
       HIPCHK(scan_excl_i64(C.cnt1 + b.bin0, C.start1 + b.bin0, b.nbins, nullptr, nullptr,
                            C.scan_temp, P->st));
       HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
-      HIPCHK(launch_bin_scatter2(P->M, g1, b, false, 1, C.sorted1, C.tile_row1, P->aoff,
+      HIPCHK(launch_bin_scatter2(P->M, g1, b, false, 1, C.sorted1_sym, C.tile_row1, P->aoff,
                                  C.tile_e0, C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1,
                                  P->st));
     }
@@ -844,6 +843,7 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     // coarse chunks (long runs per chunk); chunk-ordered with long tiles
     // beyond
     Co.sorted1 = Co.max_nb1 > MG_COARSE_SORTED_MIN ? 1 : 0;
+    Co.sorted1_sym = Co.max_nb1 > MG_COARSE_SORTED_SYM_MIN ? 1 : 0;
     Co.tile1 = Co.sorted1 ? 4096 : 1024;
     if (o.tile_products > 0) Co.tile1 = P->tile;
     while (Co.tile1 > 256 &&

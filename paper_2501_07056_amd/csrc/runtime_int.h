@@ -19,9 +19,13 @@
 #define MG_SORTED_OUT 0
 #endif
 // the coarse level's first reorder writes in chunk order when rows span more
-// coarse chunks than this (short runs per chunk in the expansion order)
+// coarse chunks than this (short runs per chunk in the expansion order); the
+// symbolic phase's reorder (columns only) gains from it only further on
 #ifndef MG_COARSE_SORTED_MIN
 #define MG_COARSE_SORTED_MIN 256
+#endif
+#ifndef MG_COARSE_SORTED_SYM_MIN
+#define MG_COARSE_SORTED_SYM_MIN 512
 #endif
 #ifndef MG_L2_TILE
 #define MG_L2_TILE 2048
@@ -165,7 +169,7 @@ struct magnus_plan_s {
   };
   struct Coarse {
     int64_t nrows = 0, coarse_range = 0, max_nb1 = 1, max_nb2 = 1, nv = 0, nbins2 = 0;
-    int cshift = 20, tile1 = 4096, tile2 = MG_L2_TILE, sorted1 = 1;
+    int cshift = 20, tile1 = 4096, tile2 = MG_L2_TILE, sorted1 = 1, sorted1_sym = 1;
     ChunkGeom g1{};
     std::vector<BatchArgs> b1;  // level-1 batches
     std::vector<CBatch> cb;     // their level-2 parts
@@ -174,7 +178,7 @@ struct magnus_plan_s {
     // per coarse chunk
     int64_t *cnt1 = nullptr, *start1 = nullptr, *nnz1 = nullptr, *out1 = nullptr;
     int64_t *minc2 = nullptr, *maxc2 = nullptr, *vnb = nullptr;
-    int32_t *row1 = nullptr, *big_all = nullptr, *small_all = nullptr, *ident = nullptr;
+    int32_t *row1 = nullptr, *big_all = nullptr, *small_all = nullptr;
     unsigned long long* cur1 = nullptr;
     int64_t *flags = nullptr, *pos = nullptr, *nbig_dev = nullptr;  // split scratch
     int32_t* item_counts = nullptr;  // per batch: dense items, sort items
