@@ -304,8 +304,22 @@ magnus_status_t setup_coarse(magnus_plan_s* P) {
   C.scan_temp = palloc(P, scan_temp_bytes(nv + 1));
   C.item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2 * std::max<int64_t>(1, nbat));
   C.work = (unsigned int*)palloc(P, sizeof(int64_t) * 2 * std::max<int64_t>(1, nbat));
-  C.ws1_col = (uint32_t*)palloc(P, sizeof(uint32_t) * C.ws_products);
-  C.ws1_val = palloc(P, (size_t)vs * C.ws_products);
+  // the first reorder is done once, with values, in the symbolic phase when
+  // all the coarse rows' products fit the workspace cap (max_workspace_bytes,
+  // else a quarter of the device memory)
+  C.ip_total = tots[0];
+  {
+    int64_t cap = h->opts.max_workspace_bytes;
+    if (cap <= 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      cap = (int64_t)(tot / 4);
+    }
+    C.keep_ws1 = C.ip_total * (4 + vs) <= cap;
+  }
+  const int64_t n_ws1 = C.keep_ws1 ? C.ip_total : C.ws_products;
+  C.ws1_col = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, n_ws1));
+  C.ws1_val = palloc(P, (size_t)vs * std::max<int64_t>(1, n_ws1));
   C.ws2_col = (uint16_t*)palloc(P, sizeof(uint16_t) * C.ws_products);
   C.ws2_val = palloc(P, (size_t)vs * C.ws_products);
   if (!C.cnt1 || !C.start1 || !C.nnz1 || !C.out1 || !C.row1 || !C.cur1 || !C.minc2 ||
@@ -408,11 +422,15 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
     const BatchArgs& b = C.b1[bi];
     magnus_plan_s::CBatch& cb = C.cb[bi];
     int32_t* ic = C.item_counts + 2 * bi;
+    uint32_t* w1c = C.col1(b);
+    void* w1v = C.val1(b, (int64_t)P->s_val);
     {
-      // per product: B column read, 32-bit column written; per A entry:
-      // column, product offset, B row pointer (twice: histogram and reorder)
+      // per product: B column read (twice: histogram and reorder), 32-bit
+      // column written (with the kept workspace, B value read and product
+      // written too); per tile the A entries' metadata
+      const double pv = C.keep_ws1 ? 2 * P->s_val : 0;
       ProfScope ps(h, P->st, "coarse_reorder (symbolic, level 1)",
-                   (double)b.nip * (2 * P->s_col + 4) +
+                   (double)b.nip * (2 * P->s_col + 4 + pv) +
                        2.0 * (double)b.nip / std::max<int64_t>(1, g1.tile) * 64);
       HIPCHK(launch_fill_i64(C.cnt1 + b.bin0, b.nbins, 0, P->st));
       HIPCHK(launch_bin_hist(P->M, g1, b, C.tile_row1, P->aoff, C.tile_e0, C.cnt1, C.row1,
@@ -420,9 +438,9 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
       HIPCHK(scan_excl_i64(C.cnt1 + b.bin0, C.start1 + b.bin0, b.nbins, nullptr, nullptr,
                            C.scan_temp, P->st));
       HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
-      HIPCHK(launch_bin_scatter2(P->M, g1, b, false, 1, C.sorted1_sym, C.tile_row1, P->aoff,
-                                 C.tile_e0, C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1,
-                                 P->st));
+      HIPCHK(launch_bin_scatter2(P->M, g1, b, C.keep_ws1, 1,
+                                 C.keep_ws1 ? C.sorted1 : C.sorted1_sym, C.tile_row1, P->aoff,
+                                 C.tile_e0, C.start1, C.cur1, w1c, w1v, C.max_nb1, P->st));
     }
     cb.big = C.big_all + b.bin0;
     cb.small = C.small_all + b.bin0;
@@ -436,8 +454,7 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
       ProfScope ps(h, P->st, "coarse_sort (symbolic, small coarse chunks)",
                    (double)(b.nip) * 4);
       HIPCHK(launch_vrow_sort(false, P->M.f64, cb.small, cb.nsmall, C.cnt1, C.start1, C.minc2,
-                              C.ws1_col, C.ws1_val, C.nnz1, nullptr, nullptr, 0, nullptr,
-                              P->st));
+                              w1c, w1v, C.nnz1, nullptr, nullptr, 0, nullptr, P->st));
     }
     if (cb.nbig > 0) {
       s = coarse_fine_setup(P, bi);
@@ -448,8 +465,8 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
         // per product: 32-bit column read; per fine chunk: three words out
         ProfScope ps(h, P->st, "coarse_bitmap (symbolic, level 2)",
                      (double)b2.nip * 4 + (double)b2.nbins * 20);
-        HIPCHK(launch_vrow_bitmap(g2, C.cshift, 0, cb.nbig, C.max_nb2, C.start1, C.ws1_col,
-                                  cb.cnt2, cb.nnz2, cb.row2, C.nnz1, P->st));
+        HIPCHK(launch_vrow_bitmap(g2, C.cshift, 0, cb.nbig, C.max_nb2, C.start1, w1c, cb.cnt2,
+                                  cb.nnz2, cb.row2, C.nnz1, P->st));
         HIPCHK(scan_excl_i64(cb.cnt2, cb.start2, b2.nbins, nullptr, nullptr, cb.scan_temp,
                              P->st));
         HIPCHK(launch_bin_group(g2, b2, cb.cnt2, P->dense_min, P->group_max, cb.dense2,
@@ -460,16 +477,14 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
         ProfScope ps(h, P->st, "coarse_count (symbolic, level 2)",
                      (double)b2.nip * (4 + 4 + 2 + 2) + (double)b2.nbins * 24);
         HIPCHK(launch_fill_i64(cb.cnt2, b2.nbins, 0, P->st));
-        HIPCHK(launch_l2_hist(g2, b2, cb.tile_row2, C.start1, C.ws1_col, cb.cnt2, C.max_nb2,
-                              P->st));
+        HIPCHK(launch_l2_hist(g2, b2, cb.tile_row2, C.start1, w1c, cb.cnt2, C.max_nb2, P->st));
         HIPCHK(scan_excl_i64(cb.cnt2, cb.start2, b2.nbins, nullptr, nullptr, cb.scan_temp,
                              P->st));
         HIPCHK(launch_bin_group(g2, b2, cb.cnt2, P->dense_min, P->group_max, cb.dense2,
                                 cb.sort2, ic, P->st));
         HIPCHK(launch_fill_i64((int64_t*)cb.cur2, b2.nbins, 0, P->st));
-        HIPCHK(launch_l2_scatter(g2, b2, false, P->M.f64, cb.tile_row2, C.start1, C.ws1_col,
-                                 C.ws1_val, cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2,
-                                 P->st));
+        HIPCHK(launch_l2_scatter(g2, b2, false, P->M.f64, cb.tile_row2, C.start1, w1c, w1v,
+                                 cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2, P->st));
         unsigned int* wk = C.work + 4 * bi + 2;
         HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
         HIPCHK(launch_bin_accum(g2, b2, false, P->M.f64, cb.start2, cb.cnt2, cb.row2, cb.dense2,
@@ -496,16 +511,17 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
     const BatchArgs& b = C.b1[bi];
     magnus_plan_s::CBatch& cb = C.cb[bi];
     HIPCHK(launch_bin_rows(C.g1, b.k0, b.k1, C.nnz1, nullptr, P->crp, C.out1, true, P->st));
-    HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
-    {
+    uint32_t* w1c = C.col1(b);
+    void* w1v = C.val1(b, (int64_t)vs);
+    if (!C.keep_ws1) {
+      HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
       // per product: B column and value read, 32-bit column and product
       // written; per A entry: column, value, product offset, B row
       ProfScope ps(h, P->st, "coarse_scatter (numeric, level 1)",
                    (double)b.nip * (P->s_col + vs + 4 + vs) +
                        (double)b.nent * (P->s_col + vs + 8 + P->s_rp));
       HIPCHK(launch_bin_scatter2(P->M, C.g1, b, true, 1, C.sorted1, C.tile_row1, P->aoff,
-                                 C.tile_e0, C.start1, C.cur1, C.ws1_col, C.ws1_val, C.max_nb1,
-                                 P->st));
+                                 C.tile_e0, C.start1, C.cur1, w1c, w1v, C.max_nb1, P->st));
     }
     {
       // per product of a small coarse chunk: column and value read; per
@@ -513,7 +529,7 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
       ProfScope ps(h, P->st, "coarse_sort (numeric, small coarse chunks)",
                    (double)(b.nip - cb.nip2) * (4 + vs));
       HIPCHK(launch_vrow_sort(true, P->M.f64, cb.small, cb.nsmall, C.cnt1, C.start1, C.minc2,
-                              C.ws1_col, C.ws1_val, C.nnz1, C.out1, ccol, col64, cval, P->st));
+                              w1c, w1v, C.nnz1, C.out1, ccol, col64, cval, P->st));
     }
     if (cb.nbig == 0) continue;
     const BatchArgs& b2 = cb.b2;
@@ -524,9 +540,8 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
       // written
       ProfScope ps(h, P->st, "fine_scatter (numeric, level 2)",
                    (double)b2.nip * (4 + vs + 2 + vs));
-      HIPCHK(launch_l2_scatter(cb.g2, b2, true, P->M.f64, cb.tile_row2, C.start1, C.ws1_col,
-                               C.ws1_val, cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2,
-                               P->st));
+      HIPCHK(launch_l2_scatter(cb.g2, b2, true, P->M.f64, cb.tile_row2, C.start1, w1c, w1v,
+                               cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2, P->st));
     }
     unsigned int* wk = C.work + 4 * bi;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));

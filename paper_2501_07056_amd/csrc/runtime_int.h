@@ -183,12 +183,20 @@ struct magnus_plan_s {
     int64_t *flags = nullptr, *pos = nullptr, *nbig_dev = nullptr;  // split scratch
     int32_t* item_counts = nullptr;  // per batch: dense items, sort items
     unsigned int* work = nullptr;    // per batch: persistent-kernel counters
+    // first workspace: one batch's products, or, when every coarse row's
+    // products fit the budget (keep_ws1), all of them, written with their
+    // values by the symbolic phase and read again by the numeric phase
     uint32_t* ws1_col = nullptr;
     void* ws1_val = nullptr;
+    bool keep_ws1 = false;
     uint16_t* ws2_col = nullptr;
     void* ws2_val = nullptr;
-    int64_t ws_products = 0;
+    int64_t ws_products = 0, ip_total = 0;
     void* scan_temp = nullptr;  // scans of up to nv + 1 entries
+    uint32_t* col1(const BatchArgs& b) const { return ws1_col + (keep_ws1 ? b.ip0 : 0); }
+    void* val1(const BatchArgs& b, int64_t vs) const {
+      return (char*)ws1_val + (keep_ws1 ? b.ip0 * vs : 0);
+    }
   } co;
 };
 

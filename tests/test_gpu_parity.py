@@ -90,9 +90,13 @@ def test_coarse_level_er(ctx, vt):
     B = wl.erdos_renyi(5000, 1 << 18, 100, wl.seed(89), val_dtype=vt)
     ref = oracle.spgemm(A, B)
     log(f"coarse er vt={vt.__name__}")
-    for cc in (4, 64, -1):
+    # 4 / 64 chunks per coarse chunk with the first workspace kept between
+    # the phases; 64 under a 2 MiB workspace cap (first reorder redone in the
+    # numeric phase, many batches); the coarse level off
+    for cc, cap in ((4, 0), (64, 0), (64, 2 << 20), (-1, 0)):
         rp, col, val, info = gpu_product(ctx, A, B, force_category="chunked", lds_bytes=16384,
-                                         coarse_chunks=cc, batch_products=400000)
+                                         coarse_chunks=cc, batch_products=0 if cap else 400000,
+                                         max_workspace_bytes=cap)
         if cc > 0:
             assert info["coarse_rows"] == A.nrows and info["coarse_chunks"] > A.nrows
             assert info["rows_by_category"][2] == A.nrows and info["n_batches"] == 0
@@ -102,7 +106,8 @@ def test_coarse_level_er(ctx, vt):
         else:
             assert info["coarse_rows"] == 0
         compare(rp, col, val, ref, vt, exact=False)
-    ctx.set_options(force_category="auto", lds_bytes=0, coarse_chunks=0, batch_products=0)
+    ctx.set_options(force_category="auto", lds_bytes=0, coarse_chunks=0, batch_products=0,
+                    max_workspace_bytes=0)
 
 
 def test_coarse_level_rmat(ctx):
@@ -119,6 +124,28 @@ def test_coarse_level_rmat(ctx):
     assert 0 < info["coarse_fine_chunks"] < 4 * info["coarse_chunks"]
     compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
     ctx.set_options(force_category="auto", chunk_shift=0, coarse_chunks=0, batch_products=0)
+
+
+def test_coarse_chunk_size_boundary(ctx):
+    """One row whose coarse chunks (256 columns: chunks of 2^6, 4 per coarse
+    chunk) hold exactly 1024 products (sorted directly), 1025 (fine level),
+    none, and 1, with repeated columns; the products are a_j * 1 with
+    integer a_j, so the sums are exact."""
+    rng = np.random.default_rng(93)
+    parts = [rng.integers(0, 256, 1024), rng.integers(256, 512, 1025),
+             np.array([1023]), rng.integers(1024, 1280, 700)]
+    cols = np.concatenate(parts)
+    n = len(cols)
+    a = rng.integers(-4, 5, n).astype(np.float64)
+    A = CSR(2, n, np.array([0, n, n], np.int64), np.arange(n, dtype=np.int32), a)
+    B = CSR(n, 1280, np.arange(n + 1, dtype=np.int64), cols.astype(np.int32), np.ones(n))
+    log("coarse chunk size boundary")
+    rp, col, val, info = gpu_product(ctx, A, B, force_category="chunked", chunk_shift=6,
+                                     coarse_chunks=4)
+    assert info["coarse_rows"] == 1 and info["coarse_chunks"] == 5
+    assert info["coarse_fine_chunks"] == 4  # only the 1025-product coarse chunk
+    compare(rp, col, val, oracle.spgemm(A, B), np.float64, exact=True)
+    ctx.set_options(force_category="auto", chunk_shift=0, coarse_chunks=0)
 
 
 @pytest.mark.parametrize("cit", [np.int32, np.int64])
