@@ -168,6 +168,10 @@ KERNEL_SYMBOLS = {
     "fine_scatter (numeric, level 2)": [("k_l2_scatter<", "true>")],
     "coarse_reorder (symbolic, level 1)": [("k_bin_hist<",),
                                            ("k_bin_scatter2<", "unsigned int, false")],
+    "coarse_reorder (symbolic, L1, values)": [("k_bin_hist<",),
+                                                   ("k_bin_scatter2<", "unsigned int, true")],
+    "coarse_sort (symbolic, small chunks)": [("k_vrow_sort<", "false>")],
+    "coarse_sort (numeric, small chunks)": [("k_vrow_sort<", "true>")],
     "coarse_bitmap (symbolic, level 2)": [("k_vrow_bitmap",)],
     "coarse_count (symbolic, level 2)": [("k_l2_hist<",), ("k_l2_scatter<", "false>")],
 }
@@ -201,7 +205,15 @@ def pmc_summary(args):
     f_write = args.copy_bytes * cwr[cw[0]][1] / (cwr[cw[0]][0] * 1024.0)
     kernels = {}
     lines = []
+    # only the library kernels the profiled run reported (several names map
+    # to the same kernel symbols in different modes)
+    seen = None
+    if args.pmc_names:
+        d = json.loads(open(args.pmc_names).read().strip().splitlines()[-1])
+        seen = {k["name"] for k in d.get("kernels", [])}
     for lib_name, pats in KERNEL_SYMBOLS.items():
+        if seen is not None and lib_name not in seen:
+            continue
         fk = sum(v[0] for k, v in fetch.items() if _match(k, pats))
         wk = sum(v[0] for k, v in write.items() if _match(k, pats))
         # dispatches of the first matching symbol = launches of the grouped kernel
@@ -652,6 +664,9 @@ def main():
                                                        "COPY_WRITE_DIR"),
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs into profiles/traffic_<workload>.md")
     ap.add_argument("--copy-bytes", type=int, default=1 << 32)
+    ap.add_argument("--pmc-names", metavar="JSON",
+                    help="with --pmc-summary: the bench line of the profiled run; only the "
+                         "library kernels it reports are summarised")
     ap.add_argument("--trace-summary", metavar="STATS_DIR",
                     help="turn a rocprofv3 --kernel-trace --stats CSV into profiles/kernels_<workload>.md")
     ap.add_argument("--trace-command", default="")

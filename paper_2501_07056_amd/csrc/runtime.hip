@@ -429,7 +429,9 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
       // column written (with the kept workspace, B value read and product
       // written too); per tile the A entries' metadata
       const double pv = C.keep_ws1 ? 2 * P->s_val : 0;
-      ProfScope ps(h, P->st, "coarse_reorder (symbolic, level 1)",
+      ProfScope ps(h, P->st,
+                   C.keep_ws1 ? "coarse_reorder (symbolic, L1, values)"
+                              : "coarse_reorder (symbolic, level 1)",
                    (double)b.nip * (2 * P->s_col + 4 + pv) +
                        2.0 * (double)b.nip / std::max<int64_t>(1, g1.tile) * 64);
       HIPCHK(launch_fill_i64(C.cnt1 + b.bin0, b.nbins, 0, P->st));
@@ -451,7 +453,7 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
     cb.nsmall = b.nbins - cb.nbig;
     {
       // per product of a small coarse chunk: 32-bit column read
-      ProfScope ps(h, P->st, "coarse_sort (symbolic, small coarse chunks)",
+      ProfScope ps(h, P->st, "coarse_sort (symbolic, small chunks)",
                    (double)(b.nip) * 4);
       HIPCHK(launch_vrow_sort(false, P->M.f64, cb.small, cb.nsmall, C.cnt1, C.start1, C.minc2,
                               w1c, w1v, C.nnz1, nullptr, nullptr, 0, nullptr, P->st));
@@ -526,7 +528,7 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
     {
       // per product of a small coarse chunk: column and value read; per
       // output: C column and value
-      ProfScope ps(h, P->st, "coarse_sort (numeric, small coarse chunks)",
+      ProfScope ps(h, P->st, "coarse_sort (numeric, small chunks)",
                    (double)(b.nip - cb.nip2) * (4 + vs));
       HIPCHK(launch_vrow_sort(true, P->M.f64, cb.small, cb.nsmall, C.cnt1, C.start1, C.minc2,
                               w1c, w1v, C.nnz1, C.out1, ccol, col64, cval, P->st));
