@@ -831,6 +831,9 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   if (P->h_stats.err & ERR_INVALID_CSR) return cleanup(MAGNUS_ERR_INVALID_CSR);
   P->colbits = bits_for((int64_t)std::max<unsigned long long>(1, P->h_stats.range_cat[0]));
   P->dense_shift = dense_rows_shift(P->h_stats.range_cat[1], P->shift);
+  if (o.tile_products <= 0 && P->h_stats.rows_cat[2] > 0 &&
+      P->h_stats.ip_cat[2] / P->h_stats.rows_cat[2] >= ((unsigned long long)1 << 18))
+    P->tile = 2048;  // long CHUNKED rows: longer tiles amortise each tile's A-entry staging
   P->max_nb = (int64_t)(P->h_stats.range_cat[2] >> P->shift) + 2;
   P->nch = P->h_list_off[CLS_CHUNKED + 1] - P->h_list_off[CLS_CHUNKED];
   if (P->max_nb > 65535 && P->nch > 0) return cleanup(MAGNUS_ERR_INVALID_ARG);
