@@ -160,7 +160,10 @@ def cpu_baseline(A, B, ip_rows, seconds: float, seed: int = 7):
 KERNEL_SYMBOLS = {
     "bin_scatter (numeric reorder)": [("k_bin_scatter2<", "unsigned short, true")],
     "bin_accum (numeric, dense+sort chunks)": [("k_accum_dense<", "true>"),
-                                               ("k_accum_sort<", "true>")],
+                                               ("k_accum_sort<", "true, false>")],
+    "bin_scatter_det (ordered reorder)": [("k_bin_scatter_det<",)],
+    "bin_accum_det (ordered dense+sort)": [("k_accum_dense_det<",),
+                                           ("k_accum_sort<", "true, true>")],
     "row_bitmap (symbolic, chunked rows)": [("k_row_bitmap<",)],
     "sort_rows (numeric)": [("k_sort_rows<",)],
     "rowinfo (setup)": [("k_rowinfo<",)],
@@ -815,7 +818,10 @@ def main():
         err = np.abs(gval - ref.ref) / np.maximum(ref.abssum, 1e-300)
         parity = {"rows": int(len(rows)), "entries": int(len(gcol)), "structure_equal": ok_struct,
                   "max_err_over_abssum": float(err.max()) if len(err) else 0.0,
-                  "within_rtol": bool(ok_struct and (err <= rtol).all()), "rtol": rtol}
+                  "within_rtol": bool(ok_struct and (err <= rtol).all()), "rtol": rtol,
+                  # every value equal to the oracle's input-precision sum taken in
+                  # the order of Eq. 1 (what the deterministic option guarantees)
+                  "bits_equal_stored_order_sum": bool(ok_struct and np.array_equal(gval, ref.val))}
         log(f"[bench] cpu oracle {cpu['value']:.3f} GFLOP/s on {cpu['cores']} cores; "
             f"sample parity {parity['within_rtol']}")
 

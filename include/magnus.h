@@ -119,7 +119,14 @@ typedef struct {
                            * wider than one coarse chunk are reordered into coarse chunks first.
                            * 0: the widest coarse chunk whose symbolic bitmap fits the LDS
                            * budget; < 0: no coarse level */
-  int32_t _reserved[3];
+  int32_t deterministic;  /* 1: every value is the row-wise sum of Eq. 1 taken in stored order
+                           * (for each entry of A's row in order, each entry of the B row in
+                           * order, from +0.0, products rounded to the value type), the same
+                           * bits on every run.  All non-empty rows go through the CHUNKED
+                           * path without the coarse level (so a row may span at most 65535
+                           * chunks); force_category and coarse_chunks are ignored.  Single
+                           * products only: batch plans and the server reject it. */
+  int32_t _reserved[2];
 } magnus_options_t;
 
 /* Sizes the plan reports (host struct). */

@@ -31,7 +31,7 @@ class Options(ctypes.Structure):
                 ("bin_dense_min", c_i32), ("tile_products", c_i32), ("dense_block", c_i32),
                 ("batch_products", c_i64), ("max_workspace_bytes", c_i64), ("validate", c_i32),
                 ("lds_bytes", c_i32), ("sort_group_max", c_i32), ("stream_hints", c_i32),
-                ("coarse_chunks", c_i32), ("_reserved", c_i32 * 3)]
+                ("coarse_chunks", c_i32), ("deterministic", c_i32), ("_reserved", c_i32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):

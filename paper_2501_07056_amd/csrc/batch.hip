@@ -83,6 +83,10 @@ magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus
                                   magnus_plan_info_t* info) {
   if (!h || !out || count < 1 || !A || !B || !nnz_out) return MAGNUS_ERR_INVALID_ARG;
   *out = nullptr;
+  if (h->opts.deterministic) {
+    h->err = "deterministic mode covers single products (magnus_plan) only";
+    return MAGNUS_ERR_INVALID_ARG;
+  }
   // descriptors, shared types, row numbering
   std::vector<Mats> mats(count);
   int64_t N = 0, annz_tot = 0;

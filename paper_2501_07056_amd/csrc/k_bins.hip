@@ -520,6 +520,108 @@ __global__ void __launch_bounds__(BIN_BS)
 }
 
 // ---------------------------------------------------------------------------
+// Order-preserving reorder (deterministic mode): the products of every chunk
+// land in the workspace in the order of Eq. 1, so that an accumulator adding
+// them in workspace order reproduces the plain row-wise sum bit for bit.  One
+// workgroup per CHUNKED row takes the row's tiles in order; each tile is
+// staged in LDS, its (chunk, product index) keys are sorted by a workgroup
+// bitonic network, and every product goes after the products that the
+// row's earlier tiles put into its chunk (a running cursor per chunk).
+// ---------------------------------------------------------------------------
+constexpr int DS_BS = 256;
+constexpr int DS_QBITS = 12;  // tile index bits of a key: tiles of <= 4096 products
+
+size_t bin_scatter_det_lds(int f64, int tile, int64_t max_nb) {
+  const size_t vs = f64 ? 8 : 4;
+  return DS_BS * (8 + 8 + 8) + (size_t)max_nb * (8 + 4 + 4) + 64 + (size_t)tile * (4 + 4 + vs) + 64;
+}
+
+// Ascending bitonic sort of n (a power of two) keys in LDS by a workgroup of
+// BS threads; starts after and ends with a barrier.
+template <int BS>
+MG_INLINE void block_bitonic_sort(uint32_t* keys, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += BS) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = keys[i], b = keys[ixj];
+          if ((a > b) == ((i & k) == 0)) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename RP, typename CI, typename V>
+__global__ void __launch_bounds__(DS_BS)
+    k_bin_scatter_det(const RP* __restrict__ arp, const CI* __restrict__ acol,
+                      const V* __restrict__ aval, const RP* __restrict__ brp,
+                      const CI* __restrict__ bcol, const V* __restrict__ bval, ChunkGeom g,
+                      int64_t k0, const int64_t* __restrict__ aoff,
+                      const int64_t* __restrict__ tile_e0, const int64_t* __restrict__ bin_start,
+                      uint16_t* ws_col, V* ws_val) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  int32_t* w_pre = (int32_t*)dsm;
+  int64_t* w_b0 = (int64_t*)(dsm + DS_BS * 8);
+  V* w_av = (V*)(w_b0 + DS_BS);
+  const int64_t k = k0 + blockIdx.x;
+  const int32_t row = g.rows[k];
+  const int64_t nbk = g.nb[k], ntk = g.nt[k], gb = g.binBase[k], tb = g.tileBase[k];
+  int64_t* cur = (int64_t*)((char*)w_av + DS_BS * 8);  // nbk: next free slot of each chunk
+  int32_t* hist = (int32_t*)(cur + nbk);                 // nbk
+  int32_t* loff = hist + nbk;                            // nbk
+  uint32_t* keys = (uint32_t*)(((uintptr_t)(loff + nbk) + 15) & ~(uintptr_t)15);
+  uint32_t* u_word = keys + g.tile;
+  V* u_val = (V*)(((uintptr_t)(u_word + g.tile) + 15) & ~(uintptr_t)15);
+  __shared__ int32_t s_tmp[DS_BS / MG_WAVE];
+  const int t = threadIdx.x;
+  const int64_t ipr = g.ip[row];
+  const int64_t a1 = arp[row + 1];
+  const uint32_t base_bin = (uint32_t)(g.minc[row] >> g.shift);
+  const uint32_t lmask = (1u << g.shift) - 1u;
+  for (int64_t q = t; q < nbk; q += DS_BS) cur[q] = bin_start[gb + q];
+  for (int64_t ti = 0; ti < ntk; ++ti) {
+    const int64_t p0 = ti * (int64_t)g.tile;
+    const int64_t p1 = (p0 + g.tile < ipr) ? (p0 + g.tile) : ipr;
+    for (int64_t q = t; q < nbk; q += DS_BS) hist[q] = 0;
+    __syncthreads();
+    expand_products<DS_BS, RP, CI, V, true>(
+        p0, p1, tile_e0[tb + ti], a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
+        [&](int32_t q, CI col, V pv) {
+          const uint32_t bin = (uint32_t)(col >> g.shift) - base_bin;
+          u_word[q] = (bin << 16) | ((uint32_t)col & lmask);
+          u_val[q] = pv;
+          atomicAdd(&hist[bin], 1);
+        });
+    __syncthreads();
+    block_excl_scan<DS_BS>(hist, loff, nbk, s_tmp);
+    const int32_t nloc = (int32_t)(p1 - p0);
+    int32_t n2 = 1;
+    while (n2 < nloc) n2 <<= 1;
+    for (int32_t q = t; q < n2; q += DS_BS)
+      keys[q] = (q < nloc) ? (((u_word[q] >> 16) << DS_QBITS) | (uint32_t)q) : 0xFFFFFFFFu;
+    __syncthreads();
+    block_bitonic_sort<DS_BS>(keys, n2);
+    // sorted position p holds the product of rank p - loff[bin] among its
+    // chunk's products in this tile, in product order
+    for (int32_t p = t; p < nloc; p += DS_BS) {
+      const uint32_t key = keys[p];
+      const uint32_t q = key & ((1u << DS_QBITS) - 1u), bin = key >> DS_QBITS;
+      const int64_t d = cur[bin] + (p - loff[bin]);
+      st_stream<HINT_WS_STORE>(&ws_col[d], (uint16_t)(u_word[q] & 0xFFFFu));
+      st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
+    }
+    __syncthreads();
+    for (int64_t q = t; q < nbk; q += DS_BS) cur[q] += hist[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Coarse level (Section 3.3).  Every chunk of 2^cshift columns that the first
 // reorder produced becomes a "virtual row" of a second chunk geometry: its
 // products sit contiguously in the first workspace with 32-bit columns local
@@ -955,13 +1057,93 @@ __global__ void __launch_bounds__(1024)
 }
 
 // ---------------------------------------------------------------------------
+// Dense chunk accumulation in workspace order (deterministic mode): one wave
+// per chunk adds the chunk's products into the LDS accumulator one by one in
+// the order they are stored, which the order-preserving reorder made the
+// order of Eq. 1.  A window of 64 products is sorted by (column, position);
+// the k-th products of all runs of equal columns are added together (distinct
+// columns), k = 0, 1, ..., so each column's additions keep their order.
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ void __launch_bounds__(MG_WAVE)
+    k_accum_dense_det(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
+                      int64_t item_base, const int64_t* __restrict__ bin_start,
+                      const int64_t* __restrict__ bin_cnt, const int32_t* __restrict__ bin_row,
+                      const uint16_t* __restrict__ ws_col, const V* __restrict__ ws_val,
+                      const int64_t* __restrict__ bin_out, void* ccol_, int col64, V* cval,
+                      unsigned int* work) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int64_t L = (int64_t)1 << g.shift;
+  V* acc = (V*)dsm;
+  uint32_t* bits = (uint32_t*)(dsm + L * sizeof(V));
+  const int l = lane();
+  const int64_t nitems = item_counts[0];
+  const int64_t nwords = L / 32;
+  for (int64_t q = l; q < nwords; q += MG_WAVE) bits[q] = 0u;
+  for (int64_t q = l; q < L; q += MG_WAVE) acc[q] = (V)0;
+  const int64_t wpl = (nwords + MG_WAVE - 1) / MG_WAVE;
+  const int64_t w0 = l * wpl, w1 = (w0 + wpl < nwords) ? (w0 + wpl) : nwords;
+  const uint64_t upto = (l == MG_WAVE - 1) ? ~0ull : ((2ull << l) - 1ull);
+  for (;;) {
+    unsigned int it = 0;
+    if (l == 0) it = atomicAdd(work, 1u);
+    it = __shfl(it, 0, MG_WAVE);
+    if ((int64_t)it >= nitems) break;
+    const int64_t gb = items[item_base + it];
+    const int64_t s0 = bin_start[gb], cnt = bin_cnt[gb];
+    for (int64_t x0 = 0; x0 < cnt; x0 += MG_WAVE) {
+      const bool ok = x0 + l < cnt;
+      const uint32_t c = ok ? (uint32_t)ws_col[s0 + x0 + l] : 0u;
+      const V v = ok ? ws_val[s0 + x0 + l] : (V)0;
+      uint32_t kk[1] = {ok ? ((c << 6) | (uint32_t)l) : 0xFFFFFFFFu};
+      bitonic_sort_keys<1>(kk);
+      const bool mine = kk[0] != 0xFFFFFFFFu;
+      const uint32_t cc = kk[0] >> 6;
+      const V vv = __shfl(v, (int)(kk[0] & 63u), MG_WAVE);
+      const uint32_t pc = __shfl_up(cc, 1, MG_WAVE);
+      const uint64_t hm = __ballot(l == 0 || pc != cc);
+      const int r = l - (63 - __clzll(hm & upto));  // position inside the run
+      const int R = wave_max(mine ? r + 1 : 0);
+      for (int rr = 0; rr < R; ++rr) {
+        if (mine && r == rr) {
+          acc[cc] = acc[cc] + vv;
+          atomicOr(&bits[cc >> 5], 1u << (cc & 31));
+        }
+      }
+    }
+    // write-out in column order: a lane owns words w0..w1
+    int64_t my = 0;
+    for (int64_t w = w0; w < w1; ++w) my += __popc(bits[w]);
+    const int64_t inc = wave_incl_scan(my);
+    const int64_t k = bin_row[gb];
+    const int64_t colbase = ((g.minc[g.rows[k]] >> g.shift) + (gb - g.binBase[k])) << g.shift;
+    int64_t pos = bin_out[gb] + inc - my;
+    for (int64_t w = w0; w < w1; ++w) {
+      uint32_t bb = bits[w];
+      if (!bb) continue;
+      bits[w] = 0u;
+      while (bb) {
+        const int bit = __ffs(bb) - 1;
+        bb &= bb - 1;
+        const int64_t lc = w * 32 + bit;
+        if (col64) st_stream<HINT_C_STORE>(&((int64_t*)ccol_)[pos], (int64_t)(colbase + lc));
+        else st_stream<HINT_C_STORE>(&((int32_t*)ccol_)[pos], (int32_t)(colbase + lc));
+        st_stream<HINT_C_STORE>(&cval[pos], acc[lc]);
+        acc[lc] = (V)0;
+        ++pos;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Packed sort of small chunks: one wave per item of <= 64 consecutive chunks
 // of one row and <= 64*E products; key = (chunk offset << shift) | local col,
 // i.e. the column relative to the item's first chunk.
 // ---------------------------------------------------------------------------
 constexpr int AS_WAVES = 4;
 
-template <typename V, int E, bool NUMERIC>
+template <typename V, int E, bool NUMERIC, bool DET>
 MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const int64_t* bin_start,
                                const int64_t* bin_cnt, const int32_t* bin_row,
                                const uint16_t* ws_col, const V* ws_val, int64_t* bin_nnz,
@@ -1022,23 +1204,37 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
     }
     const int hinc = wave_incl_scan(hc);
     const int hbase = hinc - hc;
-    V t = (V)0;
-    bool anyh = false;
+    V carry = (V)0;
+    if constexpr (DET) {
+      // lane by lane: a lane's trailing run continues from the value the
+      // previous lane's run reached, so every run sums in element order
+      V c = (V)0;
+      for (int d = 0; d < MG_WAVE; ++d) {
+        if (l == d) carry = c;
+        V r = c;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (head[e]) { t = (V)0 + v[e]; anyh = true; }
-      else t = t + v[e];
-    }
-    V s = t;
-    bool f = anyh;
+        for (int e = 0; e < E; ++e) r = head[e] ? (V)0 + v[e] : r + v[e];
+        c = __shfl(r, d, MG_WAVE);
+      }
+    } else {
+      V t = (V)0;
+      bool anyh = false;
 #pragma unroll
-    for (int d = 1; d < MG_WAVE; d <<= 1) {
-      const V ps = __shfl_up(s, d, MG_WAVE);
-      const int pf = __shfl_up((int)f, d, MG_WAVE);
-      if (l >= d && !f) { s = ps + s; f = pf != 0; }
+      for (int e = 0; e < E; ++e) {
+        if (head[e]) { t = (V)0 + v[e]; anyh = true; }
+        else t = t + v[e];
+      }
+      V s = t;
+      bool f = anyh;
+#pragma unroll
+      for (int d = 1; d < MG_WAVE; d <<= 1) {
+        const V ps = __shfl_up(s, d, MG_WAVE);
+        const int pf = __shfl_up((int)f, d, MG_WAVE);
+        if (l >= d && !f) { s = ps + s; f = pf != 0; }
+      }
+      carry = __shfl_up(s, 1, MG_WAVE);
+      if (l == 0) carry = (V)0;
     }
-    V carry = __shfl_up(s, 1, MG_WAVE);
-    if (l == 0) carry = (V)0;
     const uint32_t nextk = __shfl_down(k[0], 1, MG_WAVE) >> IDXB;
     const int64_t kk = bin_row[g0];
     const int64_t colbase = ((g.minc[g.rows[kk]] >> g.shift) + (g0 - g.binBase[kk])) << g.shift;
@@ -1064,7 +1260,7 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
   }
 }
 
-template <typename V, bool NUMERIC>
+template <typename V, bool NUMERIC, bool DET>
 __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
     k_accum_sort(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
                  int64_t item_base, const int64_t* __restrict__ bin_start,
@@ -1082,19 +1278,19 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
   const int nbg = (int)items[2 * (item_base + it) + 1];
   const int64_t P = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1] - bin_start[g0];
   if (P <= 64)
-    accum_sort_item<V, 1, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+    accum_sort_item<V, 1, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
                                    bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else if (P <= 128)
-    accum_sort_item<V, 2, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+    accum_sort_item<V, 2, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
                                    bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else if (P <= 256)
-    accum_sort_item<V, 4, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+    accum_sort_item<V, 4, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
                                    bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else if (P <= 512)
-    accum_sort_item<V, 8, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
+    accum_sort_item<V, 8, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
                                    bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
   else
-    accum_sort_item<V, 16, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val,
+    accum_sort_item<V, 16, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val,
                                     bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
 }
 
@@ -1278,9 +1474,10 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
                              const int64_t* sort_items, const int32_t* item_counts,
                              const uint16_t* ws_col, const void* ws_val, int64_t* bin_nnz,
                              const int64_t* bin_out, void* ccol, int col64, void* cval,
-                             int dense_block, unsigned int* work, int persistent_wgs,
+                             int dense_block, unsigned int* work, int persistent_wgs, bool det,
                              hipStream_t st) {
   if (b.nbins <= 0) return hipSuccess;
+  det = det && numeric;
   const size_t lds = bin_dense_lds(f64, g.shift);
   const unsigned gd = (unsigned)std::min<int64_t>(b.nbins, persistent_wgs);
   // sort items: at most one per chunk; the grid is cut below 2^32 work-items
@@ -1288,12 +1485,23 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
   const int64_t gcap = max_grid(AS_WAVES * MG_WAVE);
 #define MG_AC(V)                                                                                  \
   {                                                                                               \
-    auto kd = numeric ? k_accum_dense<V, true> : k_accum_dense<V, false>;                         \
-    hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-    hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_items, item_counts, b.bin0,         \
-                       bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out,   \
-                       ccol, col64, (V*)cval, work);                                              \
-    auto ks = numeric ? k_accum_sort<V, true> : k_accum_sort<V, false>;                           \
+    if (det) {                                                                                    \
+      /* one wave per workgroup: as many workgroups as the LDS holds, twice over */             \
+      auto kd = k_accum_dense_det<V>;                                                             \
+      hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      const unsigned gdd = (unsigned)std::min<int64_t>(b.nbins, (int64_t)persistent_wgs * 8);     \
+      hipLaunchKernelGGL(kd, gdd, MG_WAVE, lds, st, g, dense_items, item_counts, b.bin0,          \
+                         bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_out, ccol,    \
+                         col64, (V*)cval, work);                                                  \
+    } else {                                                                                      \
+      auto kd = numeric ? k_accum_dense<V, true> : k_accum_dense<V, false>;                       \
+      hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_items, item_counts, b.bin0,       \
+                         bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out, \
+                         ccol, col64, (V*)cval, work);                                            \
+    }                                                                                             \
+    auto ks = det ? k_accum_sort<V, true, true>                                                   \
+                  : (numeric ? k_accum_sort<V, true, false> : k_accum_sort<V, false, false>);     \
     for (int64_t o = 0; o < gs_all; o += gcap)                                                    \
       hipLaunchKernelGGL(ks, (unsigned)std::min(gcap, gs_all - o), AS_WAVES * MG_WAVE, 0, st, g,  \
                          sort_items, item_counts, b.bin0, bin_start, bin_cnt, bin_row, ws_col,    \
@@ -1302,6 +1510,30 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
   }
   if (f64) MG_AC(double) else MG_AC(float)
 #undef MG_AC
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+                                  const int64_t* aoff, const int64_t* tile_e0,
+                                  const int64_t* bin_start, uint16_t* ws_col, void* ws_val,
+                                  int64_t max_nb, hipStream_t st) {
+  const int64_t nrows = b.k1 - b.k0;
+  if (nrows <= 0) return hipSuccess;
+  const size_t lds = bin_scatter_det_lds(M.f64, g.tile, max_nb);
+  const int64_t cap = max_grid(DS_BS);
+  for (int64_t o = 0; o < nrows; o += cap) {
+#define MG_SD(V)                                                                                  \
+  MG_DISPATCH2(M, {                                                                               \
+    auto kf = k_bin_scatter_det<RP, CI, V>;                                                       \
+    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    hipLaunchKernelGGL(kf, (unsigned)std::min(cap, nrows - o), DS_BS, lds, st, (const RP*)M.arp,  \
+                       (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
+                       (const V*)M.bval, g, b.k0 + o, aoff, tile_e0, bin_start, ws_col,           \
+                       (V*)ws_val);                                                               \
+  });
+    if (M.f64) { MG_SD(double) } else { MG_SD(float) }
+#undef MG_SD
+  }
   return hipGetLastError();
 }
 

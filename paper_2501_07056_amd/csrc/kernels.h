@@ -171,8 +171,17 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
                             const int64_t* sort_items, const int32_t* item_counts,
                             const uint16_t* ws_col, const void* ws_val, int64_t* bin_nnz,
                             const int64_t* bin_out, void* ccol, int col64, void* cval,
-                            int dense_block, unsigned int* work, int persistent_wgs,
+                            int dense_block, unsigned int* work, int persistent_wgs, bool det,
                             hipStream_t st);
+// deterministic mode (numeric phase of CHUNKED rows): the order-preserving
+// reorder of a batch, one workgroup per row (needs bin_scatter_det_lds
+// bytes); every chunk's run lists its products in the order of Eq. 1.  With
+// det, launch_bin_accum sums each column's products in that order.
+size_t bin_scatter_det_lds(int f64, int tile, int64_t max_nb);
+hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
+                                  const int64_t* aoff, const int64_t* tile_e0,
+                                  const int64_t* bin_start, uint16_t* ws_col, void* ws_val,
+                                  int64_t max_nb, hipStream_t st);
 size_t bin_dense_lds(int f64, int shift);
 // symbolic phase of CHUNKED rows with the row's bitmap in LDS (needs
 // row_bitmap_lds bytes); writes chunk nnz, chunk product counts, chunk row

@@ -206,7 +206,7 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
     HIPCHK(launch_bin_accum(P->g, b, false, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
                             P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
                             P->bin_out, nullptr, 0, nullptr, P->dense_block, wk,
-                            P->persistent_wgs, P->st));
+                            P->persistent_wgs, false, P->st));
     HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false, P->st));
   }
   return MAGNUS_OK;
@@ -225,23 +225,31 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
     {
       // per product: B column and value read, chunk-local column and
       // product written; per A entry: column, value, product offset, B row
-      ProfScope ps(h, P->st, "bin_scatter (numeric reorder)",
-                   (double)b.nip * (P->s_col + P->s_val + 2 + P->s_val) +
-                       (double)b.nent * (P->s_col + P->s_val + 8 + P->s_rp));
-      HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, 0, P->sorted_out, P->tile_row, P->aoff,
-                                 P->tile_e0, P->bin_start, P->bin_cursor, P->ws_col, P->ws_val,
-                                 P->max_nb, P->st));
+      const double bytes = (double)b.nip * (P->s_col + P->s_val + 2 + P->s_val) +
+                           (double)b.nent * (P->s_col + P->s_val + 8 + P->s_rp);
+      if (P->det) {
+        ProfScope ps(h, P->st, "bin_scatter_det (ordered reorder)", bytes);
+        HIPCHK(launch_bin_scatter_det(P->M, P->g, b, P->aoff, P->tile_e0, P->bin_start,
+                                      P->ws_col, P->ws_val, P->max_nb, P->st));
+      } else {
+        ProfScope ps(h, P->st, "bin_scatter (numeric reorder)", bytes);
+        HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, 0, P->sorted_out, P->tile_row, P->aoff,
+                                   P->tile_e0, P->bin_start, P->bin_cursor, P->ws_col, P->ws_val,
+                                   P->max_nb, P->st));
+      }
     }
     unsigned int* wk = P->work_ctr + 4 * bi + 2;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
     {
       // per product: chunk-local column and value read; per output: C write
-      ProfScope ps(h, P->st, "bin_accum (numeric, dense+sort chunks)",
+      ProfScope ps(h, P->st,
+                   P->det ? "bin_accum_det (ordered dense+sort)"
+                          : "bin_accum (numeric, dense+sort chunks)",
                    (double)b.nip * (2 + P->s_val) + (double)b.nnz_out * (P->s_col + P->s_val));
       HIPCHK(launch_bin_accum(P->g, b, true, P->M.f64, P->bin_start, P->bin_cnt, P->bin_row,
                               P->dense_items, P->sort_items, ic, P->ws_col, P->ws_val, P->bin_nnz,
                               P->bin_out, ccol, col64, cval, P->dense_block, wk,
-                              P->persistent_wgs, P->st));
+                              P->persistent_wgs, P->det, P->st));
     }
   }
   return MAGNUS_OK;
@@ -491,7 +499,7 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
         HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
         HIPCHK(launch_bin_accum(g2, b2, false, P->M.f64, cb.start2, cb.cnt2, cb.row2, cb.dense2,
                                 cb.sort2, ic, C.ws2_col, C.ws2_val, cb.nnz2, cb.out2, nullptr, 0,
-                                nullptr, P->dense_block, wk, P->persistent_wgs, P->st));
+                                nullptr, P->dense_block, wk, P->persistent_wgs, false, P->st));
         HIPCHK(launch_bin_rows(g2, 0, cb.nbig, cb.nnz2, C.nnz1, nullptr, nullptr, false,
                                P->st));
       }
@@ -554,7 +562,7 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
       HIPCHK(launch_bin_accum(cb.g2, b2, true, P->M.f64, cb.start2, cb.cnt2, cb.row2, cb.dense2,
                               cb.sort2, C.item_counts + 2 * bi, C.ws2_col, C.ws2_val, cb.nnz2,
                               cb.out2, ccol, col64, cval, P->dense_block, wk, P->persistent_wgs,
-                              P->st));
+                              false, P->st));
     }
   }
   return MAGNUS_OK;
@@ -792,7 +800,10 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   ClassParams cp{};
   cp.sort_max = P->sort_max;
   cp.dense_max = (int64_t)1 << P->shift;
-  cp.force = (o.force_category >= 0 && o.force_category <= 2) ? o.force_category : -1;
+  P->det = o.deterministic != 0;
+  // deterministic mode: every non-empty row takes the CHUNKED path
+  cp.force = P->det ? (int)MAGNUS_CAT_CHUNKED
+                    : ((o.force_category >= 0 && o.force_category <= 2) ? o.force_category : -1);
   {
     // coarse level (the paper's m_CmaxL2 with the LDS for the L2 cache):
     // chunks of 2^cshift columns, the widest whose bitmap (the symbolic
@@ -812,7 +823,7 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
       cs = std::min(cs, sh + lg);
     }
     Co.cshift = cs;
-    Co.coarse_range = (o.coarse_chunks >= 0 && fits(cs)) ? ((int64_t)1 << cs) : 0;
+    Co.coarse_range = (!P->det && o.coarse_chunks >= 0 && fits(cs)) ? ((int64_t)1 << cs) : 0;
     cp.coarse_range = Co.coarse_range;
   }
   P->s_rp = M.rp64 ? 8 : 4;
@@ -840,8 +851,12 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   if (P->nch > 0) {
     // the reorder kernels keep per-chunk counters of a row in LDS: shrink the
     // tile if they and the staged tile do not fit
+    // (the order-preserving reorder of deterministic mode keys a tile's
+    // products by a 12-bit index: tiles of at most 4096)
+    if (P->det && P->tile > 4096) P->tile = 4096;
     auto fits = [&](int tile) {
-      return bin_scatter2_lds(M.f64, tile, P->max_nb, 0, P->sorted_out) <= (size_t)h->lds_max;
+      return bin_scatter2_lds(M.f64, tile, P->max_nb, 0, P->sorted_out) <= (size_t)h->lds_max &&
+             (!P->det || bin_scatter_det_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max);
     };
     while (P->tile > 256 && !fits(P->tile)) P->tile /= 2;
     if (!fits(P->tile)) {

@@ -139,6 +139,7 @@ struct magnus_plan_s {
   unsigned long long* bin_cursor = nullptr;
   unsigned int* work_ctr = nullptr;  // one counter per batch and phase
   bool bitmap_symbolic = false;
+  bool det = false;  // deterministic mode: order-preserving reorder, sums in Eq. 1 order
   int sorted_out = MG_SORTED_OUT;  // CHUNKED reorder writes each tile out in chunk order
   uint16_t* ws_col = nullptr;
   void* ws_val = nullptr;

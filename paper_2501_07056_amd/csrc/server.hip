@@ -491,6 +491,7 @@ magnus_status_t magnus_server_create(int device, const magnus_options_t* opts,
                                      const magnus_server_config_t* cfg, magnus_server_t* out) {
   if (!out) return MAGNUS_ERR_INVALID_ARG;
   *out = nullptr;
+  if (opts && opts->deterministic) return MAGNUS_ERR_INVALID_ARG;  // batch plans do not take it
   magnus_server_config_t c{};
   if (cfg) c = *cfg;
   if (c.memory_budget_bytes < 0 || c.workspace_cap_bytes < 0 || c.max_inflight < 0 ||

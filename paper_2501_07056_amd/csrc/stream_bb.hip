@@ -122,13 +122,13 @@ extern "C" magnus_status_t magnus_stream_chunks(magnus_handle_t h, const uint32_
   // distinct columns per chunk, and the output offsets
   SB(launch_bin_accum(g, b, false, f64, start, cnt, bin_row, dense_items, sort_items,
                       item_counts, ws_col, ws_val, cnz, out, nullptr, 0, nullptr, 256, work,
-                      pwgs, tmp.st));
+                      pwgs, false, tmp.st));
   SB(scan_excl_i64(cnz, out, nb, out + nb, nullptr, stmp, tmp.st));
   SB(hipEventRecord(ev[5], tmp.st));
   // sums into the output
   SB(launch_bin_accum(g, b, true, f64, start, cnt, bin_row, dense_items, sort_items,
                       item_counts, ws_col, ws_val, cnz, out, out_cols, 0, out_vals, 256, work + 1,
-                      pwgs, tmp.st));
+                      pwgs, false, tmp.st));
   SB(hipEventRecord(ev[6], tmp.st));
 #undef SB
   if (e != hipSuccess) r = fail_hip(h, e, "magnus_stream_chunks");

@@ -1,0 +1,87 @@
+"""Deterministic mode (GPU): with the `deterministic` option every value of C
+must equal, bit for bit, the oracle's input-precision sum, which adds the
+products of Eq. 1 in stored order (each entry of A's row in order, each entry
+of the B row in order, from +0.0).  Random values, so any other summation
+order would show up as differing low bits."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+from gpu_util import compare, gpu_product, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def ctx():
+    import paper_2501_07056_amd as mg
+    c = mg.Context(0, deterministic=1)
+    yield c
+    c.close()
+
+
+def test_det_rmat_default(ctx):
+    A, _ = wl.config2(11)
+    log("det rmat11 defaults")
+    rp, col, val, info = gpu_product(ctx, A, A)
+    ref = oracle.spgemm(A, A)
+    compare(rp, col, val, ref, np.float64, exact=True)
+    # every non-empty row went through the CHUNKED path
+    assert info["rows_by_category"][0] == 0 and info["rows_by_category"][1] == 0
+    assert info["coarse_rows"] == 0
+
+
+def test_det_rmat_many_chunks_tiles_batches(ctx):
+    """Rows spanning many chunks and many tiles, several batches, dense and
+    packed-sort chunks mixed."""
+    A, _ = wl.config2(12)
+    log("det rmat12 shift=6 tile=512 dense_min=64")
+    rp, col, val, info = gpu_product(ctx, A, A, chunk_shift=6, tile_products=512,
+                                     bin_dense_min=64, batch_products=200000)
+    assert info["n_batches"] > 1
+    compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=True)
+    # the same bits again
+    rp2, col2, val2, _ = gpu_product(ctx, A, A)
+    assert np.array_equal(rp, rp2) and np.array_equal(col, col2)
+    assert np.array_equal(val.view(np.int64), val2.view(np.int64))
+
+
+@pytest.mark.parametrize("vt", [np.float64, np.float32])
+def test_det_er(ctx, vt):
+    A = wl.erdos_renyi(3000, 5000, 12, wl.seed(80), val_dtype=vt)
+    B = wl.erdos_renyi(5000, 20000, 20, wl.seed(81), val_dtype=vt)
+    log(f"det er vt={vt.__name__}")
+    rp, col, val, info = gpu_product(ctx, A, B, chunk_shift=10)
+    compare(rp, col, val, oracle.spgemm(A, B), vt, exact=True)
+
+
+def test_det_long_runs_dense(ctx):
+    """Few columns, many products each: long runs of equal columns inside
+    every 64-product window of the ordered dense accumulator."""
+    A = wl.erdos_renyi(400, 300, 64, wl.seed(82))
+    B = wl.erdos_renyi(300, 16, 8, wl.seed(83))
+    log("det long runs")
+    rp, col, val, info = gpu_product(ctx, A, B, bin_dense_min=32)
+    compare(rp, col, val, oracle.spgemm(A, B), np.float64, exact=True)
+
+
+def test_det_table_symbolic_and_wide_types(ctx):
+    """Symbolic phase without the row bitmap (small LDS budget), 64-bit row
+    pointers and columns, f32 values."""
+    A = wl.erdos_renyi(2000, 6000, 10, wl.seed(84), val_dtype=np.float32,
+                       rowptr_dtype=np.int64, col_dtype=np.int64)
+    B = wl.erdos_renyi(6000, 9000, 14, wl.seed(85), val_dtype=np.float32,
+                       rowptr_dtype=np.int64, col_dtype=np.int64)
+    log("det table symbolic, int64 indices, f32")
+    rp, col, val, info = gpu_product(ctx, A, B, chunk_shift=8, lds_bytes=16384)
+    compare(rp, col, val, oracle.spgemm(A, B), np.float32, exact=True)
+
+
+def test_det_rejected_by_batch_plans(ctx):
+    import paper_2501_07056_amd as mg
+    A = wl.erdos_renyi(100, 100, 4, wl.seed(86))
+    dA = mg.DeviceCSR.from_host(A)
+    with pytest.raises(Exception):
+        ctx.batch_plan([(dA, dA)])

@@ -2,12 +2,15 @@
 every call include/magnus.h declares, validates arguments before touching a
 device, and its host-only model functions agree with the oracle's."""
 import ctypes
+import os
 
 import pytest
 
 import paper_2501_07056_amd as mg
 from paper_2501_07056_amd import _lib
 from oracle import chunk_model as cm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_exports_every_declared_symbol():
@@ -33,8 +36,28 @@ def test_defaults_are_model_choices():
     mg.load().magnus_options_default(ctypes.byref(o))
     assert o.force_category == -1
     for f in ("sort_max", "chunk_shift", "bin_dense_min", "tile_products", "dense_block",
-              "batch_products", "max_workspace_bytes", "validate", "lds_bytes"):
+              "batch_products", "max_workspace_bytes", "validate", "lds_bytes", "deterministic"):
         assert getattr(o, f) == 0, f
+
+
+def test_options_layout_matches_the_header():
+    """The deterministic field took one of the reserved words: the struct
+    keeps its size, and the field sits where the header puts it."""
+    hdr = open(os.path.join(ROOT, "include", "magnus.h")).read()
+    body = hdr[hdr.index("typedef struct {\n  int32_t force_category;"):]
+    body = body[:body.index("} magnus_options_t;")]
+    assert "int32_t deterministic;" in body and "int32_t _reserved[2];" in body
+    assert ctypes.sizeof(_lib.Options) == 72
+    assert _lib.Options.deterministic.offset == _lib.Options.coarse_chunks.offset + 4
+
+
+def test_deterministic_server_rejected_before_any_device_call():
+    o = _lib.Options()
+    lib = mg.load()
+    lib.magnus_options_default(ctypes.byref(o))
+    o.deterministic = 1
+    out = ctypes.c_void_p()
+    assert lib.magnus_server_create(0, ctypes.byref(o), None, ctypes.byref(out)) == 1
 
 
 def test_null_arguments_rejected_before_any_device_call():
