@@ -162,6 +162,7 @@ KERNEL_SYMBOLS = {
     "bin_accum (numeric, dense+sort chunks)": [("k_accum_dense<", "true>"),
                                                ("k_accum_sort<", "true, false>")],
     "bin_scatter_det (ordered reorder)": [("k_bin_scatter_det<",)],
+    "det_counts (symbolic, segment chunks)": [("k_det_seg_hist<",)],
     "bin_accum_det (ordered dense+sort)": [("k_accum_dense_det<",),
                                            ("k_accum_sort<", "true, true>")],
     "row_bitmap (symbolic, chunked rows)": [("k_row_bitmap<",)],

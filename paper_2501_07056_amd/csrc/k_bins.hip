@@ -522,14 +522,102 @@ __global__ void __launch_bounds__(BIN_BS)
 // ---------------------------------------------------------------------------
 // Order-preserving reorder (deterministic mode): the products of every chunk
 // land in the workspace in the order of Eq. 1, so that an accumulator adding
-// them in workspace order reproduces the plain row-wise sum bit for bit.  One
-// workgroup per CHUNKED row takes the row's tiles in order; each tile is
-// staged in LDS, its (chunk, product index) keys are sorted by a workgroup
-// bitonic network, and every product goes after the products that the
-// row's earlier tiles put into its chunk (a running cursor per chunk).
+// them in workspace order reproduces the plain row-wise sum bit for bit.
+// A row's tiles are grouped into segments of S consecutive tiles.  At plan
+// time a count pass writes, per segment, its products in each chunk of its
+// row into a table laid out [row][chunk][segment]; one exclusive scan of the
+// table then gives every segment the products that the row's earlier
+// segments put into each chunk.  In the numeric phase one workgroup per
+// segment takes the segment's tiles in order: each tile is staged in LDS, its
+// (chunk, product index) keys are sorted by a workgroup bitonic network, and
+// every product goes after those of the earlier tiles (a cursor per chunk).
 // ---------------------------------------------------------------------------
 constexpr int DS_BS = 256;
 constexpr int DS_QBITS = 12;  // tile index bits of a key: tiles of <= 4096 products
+
+// per CHUNKED row: its segments and its table entries (segments x chunks)
+__global__ void k_det_nseg(ChunkGeom g, int S, int64_t* nseg, int64_t* ntab) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.nch) return;
+  const int64_t ns = (g.nt[k] + S - 1) / S;
+  nseg[k] = ns;
+  ntab[k] = ns * g.nb[k];
+}
+
+hipError_t launch_det_nseg(const ChunkGeom& g, int S, int64_t* nseg, int64_t* ntab,
+                           hipStream_t st) {
+  if (g.nch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_det_nseg, (unsigned)((g.nch + 255) / 256), 256, 0, st, g, S, nseg, ntab);
+  return hipGetLastError();
+}
+
+// the segment's place: its row k, index s among the row's segments, tiles
+// [t0, t1) and products [p0, p1) of the row
+struct DetSeg {
+  int64_t k, s, ns, t0, t1, p0, p1;
+};
+MG_INLINE DetSeg det_seg(const ChunkGeom& g, int64_t sg, const int32_t* seg_row,
+                         const int64_t* segBase, int S) {
+  DetSeg d;
+  d.k = seg_row[sg];
+  d.s = sg - segBase[d.k];
+  d.ns = segBase[d.k + 1] - segBase[d.k];
+  d.t0 = d.s * S;
+  d.t1 = (d.t0 + S < g.nt[d.k]) ? (d.t0 + S) : g.nt[d.k];
+  const int64_t ipr = g.ip[g.rows[d.k]];
+  d.p0 = d.t0 * (int64_t)g.tile;
+  d.p1 = (d.t1 * (int64_t)g.tile < ipr) ? (d.t1 * (int64_t)g.tile) : ipr;
+  return d;
+}
+
+size_t det_seg_hist_lds(int64_t max_nb) { return DS_BS * (8 + 8) + (size_t)max_nb * 4 + 64; }
+
+template <typename RP, typename CI>
+__global__ void __launch_bounds__(DS_BS)
+    k_det_seg_hist(const RP* __restrict__ arp, const CI* __restrict__ acol,
+                   const RP* __restrict__ brp, const CI* __restrict__ bcol, ChunkGeom g,
+                   const int64_t* __restrict__ aoff, const int64_t* __restrict__ tile_e0,
+                   const int32_t* __restrict__ seg_row, const int64_t* __restrict__ segBase,
+                   const int64_t* __restrict__ tabBase, int S, int64_t sg0, int64_t* tab) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  int32_t* w_pre = (int32_t*)dsm;
+  int64_t* w_b0 = (int64_t*)(dsm + DS_BS * 8);
+  int32_t* hist = (int32_t*)(w_b0 + DS_BS);
+  const DetSeg d = det_seg(g, sg0 + blockIdx.x, seg_row, segBase, S);
+  const int32_t row = g.rows[d.k];
+  const int64_t nbk = g.nb[d.k];
+  const int sh = g.shift;
+  const uint32_t base_bin = (uint32_t)(g.minc[row] >> sh);
+  for (int64_t q = threadIdx.x; q < nbk; q += DS_BS) hist[q] = 0;
+  __syncthreads();
+  expand_products<DS_BS, RP, CI, float, false>(
+      d.p0, d.p1, tile_e0[g.tileBase[d.k] + d.t0], arp[row + 1], acol, (const float*)nullptr,
+      brp, bcol, (const float*)nullptr, aoff, w_pre, w_b0, (float*)nullptr,
+      [&](int32_t, CI col, float) { atomicAdd(&hist[(uint32_t)(col >> sh) - base_bin], 1); });
+  __syncthreads();
+  const int64_t tb = tabBase[d.k];
+  for (int64_t c = threadIdx.x; c < nbk; c += DS_BS) tab[tb + c * d.ns + d.s] = hist[c];
+}
+
+hipError_t launch_det_seg_hist(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
+                               const int64_t* tile_e0, const int32_t* seg_row,
+                               const int64_t* segBase, const int64_t* tabBase, int S,
+                               int64_t nsegs, int64_t max_nb, int64_t* tab, hipStream_t st) {
+  if (nsegs <= 0) return hipSuccess;
+  const size_t lds = det_seg_hist_lds(max_nb);
+  const int64_t cap = max_grid(DS_BS);
+  for (int64_t o = 0; o < nsegs; o += cap) {
+    MG_DISPATCH2(M, {
+      auto kf = k_det_seg_hist<RP, CI>;
+      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(kf, (unsigned)std::min(cap, nsegs - o), DS_BS, lds, st,
+                         (const RP*)M.arp, (const CI*)M.acol, (const RP*)M.brp,
+                         (const CI*)M.bcol, g, aoff, tile_e0, seg_row, segBase, tabBase, S, o,
+                         tab);
+    });
+  }
+  return hipGetLastError();
+}
 
 size_t bin_scatter_det_lds(int f64, int tile, int64_t max_nb) {
   const size_t vs = f64 ? 8 : 4;
@@ -562,16 +650,19 @@ __global__ void __launch_bounds__(DS_BS)
     k_bin_scatter_det(const RP* __restrict__ arp, const CI* __restrict__ acol,
                       const V* __restrict__ aval, const RP* __restrict__ brp,
                       const CI* __restrict__ bcol, const V* __restrict__ bval, ChunkGeom g,
-                      int64_t k0, const int64_t* __restrict__ aoff,
-                      const int64_t* __restrict__ tile_e0, const int64_t* __restrict__ bin_start,
+                      const int64_t* __restrict__ aoff, const int64_t* __restrict__ tile_e0,
+                      const int32_t* __restrict__ seg_row, const int64_t* __restrict__ segBase,
+                      const int64_t* __restrict__ tabBase, const int64_t* __restrict__ tabS,
+                      int S, int64_t sg0, const int64_t* __restrict__ bin_start,
                       uint16_t* ws_col, V* ws_val) {
   extern __shared__ __align__(16) unsigned char dsm[];
   int32_t* w_pre = (int32_t*)dsm;
   int64_t* w_b0 = (int64_t*)(dsm + DS_BS * 8);
   V* w_av = (V*)(w_b0 + DS_BS);
-  const int64_t k = k0 + blockIdx.x;
+  const DetSeg d = det_seg(g, sg0 + blockIdx.x, seg_row, segBase, S);
+  const int64_t k = d.k;
   const int32_t row = g.rows[k];
-  const int64_t nbk = g.nb[k], ntk = g.nt[k], gb = g.binBase[k], tb = g.tileBase[k];
+  const int64_t nbk = g.nb[k], gb = g.binBase[k], tb = g.tileBase[k], xb = tabBase[k];
   int64_t* cur = (int64_t*)((char*)w_av + DS_BS * 8);  // nbk: next free slot of each chunk
   int32_t* hist = (int32_t*)(cur + nbk);                 // nbk
   int32_t* loff = hist + nbk;                            // nbk
@@ -584,8 +675,10 @@ __global__ void __launch_bounds__(DS_BS)
   const int64_t a1 = arp[row + 1];
   const uint32_t base_bin = (uint32_t)(g.minc[row] >> g.shift);
   const uint32_t lmask = (1u << g.shift) - 1u;
-  for (int64_t q = t; q < nbk; q += DS_BS) cur[q] = bin_start[gb + q];
-  for (int64_t ti = 0; ti < ntk; ++ti) {
+  // the products the row's earlier segments put into each chunk
+  for (int64_t q = t; q < nbk; q += DS_BS)
+    cur[q] = bin_start[gb + q] + (tabS[xb + q * d.ns + d.s] - tabS[xb + q * d.ns]);
+  for (int64_t ti = d.t0; ti < d.t1; ++ti) {
     const int64_t p0 = ti * (int64_t)g.tile;
     const int64_t p1 = (p0 + g.tile < ipr) ? (p0 + g.tile) : ipr;
     for (int64_t q = t; q < nbk; q += DS_BS) hist[q] = 0;
@@ -612,9 +705,9 @@ __global__ void __launch_bounds__(DS_BS)
     for (int32_t p = t; p < nloc; p += DS_BS) {
       const uint32_t key = keys[p];
       const uint32_t q = key & ((1u << DS_QBITS) - 1u), bin = key >> DS_QBITS;
-      const int64_t d = cur[bin] + (p - loff[bin]);
-      st_stream<HINT_WS_STORE>(&ws_col[d], (uint16_t)(u_word[q] & 0xFFFFu));
-      st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
+      const int64_t dd = cur[bin] + (p - loff[bin]);
+      st_stream<HINT_WS_STORE>(&ws_col[dd], (uint16_t)(u_word[q] & 0xFFFFu));
+      st_stream<HINT_WS_STORE>(&ws_val[dd], u_val[q]);
     }
     __syncthreads();
     for (int64_t q = t; q < nbk; q += DS_BS) cur[q] += hist[q];
@@ -1091,24 +1184,49 @@ __global__ void __launch_bounds__(MG_WAVE)
     if ((int64_t)it >= nitems) break;
     const int64_t gb = items[item_base + it];
     const int64_t s0 = bin_start[gb], cnt = bin_cnt[gb];
-    for (int64_t x0 = 0; x0 < cnt; x0 += MG_WAVE) {
-      const bool ok = x0 + l < cnt;
-      const uint32_t c = ok ? (uint32_t)ws_col[s0 + x0 + l] : 0u;
-      const V v = ok ? ws_val[s0 + x0 + l] : (V)0;
-      uint32_t kk[1] = {ok ? ((c << 6) | (uint32_t)l) : 0xFFFFFFFFu};
-      bitonic_sort_keys<1>(kk);
-      const bool mine = kk[0] != 0xFFFFFFFFu;
-      const uint32_t cc = kk[0] >> 6;
-      const V vv = __shfl(v, (int)(kk[0] & 63u), MG_WAVE);
-      const uint32_t pc = __shfl_up(cc, 1, MG_WAVE);
-      const uint64_t hm = __ballot(l == 0 || pc != cc);
-      const int r = l - (63 - __clzll(hm & upto));  // position inside the run
-      const int R = wave_max(mine ? r + 1 : 0);
-      for (int rr = 0; rr < R; ++rr) {
-        if (mine && r == rr) {
-          acc[cc] = acc[cc] + vv;
-          atomicOr(&bits[cc >> 5], 1u << (cc & 31));
+    // DD windows of 64 products are loaded while the previous DD are added
+    constexpr int DD = 4;
+    uint32_t c4[DD];
+    V v4[DD];
+#pragma unroll
+    for (int u = 0; u < DD; ++u) {
+      const int64_t x = (int64_t)u * MG_WAVE + l;
+      c4[u] = x < cnt ? (uint32_t)ws_col[s0 + x] : 0xFFFFFFFFu;
+      v4[u] = x < cnt ? ws_val[s0 + x] : (V)0;
+    }
+    for (int64_t xb = 0; xb < cnt; xb += DD * MG_WAVE) {
+      uint32_t n4[DD];
+      V w4[DD];
+#pragma unroll
+      for (int u = 0; u < DD; ++u) {
+        const int64_t x = xb + (int64_t)(DD + u) * MG_WAVE + l;
+        n4[u] = x < cnt ? (uint32_t)ws_col[s0 + x] : 0xFFFFFFFFu;
+        w4[u] = x < cnt ? ws_val[s0 + x] : (V)0;
+      }
+#pragma unroll
+      for (int u = 0; u < DD; ++u) {
+        if (xb + (int64_t)u * MG_WAVE >= cnt) break;
+        const bool ok = c4[u] != 0xFFFFFFFFu;
+        uint32_t kk[1] = {ok ? ((c4[u] << 6) | (uint32_t)l) : 0xFFFFFFFFu};
+        bitonic_sort_keys<1>(kk);
+        const bool mine = kk[0] != 0xFFFFFFFFu;
+        const uint32_t cc = kk[0] >> 6;
+        const V vv = __shfl(v4[u], (int)(kk[0] & 63u), MG_WAVE);
+        const uint32_t pc = __shfl_up(cc, 1, MG_WAVE);
+        const uint64_t hm = __ballot(l == 0 || pc != cc);
+        const int r = l - (63 - __clzll(hm & upto));  // position inside the run
+        const int R = wave_max(mine ? r + 1 : 0);
+        for (int rr = 0; rr < R; ++rr) {
+          if (mine && r == rr) {
+            acc[cc] = acc[cc] + vv;
+            atomicOr(&bits[cc >> 5], 1u << (cc & 31));
+          }
         }
+      }
+#pragma unroll
+      for (int u = 0; u < DD; ++u) {
+        c4[u] = n4[u];
+        v4[u] = w4[u];
       }
     }
     // write-out in column order: a lane owns words w0..w1
@@ -1148,7 +1266,7 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
                                const int64_t* bin_cnt, const int32_t* bin_row,
                                const uint16_t* ws_col, const V* ws_val, int64_t* bin_nnz,
                                const int64_t* bin_out, void* ccol_, int col64, V* cval,
-                               int64_t* s_bs, int32_t* s_cnt, V* s_v) {
+                               int64_t* s_bs, int32_t* s_cnt, V* s_v, uint32_t* s_k) {
   // numeric keys carry the element index in their low bits, so the network
   // moves one 32-bit word per element and the sum of a run follows the
   // elements' order in the workspace; values are fetched from LDS afterwards
@@ -1206,16 +1324,33 @@ MG_INLINE void accum_sort_item(const ChunkGeom& g, int64_t g0, int nbg, const in
     const int hbase = hinc - hc;
     V carry = (V)0;
     if constexpr (DET) {
-      // lane by lane: a lane's trailing run continues from the value the
-      // previous lane's run reached, so every run sums in element order
-      V c = (V)0;
-      for (int d = 0; d < MG_WAVE; ++d) {
-        if (l == d) carry = c;
-        V r = c;
+      // the lane holding a run's head sums the run from +0.0 in element
+      // order, walking the sorted keys in LDS, and writes it
 #pragma unroll
-        for (int e = 0; e < E; ++e) r = head[e] ? (V)0 + v[e] : r + v[e];
-        c = __shfl(r, d, MG_WAVE);
+      for (int e = 0; e < E; ++e) s_k[l * E + e] = k[e];
+      wave_sync2();
+      const int64_t kk = bin_row[g0];
+      const int64_t colbase = ((g.minc[g.rows[kk]] >> g.shift) + (g0 - g.binBase[kk])) << g.shift;
+      const int64_t obase = bin_out[g0];
+      int hr = hbase;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (!head[e]) continue;
+        const uint32_t key = k[e] >> IDXB;
+        V run = (V)0;
+        int y = l * E + e;
+        do {
+          run = run + s_v[s_k[y] & (CAP - 1)];
+          ++y;
+        } while (y < P && (s_k[y] >> IDXB) == key);
+        const int64_t pos = obase + hr;
+        ++hr;
+        const int64_t col = colbase + (int64_t)key;
+        if (col64) st_stream<HINT_C_STORE>(&((int64_t*)ccol_)[pos], (int64_t)col);
+        else st_stream<HINT_C_STORE>(&((int32_t*)ccol_)[pos], (int32_t)col);
+        st_stream<HINT_C_STORE>(&cval[pos], run);
       }
+      return;
     } else {
       V t = (V)0;
       bool anyh = false;
@@ -1271,6 +1406,7 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
   __shared__ int64_t s_bs[AS_WAVES][MG_WAVE];
   __shared__ int32_t s_cnt[AS_WAVES][MG_WAVE];
   __shared__ V s_v[AS_WAVES][NUMERIC ? SORT_CAP : 1];
+  __shared__ uint32_t s_k[AS_WAVES][DET ? SORT_CAP : 1];
   const int w = threadIdx.x / MG_WAVE;
   const int64_t it = it0 + (int64_t)blockIdx.x * AS_WAVES + w;
   if (it >= item_counts[1]) return;
@@ -1279,19 +1415,19 @@ __global__ void __launch_bounds__(AS_WAVES * MG_WAVE)
   const int64_t P = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1] - bin_start[g0];
   if (P <= 64)
     accum_sort_item<V, 1, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w], s_k[w]);
   else if (P <= 128)
     accum_sort_item<V, 2, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w], s_k[w]);
   else if (P <= 256)
     accum_sort_item<V, 4, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w], s_k[w]);
   else if (P <= 512)
     accum_sort_item<V, 8, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val, bin_nnz,
-                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
+                                   bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w], s_k[w]);
   else
     accum_sort_item<V, 16, NUMERIC, DET>(g, g0, nbg, bin_start, bin_cnt, bin_row, ws_col, ws_val,
-                                    bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w]);
+                                    bin_nnz, bin_out, ccol_, col64, cval, s_bs[w], s_cnt[w], s_v[w], s_k[w]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1513,23 +1649,24 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
   return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
-                                  const int64_t* aoff, const int64_t* tile_e0,
+hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
+                                  const int64_t* tile_e0, const int32_t* seg_row,
+                                  const int64_t* segBase, const int64_t* tabBase,
+                                  const int64_t* tabS, int S, int64_t sg0, int64_t nsegs,
                                   const int64_t* bin_start, uint16_t* ws_col, void* ws_val,
                                   int64_t max_nb, hipStream_t st) {
-  const int64_t nrows = b.k1 - b.k0;
-  if (nrows <= 0) return hipSuccess;
+  if (nsegs <= 0) return hipSuccess;
   const size_t lds = bin_scatter_det_lds(M.f64, g.tile, max_nb);
   const int64_t cap = max_grid(DS_BS);
-  for (int64_t o = 0; o < nrows; o += cap) {
+  for (int64_t o = 0; o < nsegs; o += cap) {
 #define MG_SD(V)                                                                                  \
   MG_DISPATCH2(M, {                                                                               \
     auto kf = k_bin_scatter_det<RP, CI, V>;                                                       \
     hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-    hipLaunchKernelGGL(kf, (unsigned)std::min(cap, nrows - o), DS_BS, lds, st, (const RP*)M.arp,  \
+    hipLaunchKernelGGL(kf, (unsigned)std::min(cap, nsegs - o), DS_BS, lds, st, (const RP*)M.arp,  \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
-                       (const V*)M.bval, g, b.k0 + o, aoff, tile_e0, bin_start, ws_col,           \
-                       (V*)ws_val);                                                               \
+                       (const V*)M.bval, g, aoff, tile_e0, seg_row, segBase, tabBase, tabS, S,    \
+                       sg0 + o, bin_start, ws_col, (V*)ws_val);                                   \
   });
     if (M.f64) { MG_SD(double) } else { MG_SD(float) }
 #undef MG_SD

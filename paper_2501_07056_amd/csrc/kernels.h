@@ -173,13 +173,27 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
                             const int64_t* bin_out, void* ccol, int col64, void* cval,
                             int dense_block, unsigned int* work, int persistent_wgs, bool det,
                             hipStream_t st);
-// deterministic mode (numeric phase of CHUNKED rows): the order-preserving
-// reorder of a batch, one workgroup per row (needs bin_scatter_det_lds
-// bytes); every chunk's run lists its products in the order of Eq. 1.  With
-// det, launch_bin_accum sums each column's products in that order.
+// deterministic mode (CHUNKED rows): the order-preserving reorder.  A row's
+// tiles form segments of S tiles; launch_det_nseg gives each row its segment
+// count and table size (segments x chunks), launch_det_seg_hist fills the
+// table [row][chunk][segment] with each segment's products per chunk (plan
+// time, structure only), and after an exclusive scan of the table
+// launch_bin_scatter_det reorders segments [sg0, sg0 + nsegs) of a batch,
+// one workgroup each (bin_scatter_det_lds bytes): every chunk's run lists
+// its products in the order of Eq. 1.  With det, launch_bin_accum sums each
+// column's products in that order.
+hipError_t launch_det_nseg(const ChunkGeom& g, int S, int64_t* nseg, int64_t* ntab,
+                           hipStream_t st);
+size_t det_seg_hist_lds(int64_t max_nb);
+hipError_t launch_det_seg_hist(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
+                               const int64_t* tile_e0, const int32_t* seg_row,
+                               const int64_t* segBase, const int64_t* tabBase, int S,
+                               int64_t nsegs, int64_t max_nb, int64_t* tab, hipStream_t st);
 size_t bin_scatter_det_lds(int f64, int tile, int64_t max_nb);
-hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const BatchArgs& b,
-                                  const int64_t* aoff, const int64_t* tile_e0,
+hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const int64_t* aoff,
+                                  const int64_t* tile_e0, const int32_t* seg_row,
+                                  const int64_t* segBase, const int64_t* tabBase,
+                                  const int64_t* tabS, int S, int64_t sg0, int64_t nsegs,
                                   const int64_t* bin_start, uint16_t* ws_col, void* ws_val,
                                   int64_t max_nb, hipStream_t st);
 size_t bin_dense_lds(int f64, int shift);

@@ -101,6 +101,58 @@ magnus_status_t geometry_and_batches(magnus_plan_s* P, ChunkGeom& g, int64_t W,
   return MAGNUS_OK;
 }
 
+// Deterministic mode: segments of S tiles per CHUNKED row and, per segment,
+// the products its earlier segments put into each chunk of the row (count
+// table [row][chunk][segment] and its exclusive scan).  S doubles from 16
+// until the table (16 bytes an entry with its scan) stays within a quarter
+// of the workspace cap.
+magnus_status_t det_setup(magnus_plan_s* P, int64_t ntiles, int64_t nbins) {
+  magnus_handle_s* h = P->h;
+  const ChunkGeom& g = P->g;
+  const int64_t nch = P->nch;
+  int64_t cap = h->opts.max_workspace_bytes;
+  if (cap <= 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    cap = (int64_t)(tot / 8);
+  }
+  const int64_t cap_entries = std::max<int64_t>((int64_t)1 << 20, cap / 4 / 16);
+  int S = 16;
+  while ((int64_t)S * P->tile < ((int64_t)1 << 30) && P->max_nb * (ntiles / S + 1) + nbins > cap_entries)
+    S *= 2;
+  P->det_S = S;
+  int64_t* nseg = (int64_t*)palloc(P, sizeof(int64_t) * 2 * (nch + 1));
+  P->det_segBase = (int64_t*)palloc(P, sizeof(int64_t) * (nch + 1));
+  P->det_tabBase = (int64_t*)palloc(P, sizeof(int64_t) * (nch + 1));
+  if (!nseg || !P->det_segBase || !P->det_tabBase) return MAGNUS_ERR_OOM;
+  int64_t* ntab = nseg + nch + 1;
+  HIPCHK(launch_det_nseg(g, S, nseg, ntab, P->st));
+  HIPCHK(scan_excl_i64(nseg, P->det_segBase, nch, P->det_segBase + nch, nullptr, P->temp, P->st));
+  HIPCHK(scan_excl_i64(ntab, P->det_tabBase, nch, P->det_tabBase + nch, nullptr, P->temp, P->st));
+  P->h_det_segBase.assign(nch + 1, 0);
+  int64_t tt = 0;
+  magnus_status_t s = readback(P, {{P->det_segBase, sizeof(int64_t) * (nch + 1)},
+                                   {P->det_tabBase + nch, sizeof(int64_t)}},
+                               {P->h_det_segBase.data(), &tt});
+  if (s != MAGNUS_OK) return s;
+  const int64_t nsegs = P->h_det_segBase[nch];
+  P->det_seg_row = (int32_t*)palloc(P, sizeof(int32_t) * std::max<int64_t>(1, nsegs));
+  int64_t* tab = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, tt));
+  P->det_tabS = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, tt));
+  void* stmp = palloc(P, scan_temp_bytes(std::max<int64_t>(1, tt)));
+  if (!P->det_seg_row || !tab || !P->det_tabS || !stmp) return MAGNUS_ERR_OOM;
+  HIPCHK(launch_tiles(nseg, P->det_segBase, 0, nch, P->det_seg_row, P->st));
+  {
+    // per product: B column; per table entry: one count written
+    ProfScope ps(h, P->st, "det_counts (symbolic, segment chunks)",
+                 (double)P->h_stats.ip_cat[2] * P->s_col + (double)tt * 8);
+    HIPCHK(launch_det_seg_hist(P->M, g, P->aoff, P->tile_e0, P->det_seg_row, P->det_segBase,
+                               P->det_tabBase, S, nsegs, P->max_nb, tab, P->st));
+  }
+  HIPCHK(scan_excl_i64(tab, P->det_tabS, tt, nullptr, nullptr, stmp, P->st));
+  return MAGNUS_OK;
+}
+
 magnus_status_t setup_chunked(magnus_plan_s* P) {
   magnus_handle_s* h = P->h;
   const int64_t nch = P->nch;
@@ -157,6 +209,10 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   P->tile_e0 = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, ntiles));
   if (!P->tile_e0) return MAGNUS_ERR_OOM;
   HIPCHK(launch_tile_e0(P->M, g, P->tile_row, P->aoff, ntiles, P->tile_e0, P->st));
+  if (P->det) {
+    magnus_status_t sd = det_setup(P, ntiles, nbins);
+    if (sd != MAGNUS_OK) return sd;
+  }
   P->info.n_batches = nbat;
   P->info.n_bins = nbins;
   return MAGNUS_OK;
@@ -229,8 +285,11 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
                            (double)b.nent * (P->s_col + P->s_val + 8 + P->s_rp);
       if (P->det) {
         ProfScope ps(h, P->st, "bin_scatter_det (ordered reorder)", bytes);
-        HIPCHK(launch_bin_scatter_det(P->M, P->g, b, P->aoff, P->tile_e0, P->bin_start,
-                                      P->ws_col, P->ws_val, P->max_nb, P->st));
+        const int64_t sg0 = P->h_det_segBase[b.k0];
+        HIPCHK(launch_bin_scatter_det(P->M, P->g, P->aoff, P->tile_e0, P->det_seg_row,
+                                      P->det_segBase, P->det_tabBase, P->det_tabS, P->det_S,
+                                      sg0, P->h_det_segBase[b.k1] - sg0, P->bin_start, P->ws_col,
+                                      P->ws_val, P->max_nb, P->st));
       } else {
         ProfScope ps(h, P->st, "bin_scatter (numeric reorder)", bytes);
         HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, 0, P->sorted_out, P->tile_row, P->aoff,

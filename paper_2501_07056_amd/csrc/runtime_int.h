@@ -140,6 +140,12 @@ struct magnus_plan_s {
   unsigned int* work_ctr = nullptr;  // one counter per batch and phase
   bool bitmap_symbolic = false;
   bool det = false;  // deterministic mode: order-preserving reorder, sums in Eq. 1 order
+  // deterministic mode: segments of det_S tiles, their rows, per-row segment
+  // and table bases, the count table and its exclusive scan
+  int det_S = 16;
+  int32_t* det_seg_row = nullptr;
+  int64_t *det_segBase = nullptr, *det_tabBase = nullptr, *det_tabS = nullptr;
+  std::vector<int64_t> h_det_segBase;
   int sorted_out = MG_SORTED_OUT;  // CHUNKED reorder writes each tile out in chunk order
   uint16_t* ws_col = nullptr;
   void* ws_val = nullptr;
