@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads as wl
+from workloads import CSR
 
 from gpu_util import compare, gpu_product, log
 
@@ -77,6 +78,42 @@ def test_det_table_symbolic_and_wide_types(ctx):
     log("det table symbolic, int64 indices, f32")
     rp, col, val, info = gpu_product(ctx, A, B, chunk_shift=8, lds_bytes=16384)
     compare(rp, col, val, oracle.spgemm(A, B), np.float32, exact=True)
+
+
+def test_det_edge_cases(ctx):
+    """Empty product, 1x1, cancellation to +0.0, -0.0 products, and empty
+    rows of A and of B in a 50000-column product of 256-column chunks."""
+    log("det edge cases")
+    E = CSR(0, 5, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    B = wl.erdos_renyi(5, 7, 2, wl.seed(85))
+    rp, col, val, info = gpu_product(ctx, E, B)
+    assert len(rp) == 1 and rp[0] == 0 and len(col) == 0
+    one = CSR(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([3.0]))
+    rp, col, val, info = gpu_product(ctx, one, one)
+    assert list(rp) == [0, 1] and list(col) == [0] and list(val) == [9.0]
+    A = CSR(2, 2, np.array([0, 2, 3]), np.array([0, 1, 0], np.int32), np.array([1.0, 1.0, 1.0]))
+    Bm = CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([2.0, -2.0]))
+    rp, col, val, info = gpu_product(ctx, A, Bm)
+    assert list(col) == [0, 0] and val[0] == 0.0 and not np.signbit(val[0]) and val[1] == 2.0
+    Bz = CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([-0.0, -0.0]))
+    rp, col, val, info = gpu_product(ctx, A, Bz)
+    assert not np.signbit(val).any()
+    A = wl.erdos_renyi(400, 300, 5, wl.seed(86))
+    rpA = A.rowptr.astype(np.int64).copy()
+    keep = np.ones(A.nnz, bool)
+    for i in range(0, 400, 7):
+        keep[rpA[i]:rpA[i + 1]] = False
+    cnt = np.array([keep[rpA[i]:rpA[i + 1]].sum() for i in range(400)])
+    A2 = CSR(400, 300, np.concatenate([[0], np.cumsum(cnt)]), A.col[keep], A.val[keep])
+    Bs = wl.erdos_renyi(300, 50000, 7, wl.seed(87))
+    rpB = Bs.rowptr.astype(np.int64)
+    keepB = np.ones(Bs.nnz, bool)
+    for j in range(0, 300, 5):
+        keepB[rpB[j]:rpB[j + 1]] = False
+    cntB = np.array([keepB[rpB[j]:rpB[j + 1]].sum() for j in range(300)])
+    B2 = CSR(300, 50000, np.concatenate([[0], np.cumsum(cntB)]), Bs.col[keepB], Bs.val[keepB])
+    rp, col, val, info = gpu_product(ctx, A2, B2, chunk_shift=8)
+    compare(rp, col, val, oracle.spgemm(A2, B2), np.float64, exact=True)
 
 
 def test_det_rejected_by_batch_plans(ctx):
