@@ -39,13 +39,17 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
   __shared__ const V* s_bvalp[SR_WAVES][NUMERIC ? MG_WAVE : 1];
   __shared__ V s_av[SR_WAVES][MG_WAVE];
   __shared__ int32_t s_wslot[SR_WAVES][MG_WAVE];
-  __shared__ int64_t s_ent[SR_WAVES][MG_WAVE + 1];
-  __shared__ int64_t s_apos[SR_WAVES][MG_WAVE];
-  __shared__ int64_t s_minc[SR_WAVES][MG_WAVE];
-  __shared__ int32_t s_row[SR_WAVES][MG_WAVE];
-  __shared__ int32_t s_mat[SR_WAVES][MG_WAVE];
-  __shared__ int64_t s_cb[SR_WAVES][NUMERIC ? MG_WAVE : 1];
-  __shared__ int32_t s_aux[SR_WAVES][MG_WAVE];
+  // per-row slots: a wave takes R = 64 / 2^c rows of the classes with one
+  // element per lane and a single row beyond, so only E = 1 needs 64 slots
+  // (the LDS saved raises the occupancy of the larger classes)
+  constexpr int RS = (E == 1) ? MG_WAVE : 1;
+  __shared__ int64_t s_ent[SR_WAVES][RS];
+  __shared__ int64_t s_apos[SR_WAVES][RS];
+  __shared__ int64_t s_minc[SR_WAVES][RS];
+  __shared__ int32_t s_row[SR_WAVES][RS];
+  __shared__ int32_t s_mat[SR_WAVES][RS];
+  __shared__ int64_t s_cb[SR_WAVES][NUMERIC ? RS : 1];
+  __shared__ int32_t s_aux[SR_WAVES][RS];
 
   const int w = threadIdx.x / MG_WAVE;
   const int l = lane();
@@ -53,6 +57,10 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
   const int64_t r0 = tile * R;
   if (r0 >= count) return;  // whole wave leaves together
   const int nr = (int)((count - r0) < R ? (count - r0) : R);
+  if (nr > RS) {  // more rows per wave than the slots hold: not a launch this file makes
+    if (l == 0) atomicOr(&stats->err, ERR_STAGE_OVERFLOW);
+    return;
+  }
 
   int64_t ne = 0;
   if (l < nr) {
@@ -70,10 +78,11 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
     if (NUMERIC) s_cb[w][l] = src.tab ? crp[M.row0] : 0;
   }
   const int64_t einc = wave_incl_scan(ne);
-  s_ent[w][l] = einc - ne;
   const int64_t ntot = __shfl(einc, MG_WAVE - 1, MG_WAVE);
-  if (l == 0) s_ent[w][MG_WAVE] = ntot;
-  s_aux[w][l] = 0;
+  if (l < RS) {
+    s_ent[w][l] = einc - ne;
+    s_aux[w][l] = 0;
+  }
   wave_sync();
 
   const K kmask = ((K)1 << colbits) - 1;
@@ -304,7 +313,7 @@ hipError_t sort_rows_cls(const RowSrc& src, int cls, bool numeric, const int32_t
   // class c holds rows with ip in (2^(c-1), 2^c]: E = max(1, 2^c / 64) per
   // lane, R = 64 * E / 2^c rows per wave
   const int E = (cls <= 6) ? 1 : (1 << (cls - 6));
-  const int R = (cls <= 6) ? (64 >> cls) : 1;
+  const int R = (cls <= 6) ? (64 >> cls) : 1;  // R > 1 only with E = 1 (the kernel's slots)
   int slotbits = 0;
   while ((1 << slotbits) < R) ++slotbits;
   int capbits = 0;
