@@ -124,7 +124,8 @@ typedef struct {
                            * order, from +0.0, products rounded to the value type), the same
                            * bits on every run.  All non-empty rows go through the CHUNKED
                            * path without the coarse level (so a row may span at most 65535
-                           * chunks); force_category and coarse_chunks are ignored.  Single
+                           * chunks), with chunks a quarter of the usual length unless
+                           * chunk_shift is set; force_category and coarse_chunks are ignored.  Single
                            * products only: batch plans and the server reject it. */
   int32_t _reserved[2];
 } magnus_options_t;

@@ -528,12 +528,11 @@ __global__ void __launch_bounds__(BIN_BS)
 // row into a table laid out [row][chunk][segment]; one exclusive scan of the
 // table then gives every segment the products that the row's earlier
 // segments put into each chunk.  In the numeric phase one workgroup per
-// segment takes the segment's tiles in order: each tile is staged in LDS, its
-// (chunk, product index) keys are sorted by a workgroup bitonic network, and
-// every product goes after those of the earlier tiles (a cursor per chunk).
+// segment takes the segment's tiles in order: each tile is staged in LDS and
+// one wave walks it in product order, giving every product the next slot of
+// its chunk (a cursor per chunk, started from the scanned table).
 // ---------------------------------------------------------------------------
 constexpr int DS_BS = 256;
-constexpr int DS_QBITS = 12;  // tile index bits of a key: tiles of <= 4096 products
 
 // per CHUNKED row: its segments and its table entries (segments x chunks)
 __global__ void k_det_nseg(ChunkGeom g, int S, int64_t* nseg, int64_t* ntab) {
@@ -621,28 +620,7 @@ hipError_t launch_det_seg_hist(const Mats& M, const ChunkGeom& g, const int64_t*
 
 size_t bin_scatter_det_lds(int f64, int tile, int64_t max_nb) {
   const size_t vs = f64 ? 8 : 4;
-  return DS_BS * (8 + 8 + 8) + (size_t)max_nb * (8 + 4 + 4) + 64 + (size_t)tile * (4 + 4 + vs) + 64;
-}
-
-// Ascending bitonic sort of n (a power of two) keys in LDS by a workgroup of
-// BS threads; starts after and ends with a barrier.
-template <int BS>
-MG_INLINE void block_bitonic_sort(uint32_t* keys, int n) {
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n; i += BS) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint32_t a = keys[i], b = keys[ixj];
-          if ((a > b) == ((i & k) == 0)) {
-            keys[i] = b;
-            keys[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  return DS_BS * (8 + 8 + 8) + (size_t)max_nb * 8 + 64 + (size_t)tile * (4 + vs + 8) + 64;
 }
 
 template <typename RP, typename CI, typename V>
@@ -664,53 +642,63 @@ __global__ void __launch_bounds__(DS_BS)
   const int32_t row = g.rows[k];
   const int64_t nbk = g.nb[k], gb = g.binBase[k], tb = g.tileBase[k], xb = tabBase[k];
   int64_t* cur = (int64_t*)((char*)w_av + DS_BS * 8);  // nbk: next free slot of each chunk
-  int32_t* hist = (int32_t*)(cur + nbk);                 // nbk
-  int32_t* loff = hist + nbk;                            // nbk
-  uint32_t* keys = (uint32_t*)(((uintptr_t)(loff + nbk) + 15) & ~(uintptr_t)15);
-  uint32_t* u_word = keys + g.tile;
+  uint32_t* u_word = (uint32_t*)(((uintptr_t)(cur + nbk) + 15) & ~(uintptr_t)15);
   V* u_val = (V*)(((uintptr_t)(u_word + g.tile) + 15) & ~(uintptr_t)15);
-  __shared__ int32_t s_tmp[DS_BS / MG_WAVE];
-  const int t = threadIdx.x;
+  int64_t* dst = (int64_t*)(u_val + g.tile);
+  const int t = threadIdx.x, l = lane();
   const int64_t ipr = g.ip[row];
   const int64_t a1 = arp[row + 1];
   const uint32_t base_bin = (uint32_t)(g.minc[row] >> g.shift);
   const uint32_t lmask = (1u << g.shift) - 1u;
+  // bits of a chunk index of this row
+  const int nbits = (nbk > 1) ? 32 - __clz((unsigned)(nbk - 1)) : 0;
+  const uint64_t below = (1ull << l) - 1ull;
   // the products the row's earlier segments put into each chunk
   for (int64_t q = t; q < nbk; q += DS_BS)
     cur[q] = bin_start[gb + q] + (tabS[xb + q * d.ns + d.s] - tabS[xb + q * d.ns]);
   for (int64_t ti = d.t0; ti < d.t1; ++ti) {
     const int64_t p0 = ti * (int64_t)g.tile;
     const int64_t p1 = (p0 + g.tile < ipr) ? (p0 + g.tile) : ipr;
-    for (int64_t q = t; q < nbk; q += DS_BS) hist[q] = 0;
-    __syncthreads();
+    __syncthreads();  // the previous tile's copy-out has read u_word, u_val and dst
     expand_products<DS_BS, RP, CI, V, true>(
         p0, p1, tile_e0[tb + ti], a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
         [&](int32_t q, CI col, V pv) {
           const uint32_t bin = (uint32_t)(col >> g.shift) - base_bin;
           u_word[q] = (bin << 16) | ((uint32_t)col & lmask);
           u_val[q] = pv;
-          atomicAdd(&hist[bin], 1);
         });
     __syncthreads();
-    block_excl_scan<DS_BS>(hist, loff, nbk, s_tmp);
     const int32_t nloc = (int32_t)(p1 - p0);
-    int32_t n2 = 1;
-    while (n2 < nloc) n2 <<= 1;
-    for (int32_t q = t; q < n2; q += DS_BS)
-      keys[q] = (q < nloc) ? (((u_word[q] >> 16) << DS_QBITS) | (uint32_t)q) : 0xFFFFFFFFu;
+    if (t < MG_WAVE) {
+      // one wave walks the tile in product order, 64 products at a time: a
+      // product's slot is its chunk's cursor plus the number of earlier
+      // products of the window in the same chunk (lanes matched bit by bit
+      // of the chunk index); the lowest lane of each chunk advances the cursor
+      for (int32_t w0 = 0; w0 < nloc; w0 += MG_WAVE) {
+        const int32_t q = w0 + l;
+        const bool ok = q < nloc;
+        const uint32_t bin = ok ? (u_word[q] >> 16) : 0u;
+        uint64_t m = __ballot(ok);
+        for (int b = 0; b < nbits; ++b) {
+          const bool bit = (bin >> b) & 1u;
+          const uint64_t bb = __ballot(bit);
+          m &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(m & below);
+        int64_t base = 0;
+        if (ok) {
+          base = cur[bin];
+          dst[q] = base + rank;
+        }
+        if (ok && rank == 0) cur[bin] = base + __popcll(m);
+      }
+    }
     __syncthreads();
-    block_bitonic_sort<DS_BS>(keys, n2);
-    // sorted position p holds the product of rank p - loff[bin] among its
-    // chunk's products in this tile, in product order
-    for (int32_t p = t; p < nloc; p += DS_BS) {
-      const uint32_t key = keys[p];
-      const uint32_t q = key & ((1u << DS_QBITS) - 1u), bin = key >> DS_QBITS;
-      const int64_t dd = cur[bin] + (p - loff[bin]);
+    for (int32_t q = t; q < nloc; q += DS_BS) {
+      const int64_t dd = dst[q];
       st_stream<HINT_WS_STORE>(&ws_col[dd], (uint16_t)(u_word[q] & 0xFFFFu));
       st_stream<HINT_WS_STORE>(&ws_val[dd], u_val[q]);
     }
-    __syncthreads();
-    for (int64_t q = t; q < nbk; q += DS_BS) cur[q] += hist[q];
   }
 }
 

@@ -804,7 +804,11 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   const magnus_options_t& o = h->opts;
   const int lds = o.lds_bytes > 0 ? std::min(o.lds_bytes, h->lds_max) : h->lds_max;
   P->lds_budget = lds;
-  P->shift = o.chunk_shift > 0 ? std::min(o.chunk_shift, 16) : default_shift(M.f64, lds);
+  // deterministic mode defaults to chunks a quarter as long: its dense
+  // accumulator is one wave per accumulator, and smaller chunks move most
+  // products to the packed sorts, which keep more of the device busy
+  P->shift = o.chunk_shift > 0 ? std::min(o.chunk_shift, 16)
+                               : default_shift(M.f64, lds) - (o.deterministic ? 2 : 0);
   P->sort_max = o.sort_max > 0 ? std::min<int64_t>(o.sort_max, SORT_CAP + 1) : SORT_CAP + 1;
   P->group_max = o.sort_group_max > 0 ? std::min<int64_t>(o.sort_group_max, SORT_CAP) : SORT_CAP;
   P->dense_min = o.bin_dense_min > 0 ? o.bin_dense_min : P->group_max;
@@ -910,9 +914,6 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   if (P->nch > 0) {
     // the reorder kernels keep per-chunk counters of a row in LDS: shrink the
     // tile if they and the staged tile do not fit
-    // (the order-preserving reorder of deterministic mode keys a tile's
-    // products by a 12-bit index: tiles of at most 4096)
-    if (P->det && P->tile > 4096) P->tile = 4096;
     auto fits = [&](int tile) {
       return bin_scatter2_lds(M.f64, tile, P->max_nb, 0, P->sorted_out) <= (size_t)h->lds_max &&
              (!P->det || bin_scatter_det_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max);
