@@ -664,7 +664,7 @@ def main():
                          "Section 4.3) | batch | serve | micro (building blocks, Section 4.1)")
     ap.add_argument("--mer-d", type=int, default=1024,
                     help="entries per row of A and of B for --workload mer<log m_C>")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--option", action="append", default=[],
                     help="library option name=value (repeatable)")
