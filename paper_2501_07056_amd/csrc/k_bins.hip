@@ -186,8 +186,8 @@ __global__ void k_tile_e0(const RP* __restrict__ arp, ChunkGeom g, const int32_t
 // product offsets relative to p0, B row starts, A values); threads take
 // products striped by BS, so the B loads of a wave are contiguous.  The
 // window's products are taken in super-chunks of 16*BS: first the A entry
-// holding the first product of every group of 64 products is recorded
-// (each entry marks the group starts inside its own product range), then a
+// holding the first product of every group of 64 products is recorded (one
+// binary search over the window per group), then a
 // product's entry is found by a binary search between the entries of its
 // group's start and the next group's start (0 steps inside long B rows, a
 // few for short ones).  Four products per thread are gathered before any is
@@ -230,13 +230,12 @@ MG_INLINE void expand_products(int64_t p0, int64_t p1, int64_t e0, int64_t a1,
     for (int32_t s0 = wstart; s0 < wend; s0 += SC) {
       const int32_t s1 = (wend - s0 < SC) ? wend : s0 + SC;
       // the entry holding each group start s0 + 64 G (entries partition the
-      // products; empty entries hold none)
-      if (t < nvalid) {
-        int32_t lo = w_pre[t] > s0 ? w_pre[t] : s0;
-        int32_t hi = (t + 1 < nvalid) ? w_pre[t + 1] : wend;
-        hi = hi < s1 ? hi : s1;
-        for (int32_t G = (lo - s0 + MG_WAVE - 1) / MG_WAVE; s0 + G * MG_WAVE < hi; ++G)
-          s_grp[G] = t;
+      // products; empty entries hold none): one search per group, so a long
+      // entry does not mark its groups one by one while the others wait
+      {
+        const int32_t ng = (s1 - s0 + MG_WAVE - 1) / MG_WAVE;
+        for (int32_t G = t; G < ng; G += BS)
+          s_grp[G] = upper_index(w_pre, 0, nvalid, s0 + G * MG_WAVE);
       }
       if (t == 0) s_grp[NG] = nvalid - 1;
       __syncthreads();
