@@ -113,7 +113,8 @@ typedef struct {
   int64_t max_workspace_bytes; /* cap on the plan's device memory (0: 40% of free memory) */
   int32_t validate;       /* 1: check CSR invariants of A and B (one extra pass) */
   int32_t lds_bytes;      /* LDS budget per workgroup (0: device maximum) */
-  int32_t sort_group_max; /* products per packed sort group of small chunks (<= 1024) */
+  int32_t sort_group_max; /* products per packed sort group of small chunks (<= 1024; 0: 512);
+                           * a chunk below bin_dense_min but above this is sorted alone */
   int32_t stream_hints;   /* non-temporal accesses: 1 workspace stores, 2 workspace loads, 4 C stores */
   int32_t coarse_chunks;  /* chunks per coarse chunk (power of two, Section 3.3): CHUNKED rows
                            * wider than one coarse chunk are reordered into coarse chunks first.
