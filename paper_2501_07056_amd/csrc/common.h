@@ -24,15 +24,6 @@ MG_INLINE int64_t ld64(const T* p, int64_t i) { return (int64_t)p[i]; }
 
 MG_INLINE int lane() { return (int)__lane_id(); }
 
-// Tile order of the reorder: workgroup b takes tile (b mod X) * n/X + b / X
-// (a bijection of [0, n)), so that the tiles in flight at once come from X
-// regions of the batch, and their workspace writes from X distant places.
-MG_INLINE int64_t tile_spread(int64_t b, int64_t n, int64_t X) {
-  if (X <= 1) return b;
-  const int64_t q = n / X, r = n % X, x = b % X;
-  return x * q + (x < r ? x : r) + b / X;
-}
-
 // Streaming accesses for data touched once (the reordered intermediate
 // product and C): non-temporal, so they do not evict B's rows and the
 // accumulators' neighbours from L2 and the memory-side cache.  This is the

@@ -130,7 +130,7 @@ template <typename RP>
 MG_INLINE void tile_setup(const ChunkGeom& g, const BatchArgs& b, const int32_t* tile_row,
                           const RP* arp, const int64_t* aoff, TileCtx& c,
                           const int64_t* tile_e0 = nullptr) {
-  const int64_t tg = b.tile0 + tile_spread(blockIdx.x, gridDim.x, b.spread);
+  const int64_t tg = b.tile0 + blockIdx.x;
   c.k = tile_row[tg];
   c.ti = tg - g.tileBase[c.k];
   c.row = g.rows[c.k];

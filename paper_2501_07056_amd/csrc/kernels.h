@@ -159,7 +159,6 @@ struct BatchArgs {
   int64_t bin0, nbins;     // global bin range
   int64_t ip0, nip;        // global product range (batch workspace offset = ip - ip0)
   int64_t nent, nnz_out;   // A entries of the batch's rows; nnz of C they produce
-  int64_t spread;          // tile order of the reorder (tile_spread; <= 1: in order)
 };
 // per-chunk product totals of a batch (bin_cnt zeroed before), and each
 // chunk's row

@@ -93,11 +93,6 @@ magnus_status_t geometry_and_batches(magnus_plan_s* P, ChunkGeom& g, int64_t W,
       ba.ntiles = tots[1] - ba.tile0;
       ba.nbins = tots[2] - ba.bin0;
     }
-    // rows of few tiles: the tiles in flight are spread over the batch (their
-    // workspace writes then come from many distant places); rows of many
-    // tiles keep the order, so that a row's tiles fill its chunks together
-    ba.spread = (ba.ntiles < MG_SPREAD_ROW_TILES * std::max<int64_t>(1, ba.k1 - ba.k0))
-                    ? MG_TILE_SPREAD : 1;
     ws_products = std::max(ws_products, ba.nip);
     max_tiles = std::max(max_tiles, ba.ntiles);
     batches.push_back(ba);

@@ -34,16 +34,6 @@
 // average) are counted with a bitmap in the symbolic phase (measured on
 // uniform rows: the bitmap is faster at 1/128, the count-mode accumulators
 // at 1/1024)
-// tile order of the reorder: batches whose rows average fewer than
-// MG_SPREAD_ROW_TILES tiles take their tiles from MG_TILE_SPREAD regions at
-// once (config 2, 53 tiles a row: reorder 156 -> 130 ms on average over
-// workspace placements; massive uniform at 2^20, 512 a row, is slower so)
-#ifndef MG_TILE_SPREAD
-#define MG_TILE_SPREAD 512
-#endif
-#ifndef MG_SPREAD_ROW_TILES
-#define MG_SPREAD_ROW_TILES 128
-#endif
 #ifndef MG_BITMAP_DENSITY
 #define MG_BITMAP_DENSITY 512
 #endif
