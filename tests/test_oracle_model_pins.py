@@ -116,7 +116,8 @@ def test_golden_numbers_match_model():
     assert L * 5 < 2 * MiB < 2 * L * 5
     assert cm.pow2_nearest((2 * MiB) ** 2 / (4 * 5 * 136)) == \
         g["fine_level_breaking_point_stream_length"]["value"]
-    assert cm.paper_fine_nchunks(1 << 29, 5, 136) == g["optimal_fine_chunks_at_2e29"]["value"]
+    # derived (not printed): Eq. 3 at stream length 2^29, see the golden file
+    assert cm.paper_fine_nchunks(1 << 29, 5, 136) == g["_derived"]["optimal_fine_chunks_at_2e29"]["value"]
     cx = g["coarse_crossover_mC"]
     assert cm.paper_mcmax(1 * MiB, 1, 136) == cx["SKX"]
     assert cm.paper_mcmax(2 * MiB, 1, 136) == cx["SPR"] == cx["EMR"]

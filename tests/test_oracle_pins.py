@@ -354,3 +354,145 @@ def test_config3_ip_closed_form_small():
     A, B = wl.config3(logn=12)
     ipr = oracle.ip(A, B)
     assert (ipr == 256).all() and ipr.sum() == 256 << 12
+
+
+# ---------------------------------------------------------------- val: order and precision
+def _col0_chain(vt, bvals, avals=None):
+    """A is 1 x k with its entries in stored order on columns 0..k-1; B row j
+    holds one entry on column 0 with value bvals[j]: C[0, 0] sums the k
+    products a_j * b_j in A's stored order (Algorithm 1's update order)."""
+    k = len(bvals)
+    avals = [1.0] * k if avals is None else avals
+    A = CSR(1, k, np.array([0, k], dtype=np.int64), np.arange(k, dtype=np.int32),
+            np.array(avals, dtype=vt))
+    B = CSR(k, 1, np.arange(k + 1, dtype=np.int64), np.zeros(k, dtype=np.int32),
+            np.array(bvals, dtype=vt))
+    return oracle.spgemm(A, B)
+
+
+def test_val_f64_stored_order_closed_form():
+    # products [2^53, 1, -2^53]: (+0 + 2^53) + 1 is a tie between 2^53 and
+    # 2^53 + 2 and rounds to even (2^53); minus 2^53 gives 0.  The exact sum
+    # (the long double reference) is 1.
+    big = 2.0 ** 53
+    r = _col0_chain(np.float64, [big, 1.0, -big])
+    assert r.val[0] == 0.0 and r.ref[0] == 1.0
+    # the reverse storage order: -2^53 + 1 = -(2^53 - 1) is exact, then + 2^53
+    r2 = _col0_chain(np.float64, [-big, 1.0, big])
+    assert r2.val[0] == 1.0 and r2.ref[0] == 1.0
+    # a sum taken in sorted-by-magnitude or any other order would differ from
+    # one of the two; the stored order is what decides
+
+
+def test_val_f32_stored_order_and_input_precision():
+    # f32: 2^24 + 1 rounds to 2^24 in single precision, so the stored-order
+    # single-precision sum of [2^24, 1, -2^24] is 0; a sum carried in double
+    # (then rounded to f32) would give 1, as the double reference does
+    big = 2.0 ** 24
+    r = _col0_chain(np.float32, [big, 1.0, -big])
+    assert r.val[0] == 0.0
+    assert r.ref[0] == 1.0
+    r2 = _col0_chain(np.float32, [-big, 1.0, big])
+    assert r2.val[0] == 1.0
+
+
+def test_val_products_rounded_before_the_add():
+    # f32 products are rounded to single precision before they are added (no
+    # fused multiply-add): a = 1 + 2^-12, b = 1 + 2^-12 gives a*b = 1 + 2^-11
+    # + 2^-24, which rounds (tie, to even) to 1 + 2^-11 in f32; adding -1
+    # then leaves exactly 2^-11.  A fused or double-precision product would
+    # keep the 2^-24 term.
+    a = 1.0 + 2.0 ** -12
+    r = _col0_chain(np.float32, [a, -1.0], avals=[a, 1.0])
+    assert r.val[0] == np.float32(2.0 ** -11)
+    assert r.ref[0] == 2.0 ** -11 + 2.0 ** -24
+
+
+def test_val_starts_from_positive_zero():
+    # every slot starts at +0.0 (Algorithm 1): a single product -0.0 gives
+    # +0.0 + -0.0 = +0.0, and two -0.0 products give +0.0 as well
+    for vt in (np.float64, np.float32):
+        r = _col0_chain(vt, [-0.0])
+        assert r.val[0] == 0.0 and not np.signbit(r.val[0])
+        r = _col0_chain(vt, [-0.0, -0.0])
+        assert not np.signbit(r.val[0])
+
+
+@pytest.mark.parametrize("vt", [np.float64, np.float32])
+def test_val_random_matches_stored_order_loop(vt):
+    # a plain loop in numpy scalars of the value type: products rounded to
+    # the type, added in A-then-B stored order from +0.0
+    A = _rand_csr(wl.seed(78), 30, 25, 7, vt)
+    B = _rand_csr(wl.seed(79), 25, 35, 7, vt)
+    r = oracle.spgemm(A, B)
+    arp, brp = A.rowptr.astype(np.int64), B.rowptr.astype(np.int64)
+    T = np.dtype(vt).type
+    for i in range(A.nrows):
+        acc = {}
+        for p in range(arp[i], arp[i + 1]):
+            j = int(A.col[p])
+            for q in range(brp[j], brp[j + 1]):
+                k = int(B.col[q])
+                prod = T(A.val[p]) * T(B.val[q])
+                acc[k] = T(acc.get(k, T(0.0)) + prod)
+        cols = sorted(acc)
+        got = r.val[r.rowptr[i]:r.rowptr[i + 1]]
+        want = np.array([acc[k] for k in cols], dtype=vt).astype(np.float64)
+        assert np.array_equal(got.view(np.int64), want.view(np.int64))
+
+
+# ---------------------------------------------------------------- ideal volume, hand count
+def _counted_gustavson_bytes(A, B, w):
+    """Bytes a two-phase Gustavson product reads and writes when every array
+    access is tallied at its own width w[name]: the symbolic phase reads A's
+    row pointers, A's columns, both row pointers of every referenced B row
+    and B's columns; the numeric phase reads all of those again plus A's and
+    B's values, and writes C (Section 4.3: B rows are not reused)."""
+    rd = 0
+    arp, brp = A.rowptr.astype(np.int64), B.rowptr.astype(np.int64)
+    nnz_c = 0
+    for phase in ("symbolic", "numeric"):
+        rd += (A.nrows + 1) * w["rp_a"]          # A.rowPtr, one pass per phase
+        for i in range(A.nrows):
+            seen = set()
+            for p in range(arp[i], arp[i + 1]):
+                rd += w["col_a"]                  # A.col[p]
+                if phase == "numeric":
+                    rd += w["val"]                # A.val[p]
+                j = int(A.col[p])
+                rd += 2 * w["rp_b"]               # B.rowPtr[j], B.rowPtr[j + 1]
+                for q in range(brp[j], brp[j + 1]):
+                    rd += w["col_b"]              # B.col[q]
+                    if phase == "numeric":
+                        rd += w["val"]            # B.val[q]
+                    seen.add(int(B.col[q]))
+            if phase == "numeric":
+                nnz_c += len(seen)
+    wr = (A.nrows + 1) * w["rp_c"] + nnz_c * (w["col_c"] + w["val"])
+    return rd, wr, nnz_c
+
+
+def test_ideal_volume_matches_hand_count():
+    # widths that differ for every array, so a dropped term, a term with the
+    # wrong width or a wrong factor changes the total
+    w = dict(rp_a=2, rp_b=3, col_a=5, col_b=7, val=11, rp_c=13, col_c=17)
+    D1 = np.array([[1, 0, 2], [0, 0, 0], [3, 4, 5]], dtype=np.float64)
+    D2 = np.array([[0, 6, 0], [7, 0, 8], [9, 1, 0]], dtype=np.float64)
+    A, B = csr_from_dense(D1), csr_from_dense(D2)
+    rd, wr, nnz_c = _counted_gustavson_bytes(A, B, w)
+    ipv = int(oracle.ip(A, B).sum())
+    assert ipv == (1 + 2) + (1 + 2 + 2)  # row 0: B rows 0, 2; row 2: B rows 0, 1, 2
+    assert nnz_c == oracle.spgemm(A, B).nnz == 5
+    r, wv = oracle.ideal_volume(A.nrows, A.nnz, ipv, A.nrows, nnz_c, s_rp_a=w["rp_a"],
+                                s_rp_b=w["rp_b"], s_col_a=w["col_a"], s_col_b=w["col_b"],
+                                s_val=w["val"], s_rp_c=w["rp_c"], s_col_c=w["col_c"])
+    assert (r, wv) == (rd, wr)
+    # the same on a random rectangular case
+    A = _rand_csr(wl.seed(80), 17, 13, 4, np.float64)
+    B = _rand_csr(wl.seed(81), 13, 19, 5, np.float64)
+    rd, wr, nnz_c = _counted_gustavson_bytes(A, B, w)
+    r, wv = oracle.ideal_volume(A.nrows, A.nnz, int(oracle.ip(A, B).sum()), A.nrows, nnz_c,
+                                s_rp_a=w["rp_a"], s_rp_b=w["rp_b"], s_col_a=w["col_a"],
+                                s_col_b=w["col_b"], s_val=w["val"], s_rp_c=w["rp_c"],
+                                s_col_c=w["col_c"])
+    assert (r, wv) == (rd, wr)
