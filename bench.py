@@ -110,6 +110,34 @@ def stored_traffic(kernel: str, wl_name: str):
     return None, None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def config1_oracle_times():
+    """The oracle on the whole of config 1 (C = A*A, 4096 x 4096, 8 per row):
+    one thread and all the process's cores, the mean of 10 runs after one."""
+    import oracle
+    import workloads as wl
+    A, _ = wl.config1()
+    cores = len(os.sched_getaffinity(0))
+    out = {}
+    for name, nt in (("one_thread", 1), ("all_cores", cores)):
+        oracle.spgemm(A, A, nthreads=nt)
+        t0 = time.perf_counter()
+        for _ in range(10):
+            oracle.spgemm(A, A, nthreads=nt)
+        out[name + "_us"] = round((time.perf_counter() - t0) / 10 * 1e6, 1)
+    out["cores"] = cores
+    return out
+
+
 def cpu_baseline(A, B, ip_rows, seconds: float, seed: int = 7):
     """Oracle rate on rows drawn with probability proportional to their
     intermediate-product count (so the sample has the workload's mix)."""
@@ -157,7 +185,7 @@ def cpu_baseline(A, B, ip_rows, seconds: float, seed: int = 7):
     res = {"value": 2.0 * ipw / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
            "sample": f"{len(rows)} rows drawn with probability proportional to their "
                      f"intermediate products ({ipw} products, {dt:.1f} s)",
-           "seconds": dt}
+           "seconds": dt, "cpu_model": cpu_model()}
     return res, rows, ref
 
 
@@ -184,25 +212,136 @@ KERNEL_SYMBOLS = {
     "coarse_sort (numeric, small chunks)": [("k_vrow_sort<", "true>")],
     "coarse_bitmap (symbolic, level 2)": [("k_vrow_bitmap",)],
     "coarse_count (symbolic, level 2)": [("k_l2_hist<",), ("k_l2_scatter<", "false>")],
+    "run_bin (symbolic, runs per chunk)": [("k_run_rows<",)],
+    "run_count (symbolic, chunks from runs)": [("k_run_dense<", "false>"),
+                                               ("k_run_sort<", "false>")],
+    "run_accum (numeric, chunks from runs)": [("k_run_dense<", "true>"),
+                                                         ("k_run_sort<", "true>")],
 }
+
+# gfx950 (MI355X) unit counts used by the counter-derived figures
+N_XCD, N_CU, N_SIMD = 8, 256, 1024
 
 
 def _match(name, pats):
     return any(all(p in name for p in tup) for tup in pats)
 
 
-def _pmc_totals(d, counter):
+def _counter_rows(d):
+    """(dispatch id, kernel name, counter, value) of every counter sample
+    under d, from rocprofv3's CSV output or its rocpd SQLite database."""
     import csv
-    tot = {}
+    import sqlite3
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
-            if r["Counter_Name"] != counter:
-                continue
-            name = r["Kernel_Name"]
-            t = tot.setdefault(name, [0.0, set()])
-            t[0] += float(r["Counter_Value"])
-            t[1].add(r["Dispatch_Id"])
+            yield r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+    for f in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+        con = sqlite3.connect(f)
+        q = "select dispatch_id, kernel_name, counter_name, value from counters_collection"
+        for did, kn, cn, v in con.execute(q):
+            yield str(did), kn, cn, float(v)
+        con.close()
+
+
+def _pmc_totals(d, counter):
+    tot = {}
+    for did, name, cn, v in _counter_rows(d):
+        if cn != counter:
+            continue
+        t = tot.setdefault(name, [0.0, set()])
+        t[0] += v
+        t[1].add(did)
     return {k: (v[0], len(v[1])) for k, v in tot.items()}
+
+
+SQ_PASSES = (
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_INSTS_VALU SQ_INSTS_LDS "
+    "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE",
+    "SQ_ACTIVE_INST_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_WAIT_ANY "
+    "SQ_ACTIVE_INST_ANY SQ_INSTS_BRANCH SQ_INST_CYCLES_VMEM GRBM_GUI_ACTIVE",
+)
+
+
+def sq_summary(args):
+    """Occupancy, waits, VALU and LDS figures per library kernel from two
+    rocprofv3 --pmc runs of one bench step (SQ_PASSES), written to
+    profiles/counters_<workload>.md."""
+    per = {}   # kernel (name with template arguments) -> counter -> dispatch -> value
+    wanted = [p for pats in KERNEL_SYMBOLS.values() for p in pats]
+    for di, d in enumerate(args.sq_summary):
+        for did0, name, cn, v in _counter_rows(d):
+            did = (di, did0)  # dispatch ids restart in every run
+            if not _match(name, wanted):
+                continue
+            key = name.split("(")[0].replace("void ", "").replace("mg::", "").strip()
+            per.setdefault(key, {}).setdefault(cn, {}).setdefault(did, 0.0)
+            per[key][cn][did] += v
+    # the sources the profiled run was built from: its bench line's digest
+    sha = src_digest()
+    logf = args.sq_summary[0].rstrip("/") + ".log"
+    if os.path.exists(logf):
+        for line in open(logf):
+            if line.startswith("{") and '"src_sha"' in line:
+                sha = json.loads(line)["src_sha"]
+    rows, js = [], {}
+    for lib_name, cs in per.items():
+        def tot(c):
+            return sum(cs.get(c, {}).values())
+        # GRBM_GUI_ACTIVE counts every XCD's busy cycles: one XCD's share is
+        # the kernel's cycles; wave cycles and VALU-active cycles count in
+        # units of 4 cycles
+        launches = max(len(cs.get("SQ_WAVES", {})), 1)
+        grbm_a = sum(v for k, v in cs.get("GRBM_GUI_ACTIVE", {}).items()
+                     if k in cs.get("SQ_WAVES", {}))
+        grbm_b = sum(v for k, v in cs.get("GRBM_GUI_ACTIVE", {}).items()
+                     if k in cs.get("SQ_WAIT_ANY", {}))
+        cyc_a, cyc_b = grbm_a / N_XCD, grbm_b / N_XCD
+        if cyc_a <= 0 or cyc_b <= 0:
+            continue
+        waves = tot("SQ_WAVES")
+        occ = 4.0 * tot("SQ_WAVE_CYCLES") / (cyc_a * N_CU)
+        wait = tot("SQ_WAIT_ANY") / max(1.0, tot("SQ_WAVE_CYCLES") * cyc_b / cyc_a)
+        valu_busy = 4.0 * tot("SQ_ACTIVE_INST_VALU") / (cyc_b * N_SIMD)
+        bank = tot("SQ_LDS_BANK_CONFLICT") / (cyc_a * N_CU)
+        d = {"launches": launches, "waves_per_launch": waves / launches,
+             "mean_waves_per_cu": occ, "wait_frac": wait, "valu_busy": valu_busy,
+             "lds_bank_conflict_frac": bank,
+             "valu_per_wave": tot("SQ_INSTS_VALU") / max(waves, 1),
+             "lds_per_wave": tot("SQ_INSTS_LDS") / max(waves, 1),
+             "vmem_rd_per_wave": tot("SQ_INSTS_VMEM_RD") / max(waves, 1) * cyc_a / cyc_b,
+             "vmem_wr_per_wave": tot("SQ_INSTS_VMEM_WR") / max(waves, 1) * cyc_a / cyc_b,
+             "kernel_ms_per_launch": cyc_a / launches / 2.4e6}
+        js[lib_name] = d
+        if d["kernel_ms_per_launch"] * launches < 0.5:
+            continue  # sub-millisecond kernels: figures dominated by launch edges
+        rows.append(f"| {lib_name} | {launches} | {d['kernel_ms_per_launch']:.2f} | "
+                    f"{d['waves_per_launch']:.4g} | {occ:.1f} | {100 * wait:.0f}% | "
+                    f"{100 * valu_busy:.1f}% | {100 * bank:.1f}% | {d['valu_per_wave']:.4g} | "
+                    f"{d['lds_per_wave']:.4g} |")
+    out = os.path.join(ROOT, "profiles", f"counters_{args.workload}.md")
+    cmd = f"python bench.py --workload {args.workload} --steps 1 --warmup 0 --no-cpu"
+    with open(out, "w") as fh:
+        fh.write(f"# SQ counters per kernel, workload {args.workload}\n\n")
+        fh.write("Two counter runs of one bench step (each its own process):\n\n")
+        for i, ps in enumerate(SQ_PASSES):
+            fh.write(f"- `rocprofv3 --pmc {ps} -d <dir{i}> -o run -- {cmd}`\n")
+        fh.write(f"\nthen `python bench.py --workload {args.workload} --sq-summary <dir0> <dir1>`.\n\n")
+        fh.write("Definitions (gfx950: 8 XCDs, 256 CUs, 1024 SIMDs; GRBM_GUI_ACTIVE sums the busy "
+                 "cycles of every XCD, so one XCD's share is the kernel's cycles T; "
+                 "SQ_WAVE_CYCLES and SQ_ACTIVE_INST_VALU count units of 4 cycles):\n\n"
+                 "- waves/CU = 4 * SQ_WAVE_CYCLES / (T * 256), the mean resident waves per CU;\n"
+                 "- wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES, the share of wave time spent waiting;\n"
+                 "- VALU busy = 4 * SQ_ACTIVE_INST_VALU / (T * 1024);\n"
+                 "- LDS bank conflicts = SQ_LDS_BANK_CONFLICT / (T * 256), the share of each "
+                 "CU's cycles its LDS spent on bank conflicts;\n"
+                 "- VALU and LDS instructions per wave = SQ_INSTS_* / SQ_WAVES.\n\n")
+        fh.write(f"Sources of the profiled run: `src_sha {sha}` (the bench line's digest).\n\n")
+        fh.write("| kernel | launches | ms/launch (T) | waves/launch | waves/CU | wait | VALU busy "
+                 "| LDS bank conflicts | VALU instr/wave | LDS instr/wave |\n"
+                 "|---|---|---|---|---|---|---|---|---|---|\n")
+        fh.write("\n".join(rows) + "\n\n(Kernels under 0.5 ms in total are in the JSON line only.)\n\n")
+        fh.write("counters-json:" + json.dumps({"src_sha": sha, "kernels": js}) + "\n")
+    log(f"[bench] wrote {out}")
 
 
 def pmc_summary(args):
@@ -680,6 +819,9 @@ def main():
     ap.add_argument("--trace-summary", metavar="STATS_DIR",
                     help="turn a rocprofv3 --kernel-trace --stats CSV into profiles/kernels_<workload>.md")
     ap.add_argument("--trace-command", default="")
+    ap.add_argument("--sq-summary", nargs="+", metavar="PMC_DIR",
+                    help="turn the rocprofv3 --pmc runs of SQ_PASSES into "
+                         "profiles/counters_<workload>.md")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="products of the batch workload (--workload batch)")
     ap.add_argument("--no-tune", action="store_true", help="batch workload: library defaults")
@@ -695,6 +837,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args)
+        return
+    if args.sq_summary:
+        sq_summary(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -799,6 +944,9 @@ def main():
     ctx.profile(False)
     del src, dst
     copy_gbs = ck["bytes"] / ck["ms"] / 1e6
+    # the whole step against the paper's ideal volume, beside the dominant
+    # kernel's own figure
+    roof["step_ideal_volume_frac"] = ideal["frac_of_peak"]
     ideal.update({"copy_GBps": round(copy_gbs, 1),
                   "t_ideal_copy_ms": vid / (copy_gbs * 1e9) * 1e3,
                   "multiple_of_ideal_at_copy_bw": round(ms / (vid / (copy_gbs * 1e9) * 1e3), 3)})
@@ -813,6 +961,7 @@ def main():
         ipr, _ = ctx.row_ip(dA, dB)
         ipr = ipr.cpu().numpy()
         cpu, rows, ref = cpu_baseline(A, B, ipr, args.cpu_seconds)
+        cpu["config1_oracle"] = config1_oracle_times()
         # the sampled rows of the last timed C against the oracle
         rp = C.rowptr.cpu().numpy()
         idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])

@@ -128,7 +128,14 @@ typedef struct {
                            * chunks), with chunks a quarter of the usual length unless
                            * chunk_shift is set; force_category and coarse_chunks are ignored.  Single
                            * products only: batch plans and the server reject it. */
-  int32_t _reserved[2];
+  int32_t chunk_runs;     /* how CHUNKED rows are reordered into chunks (Algorithm 3): by
+                           * single products (-1), or by runs, i.e. the part of one B row
+                           * in one chunk, which B's ascending columns keep contiguous, so
+                           * each chunk's accumulator reads its products from B through
+                           * its list of runs (1); 0: by runs when the rows' products
+                           * number at least 8 per run and the run lists fit the
+                           * workspace cap.  Deterministic mode always reorders products. */
+  int32_t _reserved;
 } magnus_options_t;
 
 /* Sizes the plan reports (host struct). */
@@ -154,7 +161,8 @@ typedef struct {
   int64_t coarse_chunks;   /* their coarse chunks (2^coarse_shift columns each) */
   int64_t coarse_fine_chunks; /* chunks of 2^chunk_shift columns inside the coarse chunks */
   int32_t coarse_shift;
-  int32_t _pad1;
+  int32_t run_binned;      /* 1: CHUNKED rows were reordered by runs (options.chunk_runs) */
+  int64_t n_runs;          /* runs of those rows (0 otherwise) */
 } magnus_plan_info_t;
 
 typedef struct magnus_handle_s* magnus_handle_t;
@@ -179,15 +187,24 @@ magnus_status_t magnus_set_allocator(magnus_handle_t h, magnus_alloc_fn alloc, m
 /* Plan: the setup phase (chunk-count model, intermediate-product count per
  * row, categorisation; Section 3.1) and the precise symbolic phase (exact
  * nnz of every row of C followed by a prefix sum; Section 2.1).  Synchronises
- * `stream` once.  On success *plan owns device memory until
- * magnus_plan_destroy; A and B must stay unchanged until then.  info may be
- * NULL. */
+ * `stream` (a few times: sizes are read back between passes).  On success
+ * *plan owns device memory until magnus_plan_destroy; A and B must stay
+ * unchanged until then.  info may be NULL.
+ * With options.validate, A and B are checked first and the result read back
+ * before any pass indexes B by A's columns: MAGNUS_ERR_INVALID_CSR for
+ * rowptr[0] != 0, decreasing row pointers, rowptr[n] != nnz, a column
+ * outside [0, ncols), or a B row whose columns are not strictly ascending.
+ * When an allocation fails and some row batch of CHUNKED rows (Section 3.3's
+ * batching) was wider than the longest row, the plan is made again with
+ * batches half as wide, up to four times, before MAGNUS_ERR_OOM. */
 magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
                             void* stream, magnus_plan_t* plan, magnus_plan_info_t* info);
 
 /* Numeric phase: writes C.rowptr, C.col, C.val (C.capacity >= info.nnz_c,
  * C.nrows == A.nrows, C.ncols == B.ncols).  *nnz_out (host) receives nnz(C).
- * Returns MAGNUS_ERR_CAPACITY (nothing written) when capacity is short.
+ * Checked before anything is launched, in this order:
+ * MAGNUS_ERR_INDEX_OVERFLOW when C.rowptr_type is MAGNUS_I32 and nnz(C)
+ * >= 2^31, then MAGNUS_ERR_CAPACITY when C.capacity < nnz(C).
  * Does not synchronise the stream. */
 magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t plan, const magnus_csr_t* A,
                                const magnus_csr_t* B, const magnus_csr_out_t* C, int64_t* nnz_out,
@@ -195,6 +212,28 @@ magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t plan, const magn
 
 magnus_status_t magnus_plan_destroy(magnus_plan_t plan);
 magnus_status_t magnus_plan_get_info(magnus_plan_t plan, magnus_plan_info_t* info);
+
+/* The whole product in one call (Section 2.1's problem statement: CSR A and
+ * B in, CSR C out): magnus_plan, then C's three arrays from the handle's
+ * allocator (exactly nnz(C) entries, known from the precise symbolic phase),
+ * then magnus_execute, then magnus_plan_destroy.
+ *   c_rowptr_type: MAGNUS_I32 or MAGNUS_I64, the type of C's row pointers.
+ *   C (host struct, out): on success every field is set: device pointers to
+ *     rowptr (nrows + 1 entries), col and val (capacity = nnz(C) entries),
+ *     C.col_type = B's, C.val_type = A's.  On failure it is zeroed and
+ *     nothing stays allocated.  The caller owns C's memory and returns it
+ *     with magnus_csr_free.
+ * Synchronises `stream` as magnus_plan does; the numeric phase is still in
+ * flight on `stream` when the call returns.  Errors: those of magnus_plan
+ * and magnus_execute; MAGNUS_ERR_INDEX_OVERFLOW when nnz(C) needs 64-bit
+ * row pointers but c_rowptr_type is MAGNUS_I32 (no numeric launch);
+ * MAGNUS_ERR_OOM when the allocator fails (a plan whose allocations fail is
+ * retried with row batches half as wide, up to four times). */
+magnus_status_t magnus_spgemm(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                              int32_t c_rowptr_type, magnus_csr_out_t* C, void* stream);
+/* Returns the three arrays of a C made by magnus_spgemm to the handle's
+ * allocator (in stream order on `stream`) and clears its pointers. */
+magnus_status_t magnus_csr_free(magnus_handle_t h, magnus_csr_out_t* C, void* stream);
 
 /* Intermediate-product count per row (the setup phase's per-row count,
  * Section 3.1 / n_interProd of Section 4.3).  ip_out: device int64[A.nrows];
@@ -403,6 +442,24 @@ magnus_status_t magnus_server_result(magnus_server_t server, int64_t request_id,
 /* Frees a finished request's C and forgets the request. */
 magnus_status_t magnus_server_release(magnus_server_t server, int64_t request_id);
 magnus_status_t magnus_server_get_stats(magnus_server_t server, magnus_server_stats_t* stats);
+
+/* A request that reached a final state (done, rejected or failed). */
+typedef struct {
+  int64_t request_id;
+  int32_t state;       /* MAGNUS_REQ_DONE, MAGNUS_REQ_REJECTED or MAGNUS_REQ_FAILED */
+  int32_t status;      /* magnus_status_t: MAGNUS_OK when done */
+  int64_t nnz;         /* nnz(C) when done */
+  double latency_ms;   /* submit -> C complete on the device; -1 unless done */
+} magnus_completion_t;
+
+/* Takes, without waiting, up to max completions in the order the scheduler
+ * saw them finish; *n (host) receives how many were written to out (host
+ * array).  Each request is reported once.  A completion is queued for every
+ * submitted request, whether or not its state was also read by
+ * magnus_server_query, until the request is released or the server is
+ * destroyed; a request released before it is polled is not reported. */
+magnus_status_t magnus_server_poll(magnus_server_t server, magnus_completion_t* out, int32_t max,
+                                   int32_t* n);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,8 @@ class Options(ctypes.Structure):
                 ("bin_dense_min", c_i32), ("tile_products", c_i32), ("dense_block", c_i32),
                 ("batch_products", c_i64), ("max_workspace_bytes", c_i64), ("validate", c_i32),
                 ("lds_bytes", c_i32), ("sort_group_max", c_i32), ("stream_hints", c_i32),
-                ("coarse_chunks", c_i32), ("deterministic", c_i32), ("_reserved", c_i32 * 2)]
+                ("coarse_chunks", c_i32), ("deterministic", c_i32), ("chunk_runs", c_i32),
+                ("_reserved", c_i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -43,7 +44,7 @@ class PlanInfo(ctypes.Structure):
                 ("chunk_shift", c_i32), ("sort_max", c_i32), ("bin_dense_min", c_i32),
                 ("tile_products", c_i32), ("symbolic_ms", ctypes.c_double),
                 ("coarse_rows", c_i64), ("coarse_chunks", c_i64), ("coarse_fine_chunks", c_i64),
-                ("coarse_shift", c_i32), ("_pad1", c_i32)]
+                ("coarse_shift", c_i32), ("run_binned", c_i32), ("n_runs", c_i64)]
 
     def as_dict(self):
         d = {}
@@ -69,6 +70,11 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, c_i64) for n in ("submitted", "completed", "rejected", "failed", "batches",
                                      "batched_requests", "exact_probes", "reserved_bytes",
                                      "budget_bytes", "queued", "running")]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("request_id", c_i64), ("state", c_i32), ("status", c_i32), ("nnz", c_i64),
+                ("latency_ms", ctypes.c_double)]
 
 
 class StreamTimes(ctypes.Structure):
@@ -131,6 +137,8 @@ def load(path: str = LIB_PATH):
     lib.magnus_execute.argtypes = [c_vp, c_vp, P(CsrDesc), P(CsrDesc), P(CsrOutDesc), P(c_i64),
                                    c_vp]
     lib.magnus_plan_destroy.argtypes = [c_vp]
+    lib.magnus_spgemm.argtypes = [c_vp, P(CsrDesc), P(CsrDesc), c_i32, P(CsrOutDesc), c_vp]
+    lib.magnus_csr_free.argtypes = [c_vp, P(CsrOutDesc), c_vp]
     lib.magnus_plan_get_info.argtypes = [c_vp, P(PlanInfo)]
     lib.magnus_row_ip.argtypes = [c_vp, P(CsrDesc), P(CsrDesc), c_vp, P(c_i64), c_vp]
     lib.magnus_paper_chunk_model.argtypes = [c_i64, c_i64, c_i64, ctypes.c_double, P(c_i64),
@@ -159,6 +167,7 @@ def load(path: str = LIB_PATH):
     lib.magnus_server_result.argtypes = [c_vp, c_i64, P(CsrOutDesc)]
     lib.magnus_server_release.argtypes = [c_vp, c_i64]
     lib.magnus_server_get_stats.argtypes = [c_vp, P(ServerStats)]
+    lib.magnus_server_poll.argtypes = [c_vp, P(Completion), c_i32, P(c_i32)]
     for fn in declared_symbols():
         f = getattr(lib, fn)
         if fn not in ("magnus_status_string", "magnus_last_error", "magnus_options_default",

@@ -64,8 +64,13 @@ class Context:
     """A library handle bound to one device, with torch's caching allocator
     behind the library's device allocations."""
 
-    def __init__(self, device: int = 0, **options):
+    def __init__(self, device: int = 0, alloc_filter=None, **options):
+        """alloc_filter: optional callable(nbytes) -> bool; an allocation it
+        refuses is reported to the library as failed (the allocator returns
+        NULL), so callers can exercise the library's out-of-memory paths.
+        self.live_allocs counts allocations not yet freed."""
         self.lib = _lib.load()
+        self.live_allocs = 0
         self.device = device
         self.handle = ctypes.c_void_p()
         self.opts = Options()
@@ -76,12 +81,17 @@ class Context:
         dev = torch.device("cuda", device)
 
         def _alloc(n, stream, ctx):
+            if alloc_filter is not None and not alloc_filter(int(n)):
+                return None
             try:
-                return torch.cuda.caching_allocator_alloc(int(n), dev, int(stream or 0))
+                p = torch.cuda.caching_allocator_alloc(int(n), dev, int(stream or 0))
             except Exception:
                 return None
+            self.live_allocs += 1
+            return p
 
         def _free(p, n, stream, ctx):
+            self.live_allocs -= 1
             try:
                 torch.cuda.caching_allocator_delete(int(p))
             except Exception:  # interpreter shutdown: torch already torn down
@@ -169,6 +179,11 @@ class Context:
                                           ctypes.c_void_p(src.data_ptr()), nbytes, s),
               "magnus_stream_copy", self.handle)
 
+    def stream_copy_raw(self, dst: int, src: int, nbytes: int, stream=None):
+        s, keep = _stream_ptr(stream)
+        check(self.lib.magnus_stream_copy(self.handle, ctypes.c_void_p(dst), ctypes.c_void_p(src),
+                                          nbytes, s), "magnus_stream_copy", self.handle)
+
     def stream_chunks(self, cols: torch.Tensor, vals: torch.Tensor, m: int, chunk_shift: int,
                       dense_min: int = 0, stream=None):
         """The chunk building blocks on one stream of products (Section 4.1):
@@ -221,11 +236,65 @@ class Context:
         return list(ip), list(nb)
 
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, rowptr_dtype=torch.int64, stream=None):
+        """C = A*B into torch-owned tensors (plan, execute, destroy)."""
         p = self.plan(A, B, stream)
         try:
             return p.execute(rowptr_dtype=rowptr_dtype, stream=stream)
         finally:
             p.destroy()
+
+    def spgemm_lib(self, A: DeviceCSR, B: DeviceCSR, rowptr_dtype=torch.int64, stream=None):
+        """C = A*B by the C ABI's one-call product (magnus_spgemm): C comes
+        from the library's allocator, i.e. torch's caching allocator here.
+        Returns a LibCSR that owns that memory until free() (or collection)."""
+        s, keep = _stream_ptr(stream)
+        da, db = A.desc(), B.desc()
+        d = CsrOutDesc()
+        check(self.lib.magnus_spgemm(self.handle, ctypes.byref(da), ctypes.byref(db),
+                                     _ITYPE[rowptr_dtype], ctypes.byref(d), s),
+              "magnus_spgemm", self.handle)
+        return LibCSR(self, d)
+
+
+class LibCSR:
+    """A C whose arrays the library allocated (magnus_spgemm); free() hands
+    them back through magnus_csr_free."""
+
+    def __init__(self, ctx: Context, d: CsrOutDesc):
+        self.ctx, self.d = ctx, d
+
+    @property
+    def nnz(self) -> int:
+        return int(self.d.capacity)
+
+    def to_device_csr(self) -> DeviceCSR:
+        """A copy into torch-owned tensors (by the library's copy kernel)."""
+        d = self.d
+        dev = torch.device("cuda", self.ctx.device)
+        rt = torch.int64 if d.rowptr_type == 1 else torch.int32
+        ct = torch.int64 if d.col_type == 1 else torch.int32
+        vt = torch.float64 if d.val_type == 1 else torch.float32
+        out = DeviceCSR(int(d.nrows), int(d.ncols),
+                        torch.empty(int(d.nrows) + 1, dtype=rt, device=dev),
+                        torch.empty(self.nnz, dtype=ct, device=dev),
+                        torch.empty(self.nnz, dtype=vt, device=dev))
+        for t, src in ((out.rowptr, d.rowptr), (out.col, d.col), (out.val, d.val)):
+            if t.numel():
+                self.ctx.stream_copy_raw(t.data_ptr(), src, t.numel() * t.element_size())
+        return out
+
+    def free(self, stream=None):
+        if self.d is not None and self.ctx.handle:
+            s, keep = _stream_ptr(stream)
+            check(self.ctx.lib.magnus_csr_free(self.ctx.handle, ctypes.byref(self.d), s),
+                  "magnus_csr_free")
+        self.d = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Plan:
@@ -402,6 +471,17 @@ class Server:
         # can hand that memory to another request
         torch.cuda.current_stream(dev).synchronize()
         return out
+
+    def poll(self, max_n: int = 64):
+        """Final states reported since the last poll: a list of dicts
+        (request_id, state, status, nnz, latency_ms)."""
+        arr = (_lib.Completion * max_n)()
+        n = ctypes.c_int32()
+        check(self.lib.magnus_server_poll(self.ptr, arr, max_n, ctypes.byref(n)),
+              "magnus_server_poll")
+        return [{"request_id": arr[i].request_id, "state": REQ_STATE[arr[i].state],
+                 "status": arr[i].status, "nnz": arr[i].nnz, "latency_ms": arr[i].latency_ms}
+                for i in range(n.value)]
 
     def release(self, rid: int):
         check(self.lib.magnus_server_release(self.ptr, rid), "magnus_server_release")

@@ -271,6 +271,44 @@ hipError_t launch_bin_rows(const ChunkGeom& g, int64_t k0, int64_t k1, const int
                            int64_t* rownnz, const int64_t* crp, int64_t* bin_out, bool to_out,
                            hipStream_t st);
 
+// --- CHUNKED rows binned by runs (k_runs.hip) ---
+// Chunk index of B (chunks of 2^shift columns): count pass (fill = false)
+// writes cnt[j] = runs of row j + 1; after an exclusive scan into ptr
+// (nrows + 1 entries), the fill pass writes pos (run starts, then the row's
+// end) and chunk (each run's column >> shift).  Needs nnz(B) < 2^32.
+hipError_t launch_bci(const Mats& M, int shift, bool fill, int64_t* cnt, const int64_t* ptr,
+                      uint32_t* pos, uint32_t* chunk, hipStream_t st);
+// out[0] += runs of the listed rows; out[1] = max(out[1], A entries of a
+// row); out[2] += their products (ip, by row id)
+hipError_t launch_run_count(const Mats& M, const int32_t* rows, int64_t nrows, const int64_t* bptr,
+                            const int64_t* ip, unsigned long long* out, hipStream_t st);
+// hist: runs and products per chunk (bin_seg, bin_cnt) and each chunk's row;
+// otherwise the runs' scatter: B position, A entry and product offset of
+// every run, the runs of chunk b at [seg_beg[b], seg_beg[b + 1])
+size_t run_rows_lds(int64_t max_nb);
+hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const int64_t* bptr,
+                           const uint32_t* bpos, const uint32_t* bchunk, int64_t max_nb,
+                           int64_t* bin_seg, int64_t* bin_cnt, int32_t* bin_row,
+                           const int64_t* seg_beg, const int64_t* bin_start, uint32_t* seg_b,
+                           uint32_t* seg_a, int64_t* seg_off, hipStream_t st);
+// the dense items' records (6 int64 each: product start, run start,
+// products, runs, first column, chunk), built once after the grouping
+hipError_t launch_run_records(const ChunkGeom& g, int64_t nbins, const int64_t* dense_items,
+                              const int32_t* item_counts, const int64_t* bin_start,
+                              const int64_t* bin_cnt, const int32_t* bin_row,
+                              const int64_t* seg_beg, int64_t* rec, hipStream_t st);
+// the accumulators over chunks whose products are read through their runs
+// (count mode: bin_nnz; numeric: C at bin_out)
+size_t run_dense_lds(int f64, int shift, int block);
+hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bool numeric,
+                            const int64_t* bin_start, const int64_t* bin_cnt,
+                            const int32_t* bin_row, const int64_t* dense_rec,
+                            const int64_t* sort_items, const int32_t* item_counts,
+                            const int64_t* seg_beg, const int64_t* seg_off, const uint32_t* seg_b,
+                            const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
+                            void* ccol, int col64, void* cval, int dense_block,
+                            unsigned int* work, int persistent_wgs, hipStream_t st);
+
 // --- misc (k_rows.hip) ---
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_write_rowptr(const int64_t* crp, int64_t n, void* out, int out64,

@@ -23,6 +23,9 @@ magnus_status_t batch_width(magnus_plan_s* P, int64_t bytes_per_product, int64_t
     }
     W = budget / bytes_per_product;
   }
+  // a retry after the allocator failed asks for batches half as wide each time
+  W /= std::max<int64_t>(1, P->ws_div);
+  if (W <= (int64_t)P->h_stats.max_ip) P->w_at_min = true;
   if (W < (int64_t)P->h_stats.max_ip) W = (int64_t)P->h_stats.max_ip;
   if (W < 1) W = 1;
   return MAGNUS_OK;
@@ -153,6 +156,117 @@ magnus_status_t det_setup(magnus_plan_s* P, int64_t ntiles, int64_t nbins) {
   return MAGNUS_OK;
 }
 
+// Run binning of the CHUNKED rows (k_runs.hip), when options.chunk_runs
+// allows it: B's chunk index, then the rows' run total; the rows are binned
+// by runs when they hold at least RUN_MIN_LEN products per run (or the option
+// forces it) and the run lists fit the workspace cap.  *chosen reports
+// whether the plan goes this way; the arrays of the chunk geometry are then
+// set up for one batch of all CHUNKED rows.
+constexpr int64_t RUN_MIN_LEN = 8;
+
+magnus_status_t runs_setup(magnus_plan_s* P, bool& chosen) {
+  magnus_handle_s* h = P->h;
+  const magnus_options_t& o = h->opts;
+  chosen = false;
+  const int64_t kB = P->M.k;
+  if (P->det || o.chunk_runs < 0 || P->b_nnz >= ((int64_t)1 << 32) - 1 ||
+      P->a_nnz >= ((int64_t)1 << 32) || P->h_stats.max_ip >= ((unsigned long long)1 << 31) ||
+      run_rows_lds(P->max_nb) > (size_t)P->lds_budget ||
+      run_dense_lds(P->M.f64, P->shift, P->dense_block) > (size_t)h->lds_max)
+    return MAGNUS_OK;
+  // B's chunk index: runs per row (+1), their scan, then starts and chunks
+  P->bci_ptr = (int64_t*)palloc(P, sizeof(int64_t) * (kB + 1));
+  void* btmp = palloc(P, scan_temp_bytes(kB + 1) + 64);
+  unsigned long long* cnt = (unsigned long long*)palloc(P, 64);  // runs, max entries, products
+  if (!P->bci_ptr || !btmp || !cnt) return MAGNUS_ERR_OOM;
+  HIPCHK(launch_bci(P->M, P->shift, false, P->bci_ptr, nullptr, nullptr, nullptr, P->st));
+  HIPCHK(scan_excl_i64(P->bci_ptr, P->bci_ptr, kB, P->bci_ptr + kB, nullptr, btmp, P->st));
+  HIPCHK(hipMemsetAsync(cnt, 0, 24, P->st));
+  HIPCHK(launch_run_count(P->M, P->list + P->h_list_off[CLS_CHUNKED], P->nch, P->bci_ptr, P->ip,
+                          cnt, P->st));
+  int64_t nbci = 0;
+  unsigned long long hc[3] = {0, 0, 0};
+  magnus_status_t s = readback(P, {{P->bci_ptr + kB, 8}, {cnt, 24}}, {&nbci, hc});
+  if (s != MAGNUS_OK) return s;
+  const int64_t runs = (int64_t)hc[0];
+  // products of the rows listed as CHUNKED (coarse-level rows excluded)
+  const int64_t ipch = (int64_t)hc[2];
+  int64_t cap = o.max_workspace_bytes;
+  if (cap <= 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    cap = (int64_t)(tot / 8);
+  }
+  cap /= std::max<int64_t>(1, P->ws_div);
+  const bool fits = runs * 16 <= cap && hc[1] < ((unsigned long long)1 << 24);
+  const bool want = o.chunk_runs > 0 || (runs > 0 && ipch >= RUN_MIN_LEN * runs);
+  if (!fits || !want) return MAGNUS_OK;
+  P->bci_pos = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, nbci));
+  P->bci_chunk = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, nbci));
+  if (!P->bci_pos || !P->bci_chunk) return MAGNUS_ERR_OOM;
+  HIPCHK(launch_bci(P->M, P->shift, true, nullptr, P->bci_ptr, P->bci_pos, P->bci_chunk, P->st));
+  P->n_runs = runs;
+  chosen = true;
+  P->runs = true;
+  // 512-thread dense workgroups unless set (config 2: 360 -> 324 ms per step
+  // against 256; 1024 is slower)
+  if (o.dense_block != 256 && o.dense_block != 512 && o.dense_block != 1024) {
+    P->dense_block = 512;
+    const size_t dl = run_dense_lds(P->M.f64, P->shift, P->dense_block);
+    const int per_cu = std::max<int>(1, (int)(h->lds_max / std::max<size_t>(dl, 1)));
+    P->persistent_wgs = std::max(1, h->cus) * std::min(per_cu, 2048 / P->dense_block);
+    const size_t dlc = ((size_t)1 << P->shift) / 8 + (size_t)P->dense_block * 8 + 4096;
+    const int per_cu_c = std::max<int>(1, (int)(h->lds_max / dlc));
+    P->persistent_wgs_count = std::max(1, h->cus) * std::min(per_cu_c, 2048 / P->dense_block);
+  }
+
+  // the chunk geometry of one batch of all CHUNKED rows
+  ChunkGeom& g = P->g;
+  int64_t tots[3];
+  s = geometry_and_batches(P, g, INT64_MAX / 4, P->batches, P->ws_products, tots);
+  if (s != MAGNUS_OK) return s;
+  const int64_t nbins = tots[2], nch = P->nch;
+  P->ws_products = 0;
+  P->scan_temp = palloc(P, scan_temp_bytes(nbins + 1));
+  P->work_ctr = (unsigned int*)palloc(P, sizeof(int64_t) * 2);
+  P->bin_start = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_cnt = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_nnz = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_out = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->bin_row = (int32_t*)palloc(P, sizeof(int32_t) * nbins);
+  P->bin_seg = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->seg_beg = (int64_t*)palloc(P, sizeof(int64_t) * (nbins + 1));
+  P->dense_items = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
+  P->sort_items = (int64_t*)palloc(P, sizeof(int64_t) * 2 * nbins);
+  P->item_counts = (int32_t*)palloc(P, sizeof(int32_t) * 2);
+  // dense items are the chunks of >= dense_min products: at most
+  // products / dense_min of them
+  P->run_rec = (int64_t*)palloc(
+      P, sizeof(int64_t) * 6 * std::max<int64_t>(1, std::min(nbins, tots[0] / std::max<int64_t>(1, P->dense_min) + 1)));
+  P->seg_b = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, runs));
+  P->seg_a = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, runs));
+  P->seg_off = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, runs));
+  P->ent = (int64_t*)palloc(P, sizeof(int64_t) * (4 * nch + 2));
+  if (!P->aoff) P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
+  if (!P->scan_temp || !P->work_ctr || !P->bin_start || !P->bin_cnt || !P->bin_nnz ||
+      !P->bin_out || !P->bin_row || !P->bin_seg || !P->seg_beg || !P->dense_items ||
+      !P->sort_items || !P->item_counts || !P->seg_b || !P->seg_a || !P->seg_off || !P->ent ||
+      !P->run_rec ||
+      !P->aoff)
+    return MAGNUS_ERR_OOM;
+  HIPCHK(hipMemsetAsync(P->item_counts, 0, sizeof(int32_t) * 2, P->st));
+  HIPCHK(hipMemsetAsync(P->bin_nnz, 0, sizeof(int64_t) * nbins, P->st));
+  P->entBase = P->ent + nch;
+  P->nnzr = P->entBase + nch + 1;
+  P->nnzBase = P->nnzr + nch;
+  // A entries per row (for the batch's profiling bytes and nnz offsets)
+  HIPCHK(launch_aoff(P->M, g.rows, nch, P->aoff, P->ent, P->st));
+  HIPCHK(scan_excl_i64(P->ent, P->entBase, nch, P->entBase + nch, nullptr, P->temp, P->st));
+  P->info.n_batches = 1;
+  P->info.n_bins = nbins;
+  return MAGNUS_OK;
+}
+
 magnus_status_t setup_chunked(magnus_plan_s* P) {
   magnus_handle_s* h = P->h;
   const int64_t nch = P->nch;
@@ -165,6 +279,11 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
   g.shift = P->shift;
   g.tile = P->tile;
   g.hints = P->hints;
+  {
+    bool chosen = false;
+    magnus_status_t sr = runs_setup(P, chosen);
+    if (sr != MAGNUS_OK || chosen) return sr;
+  }
   void* tmp = P->temp;
   const int64_t vs = P->M.f64 ? 8 : 4;
   int64_t W = 0, tots[3];
@@ -222,6 +341,44 @@ magnus_status_t setup_chunked(magnus_plan_s* P) {
 // sizes and starts, and the accumulation work items of every batch.
 magnus_status_t chunked_symbolic(magnus_plan_s* P) {
   magnus_handle_s* h = P->h;
+  if (P->runs) {
+    // runs per chunk and products per chunk, their scans, the runs'
+    // scatter, the accumulation items, then the accumulators in count mode
+    const BatchArgs& b = P->batches[0];
+    const int64_t nbins = b.nbins;
+    {
+      const double ent = (double)P->h_stats.ent_cat[2];
+      ProfScope ps(h, P->st, "run_bin (symbolic, runs per chunk)",
+                   2.0 * (ent * (P->s_col + 16) + (double)P->n_runs * 8) +
+                       (double)P->n_runs * 16 + (double)nbins * 36);
+      HIPCHK(launch_run_rows(P->M, P->g, true, P->bci_ptr, P->bci_pos, P->bci_chunk, P->max_nb,
+                             P->bin_seg, P->bin_cnt, P->bin_row, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, P->st));
+      HIPCHK(scan_excl_i64(P->bin_cnt, P->bin_start, nbins, nullptr, nullptr, P->scan_temp,
+                           P->st));
+      HIPCHK(scan_excl_i64(P->bin_seg, P->seg_beg, nbins, P->seg_beg + nbins, nullptr,
+                           P->scan_temp, P->st));
+      HIPCHK(launch_run_rows(P->M, P->g, false, P->bci_ptr, P->bci_pos, P->bci_chunk, P->max_nb,
+                             nullptr, nullptr, nullptr, P->seg_beg, P->bin_start, P->seg_b,
+                             P->seg_a, P->seg_off, P->st));
+    }
+    HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
+                            P->sort_items, P->item_counts, P->st));
+    HIPCHK(launch_run_records(P->g, nbins, P->dense_items, P->item_counts, P->bin_start,
+                              P->bin_cnt, P->bin_row, P->seg_beg, P->run_rec, P->st));
+    unsigned int* wk = P->work_ctr;
+    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    {
+      ProfScope ps(h, P->st, "run_count (symbolic, chunks from runs)",
+                   (double)b.nip * P->s_col + (double)P->n_runs * 16 + (double)nbins * 40);
+      HIPCHK(launch_run_accum(P->M, P->g, nbins, false, P->bin_start, P->bin_cnt, P->bin_row,
+                              P->run_rec, P->sort_items, P->item_counts, P->seg_beg,
+                              P->seg_off, P->seg_b, P->seg_a, P->bin_nnz, nullptr, nullptr, 0,
+                              nullptr, P->dense_block, wk, P->persistent_wgs_count, P->st));
+    }
+    HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false, P->st));
+    return MAGNUS_OK;
+  }
   if (P->bitmap_symbolic) {
     {
       const double ipc = (double)P->h_stats.ip_cat[2], ec = (double)P->h_stats.ent_cat[2];
@@ -272,6 +429,24 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
 // reorder into the workspace, accumulate every chunk into C.
 magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* cval) {
   magnus_handle_s* h = P->h;
+  if (P->runs) {
+    const BatchArgs& b = P->batches[0];
+    HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, nullptr, P->crp, P->bin_out, true,
+                           P->st));
+    unsigned int* wk = P->work_ctr + 2;
+    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    // per product: B column and value; per run: its record and A value; per
+    // output: C written
+    ProfScope ps(h, P->st, "run_accum (numeric, chunks from runs)",
+                 (double)b.nip * (P->s_col + P->s_val) +
+                     (double)P->n_runs * (16 + P->s_val) +
+                     (double)b.nnz_out * (P->s_col + P->s_val));
+    HIPCHK(launch_run_accum(P->M, P->g, b.nbins, true, P->bin_start, P->bin_cnt, P->bin_row,
+                            P->run_rec, P->sort_items, P->item_counts, P->seg_beg, P->seg_off,
+                            P->seg_b, P->seg_a, P->bin_nnz, P->bin_out, ccol, col64, cval,
+                            P->dense_block, wk, P->persistent_wgs, P->st));
+    return MAGNUS_OK;
+  }
   for (size_t bi = 0; bi < P->batches.size(); ++bi) {
     const BatchArgs& b = P->batches[bi];
     int32_t* ic = P->item_counts + 2 * bi;
@@ -382,6 +557,7 @@ magnus_status_t setup_coarse(magnus_plan_s* P) {
       HIPCHK(hipMemGetInfo(&fr, &tot));
       cap = (int64_t)(tot / 4);
     }
+    cap /= std::max<int64_t>(1, P->ws_div);
     C.keep_ws1 = C.ip_total * (4 + vs) <= cap;
   }
   const int64_t n_ws1 = C.keep_ws1 ? C.ip_total : C.ws_products;
@@ -783,15 +959,23 @@ magnus_status_t magnus_paper_chunk_model(int64_t m_c, int64_t s_cache, int64_t s
   return MAGNUS_OK;
 }
 
-magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
-                            void* stream, magnus_plan_t* out, magnus_plan_info_t* info) {
-  if (!h || !out) return MAGNUS_ERR_INVALID_ARG;
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// One attempt at a plan; ws_div divides the row-batch width and the kept
+// workspace cap.  *shrinkable reports whether a smaller divisor's retry could
+// need less memory (some row batch was wider than the longest row).
+magnus_status_t plan_once(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                          void* stream, magnus_plan_t* out, magnus_plan_info_t* info,
+                          int64_t ws_div, bool* shrinkable) {
+  *shrinkable = false;
   Mats M{};
   magnus_status_t s = make_mats(A, B, M);
   if (s != MAGNUS_OK) return s;
   HIPCHK(hipSetDevice(h->device));
   magnus_plan_s* P = new magnus_plan_s();
+  P->ws_div = ws_div;
   P->h = h;
   P->st = (hipStream_t)stream;
   P->M = M;
@@ -826,9 +1010,17 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     const size_t dl = bin_dense_lds(M.f64, P->shift);
     const int per_cu = std::max<int>(1, (int)(h->lds_max / std::max<size_t>(dl, 1)));
     P->persistent_wgs = std::max(1, h->cus) * std::min(per_cu, 2048 / P->dense_block);
+    // count mode keeps only the bitmap in LDS: the waves per CU bound it
+    const size_t dlc = ((size_t)1 << P->shift) / 8 + (size_t)P->dense_block * 8 + 4096;
+    const int per_cu_c = std::max<int>(1, (int)(h->lds_max / dlc));
+    P->persistent_wgs_count = std::max(1, h->cus) * std::min(per_cu_c, 2048 / P->dense_block);
   }
 
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   auto cleanup = [&](magnus_status_t st) {
+    *shrinkable = (P->nch > 0 || P->co.nrows > 0) && !P->w_at_min;
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
     plan_free_all(P);
     delete P;
     return st;
@@ -858,12 +1050,17 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     if (s_ != MAGNUS_OK) return cleanup(s_);              \
   } while (0)
 
-  hipEvent_t ev0, ev1;
   PCHK(hipEventCreate(&ev0));
   PCHK(hipEventCreate(&ev1));
   PCHK(hipEventRecord(ev0, P->st));
   PCHK(hipMemsetAsync(P->stats, 0, sizeof(DevStats), P->st));
-  if (o.validate) PCHK(launch_validate(M, A->nnz, B->nnz, P->stats, P->st));
+  if (o.validate) {
+    // an invalid column would index B's row pointers out of range in the
+    // setup pass: the check is read back before anything else runs
+    PCHK(launch_validate(M, A->nnz, B->nnz, P->stats, P->st));
+    SCHK(readback(P, {{P->stats, sizeof(DevStats)}}, {&P->h_stats}));
+    if (P->h_stats.err & ERR_INVALID_CSR) return cleanup(MAGNUS_ERR_INVALID_CSR);
+  }
   ClassParams cp{};
   cp.sort_max = P->sort_max;
   cp.dense_max = (int64_t)1 << P->shift;
@@ -1026,6 +1223,7 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   (void)hipEventElapsedTime(&ms, ev0, ev1);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
+  ev0 = ev1 = nullptr;
   if (st2.err & (ERR_STAGE_OVERFLOW | ERR_BIN_OVERFLOW)) {
     h->err = "device consistency check failed in the symbolic phase";
     return cleanup(MAGNUS_ERR_INTERNAL);
@@ -1053,11 +1251,33 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
   I.coarse_chunks = P->co.nv;
   I.coarse_fine_chunks = P->co.nbins2;
   I.coarse_shift = P->co.nrows > 0 ? P->co.cshift : 0;
+  I.run_binned = P->runs ? 1 : 0;
+  I.n_runs = P->runs ? P->n_runs : 0;
   if (info) *info = I;
   *out = P;
   return MAGNUS_OK;
 #undef PCHK
 #undef SCHK
+}
+
+}  // namespace
+
+extern "C" {
+
+magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                            void* stream, magnus_plan_t* out, magnus_plan_info_t* info) {
+  if (!h || !out) return MAGNUS_ERR_INVALID_ARG;
+  *out = nullptr;
+  // when the allocator fails, row batches (Section 3.3's batching of rows
+  // until the memory limit) are halved and the plan is made again, up to
+  // four times, while a batch is still wider than the longest row
+  magnus_status_t s = MAGNUS_OK;
+  for (int64_t div = 1; div <= 16; div *= 2) {
+    bool shrinkable = false;
+    s = plan_once(h, A, B, stream, out, info, div, &shrinkable);
+    if (s != MAGNUS_ERR_OOM || !shrinkable) break;
+  }
+  return s;
 }
 
 magnus_status_t magnus_plan_get_info(magnus_plan_t P, magnus_plan_info_t* info) {
@@ -1078,8 +1298,8 @@ magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t P, const magnus_
   if (C->val_type != A->val_type || C->col_type != B->col_type) return MAGNUS_ERR_DTYPE;
   if (C->rowptr_type != MAGNUS_I32 && C->rowptr_type != MAGNUS_I64) return MAGNUS_ERR_INVALID_ARG;
   if (nnz_out) *nnz_out = P->nnz_c;
-  if (C->capacity < P->nnz_c) return MAGNUS_ERR_CAPACITY;
   if (C->rowptr_type == MAGNUS_I32 && P->nnz_c > INT32_MAX) return MAGNUS_ERR_INDEX_OVERFLOW;
+  if (C->capacity < P->nnz_c) return MAGNUS_ERR_CAPACITY;
   if (!C->rowptr || (P->nnz_c > 0 && (!C->col || !C->val))) return MAGNUS_ERR_INVALID_ARG;
   HIPCHK(hipSetDevice(h->device));
   P->M = M;  // same shapes; the pointers of this call are used
@@ -1102,6 +1322,89 @@ magnus_status_t magnus_plan_destroy(magnus_plan_t P) {
   if (!P) return MAGNUS_OK;
   plan_free_all(P);
   delete P;
+  return MAGNUS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Bytes of the three arrays of C as magnus_spgemm allocates them.
+void csr_out_bytes(const magnus_csr_out_t* C, size_t b[3]) {
+  b[0] = align256((size_t)(C->nrows + 1) * (C->rowptr_type == MAGNUS_I64 ? 8 : 4));
+  b[1] = align256(std::max<size_t>(1, (size_t)C->capacity * (C->col_type == MAGNUS_I64 ? 8 : 4)));
+  b[2] = align256(std::max<size_t>(1, (size_t)C->capacity * (C->val_type == MAGNUS_F64 ? 8 : 4)));
+}
+
+void csr_out_release(magnus_handle_s* h, magnus_csr_out_t* C, void* stream) {
+  size_t b[3];
+  csr_out_bytes(C, b);
+  void* p[3] = {C->rowptr, C->col, C->val};
+  for (int k = 0; k < 3; ++k) {
+    if (!p[k]) continue;
+    if (h->free_fn) h->free_fn(p[k], b[k], stream, h->alloc_ctx);
+    else default_free(p[k], b[k], nullptr, nullptr);
+  }
+  C->rowptr = C->col = C->val = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+magnus_status_t magnus_spgemm(magnus_handle_t h, const magnus_csr_t* A, const magnus_csr_t* B,
+                              int32_t c_rowptr_type, magnus_csr_out_t* C, void* stream) {
+  if (!h || !C) return MAGNUS_ERR_INVALID_ARG;
+  memset(C, 0, sizeof(*C));
+  if (c_rowptr_type != MAGNUS_I32 && c_rowptr_type != MAGNUS_I64) return MAGNUS_ERR_INVALID_ARG;
+  magnus_plan_t P = nullptr;
+  magnus_status_t s = magnus_plan(h, A, B, stream, &P, nullptr);
+  if (s != MAGNUS_OK) return s;
+  const int64_t nnz = P->nnz_c;
+  if (c_rowptr_type == MAGNUS_I32 && nnz > INT32_MAX) {
+    magnus_plan_destroy(P);
+    return MAGNUS_ERR_INDEX_OVERFLOW;
+  }
+  magnus_csr_out_t c{};
+  c.nrows = A->nrows;
+  c.ncols = B->ncols;
+  c.capacity = nnz;
+  c.rowptr_type = c_rowptr_type;
+  c.col_type = B->col_type;
+  c.val_type = A->val_type;
+  size_t b[3];
+  csr_out_bytes(&c, b);
+  void* p[3] = {nullptr, nullptr, nullptr};
+  for (int k = 0; k < 3; ++k) {
+    p[k] = h->alloc_fn ? h->alloc_fn(b[k], stream, h->alloc_ctx) : default_alloc(b[k], nullptr, nullptr);
+    if (!p[k]) break;
+  }
+  c.rowptr = p[0];
+  c.col = p[1];
+  c.val = p[2];
+  if (!p[0] || !p[1] || !p[2]) {
+    csr_out_release(h, &c, stream);
+    magnus_plan_destroy(P);
+    h->err = "the allocator returned no memory for C";
+    return MAGNUS_ERR_OOM;
+  }
+  int64_t got = 0;
+  s = magnus_execute(h, P, A, B, &c, &got, stream);
+  // the plan's memory goes back to the allocator in stream order (or after
+  // the device finishes, with the default hipFree)
+  magnus_plan_destroy(P);
+  if (s != MAGNUS_OK) {
+    csr_out_release(h, &c, stream);
+    return s;
+  }
+  *C = c;
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_csr_free(magnus_handle_t h, magnus_csr_out_t* C, void* stream) {
+  if (!h || !C) return MAGNUS_ERR_INVALID_ARG;
+  csr_out_release(h, C, stream);
+  C->capacity = 0;
   return MAGNUS_OK;
 }
 
@@ -1157,7 +1460,7 @@ magnus_status_t magnus_profile_read(magnus_handle_t h, magnus_kernel_stat_t* out
     (void)hipEventDestroy(rec.b);
     magnus_kernel_stat_t* s = nullptr;
     for (auto& x : agg)
-      if (strncmp(x.name, rec.name, sizeof(x.name)) == 0) s = &x;
+      if (strncmp(x.name, rec.name, sizeof(x.name) - 1) == 0) s = &x;
     if (!s) {
       magnus_kernel_stat_t z{};
       strncpy(z.name, rec.name, sizeof(z.name) - 1);

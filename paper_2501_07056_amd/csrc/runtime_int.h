@@ -129,6 +129,20 @@ struct magnus_plan_s {
   int persistent_wgs = 512;
   int hints = 0;
   int64_t sort_max = 1025, dense_min = 1024, group_max = 1024;
+  // workspace divisor of this attempt (an allocation failure retries with a
+  // larger one), and whether some row batch came out no wider than its
+  // longest row (then a larger divisor changes nothing)
+  int64_t ws_div = 1;
+  bool w_at_min = false;
+  // CHUNKED rows binned by runs (k_runs.hip): B's chunk index, the runs'
+  // count per chunk and their starts, and per run its B position, A entry
+  // and product offset
+  bool runs = false;
+  int64_t n_runs = 0;
+  int64_t *bci_ptr = nullptr, *bin_seg = nullptr, *seg_beg = nullptr, *seg_off = nullptr;
+  int64_t* run_rec = nullptr;  // 6 int64 per dense item
+  uint32_t *bci_pos = nullptr, *bci_chunk = nullptr, *seg_b = nullptr, *seg_a = nullptr;
+  int persistent_wgs_count = 512;  // count-mode accumulator workgroups (bitmap only in LDS)
   // CHUNKED rows
   int64_t nch = 0, max_nb = 1;
   ChunkGeom g{};

@@ -49,6 +49,7 @@ struct SrvReq {
 struct SrvBatch {
   magnus_batch_plan_t bp = nullptr;
   std::vector<SrvReq*> reqs;
+  std::vector<int64_t> ids;  // the requests' ids (a request may be released before its group is reaped)
   int stream = 0;
   int64_t plan_bytes = 0;
   std::atomic<int> done{0};
@@ -178,11 +179,23 @@ struct magnus_server_s {
   bool stop = false;
   std::thread thr;
   magnus_server_stats_t stats{};
+  std::deque<magnus_completion_t> completions;  // final states not yet polled
 };
 
 namespace {
 
 int64_t val_bytes(const magnus_csr_t& X) { return X.val_type == MAGNUS_F64 ? 8 : 4; }
+
+// Queues the final state of r for magnus_server_poll (S->mu held).
+void push_completion(magnus_server_s* S, const SrvReq* r) {
+  magnus_completion_t c{};
+  c.request_id = r->id;
+  c.state = r->state.load();
+  c.status = c.state == MAGNUS_REQ_DONE ? MAGNUS_OK : r->status;
+  c.nnz = c.state == MAGNUS_REQ_DONE ? r->nnz : 0;
+  c.latency_ms = c.state == MAGNUS_REQ_DONE ? 1e3 * (r->t_done.load() - r->t_submit) : -1.0;
+  S->completions.push_back(c);
+}
 int64_t col_bytes(const magnus_csr_t& X) { return X.col_type == MAGNUS_I64 ? 8 : 4; }
 
 int64_t c_bytes(const magnus_csr_t& A, const magnus_csr_t& B, int64_t nnz) {
@@ -201,6 +214,7 @@ void fail_group(magnus_server_s* S, std::vector<SrvReq*>& g, int sidx, magnus_st
     r->status = st;
     r->state.store(MAGNUS_REQ_FAILED);
     S->stats.failed++;
+    push_completion(S, r);
   }
   S->running -= (int)g.size();
   if (sidx >= 0) S->stream_busy[sidx] = 0;
@@ -223,6 +237,7 @@ void compute_bounds(magnus_server_s* S, std::vector<SrvReq*>& need) {
       r->status = s;
       r->state.store(MAGNUS_REQ_FAILED);
       S->stats.failed++;
+      push_completion(S, r);
       continue;
     }
     const int64_t vs = val_bytes(A[i]);
@@ -255,6 +270,7 @@ void probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
     r->state.store(s != MAGNUS_OK ? MAGNUS_REQ_FAILED : MAGNUS_REQ_REJECTED);
     if (s != MAGNUS_OK) S->stats.failed++;
     else S->stats.rejected++;
+    push_completion(S, r);
     for (auto it = S->pending.begin(); it != S->pending.end(); ++it)
       if (*it == r) {
         S->pending.erase(it);
@@ -356,6 +372,7 @@ void launch_group(magnus_server_s* S, std::vector<SrvReq*> g, int sidx) {
   auto B_ = std::make_unique<SrvBatch>();
   B_->bp = bp;
   B_->reqs = g;
+  for (SrvReq* r : g) B_->ids.push_back(r->id);
   B_->stream = sidx;
   B_->plan_bytes = plan_bytes;
   SrvBatch* raw = B_.get();
@@ -393,6 +410,10 @@ void sched_loop(magnus_server_s* S) {
         S->running -= (int)B->reqs.size();
         S->reserved -= B->plan_bytes;
         S->stats.completed += (int64_t)B->reqs.size();
+        for (int64_t id : B->ids) {
+          auto f = S->reqs.find(id);
+          if (f != S->reqs.end()) push_completion(S, f->second.get());
+        }
       }
       if (S->stop && S->pending.empty() && S->inflight.empty()) break;
     }
@@ -667,9 +688,27 @@ magnus_status_t magnus_server_release(magnus_server_t S, int64_t request_id) {
     r->mem = nullptr;
     S->reserved -= r->held;
     r->held = 0;
+    for (auto c = S->completions.begin(); c != S->completions.end(); ++c)
+      if (c->request_id == request_id) {
+        S->completions.erase(c);
+        break;
+      }
     S->reqs.erase(it);
   }
   S->cv.notify_one();
+  return MAGNUS_OK;
+}
+
+magnus_status_t magnus_server_poll(magnus_server_t S, magnus_completion_t* out, int32_t max,
+                                   int32_t* n) {
+  if (!S || !n || max < 0 || (max > 0 && !out)) return MAGNUS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  int32_t k = 0;
+  while (k < max && !S->completions.empty()) {
+    out[k++] = S->completions.front();
+    S->completions.pop_front();
+  }
+  *n = k;
   return MAGNUS_OK;
 }
 

@@ -59,10 +59,10 @@ def test_rmat_auto_small_chunks(ctx):
     A, _ = wl.config2(12)
     log("rmat12 shift=8 tile=512")
     rp, col, val, info = gpu_product(ctx, A, A, force_category="chunked", chunk_shift=8,
-                                     tile_products=512, batch_products=200000)
-    assert info["n_batches"] > 1
+                                     tile_products=512, batch_products=200000, chunk_runs=-1)
+    assert info["n_batches"] > 1 and info["run_binned"] == 0
     compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
-    ctx.set_options(chunk_shift=0, tile_products=0, batch_products=0)
+    ctx.set_options(chunk_shift=0, tile_products=0, batch_products=0, chunk_runs=0)
 
 
 def test_rmat_table_symbolic(ctx):
@@ -74,10 +74,11 @@ def test_rmat_table_symbolic(ctx):
     for shift in (8, 10):
         rp, col, val, info = gpu_product(ctx, A, A, force_category="chunked", chunk_shift=shift,
                                          tile_products=1024, lds_bytes=16384,
-                                         batch_products=300000)
+                                         batch_products=300000, chunk_runs=-1)
+        assert info["run_binned"] == 0
         compare(rp, col, val, oracle.spgemm(A, A), np.float64, exact=False)
     ctx.set_options(chunk_shift=0, tile_products=0, batch_products=0, lds_bytes=0,
-                    force_category="auto")
+                    force_category="auto", chunk_runs=0)
 
 
 @pytest.mark.parametrize("vt", [np.float64, np.float32])

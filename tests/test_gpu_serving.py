@@ -186,3 +186,64 @@ def test_serving_errors():
             srv.release(12345)
     finally:
         srv.close()
+
+
+def test_serving_arrivals_during_a_running_group_and_poll():
+    """Random f64 values: requests submitted while an earlier group is still
+    on the device are admitted and overlapped; each result equals the same
+    product computed alone within N5 (rtol * sum|a_ik b_kj| from the oracle),
+    and magnus_server_poll reports every request exactly once."""
+    import torch
+
+    import paper_2501_07056_amd as mg
+    ops = _operands("uniform")
+    ops.append(wl.rmat(15, wl.seed(315), val_kind="uniform", val_dtype=np.float64,
+                       rowptr_dtype=np.int32, col_dtype=np.int32))
+    big = len(ops) - 1
+    dev = [mg.DeviceCSR.from_host(X) for X in ops]
+    srv = mg.Server(0, max_batch=3, streams=2)
+    ctx = mg.Context(0)
+    try:
+        for X in dev:
+            srv.register(X)
+        first = srv.submit(big, big)
+        t0 = time.time()
+        while srv.query(first)["state"] == "queued":
+            assert time.time() - t0 < 60
+            time.sleep(0.0002)
+        during = srv.query(first)["state"] == "running"
+        pairs = [(big, big)] + [(i % big, i % big) for i in range(12)]
+        rids = [first]
+        for a, b in pairs[1:]:
+            rids.append(srv.submit(a, b))
+            time.sleep(0.0005)
+        log(f"arrivals while the first group runs: {during}")
+        seen = {}
+        t0 = time.time()
+        while len(seen) < len(rids):
+            for c in srv.poll(8):
+                assert c["request_id"] not in seen, "request reported twice"
+                seen[c["request_id"]] = c
+            assert time.time() - t0 < 120, f"{len(seen)} of {len(rids)} reported"
+            time.sleep(0.001)
+        assert srv.poll(8) == []
+        for rid, (a, b) in zip(rids, pairs):
+            c = seen[rid]
+            info = srv.query(rid)
+            assert c["state"] == "done" and c["status"] == 0 and c["nnz"] == info["nnz"]
+            assert abs(c["latency_ms"] - info["latency_ms"]) < 1e-6
+            got = _host(srv.result(rid))
+            torch.cuda.synchronize()
+            alone = _host(ctx.spgemm(dev[a], dev[b]))
+            torch.cuda.synchronize()
+            ref = oracle.spgemm(ops[a], ops[b])
+            compare(*got, ref, np.float64, exact=False)
+            assert np.array_equal(got[0], alone[0]) and np.array_equal(got[1], alone[1])
+            assert (np.abs(got[2] - alone[2]) <= 2e-12 * ref.abssum).all(), \
+                f"request {rid}: served and alone differ beyond the tolerance"
+            srv.release(rid)
+        st = srv.stats()
+        assert st["completed"] == len(rids) and st["failed"] == 0 and st["reserved_bytes"] == 0
+    finally:
+        srv.close()
+        ctx.close()

@@ -41,14 +41,16 @@ def test_defaults_are_model_choices():
 
 
 def test_options_layout_matches_the_header():
-    """The deterministic field took one of the reserved words: the struct
-    keeps its size, and the field sits where the header puts it."""
+    """The deterministic and chunk_runs fields took reserved words: the
+    struct keeps its size, and the fields sit where the header puts them."""
     hdr = open(os.path.join(ROOT, "include", "magnus.h")).read()
     body = hdr[hdr.index("typedef struct {\n  int32_t force_category;"):]
     body = body[:body.index("} magnus_options_t;")]
-    assert "int32_t deterministic;" in body and "int32_t _reserved[2];" in body
+    assert "int32_t deterministic;" in body and "int32_t chunk_runs;" in body
+    assert "int32_t _reserved;" in body
     assert ctypes.sizeof(_lib.Options) == 72
     assert _lib.Options.deterministic.offset == _lib.Options.coarse_chunks.offset + 4
+    assert _lib.Options.chunk_runs.offset == _lib.Options.deterministic.offset + 4
 
 
 def test_deterministic_server_rejected_before_any_device_call():
