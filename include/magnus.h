@@ -51,7 +51,7 @@ typedef enum {
   MAGNUS_ERR_INVALID_CSR = 4,    /* only with options.validate */
   MAGNUS_ERR_INDEX_OVERFLOW = 5, /* nnz(C) does not fit C's row pointer type */
   MAGNUS_ERR_CAPACITY = 6,       /* C.capacity < nnz(C); *nnz_out = nnz(C) */
-  MAGNUS_ERR_WORKSPACE = 7,      /* caller workspace too small */
+  MAGNUS_ERR_WORKSPACE = 7,      /* a fixed scratch array too small for the request */
   MAGNUS_ERR_OOM = 8,            /* the allocator returned null */
   MAGNUS_ERR_REJECTED = 9,       /* server: request can never fit */
   MAGNUS_ERR_HIP = 10,           /* a HIP call failed; see magnus_last_error */
@@ -281,6 +281,23 @@ magnus_status_t magnus_stream_copy(magnus_handle_t h, void* dst, const void* src
  * when total is requested. */
 magnus_status_t magnus_exclusive_scan_i64(magnus_handle_t h, const int64_t* in, int64_t* out,
                                           int64_t n, int64_t* total, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * exclusive prefix sum of magnus_exclusive_scan_i64 without any allocation.
+ * Its block partial sums live in a fixed array of the library in device
+ * memory (8.5 MiB on every device the library runs on, held until the process
+ * ends; its address is looked up once per device by magnus_create).
+ *   in, out: device int64[n] (may alias); n <= 2^31, else
+ *     MAGNUS_ERR_WORKSPACE with nothing launched.
+ *   total: DEVICE pointer receiving the sum (may be NULL).
+ * Never synchronises and calls no allocator.  Every call on one device uses
+ * the same array and leaves in it what the last call wrote: calls whose
+ * execution overlaps on one device (other streams, threads or handles) race,
+ * so the caller orders them. */
+magnus_status_t magnus_exclusive_scan_i64_noalloc(magnus_handle_t h, const int64_t* in,
+                                                  int64_t* out, int64_t n, int64_t* total,
+                                                  void* stream);
 
 /* Building blocks on one stream of intermediate products (the reordering
  * and accumulation microbenchmarks of Section 4.1, Figs. 4-6): the n

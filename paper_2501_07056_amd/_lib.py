@@ -145,6 +145,7 @@ def load(path: str = LIB_PATH):
                                              P(c_i64), P(c_i64)]
     lib.magnus_gpu_chunk_shift.argtypes = [c_i32, c_i64, P(c_i32)]
     lib.magnus_exclusive_scan_i64.argtypes = [c_vp, c_vp, c_vp, c_i64, P(c_i64), c_vp]
+    lib.magnus_exclusive_scan_i64_noalloc.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]
     lib.magnus_profile_enable.argtypes = [c_vp, c_i32]
     lib.magnus_profile_read.argtypes = [c_vp, P(KernelStat), c_i32, P(c_i32)]
     lib.magnus_stream_copy.argtypes = [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]

@@ -897,6 +897,16 @@ magnus_status_t magnus_create(magnus_handle_t* out, int device, const magnus_opt
     h->lds_max = v;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
     h->cus = v;
+  {
+    // the allocation-free entry points' scratch: its address on this device
+    void* p = nullptr;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = noalloc_scratch(device, &p);
+    if (e != hipSuccess) {
+      delete h;
+      return MAGNUS_ERR_HIP;
+    }
+  }
   *out = h;
   return MAGNUS_OK;
 }

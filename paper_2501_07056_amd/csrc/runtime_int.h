@@ -99,6 +99,10 @@ inline void* default_alloc(size_t n, void*, void*) {
 }
 inline void default_free(void* p, size_t, void*, void*) { (void)hipFree(p); }
 
+// Device address of this device's fixed scratch array (noalloc.hip), looked
+// up with the device current once per device.
+hipError_t noalloc_scratch(int device, void** out);
+
 inline int bits_for(int64_t range) {
   int b = 1;
   while (b < 62 && ((int64_t)1 << b) < range) ++b;
