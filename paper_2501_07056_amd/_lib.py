@@ -119,6 +119,9 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # an alternative build of the same sources (A/B timing of compile-time
+    # variants) may be named by MAGNUS_LIB
+    path = os.environ.get("MAGNUS_LIB", path)
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
     lib = ctypes.CDLL(path)

@@ -200,6 +200,14 @@ __global__ void __launch_bounds__(RR_BS)
 #ifndef MG_RUN_UNROLL
 #define MG_RUN_UNROLL 8
 #endif
+// dense chunks: runs walked by whole waves (long) or single threads (short)
+// instead of the product-to-run search
+#ifndef MG_RUN_WAVES
+#define MG_RUN_WAVES 0
+#endif
+#ifndef MG_RUN_LONG
+#define MG_RUN_LONG 32
+#endif
 
 // Per dense item, everything its workgroup needs before the first product:
 // product start and count, run start and count, the chunk's first column,
@@ -225,9 +233,14 @@ __global__ void k_run_records(ChunkGeom g, const int64_t* __restrict__ items,
   r[5] = gb;
 }
 
+// runs staged per window: at most 512, so that two 1024-thread workgroups
+// with an f64 accumulator of 2^13 columns fit the LDS of one CU
+constexpr int RUN_WIN = 512;
+
 size_t run_dense_lds(int f64, int shift, int block) {
   const size_t L = (size_t)1 << shift, vs = f64 ? 8 : 4;
-  return L * vs + (L / 32) * 4 + (size_t)block * (4 + 4 + vs) + (size_t)(block / 4 + 2) * 4 + 128;
+  const size_t wr = (size_t)std::min(block, RUN_WIN);
+  return L * vs + (L / 32) * 4 + wr * (4 + 4 + vs) + (size_t)(block / 4 + 2) * 4 + 128;
 }
 
 template <typename CI, typename V, bool NUMERIC>
@@ -237,17 +250,20 @@ __global__ void __launch_bounds__(1024)
                 const uint32_t* __restrict__ seg_a, const V* __restrict__ aval,
                 const CI* __restrict__ bcol, const V* __restrict__ bval, int64_t* bin_nnz,
                 const int64_t* __restrict__ bin_out, void* ccol_, int col64, V* cval,
-                unsigned int* work) {
+                unsigned int* work, uint32_t* chunk_bm) {
+  // count mode stores every item's column bitmap in chunk_bm (L / 32 words
+  // per item); the numeric phase reads it back instead of setting bits
   extern __shared__ __align__(16) unsigned char dsm[];
   constexpr int U = NUMERIC ? MG_RUN_UNROLL : 4;
   const int BS = blockDim.x;
+  const int WR = BS < RUN_WIN ? BS : RUN_WIN;
   const int64_t L = (int64_t)1 << g.shift;
   V* acc = (V*)dsm;
   uint32_t* bits = (uint32_t*)(dsm + (NUMERIC ? L * sizeof(V) : 0));
   V* w_av = (V*)(bits + L / 32);
-  int32_t* w_pre = (int32_t*)(w_av + (NUMERIC ? BS : 0));
-  uint32_t* w_b = (uint32_t*)(w_pre + BS);
-  int32_t* s_grp = (int32_t*)(w_b + BS);  // BS / 4 + 1
+  int32_t* w_pre = (int32_t*)(w_av + (NUMERIC ? WR : 0));
+  uint32_t* w_b = (uint32_t*)(w_pre + WR);
+  int32_t* s_grp = (int32_t*)(w_b + WR);  // BS / 4 + 1
   __shared__ int64_t sh_w[16];
   __shared__ unsigned int sh_item;
   __shared__ int64_t sh_rec[RUN_REC];
@@ -286,16 +302,68 @@ __global__ void __launch_bounds__(1024)
       if (nxt < nitems)
         for (int k = 0; k < RUN_REC; ++k) nr[k] = rec[RUN_REC * (int64_t)nxt + k];
     }
-    for (int64_t sb = sg0; sb < sg1; sb += BS) {
+    for (int64_t sb = sg0; sb < sg1; sb += WR) {
       const int64_t s = sb + t;
-      if (s < sg1) {
+      if (t < WR && s < sg1) {
         w_pre[t] = (int32_t)(seg_off[s] - s0);
         w_b[t] = seg_b[s];
         if (NUMERIC) w_av[t] = aval[seg_a[s]];
       }
-      const int nvalid = (int)((sg1 - sb) < BS ? (sg1 - sb) : BS);
-      const int32_t wend = (sb + BS < sg1) ? (int32_t)(seg_off[sb + BS] - s0) : (int32_t)cnt;
+      const int nvalid = (int)((sg1 - sb) < WR ? (sg1 - sb) : WR);
+      const int32_t wend = (sb + WR < sg1) ? (int32_t)(seg_off[sb + WR] - s0) : (int32_t)cnt;
       __syncthreads();
+#if MG_RUN_WAVES
+      // runs of at least RUN_LONG products: one wave per run, lanes along
+      // the run (coalesced gathers, no search); shorter runs: one thread
+      // per run, walking it
+      for (int i = wv; i < nvalid; i += nw) {
+        const int32_t p0 = w_pre[i];
+        const int32_t len = ((i + 1 < nvalid) ? w_pre[i + 1] : wend) - p0;
+        if (len < MG_RUN_LONG) continue;
+        const uint32_t b0 = w_b[i];
+        const V av = NUMERIC ? w_av[i] : (V)0;
+        for (int32_t j = lane(); j < len; j += 2 * MG_WAVE) {
+          const bool ok1 = j + MG_WAVE < len;
+          const uint32_t c0 = (uint32_t)((int64_t)bcol[b0 + j] - colbase);
+          const uint32_t c1 = ok1 ? (uint32_t)((int64_t)bcol[b0 + j + MG_WAVE] - colbase) : 0u;
+          V v0 = (V)0, v1 = (V)0;
+          if (NUMERIC) {
+            v0 = av * bval[b0 + j];
+            if (ok1) v1 = av * bval[b0 + j + MG_WAVE];
+          }
+          if (NUMERIC) atomicAdd(&acc[c0], v0);
+          else atomicOr(&bits[c0 >> 5], 1u << (c0 & 31));
+          if (ok1) {
+            if (NUMERIC) atomicAdd(&acc[c1], v1);
+            else atomicOr(&bits[c1 >> 5], 1u << (c1 & 31));
+          }
+        }
+      }
+      for (int i = t; i < nvalid; i += BS) {
+        const int32_t p0 = w_pre[i];
+        const int32_t len = ((i + 1 < nvalid) ? w_pre[i + 1] : wend) - p0;
+        if (len >= MG_RUN_LONG) continue;
+        const uint32_t b0 = w_b[i];
+        const V av = NUMERIC ? w_av[i] : (V)0;
+        for (int32_t j = 0; j < len; j += 4) {
+          uint32_t c4[4];
+          V v4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool ok = j + u < len;
+            c4[u] = ok ? (uint32_t)((int64_t)bcol[b0 + j + u] - colbase) : 0u;
+            v4[u] = (NUMERIC && ok) ? av * bval[b0 + j + u] : (V)0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (j + u >= len) continue;
+            if (NUMERIC) atomicAdd(&acc[c4[u]], v4[u]);
+            else atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
+          }
+        }
+      }
+      __syncthreads();
+#else
       const int32_t wstart = w_pre[0];
       for (int32_t q0 = wstart; q0 < wend; q0 += SC) {
         const int32_t q1 = (wend - q0 < SC) ? wend : q0 + SC;
@@ -332,16 +400,18 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
-            atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
             if (NUMERIC) atomicAdd(&acc[c4[u]], v4[u]);
+            else atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
           }
         }
         __syncthreads();
       }
+#endif
     }
     __syncthreads();
+    uint32_t* gbm = chunk_bm + it * nwords;
     int64_t my = 0;
-    for (int64_t w = w0; w < w1; ++w) my += __popc(bits[w]);
+    for (int64_t w = w0; w < w1; ++w) my += __popc(NUMERIC ? gbm[w] : bits[w]);
     const int64_t inc = wave_incl_scan(my);
     if (lane() == MG_WAVE - 1) sh_w[wv] = inc;
     __syncthreads();
@@ -352,14 +422,15 @@ __global__ void __launch_bounds__(1024)
     }
     if (!NUMERIC) {
       if (t == 0) bin_nnz[gb] = total;
-      for (int64_t w = w0; w < w1; ++w) bits[w] = 0u;
+      for (int64_t w = w0; w < w1; ++w) {
+        gbm[w] = bits[w];
+        bits[w] = 0u;
+      }
       continue;
     }
     int64_t pos = bin_out[gb] + before + inc - my;
     for (int64_t w = w0; w < w1; ++w) {
-      uint32_t bb = bits[w];
-      if (!bb) continue;
-      bits[w] = 0u;
+      uint32_t bb = gbm[w];
       while (bb) {
         const int bit = __ffs(bb) - 1;
         bb &= bb - 1;
@@ -642,12 +713,13 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             const int64_t* seg_beg, const int64_t* seg_off, const uint32_t* seg_b,
                             const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
                             void* ccol, int col64, void* cval, int dense_block,
-                            unsigned int* work, int persistent_wgs, hipStream_t st) {
+                            unsigned int* work, int persistent_wgs, uint32_t* chunk_bm,
+                            hipStream_t st) {
   if (nbins <= 0) return hipSuccess;
   // count mode keeps no values in LDS
   const size_t lds = run_dense_lds(M.f64, g.shift, dense_block) -
                      (numeric ? 0 : ((size_t)1 << g.shift) * (M.f64 ? 8 : 4) +
-                                        (size_t)dense_block * (M.f64 ? 8 : 4));
+                                        (size_t)std::min(dense_block, RUN_WIN) * (M.f64 ? 8 : 4));
   const unsigned gd = (unsigned)std::min<int64_t>(nbins, persistent_wgs);
   const int64_t gs_all = (nbins + RS_WAVES - 1) / RS_WAVES;
   const int64_t gcap = max_grid(RS_WAVES * MG_WAVE);
@@ -657,7 +729,7 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
     hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_rec, item_counts, seg_off, seg_b,   \
                        seg_a, (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval, bin_nnz,     \
-                       bin_out, ccol, col64, (V*)cval, work);                                     \
+                       bin_out, ccol, col64, (V*)cval, work, chunk_bm);                           \
     auto ks = numeric ? k_run_sort<CI, V, true> : k_run_sort<CI, V, false>;                       \
     for (int64_t o = 0; o < gs_all; o += gcap)                                                    \
       hipLaunchKernelGGL(ks, (unsigned)std::min(gcap, gs_all - o), RS_WAVES * MG_WAVE, 0, st, g,  \

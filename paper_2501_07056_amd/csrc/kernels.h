@@ -307,7 +307,8 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             const int64_t* seg_beg, const int64_t* seg_off, const uint32_t* seg_b,
                             const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
                             void* ccol, int col64, void* cval, int dense_block,
-                            unsigned int* work, int persistent_wgs, hipStream_t st);
+                            unsigned int* work, int persistent_wgs, uint32_t* chunk_bm,
+                            hipStream_t st);
 
 // --- misc (k_rows.hip) ---
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);

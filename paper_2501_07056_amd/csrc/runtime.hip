@@ -208,6 +208,9 @@ magnus_status_t runs_setup(magnus_plan_s* P, bool& chosen) {
   P->n_runs = runs;
   chosen = true;
   P->runs = true;
+  // packed sorts of up to 1024 products unless set (config 2: 301.6 -> 298.0
+  // ms per step against 512; 256 is slower)
+  if (o.sort_group_max <= 0) P->group_max = SORT_CAP;
   // 512-thread dense workgroups unless set (config 2: 360 -> 324 ms per step
   // against 256; 1024 is slower)
   if (o.dense_block != 256 && o.dense_block != 512 && o.dense_block != 1024) {
@@ -366,6 +369,17 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
                             P->sort_items, P->item_counts, P->st));
     HIPCHK(launch_run_records(P->g, nbins, P->dense_items, P->item_counts, P->bin_start,
                               P->bin_cnt, P->bin_row, P->seg_beg, P->run_rec, P->st));
+    // the dense items' column bitmaps (2^shift bits each), written by the
+    // count pass and read by the numeric one
+    {
+      int32_t ic[2] = {0, 0};
+      magnus_status_t sr = readback(P, {{P->item_counts, 8}}, {ic});
+      if (sr != MAGNUS_OK) return sr;
+      P->n_dense_run = ic[0];
+      P->chunk_bm = (uint32_t*)palloc(
+          P, (size_t)std::max<int64_t>(1, P->n_dense_run) * (((size_t)1 << P->shift) / 8));
+      if (!P->chunk_bm) return MAGNUS_ERR_OOM;
+    }
     unsigned int* wk = P->work_ctr;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
     {
@@ -374,7 +388,8 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
       HIPCHK(launch_run_accum(P->M, P->g, nbins, false, P->bin_start, P->bin_cnt, P->bin_row,
                               P->run_rec, P->sort_items, P->item_counts, P->seg_beg,
                               P->seg_off, P->seg_b, P->seg_a, P->bin_nnz, nullptr, nullptr, 0,
-                              nullptr, P->dense_block, wk, P->persistent_wgs_count, P->st));
+                              nullptr, P->dense_block, wk, P->persistent_wgs_count, P->chunk_bm,
+                              P->st));
     }
     HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false, P->st));
     return MAGNUS_OK;
@@ -444,7 +459,7 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
     HIPCHK(launch_run_accum(P->M, P->g, b.nbins, true, P->bin_start, P->bin_cnt, P->bin_row,
                             P->run_rec, P->sort_items, P->item_counts, P->seg_beg, P->seg_off,
                             P->seg_b, P->seg_a, P->bin_nnz, P->bin_out, ccol, col64, cval,
-                            P->dense_block, wk, P->persistent_wgs, P->st));
+                            P->dense_block, wk, P->persistent_wgs, P->chunk_bm, P->st));
     return MAGNUS_OK;
   }
   for (size_t bi = 0; bi < P->batches.size(); ++bi) {

@@ -145,6 +145,8 @@ struct magnus_plan_s {
   int64_t n_runs = 0;
   int64_t *bci_ptr = nullptr, *bin_seg = nullptr, *seg_beg = nullptr, *seg_off = nullptr;
   int64_t* run_rec = nullptr;  // 6 int64 per dense item
+  uint32_t* chunk_bm = nullptr;  // column bitmap of every dense item
+  int64_t n_dense_run = 0;
   uint32_t *bci_pos = nullptr, *bci_chunk = nullptr, *seg_b = nullptr, *seg_a = nullptr;
   int persistent_wgs_count = 512;  // count-mode accumulator workgroups (bitmap only in LDS)
   // CHUNKED rows
