@@ -437,7 +437,9 @@ def batch_main(args, opts):
     tuned = None
     if not args.no_tune:
         tuned = autotune.tune(ctx, pairs, cache_path=args.tune_cache, log=log)
-        ctx.set_options(dense_block=tuned["dense_block"])
+        ctx.set_options(dense_block=tuned["dense_block"], chunk_shift=tuned["chunk_shift"],
+                        bin_dense_min=tuned["bin_dense_min"],
+                        sort_group_max=tuned["sort_group_max"])
     sort_max = tuned["sort_max"] if tuned else None
 
     def batched_step(graph=True):
@@ -448,13 +450,13 @@ def batch_main(args, opts):
         return outs, info
 
     def per_call_step():
+        # one magnus_spgemm call per product (plan with its readbacks, C from
+        # the allocator, execute), C freed after the step
         outs = []
         for b, (dA, dB) in enumerate(pairs):
             if sort_max is not None:
                 ctx.set_options(sort_max=sort_max[b])
-            p = ctx.plan(dA, dB)
-            outs.append(p.execute(rowptr_dtype=torch.int64))
-            p.destroy()
+            outs.append(ctx.spgemm_lib(dA, dB, rowptr_dtype=torch.int64))
         return outs
 
     def timed(fn, steps, warmup):
@@ -488,6 +490,9 @@ def batch_main(args, opts):
     torch.cuda.synchronize()
     ms_graph, _ = timed(lambda: bp.execute(outs, graph=True), args.steps, 1)
     ms_eager, _ = timed(lambda: bp.execute(outs, graph=False), args.steps, 1)
+    bp.execute(outs, graph=True, persistent=True)
+    torch.cuda.synchronize()
+    ms_graph_p, _ = timed(lambda: bp.execute(outs, graph=True, persistent=True), args.steps, 1)
     plans = []
     for b, (dA, dB) in enumerate(pairs):
         if sort_max is not None:
@@ -503,7 +508,7 @@ def batch_main(args, opts):
     for p in plans:
         p.destroy()
     log(f"[bench] numeric only: graph {ms_graph:.2f} ms, eager {ms_eager:.2f} ms, "
-        f"per-call {ms_pexec:.2f} ms")
+        f"graph with persistent stages {ms_graph_p:.2f} ms, per-call {ms_pexec:.2f} ms")
 
     # sampled parity of the kept batch outputs against the oracle
     rng = np.random.default_rng(11)
@@ -541,6 +546,7 @@ def batch_main(args, opts):
            "per_call": {"ms_per_step": round(ms_p, 3), "GFLOPs": gf(ms_p),
                         "batched_speedup": round(ms_p / ms_b, 3)},
            "numeric_only": {"graph_ms": round(ms_graph, 3), "eager_ms": round(ms_eager, 3),
+                            "graph_persistent_ms": round(ms_graph_p, 3),
                             "per_call_ms": round(ms_pexec, 3), "graph_GFLOPs": gf(ms_graph),
                             "per_call_GFLOPs": gf(ms_pexec)},
            "sample_parity": parity, "src_sha": src_digest()}

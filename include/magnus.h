@@ -359,6 +359,12 @@ magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus
 /* Execution modes of magnus_batch_execute. */
 #define MAGNUS_BATCH_GRAPH 0 /* numeric launches captured once into a HIP graph, then replayed */
 #define MAGNUS_BATCH_EAGER 1 /* the same launches issued one by one */
+/* OR-ed with either mode: each numeric stage (one SORT size class, or the
+ * DENSE rows) runs as one persistent kernel whose waves (SORT) or workgroups
+ * (DENSE) take runs of row tiles from a device counter, instead of one grid
+ * with a wave or workgroup per tile.  Same results; on gfx950 the plain
+ * grids are faster, so this is off unless asked for. */
+#define MAGNUS_BATCH_PERSISTENT 2
 
 /* Numeric phase of every product: writes C[b].rowptr/col/val (host array of
  * `count` output descriptors; C[b].capacity >= nnz_out[b] of the plan).  The

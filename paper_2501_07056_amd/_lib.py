@@ -97,6 +97,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, c_vp, ctypes.c_size_t, c_vp, c_vp)
 
 BATCH_GRAPH = 0
 BATCH_EAGER = 1
+BATCH_PERSISTENT = 2
 
 STATUS = {}
 _lib = None

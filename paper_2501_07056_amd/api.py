@@ -368,7 +368,7 @@ class BatchPlan:
         return outs
 
     def execute(self, outs=None, rowptr_dtype=torch.int64, graph: bool = True, stream=None,
-                pairs=None):
+                pairs=None, persistent: bool = False):
         s, keep = _stream_ptr(stream)
         pairs = self.pairs if pairs is None else pairs
         if outs is None:
@@ -378,6 +378,8 @@ class BatchPlan:
         db = (CsrDesc * n)(*[b.desc() for _, b in pairs])
         dc = (CsrOutDesc * n)(*[_out_desc(C) for C in outs])
         mode = _lib.BATCH_GRAPH if graph else _lib.BATCH_EAGER
+        if persistent:
+            mode |= _lib.BATCH_PERSISTENT
         check(self.ctx.lib.magnus_batch_execute(self.ctx.handle, self.ptr, n, da, db, dc, mode, s),
               "magnus_batch_execute", self.ctx.handle)
         return outs

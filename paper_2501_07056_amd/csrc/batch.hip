@@ -2,9 +2,17 @@
 // after another and each phase of the method (setup and categorisation,
 // Section 3.1; precise symbolic count and prefix sum, Section 2.1; numeric
 // accumulation of SORT and DENSE rows, Algorithms 1 and 2) is one set of
-// launches over the whole batch.  The numeric launches are captured once into
-// a HIP graph and replayed on every execute.  Products with CHUNKED rows
-// (Algorithm 3) are planned and executed on their own.
+// launches over the whole batch.  In the numeric phase every stage (one SORT
+// size class, or the DENSE rows) is one grid over the rows of all products,
+// or, on request, one persistent kernel whose waves or workgroups pull
+// (product, row range) tiles from a device counter.  Products with CHUNKED
+// rows (Algorithm 3) are planned on their own.  The numeric launches of the
+// whole batch, those of the CHUNKED products included, are captured once into
+// a HIP graph whose stages are independent branches (they write disjoint rows
+// of C), so the device overlaps them; replays read a pointer table refreshed
+// before each launch.
+#include <array>
+
 #include "runtime_int.h"
 
 using namespace mgrt;
@@ -29,10 +37,17 @@ struct magnus_batch_plan_s {
   // pinned staging of the pointer table, and the event that frees it
   MatEnt* h_tab = nullptr;
   hipEvent_t tab_ev = nullptr;
-  // captured numeric launches
+  // captured numeric launches: the capture stream, the branch streams and
+  // their events, and the CHUNKED products' buffers the graph was made with
   hipStream_t cap_st = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<hipStream_t> br_st;
+  std::vector<hipEvent_t> br_ev;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<std::array<const void*, 9>> cap_ptrs;
+  bool cap_persistent = false;   // the stage kind the graph was captured with
+  unsigned int* work = nullptr;  // one tile counter per stage
   double numeric_bytes = 0;
 };
 
@@ -45,6 +60,9 @@ void batch_free(magnus_batch_plan_s* P) {
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
   if (P->cap_st) (void)hipStreamDestroy(P->cap_st);
+  for (auto s_ : P->br_st) (void)hipStreamDestroy(s_);
+  for (auto e_ : P->br_ev) (void)hipEventDestroy(e_);
+  if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
   if (P->tab_ev) {
     (void)hipEventSynchronize(P->tab_ev);
     (void)hipEventDestroy(P->tab_ev);
@@ -54,23 +72,80 @@ void batch_free(magnus_batch_plan_s* P) {
   delete P;
 }
 
-// The numeric launches of the batch, in stream order (captured into the graph
-// or issued directly).
-magnus_status_t batch_numeric(magnus_batch_plan_s* P, hipStream_t st) {
+constexpr int NBRANCH = 4;
+
+// The numeric launches of the batch.  Eager: every stage in stream order on
+// st, then the CHUNKED products.  Branched (for the graph): the stages and
+// the CHUNKED products are spread over NBRANCH streams forked from st and
+// joined back into it.  persistent: each stage is a persistent kernel
+// pulling tiles from its counter in P->work (plain grids otherwise).
+magnus_status_t batch_numeric(magnus_batch_plan_s* P, hipStream_t st, bool branched,
+                              bool persistent, int32_t count, const magnus_csr_t* A,
+                              const magnus_csr_t* B, const magnus_csr_out_t* Cout) {
   magnus_plan_s* C = &P->core;
   magnus_handle_s* h = C->h;
+  // the stages' tile counters start at 0 (a kernel, not a memset node)
+  HIPCHK(launch_fill_i64((int64_t*)P->work, (NCLS + 2) / 2, 0, st));
+  std::vector<hipStream_t> used;
+  int next = 0;
+  auto stream_for = [&](hipStream_t& s) -> hipError_t {
+    if (!branched) {
+      s = st;
+      return hipSuccess;
+    }
+    s = P->br_st[next % NBRANCH];
+    if (next < NBRANCH) {
+      hipError_t e = hipStreamWaitEvent(s, P->fork_ev, 0);
+      if (e != hipSuccess) return e;
+      used.push_back(s);
+    }
+    ++next;
+    return hipSuccess;
+  };
+  if (branched) HIPCHK(hipEventRecord(P->fork_ev, st));
   for (int c = 0; c < NSORT_CLS; ++c) {
     const int64_t cnt = C->h_list_off[c + 1] - C->h_list_off[c];
-    if (cnt > 0)
-      HIPCHK(launch_sort_rows(P->T, P->src, c, true, C->list, C->h_list_off[c], cnt, C->minc,
-                              C->colbits, C->crp, C->crp, C->stats, st));
+    if (cnt <= 0) continue;
+    hipStream_t s = nullptr;
+    HIPCHK(stream_for(s));
+    HIPCHK(launch_sort_rows(P->T, P->src, c, true, C->list, C->h_list_off[c], cnt, C->minc,
+                            C->colbits, C->crp, C->crp, C->stats, s,
+                            persistent ? P->work + c : nullptr));
   }
   const int64_t nd = C->h_list_off[CLS_DENSE + 1] - C->h_list_off[CLS_DENSE];
-  if (nd > 0)
+  if (nd > 0) {
+    hipStream_t s = nullptr;
+    HIPCHK(stream_for(s));
     HIPCHK(launch_dense_rows(P->T, P->src, true, C->list, C->h_list_off[CLS_DENSE], nd, C->minc,
-                             C->maxc, C->dense_shift, C->dense_block, C->crp, C->crp, st));
+                             C->maxc, C->dense_shift, C->dense_block, C->crp, C->crp, s,
+                             persistent ? P->work + CLS_DENSE : nullptr));
+  }
+  for (int32_t b = 0; b < count; ++b) {
+    if (!P->alone[b]) continue;
+    hipStream_t s = nullptr;
+    HIPCHK(stream_for(s));
+    int64_t nz = 0;
+    magnus_status_t r = magnus_execute(h, P->alone[b], &A[b], &B[b], &Cout[b], &nz, s);
+    if (r != MAGNUS_OK) return r;
+  }
+  for (size_t k = 0; k < used.size(); ++k) {
+    HIPCHK(hipEventRecord(P->br_ev[k], used[k]));
+    HIPCHK(hipStreamWaitEvent(st, P->br_ev[k], 0));
+  }
   HIPCHK(launch_write_rowptr_batch(P->src, C->crp, P->N, P->nmat, P->flags, st));
   return MAGNUS_OK;
+}
+
+// The buffers of the CHUNKED products (their launches take them directly).
+std::vector<std::array<const void*, 9>> alone_ptrs(const magnus_batch_plan_s* P, int32_t count,
+                                                   const magnus_csr_t* A, const magnus_csr_t* B,
+                                                   const magnus_csr_out_t* Cout) {
+  std::vector<std::array<const void*, 9>> v;
+  for (int32_t b = 0; b < count; ++b)
+    if (P->alone[b])
+      v.push_back({A[b].rowptr, A[b].col, A[b].val, B[b].rowptr, B[b].col, B[b].val,
+                   Cout[b].rowptr, Cout[b].col, Cout[b].val});
+  return v;
 }
 
 }  // namespace
@@ -186,6 +261,7 @@ magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus
   P->mat_of_row = (int32_t*)palloc(C, sizeof(int32_t) * n1);
   P->flags = (int32_t*)palloc(C, sizeof(int32_t) * count);
   P->mat_off = (int64_t*)palloc(C, sizeof(int64_t) * (count + 1));
+  P->work = (unsigned int*)palloc(C, sizeof(unsigned int) * (NCLS + 2));
   C->stats = (DevStats*)palloc(C, sizeof(DevStats));
   C->ip = (int64_t*)palloc(C, sizeof(int64_t) * n1);
   C->minc = (int64_t*)palloc(C, sizeof(int64_t) * n1);
@@ -196,7 +272,7 @@ magnus_status_t magnus_batch_plan(magnus_handle_t h, int32_t count, const magnus
   C->list_off = (int64_t*)palloc(C, sizeof(int64_t) * (NCLS + 1));
   C->temp = palloc(C, std::max(classify_temp_bytes(N), scan_temp_bytes(N + 1)) + 1024);
   if (!P->d_tab || !P->d_row0 || !P->d_row0_i32 || !P->mat_of_row || !P->flags || !P->mat_off ||
-      !C->stats || !C->ip || !C->minc || !C->maxc || !C->crp || !C->cls || !C->list ||
+      !P->work || !C->stats || !C->ip || !C->minc || !C->maxc || !C->crp || !C->cls || !C->list ||
       !C->list_off || !C->temp)
     return cleanup(MAGNUS_ERR_OOM);
   P->src.one = P->h_tab[0];
@@ -341,6 +417,8 @@ magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t P, i
                                      const magnus_csr_t* A, const magnus_csr_t* B,
                                      const magnus_csr_out_t* Cout, int32_t mode, void* stream) {
   if (!h || !P || !A || !B || !Cout || count != P->nmat) return MAGNUS_ERR_INVALID_ARG;
+  const bool persistent = (mode & MAGNUS_BATCH_PERSISTENT) != 0;
+  mode &= ~MAGNUS_BATCH_PERSISTENT;
   if (mode != MAGNUS_BATCH_GRAPH && mode != MAGNUS_BATCH_EAGER) return MAGNUS_ERR_INVALID_ARG;
   magnus_plan_s* C = &P->core;
   // every descriptor is checked before anything is launched
@@ -383,17 +461,42 @@ magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t P, i
     ProfScope ps(h, st, mode == MAGNUS_BATCH_GRAPH ? "batch execute (graph)" : "batch execute",
                  P->numeric_bytes);
     if (mode == MAGNUS_BATCH_EAGER) {
-      magnus_status_t r = batch_numeric(P, st);
+      magnus_status_t r = batch_numeric(P, st, false, persistent, count, A, B, Cout);
       if (r != MAGNUS_OK) return r;
     } else {
+      // the CHUNKED products' launches hold their buffers: a call with other
+      // buffers for them, or with the other stage kind, captures the graph
+      // again
+      const auto ptrs = alone_ptrs(P, count, A, B, Cout);
+      if (P->exec && (ptrs != P->cap_ptrs || persistent != P->cap_persistent)) {
+        (void)hipGraphExecDestroy(P->exec);
+        (void)hipGraphDestroy(P->graph);
+        P->exec = nullptr;
+        P->graph = nullptr;
+      }
       if (!P->exec) {
         // capture on a private stream: nothing runs while capturing, and the
         // caller's stream may be the null stream, which cannot be captured
         if (!P->cap_st) HIPCHK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
+        if (P->br_st.empty()) {
+          for (int k = 0; k < NBRANCH; ++k) {
+            hipStream_t bs = nullptr;
+            hipEvent_t be = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+            P->br_st.push_back(bs);
+            HIPCHK(hipEventCreateWithFlags(&be, hipEventDisableTiming));
+            P->br_ev.push_back(be);
+          }
+          HIPCHK(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+        }
+        // no profiling events inside the captured launches
+        const bool prof = h->prof;
+        h->prof = false;
         HIPCHK(hipStreamBeginCapture(P->cap_st, hipStreamCaptureModeRelaxed));
-        magnus_status_t r = batch_numeric(P, P->cap_st);
+        magnus_status_t r = batch_numeric(P, P->cap_st, true, persistent, count, A, B, Cout);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(P->cap_st, &g);
+        h->prof = prof;
         if (r != MAGNUS_OK) {
           if (g) (void)hipGraphDestroy(g);
           return r;
@@ -401,15 +504,11 @@ magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t P, i
         if (e != hipSuccess) return fail_hip(h, e, "hipStreamEndCapture");
         P->graph = g;
         HIPCHK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+        P->cap_ptrs = ptrs;
+        P->cap_persistent = persistent;
       }
       HIPCHK(hipGraphLaunch(P->exec, st));
     }
-  }
-  for (int32_t b = 0; b < count; ++b) {
-    if (!P->alone[b]) continue;
-    int64_t nz = 0;
-    magnus_status_t r = magnus_execute(h, P->alone[b], &A[b], &B[b], &Cout[b], &nz, stream);
-    if (r != MAGNUS_OK) return r;
   }
   (void)C;
   return MAGNUS_OK;

@@ -370,10 +370,10 @@ MG_INLINE int64_t block_excl_scan64(int64_t v, int64_t* sh_w, int64_t& total) {
 }
 
 template <typename RP, typename CI, typename V, bool NUMERIC>
-__global__ void __launch_bounds__(1024)
-    k_dense_rows(RowSrc src, const int32_t* __restrict__ list, const int64_t* __restrict__ minc,
-                 const int64_t* __restrict__ maxc, int shift, int64_t* rownnz,
-                 const int64_t* __restrict__ crp) {
+MG_INLINE void dense_row(const RowSrc& src, const int32_t* __restrict__ list,
+                         const int64_t* __restrict__ minc, const int64_t* __restrict__ maxc,
+                         int shift, int64_t* rownnz, const int64_t* __restrict__ crp,
+                         int64_t idx) {
   extern __shared__ __align__(16) unsigned char dsm[];
   const int BS = blockDim.x;
   const int64_t L = (int64_t)1 << shift;
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(1024)
   __shared__ int64_t sh_w[16];
 
   const int t = threadIdx.x;
-  const int32_t row = list[blockIdx.x];
+  const int32_t row = list[idx];
   const MatEnt& M = src.tab ? src.tab[src.mat_of_row[row]] : src.one;
   const int64_t lrow = row - M.row0;
   const RP* __restrict__ arp = (const RP*)M.arp;
@@ -458,15 +458,58 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
+// One row per workgroup from the grid (work == nullptr), or persistent
+// workgroups taking rows from the counter *work (holding 0) until done.
+template <typename RP, typename CI, typename V, bool NUMERIC>
+__global__ void __launch_bounds__(1024)
+    k_dense_rows(RowSrc src, const int32_t* __restrict__ list, const int64_t* __restrict__ minc,
+                 const int64_t* __restrict__ maxc, int shift, int64_t* rownnz,
+                 const int64_t* __restrict__ crp) {
+  dense_row<RP, CI, V, NUMERIC>(src, list, minc, maxc, shift, rownnz, crp, blockIdx.x);
+}
+
+template <typename RP, typename CI, typename V, bool NUMERIC>
+__global__ void __launch_bounds__(1024)
+    k_dense_rows_persistent(RowSrc src, const int32_t* __restrict__ list,
+                            const int64_t* __restrict__ minc, const int64_t* __restrict__ maxc,
+                            int shift, int64_t* rownnz, const int64_t* __restrict__ crp,
+                            int64_t count, unsigned int* work) {
+  __shared__ unsigned int sh_idx;
+  for (;;) {
+    __syncthreads();  // the previous row's LDS reads are done
+    if (threadIdx.x == 0) sh_idx = atomicAdd(work, 1u);
+    __syncthreads();
+    const int64_t idx = sh_idx;
+    if (idx >= count) return;
+    dense_row<RP, CI, V, NUMERIC>(src, list, minc, maxc, shift, rownnz, crp, idx);
+  }
+}
+
 template <typename RP, typename CI, typename V>
 static hipError_t dense_rows_t(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
                                const int64_t* minc, const int64_t* maxc, int shift, int block,
-                               int64_t* rownnz, const int64_t* crp, hipStream_t st) {
+                               int64_t* rownnz, const int64_t* crp, unsigned int* work,
+                               hipStream_t st) {
   if (count == 0) return hipSuccess;
   const size_t lds = dense_rows_lds(sizeof(V) == 8, shift, block);
-  auto kn = k_dense_rows<RP, CI, V, true>;
-  auto kc = k_dense_rows<RP, CI, V, false>;
-  auto k = numeric ? kn : kc;
+  if (work) {
+    auto kp = numeric ? k_dense_rows_persistent<RP, CI, V, true>
+                      : k_dense_rows_persistent<RP, CI, V, false>;
+    hipError_t e =
+        hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, block, lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = std::min<int64_t>((int64_t)per_cu * std::max(cus, 1), count);
+    hipLaunchKernelGGL(kp, (unsigned)grid, block, lds, st, src, list, minc, maxc, shift, rownnz,
+                       crp, count, work);
+    return hipGetLastError();
+  }
+  auto k = numeric ? k_dense_rows<RP, CI, V, true> : k_dense_rows<RP, CI, V, false>;
   hipError_t e =
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -740,10 +783,10 @@ hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats
 hipError_t launch_dense_rows(const Mats& M, const RowSrc& src, bool numeric, const int32_t* list,
                              int64_t begin, int64_t count, const int64_t* minc,
                              const int64_t* maxc, int shift, int block, int64_t* rownnz,
-                             const int64_t* crp, hipStream_t st) {
+                             const int64_t* crp, hipStream_t st, unsigned int* work) {
   hipError_t e = hipSuccess;
   MG_DISPATCH3(M, e = (dense_rows_t<RP, CI, V>(src, numeric, list + begin, count, minc, maxc,
-                                                shift, block, rownnz, crp, st)));
+                                                shift, block, rownnz, crp, work, st)));
   return e;
 }
 

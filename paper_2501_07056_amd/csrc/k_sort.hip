@@ -30,11 +30,12 @@ RowSrc single_src(const Mats& M, void* ccol, void* cval) {
 hipError_t launch_sort_rows(const Mats& M, const RowSrc& src, int cls, bool numeric,
                             const int32_t* list, int64_t begin, int64_t count, const int64_t* minc,
                             int colbits, int64_t* rownnz, const int64_t* crp, DevStats* stats,
-                            hipStream_t st) {
+                            hipStream_t st, unsigned int* work, int persistent_blocks) {
   if (count <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
   MG_DISPATCH3(M, e = (sort_rows_cls<RP, CI, V>(src, cls, numeric, list + begin, count, minc,
-                                                 colbits, rownnz, crp, stats, st)));
+                                                 colbits, rownnz, crp, stats, work,
+                                                 persistent_blocks, st)));
   return e;
 }
 

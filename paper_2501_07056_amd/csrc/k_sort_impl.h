@@ -26,11 +26,14 @@ constexpr int SR_WAVES = 4;
 template <typename K>
 MG_INLINE K key_max() { return (K)~(K)0; }
 
+// One tile (R consecutive rows of the class list, one wave).
 template <typename RP, typename CI, typename V, int E, typename K, bool NUMERIC>
-__global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
-    k_sort_rows(RowSrc src, const int32_t* __restrict__ list, int64_t count, int R, int colbits,
-                const int64_t* __restrict__ minc, int64_t* rownnz, const int64_t* __restrict__ crp,
-                DevStats* stats) {
+MG_INLINE void sort_rows_tile(RowSrc src, const int32_t* __restrict__ list, int64_t count,
+                              int R, int colbits, const int64_t* __restrict__ minc,
+                              int64_t* rownnz, const int64_t* __restrict__ crp, DevStats* stats,
+                              int tile_in) {
+  // the tile index is wave-uniform: keep it in a scalar register
+  const int64_t tile = __builtin_amdgcn_readfirstlane(tile_in);
   constexpr int CAP = MG_WAVE * E;
   __shared__ K s_key[SR_WAVES][CAP];
   __shared__ V s_val[SR_WAVES][NUMERIC ? CAP : 1];
@@ -53,7 +56,6 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
 
   const int w = threadIdx.x / MG_WAVE;
   const int l = lane();
-  const int64_t tile = (int64_t)blockIdx.x * SR_WAVES + w;
   const int64_t r0 = tile * R;
   if (r0 >= count) return;  // whole wave leaves together
   const int nr = (int)((count - r0) < R ? (count - r0) : R);
@@ -276,11 +278,60 @@ __global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
   }
 }
 
+// One tile per wave from the grid (work == nullptr), or persistent waves that
+// take tiles from the counter *work until the list is done.
+// One tile per wave from the grid (work == nullptr), or persistent waves that
+// take runs of `grab` consecutive tiles from the counter *work (one atomic
+// per run, so the counter is not a point of contention) until the list is
+// done.
+// (Two kernels rather than one with both paths: one inlined copy of the tile
+// per kernel keeps its register count, and so its occupancy.)
+template <typename RP, typename CI, typename V, int E, typename K, bool NUMERIC>
+__global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
+    k_sort_rows(RowSrc src, const int32_t* __restrict__ list, int64_t count, int R, int colbits,
+                const int64_t* __restrict__ minc, int64_t* rownnz, const int64_t* __restrict__ crp,
+                DevStats* stats) {
+  sort_rows_tile<RP, CI, V, E, K, NUMERIC>(src, list, count, R, colbits, minc, rownnz, crp, stats,
+                                           (int)(blockIdx.x * SR_WAVES + threadIdx.x / MG_WAVE));
+}
+
+template <typename RP, typename CI, typename V, int E, typename K, bool NUMERIC>
+__global__ void __launch_bounds__(SR_WAVES * MG_WAVE)
+    k_sort_rows_persistent(RowSrc src, const int32_t* __restrict__ list, int64_t count, int R,
+                           int colbits, const int64_t* __restrict__ minc, int64_t* rownnz,
+                           const int64_t* __restrict__ crp, DevStats* stats, unsigned int* work,
+                           int grab) {
+  const int64_t ntiles = (count + R - 1) / R;
+  for (;;) {
+    unsigned int tt = 0;
+    if (lane() == 0) tt = atomicAdd(work, (unsigned int)grab);
+    const int64_t t0 = (int64_t)__shfl(tt, 0, MG_WAVE);
+    if (t0 >= ntiles) return;  // the whole wave leaves together
+    const int64_t t1 = (t0 + grab < ntiles) ? t0 + grab : ntiles;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+      sort_rows_tile<RP, CI, V, E, K, NUMERIC>(src, list, count, R, colbits, minc, rownnz, crp,
+                                               stats, (int)tile);
+      wave_sync();  // the tile's LDS is read before the next tile writes it
+    }
+  }
+}
+
 template <typename RP, typename CI, typename V, int E, typename K>
 static void sort_rows_launch(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
                              int R, int colbits, const int64_t* minc, int64_t* rownnz,
-                             const int64_t* crp, DevStats* stats, unsigned grid, hipStream_t st) {
+                             const int64_t* crp, DevStats* stats, unsigned grid, unsigned int* work,
+                             int grab, hipStream_t st) {
   if (grid == 0) return;
+  if (work) {
+    if (numeric)
+      hipLaunchKernelGGL((k_sort_rows_persistent<RP, CI, V, E, K, true>), grid, SR_WAVES * MG_WAVE,
+                         0, st, src, list, count, R, colbits, minc, rownnz, crp, stats, work, grab);
+    else
+      hipLaunchKernelGGL((k_sort_rows_persistent<RP, CI, V, E, K, false>), grid,
+                         SR_WAVES * MG_WAVE, 0, st, src, list, count, R, colbits, minc, rownnz,
+                         crp, stats, work, grab);
+    return;
+  }
   if (numeric)
     hipLaunchKernelGGL((k_sort_rows<RP, CI, V, E, K, true>), grid, SR_WAVES * MG_WAVE, 0, st, src,
                        list, count, R, colbits, minc, rownnz, crp, stats);
@@ -292,7 +343,32 @@ static void sort_rows_launch(const RowSrc& src, bool numeric, const int32_t* lis
 template <typename RP, typename CI, typename V, int E, typename K>
 static hipError_t sort_rows_t(const RowSrc& src, bool numeric, const int32_t* list, int64_t count,
                               int R, int colbits, const int64_t* minc, int64_t* rownnz,
-                              const int64_t* crp, DevStats* stats, hipStream_t st) {
+                              const int64_t* crp, DevStats* stats, unsigned int* work,
+                              int persistent_blocks, hipStream_t st) {
+  if (work) {
+    // persistent: as many workgroups as are resident at once (at most
+    // persistent_blocks), each wave pulling tiles; the counter starts at 0
+    int per_cu = 0, dev = 0, cus = 1;
+    auto kf = numeric ? k_sort_rows_persistent<RP, CI, V, E, K, true>
+                      : k_sort_rows_persistent<RP, CI, V, E, K, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, SR_WAVES * MG_WAVE, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t tiles = (count + R - 1) / R;
+    int64_t grid = std::min<int64_t>((int64_t)per_cu * std::max(cus, 1),
+                                     (tiles + SR_WAVES - 1) / SR_WAVES);
+    if (persistent_blocks > 0) grid = std::min<int64_t>(grid, persistent_blocks);
+    grid = std::max<int64_t>(grid, 1);
+    // about 16 grabs per wave, each of consecutive tiles
+    const int64_t grab = std::max<int64_t>(1, std::min<int64_t>(
+        1 << 16, tiles / (grid * SR_WAVES * 16)));
+    sort_rows_launch<RP, CI, V, E, K>(src, numeric, list, count, R, colbits, minc, rownnz, crp,
+                                      stats, (unsigned)grid, work, (int)grab, st);
+    return hipGetLastError();
+  }
   // a wave takes R rows; pieces of at most max_grid blocks of SR_WAVES waves
   const int64_t rows_cap = max_grid(SR_WAVES * MG_WAVE) * SR_WAVES * R;
   for (int64_t o = 0; o < count; o += rows_cap) {
@@ -300,7 +376,7 @@ static hipError_t sort_rows_t(const RowSrc& src, bool numeric, const int32_t* li
     const int64_t tiles = (n + R - 1) / R;
     const unsigned grid = (unsigned)((tiles + SR_WAVES - 1) / SR_WAVES);
     sort_rows_launch<RP, CI, V, E, K>(src, numeric, list + o, n, R, colbits, minc, rownnz, crp,
-                                      stats, grid, st);
+                                      stats, grid, nullptr, 1, st);
   }
   return hipGetLastError();
 }
@@ -309,7 +385,8 @@ static hipError_t sort_rows_t(const RowSrc& src, bool numeric, const int32_t* li
 template <typename RP, typename CI, typename V>
 hipError_t sort_rows_cls(const RowSrc& src, int cls, bool numeric, const int32_t* list,
                          int64_t count, const int64_t* minc, int colbits, int64_t* rownnz,
-                         const int64_t* crp, DevStats* stats, hipStream_t st) {
+                         const int64_t* crp, DevStats* stats, unsigned int* work,
+                         int persistent_blocks, hipStream_t st) {
   // class c holds rows with ip in (2^(c-1), 2^c]: E = max(1, 2^c / 64) per
   // lane, R = 64 * E / 2^c rows per wave
   const int E = (cls <= 6) ? 1 : (1 << (cls - 6));
@@ -325,9 +402,11 @@ hipError_t sort_rows_cls(const RowSrc& src, int cls, bool numeric, const int32_t
   if (E == EE) {                                                                                \
     if (k64)                                                                                    \
       return sort_rows_t<RP, CI, V, EE, uint64_t>(src, numeric, list, count, R, colbits, minc,  \
-                                                  rownnz, crp, stats, st);                      \
+                                                  rownnz, crp, stats, work, persistent_blocks,  \
+                                                  st);                                          \
     return sort_rows_t<RP, CI, V, EE, uint32_t>(src, numeric, list, count, R, colbits, minc,    \
-                                                rownnz, crp, stats, st);                        \
+                                                rownnz, crp, stats, work, persistent_blocks,    \
+                                                st);                                            \
   }
   MG_SR(1) MG_SR(2) MG_SR(4) MG_SR(8) MG_SR(16)
 #undef MG_SR
@@ -337,9 +416,11 @@ hipError_t sort_rows_cls(const RowSrc& src, int cls, bool numeric, const int32_t
 #define MG_SORT_INSTANTIATE(RP, V)                                                              \
   template hipError_t sort_rows_cls<RP, int32_t, V>(const RowSrc&, int, bool, const int32_t*,   \
                                                      int64_t, const int64_t*, int, int64_t*,    \
-                                                     const int64_t*, DevStats*, hipStream_t);   \
+                                                     const int64_t*, DevStats*, unsigned int*,  \
+                                                     int, hipStream_t);                         \
   template hipError_t sort_rows_cls<RP, int64_t, V>(const RowSrc&, int, bool, const int32_t*,   \
                                                      int64_t, const int64_t*, int, int64_t*,    \
-                                                     const int64_t*, DevStats*, hipStream_t);
+                                                     const int64_t*, DevStats*, unsigned int*,  \
+                                                     int, hipStream_t);
 
 }  // namespace mg

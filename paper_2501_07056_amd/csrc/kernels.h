@@ -88,18 +88,21 @@ hipError_t launch_validate(const Mats& M, int64_t a_nnz, int64_t b_nnz, DevStats
 size_t classify_temp_bytes(int64_t n);
 hipError_t launch_classify(const int32_t* cls, int64_t n, int32_t* list, int64_t* list_off,
                            void* temp, hipStream_t st);
-// SORT rows of class c (count mode writes rownnz; numeric writes C).
+// SORT rows of class c (count mode writes rownnz; numeric writes C).  With
+// work (a device counter holding 0), persistent waves pull the tiles, on at
+// most persistent_blocks workgroups (<= 0: as many as are resident).
 hipError_t launch_sort_rows(const Mats& M, const RowSrc& src, int cls, bool numeric,
                             const int32_t* list, int64_t begin, int64_t count, const int64_t* minc,
                             int colbits, int64_t* rownnz, const int64_t* crp, DevStats* stats,
-                            hipStream_t st);
+                            hipStream_t st, unsigned int* work = nullptr,
+                            int persistent_blocks = 0);
 // RowSrc for a single product
 RowSrc single_src(const Mats& M, void* ccol, void* cval);
 // DENSE rows: one workgroup per row, column range <= 2^shift.
 hipError_t launch_dense_rows(const Mats& M, const RowSrc& src, bool numeric, const int32_t* list,
                              int64_t begin, int64_t count, const int64_t* minc,
                              const int64_t* maxc, int shift, int block, int64_t* rownnz,
-                             const int64_t* crp, hipStream_t st);
+                             const int64_t* crp, hipStream_t st, unsigned int* work = nullptr);
 // --- batches of products (rows of all products concatenated) ---
 // mat_of_row[r] = b for row0[b] <= r < row0[b + 1]
 hipError_t launch_mat_of_row(const int64_t* row0, int64_t nmat, int64_t nrows, int32_t* mat_of_row,

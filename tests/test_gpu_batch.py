@@ -206,3 +206,86 @@ def test_batch_errors(ctx):
         _check_all(outs, [(A32, A32), (A32, A32)], np.float32, exact=False)
     finally:
         bp.destroy()
+
+
+def test_batch_chunked_products_in_the_graph(ctx):
+    """Integer values: a batch whose CHUNKED products (wide R-MAT rows, both
+    reorders) run inside the captured graph, on its branches, beside the SORT
+    and DENSE stages.  Replays on the same buffers, then on new ones (the
+    graph is captured again), each equal to the eager launches bit for bit
+    and to the oracle."""
+    import torch
+    R, _ = wl.config2(11)
+    Ri = wl.CSR(R.nrows, R.ncols, R.rowptr, R.col, wl.values(R.nnz, wl.seed(96), "int", np.float64))
+    small = _small_config4(6, lo=64, hi=512, kind="int", vt=np.float64)
+    pairs_host = small[:2] + [(Ri, Ri)] + small[2:4] + [(Ri, Ri)] + small[4:]
+    pairs = _dev(pairs_host)
+    for runs in (1, -1):
+        ctx.set_options(chunk_shift=8, sort_max=65, chunk_runs=runs)
+        try:
+            bp = ctx.batch_plan(pairs)
+            try:
+                eager = [_host(C) for C in bp.execute(graph=False)]
+                torch.cuda.synchronize()
+                _check_all_host(eager, pairs_host, exact=True)
+                outs = bp.alloc_outputs()
+                for rep in range(4):
+                    if rep == 2:
+                        outs = bp.alloc_outputs()  # new buffers: captured again
+                    log(f"chunked in graph runs={runs} replay {rep}")
+                    for C in outs:
+                        C.val.fill_(123.0)
+                    torch.cuda.synchronize()
+                    bp.execute(outs, graph=True)
+                    torch.cuda.synchronize()
+                    for b, C in enumerate(outs):
+                        for x, y in zip(_host(C), eager[b]):
+                            assert np.array_equal(x, y), f"replay {rep} product {b} differs"
+            finally:
+                bp.destroy()
+        finally:
+            ctx.set_options(chunk_shift=0, sort_max=0, chunk_runs=0)
+
+
+def _check_all_host(hosts, pairs_host, exact):
+    for (rp, col, val), (A, B) in zip(hosts, pairs_host):
+        compare(rp, col, val, oracle.spgemm(A, B), np.float64, exact=exact)
+
+
+def test_persistent_stages_match_plain_grids(ctx):
+    """Integer values: each stage as one persistent kernel pulling row tiles
+    from a device counter (eager and graph, the counters cleared by a kernel on
+    every replay) gives the plain grids' results bit for bit.  A small batch
+    is checked against the oracle; a large one (far more SORT tiles than
+    resident waves, so every wave takes several runs of tiles) against the
+    plain grids only."""
+    import torch
+    small = _small_config4(10, lo=64, hi=4096, kind="int", vt=np.float64)
+    big = []
+    for b in range(6):
+        A = wl.erdos_renyi(120000, 120000, 5, wl.seed(1100 + b), val_kind="int",
+                           val_dtype=np.float64, rowptr_dtype=np.int32, col_dtype=np.int32)
+        big.append((A, A))
+    for name, pairs_host in (("small", small), ("large", big)):
+        pairs = _dev(pairs_host)
+        sm = [1025 if b % 3 else 1 for b in range(len(pairs))]  # every third all-DENSE
+        bp = ctx.batch_plan(pairs, sort_max=sm)
+        try:
+            plain = [_host(C) for C in bp.execute(graph=False)]
+            torch.cuda.synchronize()
+            if name == "small":
+                _check_all_host(plain, pairs_host, exact=True)
+            outs = bp.alloc_outputs()
+            for rep, (graph, pers) in enumerate(((False, True), (True, True), (True, True),
+                                                  (True, False), (True, True))):
+                log(f"persistent {name} rep {rep} graph={graph} persistent={pers}")
+                for C in outs:
+                    C.val.fill_(123.0)
+                torch.cuda.synchronize()
+                bp.execute(outs, graph=graph, persistent=pers)
+                torch.cuda.synchronize()
+                for b, C in enumerate(outs):
+                    for x, y in zip(_host(C), plain[b]):
+                        assert np.array_equal(x, y), f"{name} rep {rep} product {b} differs"
+        finally:
+            bp.destroy()
