@@ -34,15 +34,28 @@ constexpr int HINT_WS_STORE = 1, HINT_WS_LOAD = 2, HINT_C_STORE = 4;
 #ifndef MG_NT_MASK
 #define MG_NT_MASK 1
 #endif
+//
+// All of these take pointers into device memory (global address space).  The
+// compiler cannot always see that (a pointer read back from LDS or from a
+// table in memory is a generic one), and then emits flat accesses, which
+// count against the wait counter that LDS accesses share: every wait for an
+// LDS read would also wait for the outstanding gathers.  The casts give the
+// global forms.
+template <typename T>
+using gmem_t = __attribute__((address_space(1))) T;
+template <typename T>
+MG_INLINE T ld_global(const T* p) { return *(const gmem_t<T>*)p; }
+template <typename T>
+MG_INLINE void st_global(T* p, T v) { *(gmem_t<T>*)p = v; }
 template <int CLASS, typename T>
 MG_INLINE void st_stream(T* p, T v) {
-  if constexpr ((MG_NT_MASK & CLASS) != 0) __builtin_nontemporal_store(v, p);
-  else *p = v;
+  if constexpr ((MG_NT_MASK & CLASS) != 0) __builtin_nontemporal_store(v, (gmem_t<T>*)p);
+  else *(gmem_t<T>*)p = v;
 }
 template <int CLASS, typename T>
 MG_INLINE T ld_stream(const T* p) {
-  if constexpr ((MG_NT_MASK & CLASS) != 0) return __builtin_nontemporal_load(p);
-  else return *p;
+  if constexpr ((MG_NT_MASK & CLASS) != 0) return __builtin_nontemporal_load((const gmem_t<T>*)p);
+  else return *(const gmem_t<T>*)p;
 }
 
 // Wave-wide inclusive prefix sum (64 lanes).
@@ -120,6 +133,17 @@ MG_INLINE int upper_index(const T* pre, int lo, int hi, S x) {
     if ((S)pre[mid] <= x) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// The same over exactly 64 nondecreasing entries with pre[0] <= x (entries
+// past the live ones padded with a value above every x): six fixed steps
+// with no branch, so the searches of several products interleave.
+template <typename T, typename S>
+MG_INLINE int upper_index64(const T* pre, S x) {
+  int k = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1) k = ((S)pre[k + step] <= x) ? k + step : k;
+  return k;
 }
 
 // -------------------------------------------------------------------------

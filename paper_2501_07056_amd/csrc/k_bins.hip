@@ -607,7 +607,7 @@ hipError_t launch_det_seg_hist(const Mats& M, const ChunkGeom& g, const int64_t*
   for (int64_t o = 0; o < nsegs; o += cap) {
     MG_DISPATCH2(M, {
       auto kf = k_det_seg_hist<RP, CI>;
-      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       hipLaunchKernelGGL(kf, (unsigned)std::min(cap, nsegs - o), DS_BS, lds, st,
                          (const RP*)M.arp, (const CI*)M.acol, (const RP*)M.brp,
                          (const CI*)M.bcol, g, aoff, tile_e0, seg_row, segBase, tabBase, S, o,
@@ -1583,7 +1583,7 @@ hipError_t launch_bin_hist(const Mats& M, const ChunkGeom& g, const BatchArgs& b
     bp.ntiles = std::min(cap, b.ntiles - o);
     MG_DISPATCH2(M, {
       auto kf = k_bin_hist<RP, CI>;
-      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, (const RP*)M.arp,
                          (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, bp, tile_row,
                          aoff, tile_e0, (unsigned long long*)bin_cnt, bin_row);
@@ -1603,22 +1603,26 @@ hipError_t launch_bin_accum(const ChunkGeom& g, const BatchArgs& b, bool numeric
   det = det && numeric;
   const size_t lds = bin_dense_lds(f64, g.shift);
   const unsigned gd = (unsigned)std::min<int64_t>(b.nbins, persistent_wgs);
-  // sort items: at most one per chunk; the grid is cut below 2^32 work-items
-  const int64_t gs_all = (b.nbins + AS_WAVES - 1) / AS_WAVES;
+  // sort items: one wave each, as many as the host read back, else the bound
+  // of one per chunk (waves past the count leave at once); the grid is cut
+  // below 2^32 work-items
+  const int64_t gs_all = ((b.n_sort >= 0 ? b.n_sort : b.nbins) + AS_WAVES - 1) / AS_WAVES;
   const int64_t gcap = max_grid(AS_WAVES * MG_WAVE);
 #define MG_AC(V)                                                                                  \
   {                                                                                               \
     if (det) {                                                                                    \
       /* one wave per workgroup: as many workgroups as the LDS holds, twice over */             \
       auto kd = k_accum_dense_det<V>;                                                             \
-      hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      (void)hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                                (int)lds);                                                        \
       const unsigned gdd = (unsigned)std::min<int64_t>(b.nbins, (int64_t)persistent_wgs * 8);     \
       hipLaunchKernelGGL(kd, gdd, MG_WAVE, lds, st, g, dense_items, item_counts, b.bin0,          \
                          bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_out, ccol,    \
                          col64, (V*)cval, work);                                                  \
     } else {                                                                                      \
       auto kd = numeric ? k_accum_dense<V, true> : k_accum_dense<V, false>;                       \
-      hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      (void)hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                                (int)lds);                                                        \
       hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_items, item_counts, b.bin0,       \
                          bin_start, bin_cnt, bin_row, ws_col, (const V*)ws_val, bin_nnz, bin_out, \
                          ccol, col64, (V*)cval, work);                                            \
@@ -1649,7 +1653,7 @@ hipError_t launch_bin_scatter_det(const Mats& M, const ChunkGeom& g, const int64
 #define MG_SD(V)                                                                                  \
   MG_DISPATCH2(M, {                                                                               \
     auto kf = k_bin_scatter_det<RP, CI, V>;                                                       \
-    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kf, (unsigned)std::min(cap, nsegs - o), DS_BS, lds, st, (const RP*)M.arp,  \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
                        (const V*)M.bval, g, aoff, tile_e0, seg_row, segBase, tabBase, tabS, S,    \
@@ -1670,7 +1674,7 @@ hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* a
   for (int64_t o = 0; o < g.nch; o += cap) {
     MG_DISPATCH2(M, {
       auto kf = k_row_bitmap<RP, CI>;
-      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       hipLaunchKernelGGL(kf, (unsigned)std::min(cap, g.nch - o), RB_BS, lds, st, (const RP*)M.arp,
                          (const CI*)M.acol, (const RP*)M.brp, (const CI*)M.bcol, g, aoff, bin_nnz,
                          bin_cnt, bin_row, rownnz, o);
@@ -1710,7 +1714,7 @@ hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArg
                                 : k_bin_scatter2<RP, CI, V, LC, true, false>)                      \
                       : (sorted ? k_bin_scatter2<RP, CI, V, LC, false, true>                       \
                                 : k_bin_scatter2<RP, CI, V, LC, false, false>);                    \
-    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
                        (const V*)M.bval, g, bp, tile_row, aoff, tile_e0, bin_start, bin_cursor,   \
@@ -1812,7 +1816,7 @@ hipError_t launch_vrow_bitmap(const ChunkGeom& g2, int cshift, int64_t k0, int64
                               int64_t* vnnz, hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
   const size_t lds = vrow_bitmap_lds(cshift, max_nb2);
-  hipFuncSetAttribute((const void*)k_vrow_bitmap, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_vrow_bitmap, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   const int64_t cap = max_grid(VB_BS);
   for (int64_t o = k0; o < k1; o += cap)
@@ -1832,7 +1836,7 @@ hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool nume
 #define MG_L2(V)                                                                                  \
   {                                                                                               \
     auto kf = numeric ? k_l2_scatter<V, true> : k_l2_scatter<V, false>;                           \
-    hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     for (int64_t o = 0; o < b2.ntiles; o += cap) {                                                \
       BatchArgs bp = b2;                                                                          \
       bp.tile0 = b2.tile0 + o;                                                                    \

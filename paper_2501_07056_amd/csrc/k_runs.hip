@@ -200,14 +200,6 @@ __global__ void __launch_bounds__(RR_BS)
 #ifndef MG_RUN_UNROLL
 #define MG_RUN_UNROLL 8
 #endif
-// dense chunks: runs walked by whole waves (long) or single threads (short)
-// instead of the product-to-run search
-#ifndef MG_RUN_WAVES
-#define MG_RUN_WAVES 0
-#endif
-#ifndef MG_RUN_LONG
-#define MG_RUN_LONG 32
-#endif
 
 // Per dense item, everything its workgroup needs before the first product:
 // product start and count, run start and count, the chunk's first column,
@@ -215,21 +207,38 @@ __global__ void __launch_bounds__(RR_BS)
 // (item -> chunk -> row -> column base) at the start of every chunk.
 constexpr int RUN_REC = 6;
 
+// column chunk index of bin gb, and its key in the XCD order
+MG_INLINE int64_t bin_chunk(const ChunkGeom& g, const int32_t* bin_row, int64_t gb) {
+  const int64_t kk = bin_row[gb];
+  return (g.minc[g.rows[kk]] >> g.shift) + (gb - g.binBase[kk]);
+}
+MG_INLINE int64_t xcd_key(int64_t c, int64_t cpx) { return (c % N_XCD) * cpx + c / N_XCD; }
+
+__global__ void k_dense_key_hist(ChunkGeom g, const int64_t* __restrict__ items,
+                                 const int32_t* item_counts, const int32_t* __restrict__ bin_row,
+                                 int64_t cpx, unsigned long long* cnt) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= item_counts[0]) return;
+  atomicAdd(&cnt[xcd_key(bin_chunk(g, bin_row, items[it]), cpx)], 1ull);
+}
+
 __global__ void k_run_records(ChunkGeom g, const int64_t* __restrict__ items,
                               const int32_t* item_counts, const int64_t* __restrict__ bin_start,
                               const int64_t* __restrict__ bin_cnt,
                               const int32_t* __restrict__ bin_row,
-                              const int64_t* __restrict__ seg_beg, int64_t* rec) {
+                              const int64_t* __restrict__ seg_beg, int64_t cpx,
+                              unsigned long long* cur, int64_t* rec) {
   const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= item_counts[0]) return;
   const int64_t gb = items[it];
-  const int64_t kk = bin_row[gb];
-  int64_t* r = rec + RUN_REC * it;
+  const int64_t c = bin_chunk(g, bin_row, gb);
+  const int64_t pos = (int64_t)atomicAdd(&cur[xcd_key(c, cpx)], 1ull);
+  int64_t* r = rec + RUN_REC * pos;
   r[0] = bin_start[gb];
   r[1] = seg_beg[gb];
   r[2] = bin_cnt[gb];
   r[3] = seg_beg[gb + 1] - seg_beg[gb];
-  r[4] = ((g.minc[g.rows[kk]] >> g.shift) + (gb - g.binBase[kk])) << g.shift;
+  r[4] = c << g.shift;
   r[5] = gb;
 }
 
@@ -250,9 +259,12 @@ __global__ void __launch_bounds__(1024)
                 const uint32_t* __restrict__ seg_a, const V* __restrict__ aval,
                 const CI* __restrict__ bcol, const V* __restrict__ bval, int64_t* bin_nnz,
                 const int64_t* __restrict__ bin_out, void* ccol_, int col64, V* cval,
-                unsigned int* work, uint32_t* chunk_bm) {
+                unsigned int* work, uint32_t* chunk_bm, const int64_t* __restrict__ xcd_start,
+                int64_t cpx) {
   // count mode stores every item's column bitmap in chunk_bm (L / 32 words
-  // per item); the numeric phase reads it back instead of setting bits
+  // per item); the numeric phase reads it back instead of setting bits.
+  // Items (records in XCD order) are taken from this XCD's counter work[x],
+  // then, when it is done, from the others' in turn.
   extern __shared__ __align__(16) unsigned char dsm[];
   constexpr int U = NUMERIC ? MG_RUN_UNROLL : 4;
   const int BS = blockDim.x;
@@ -265,7 +277,7 @@ __global__ void __launch_bounds__(1024)
   uint32_t* w_b = (uint32_t*)(w_pre + WR);
   int32_t* s_grp = (int32_t*)(w_b + WR);  // BS / 4 + 1
   __shared__ int64_t sh_w[16];
-  __shared__ unsigned int sh_item;
+  __shared__ int64_t sh_item;
   __shared__ int64_t sh_rec[RUN_REC];
   const int t = threadIdx.x;
   const int64_t nitems = item_counts[0];
@@ -279,12 +291,26 @@ __global__ void __launch_bounds__(1024)
   const int wv = t / MG_WAVE, nw = BS / MG_WAVE;
   // thread 0 takes the next item and loads its record while the current
   // one is accumulated
-  unsigned int nxt = 0;
+  const int x0 = (int)(blockIdx.x % N_XCD);
+  int xs = 0;  // thread 0: XCD lists tried and found done
+  auto take = [&]() -> int64_t {
+    while (xs < N_XCD) {
+      const int x = (x0 + xs) % N_XCD;
+      const int64_t lo = xcd_start[x * cpx], hi = xcd_start[(x + 1) * cpx];
+      if (lo < hi) {
+        const int64_t i = lo + (int64_t)atomicAdd(&work[x], 1u);
+        if (i < hi) return i;
+      }
+      ++xs;
+    }
+    return nitems;
+  };
+  int64_t nxt = 0;
   int64_t nr[RUN_REC] = {0, 0, 0, 0, 0, 0};
   if (t == 0) {
-    nxt = atomicAdd(work, 1u);
+    nxt = take();
     if (nxt < nitems)
-      for (int k = 0; k < RUN_REC; ++k) nr[k] = rec[RUN_REC * (int64_t)nxt + k];
+      for (int k = 0; k < RUN_REC; ++k) nr[k] = rec[RUN_REC * nxt + k];
   }
   for (;;) {
     __syncthreads();
@@ -298,9 +324,9 @@ __global__ void __launch_bounds__(1024)
     const int64_t s0 = sh_rec[0], sg0 = sh_rec[1], cnt = sh_rec[2];
     const int64_t sg1 = sg0 + sh_rec[3], colbase = sh_rec[4], gb = sh_rec[5];
     if (t == 0) {
-      nxt = atomicAdd(work, 1u);
+      nxt = take();
       if (nxt < nitems)
-        for (int k = 0; k < RUN_REC; ++k) nr[k] = rec[RUN_REC * (int64_t)nxt + k];
+        for (int k = 0; k < RUN_REC; ++k) nr[k] = rec[RUN_REC * nxt + k];
     }
     for (int64_t sb = sg0; sb < sg1; sb += WR) {
       const int64_t s = sb + t;
@@ -312,58 +338,6 @@ __global__ void __launch_bounds__(1024)
       const int nvalid = (int)((sg1 - sb) < WR ? (sg1 - sb) : WR);
       const int32_t wend = (sb + WR < sg1) ? (int32_t)(seg_off[sb + WR] - s0) : (int32_t)cnt;
       __syncthreads();
-#if MG_RUN_WAVES
-      // runs of at least RUN_LONG products: one wave per run, lanes along
-      // the run (coalesced gathers, no search); shorter runs: one thread
-      // per run, walking it
-      for (int i = wv; i < nvalid; i += nw) {
-        const int32_t p0 = w_pre[i];
-        const int32_t len = ((i + 1 < nvalid) ? w_pre[i + 1] : wend) - p0;
-        if (len < MG_RUN_LONG) continue;
-        const uint32_t b0 = w_b[i];
-        const V av = NUMERIC ? w_av[i] : (V)0;
-        for (int32_t j = lane(); j < len; j += 2 * MG_WAVE) {
-          const bool ok1 = j + MG_WAVE < len;
-          const uint32_t c0 = (uint32_t)((int64_t)bcol[b0 + j] - colbase);
-          const uint32_t c1 = ok1 ? (uint32_t)((int64_t)bcol[b0 + j + MG_WAVE] - colbase) : 0u;
-          V v0 = (V)0, v1 = (V)0;
-          if (NUMERIC) {
-            v0 = av * bval[b0 + j];
-            if (ok1) v1 = av * bval[b0 + j + MG_WAVE];
-          }
-          if (NUMERIC) atomicAdd(&acc[c0], v0);
-          else atomicOr(&bits[c0 >> 5], 1u << (c0 & 31));
-          if (ok1) {
-            if (NUMERIC) atomicAdd(&acc[c1], v1);
-            else atomicOr(&bits[c1 >> 5], 1u << (c1 & 31));
-          }
-        }
-      }
-      for (int i = t; i < nvalid; i += BS) {
-        const int32_t p0 = w_pre[i];
-        const int32_t len = ((i + 1 < nvalid) ? w_pre[i + 1] : wend) - p0;
-        if (len >= MG_RUN_LONG) continue;
-        const uint32_t b0 = w_b[i];
-        const V av = NUMERIC ? w_av[i] : (V)0;
-        for (int32_t j = 0; j < len; j += 4) {
-          uint32_t c4[4];
-          V v4[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const bool ok = j + u < len;
-            c4[u] = ok ? (uint32_t)((int64_t)bcol[b0 + j + u] - colbase) : 0u;
-            v4[u] = (NUMERIC && ok) ? av * bval[b0 + j + u] : (V)0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (j + u >= len) continue;
-            if (NUMERIC) atomicAdd(&acc[c4[u]], v4[u]);
-            else atomicOr(&bits[c4[u] >> 5], 1u << (c4[u] & 31));
-          }
-        }
-      }
-      __syncthreads();
-#else
       const int32_t wstart = w_pre[0];
       for (int32_t q0 = wstart; q0 < wend; q0 += SC) {
         const int32_t q1 = (wend - q0 < SC) ? wend : q0 + SC;
@@ -406,7 +380,6 @@ __global__ void __launch_bounds__(1024)
         }
         __syncthreads();
       }
-#endif
     }
     __syncthreads();
     uint32_t* gbm = chunk_bm + it * nwords;
@@ -687,7 +660,8 @@ hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const i
     const unsigned grid = (unsigned)std::min(cap, g.nch - o);
     MG_DISPATCH2(M, {
       auto kf = hist ? k_run_rows<RP, CI, true> : k_run_rows<RP, CI, false>;
-      hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
       hipLaunchKernelGGL(kf, grid, RR_BS, lds, st, (const RP*)M.arp, (const CI*)M.acol, g, bptr,
                          bpos, bchunk, o, bin_seg, bin_cnt, bin_row, seg_beg, bin_start, seg_b,
                          seg_a, seg_off);
@@ -696,13 +670,30 @@ hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const i
   return hipGetLastError();
 }
 
-hipError_t launch_run_records(const ChunkGeom& g, int64_t nbins, const int64_t* dense_items,
+hipError_t launch_dense_order(const ChunkGeom& g, int64_t nitems, const int64_t* dense_items,
+                              const int32_t* item_counts, const int32_t* bin_row, int64_t cpx,
+                              int64_t* xcd_start, int64_t* xcd_cur, void* temp, hipStream_t st) {
+  const int64_t nk = N_XCD * cpx;
+  hipError_t e = launch_fill_i64(xcd_start, nk + 1, 0, st);
+  if (e != hipSuccess) return e;
+  if (nitems > 0)
+    hipLaunchKernelGGL(k_dense_key_hist, (unsigned)((nitems + 255) / 256), 256, 0, st, g,
+                       dense_items, item_counts, bin_row, cpx, (unsigned long long*)xcd_start);
+  e = scan_excl_i64(xcd_start, xcd_start, nk, xcd_start + nk, nullptr, temp, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(xcd_cur, xcd_start, sizeof(int64_t) * (nk + 1), hipMemcpyDeviceToDevice,
+                        st);
+}
+
+hipError_t launch_run_records(const ChunkGeom& g, int64_t nitems, const int64_t* dense_items,
                               const int32_t* item_counts, const int64_t* bin_start,
                               const int64_t* bin_cnt, const int32_t* bin_row,
-                              const int64_t* seg_beg, int64_t* rec, hipStream_t st) {
-  if (nbins <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_run_records, (unsigned)((nbins + 255) / 256), 256, 0, st, g, dense_items,
-                     item_counts, bin_start, bin_cnt, bin_row, seg_beg, rec);
+                              const int64_t* seg_beg, int64_t cpx, int64_t* xcd_cur,
+                              int64_t* rec, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_run_records, (unsigned)((nitems + 255) / 256), 256, 0, st, g, dense_items,
+                     item_counts, bin_start, bin_cnt, bin_row, seg_beg, cpx,
+                     (unsigned long long*)xcd_cur, rec);
   return hipGetLastError();
 }
 
@@ -714,6 +705,7 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
                             void* ccol, int col64, void* cval, int dense_block,
                             unsigned int* work, int persistent_wgs, uint32_t* chunk_bm,
+                            int64_t n_sort_items, const int64_t* xcd_start, int64_t cpx,
                             hipStream_t st) {
   if (nbins <= 0) return hipSuccess;
   // count mode keeps no values in LDS
@@ -721,15 +713,19 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                      (numeric ? 0 : ((size_t)1 << g.shift) * (M.f64 ? 8 : 4) +
                                         (size_t)std::min(dense_block, RUN_WIN) * (M.f64 ? 8 : 4));
   const unsigned gd = (unsigned)std::min<int64_t>(nbins, persistent_wgs);
-  const int64_t gs_all = (nbins + RS_WAVES - 1) / RS_WAVES;
+  // one wave per sort item: the count the host read back (the grid is not
+  // sized by the bins, mostly empty waves), the bins when it is not known
+  const int64_t nsi = n_sort_items >= 0 ? n_sort_items : nbins;
+  const int64_t gs_all = (nsi + RS_WAVES - 1) / RS_WAVES;
   const int64_t gcap = max_grid(RS_WAVES * MG_WAVE);
 #define MG_RA(CI, V)                                                                              \
   {                                                                                               \
     auto kd = numeric ? k_run_dense<CI, V, true> : k_run_dense<CI, V, false>;                     \
-    hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize,        \
+                              (int)lds);                                                          \
     hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_rec, item_counts, seg_off, seg_b,   \
                        seg_a, (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval, bin_nnz,     \
-                       bin_out, ccol, col64, (V*)cval, work, chunk_bm);                           \
+                       bin_out, ccol, col64, (V*)cval, work, chunk_bm, xcd_start, cpx);           \
     auto ks = numeric ? k_run_sort<CI, V, true> : k_run_sort<CI, V, false>;                       \
     for (int64_t o = 0; o < gs_all; o += gcap)                                                    \
       hipLaunchKernelGGL(ks, (unsigned)std::min(gcap, gs_all - o), RS_WAVES * MG_WAVE, 0, st, g,  \

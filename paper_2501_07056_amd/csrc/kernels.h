@@ -162,6 +162,7 @@ struct BatchArgs {
   int64_t bin0, nbins;     // global bin range
   int64_t ip0, nip;        // global product range (batch workspace offset = ip - ip0)
   int64_t nent, nnz_out;   // A entries of the batch's rows; nnz of C they produce
+  int64_t n_sort = -1;     // its sort items, once read back to the host (-1: not known)
 };
 // per-chunk product totals of a batch (bin_cnt zeroed before), and each
 // chunk's row
@@ -294,12 +295,27 @@ hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const i
                            int64_t* bin_seg, int64_t* bin_cnt, int32_t* bin_row,
                            const int64_t* seg_beg, const int64_t* bin_start, uint32_t* seg_b,
                            uint32_t* seg_a, int64_t* seg_off, hipStream_t st);
+// Dense items are dealt to the XCDs by column chunk: chunk index c goes to
+// XCD c % N_XCD, and each XCD's items are ordered by c, so the workgroups of
+// one XCD (ids congruent mod N_XCD: the dispatcher deals workgroups to the
+// XCDs round-robin) work on the same few column chunks at a time and find
+// those chunks' B entries in their L2.  key = (c % N_XCD) * cpx + c / N_XCD
+// with cpx = ceil(column chunks / N_XCD); xcd_start (N_XCD * cpx + 1
+// entries) receives the exclusive scan of the keys' counts, xcd_cur a copy
+// (the records' cursors).  temp: scan_temp_bytes(N_XCD * cpx + 1).
+constexpr int N_XCD = 8;
+// (nitems: a bound on the dense items, the launches' size)
+hipError_t launch_dense_order(const ChunkGeom& g, int64_t nitems, const int64_t* dense_items,
+                              const int32_t* item_counts, const int32_t* bin_row, int64_t cpx,
+                              int64_t* xcd_start, int64_t* xcd_cur, void* temp, hipStream_t st);
 // the dense items' records (6 int64 each: product start, run start,
-// products, runs, first column, chunk), built once after the grouping
-hipError_t launch_run_records(const ChunkGeom& g, int64_t nbins, const int64_t* dense_items,
+// products, runs, first column, chunk), built once after the grouping, each
+// at its place in the XCD order (xcd_cur advanced)
+hipError_t launch_run_records(const ChunkGeom& g, int64_t nitems, const int64_t* dense_items,
                               const int32_t* item_counts, const int64_t* bin_start,
                               const int64_t* bin_cnt, const int32_t* bin_row,
-                              const int64_t* seg_beg, int64_t* rec, hipStream_t st);
+                              const int64_t* seg_beg, int64_t cpx, int64_t* xcd_cur,
+                              int64_t* rec, hipStream_t st);
 // the accumulators over chunks whose products are read through their runs
 // (count mode: bin_nnz; numeric: C at bin_out)
 size_t run_dense_lds(int f64, int shift, int block);
@@ -311,6 +327,7 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
                             void* ccol, int col64, void* cval, int dense_block,
                             unsigned int* work, int persistent_wgs, uint32_t* chunk_bm,
+                            int64_t n_sort_items, const int64_t* xcd_start, int64_t cpx,
                             hipStream_t st);
 
 // --- misc (k_rows.hip) ---

@@ -231,7 +231,13 @@ magnus_status_t runs_setup(magnus_plan_s* P, bool& chosen) {
   const int64_t nbins = tots[2], nch = P->nch;
   P->ws_products = 0;
   P->scan_temp = palloc(P, scan_temp_bytes(nbins + 1));
-  P->work_ctr = (unsigned int*)palloc(P, sizeof(int64_t) * 2);
+  // dense item counters: N_XCD for the count pass, N_XCD for the numeric one
+  P->work_ctr = (unsigned int*)palloc(P, sizeof(unsigned int) * 2 * N_XCD);
+  P->xcd_cpx = ((((P->M.m > 0 ? P->M.m - 1 : 0) >> P->shift) + 1) + N_XCD - 1) / N_XCD;
+  P->xcd_start = (int64_t*)palloc(P, sizeof(int64_t) * (N_XCD * P->xcd_cpx + 1));
+  P->xcd_cur = (int64_t*)palloc(P, sizeof(int64_t) * (N_XCD * P->xcd_cpx + 1));
+  P->xcd_temp = palloc(P, scan_temp_bytes(N_XCD * P->xcd_cpx + 1));
+  if (!P->xcd_start || !P->xcd_cur || !P->xcd_temp) return MAGNUS_ERR_OOM;
   P->bin_start = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
   P->bin_cnt = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
   P->bin_nnz = (int64_t*)palloc(P, sizeof(int64_t) * nbins);
@@ -367,21 +373,26 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
     }
     HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
                             P->sort_items, P->item_counts, P->st));
-    HIPCHK(launch_run_records(P->g, nbins, P->dense_items, P->item_counts, P->bin_start,
-                              P->bin_cnt, P->bin_row, P->seg_beg, P->run_rec, P->st));
-    // the dense items' column bitmaps (2^shift bits each), written by the
-    // count pass and read by the numeric one
+    // the item counts size the launches over the items, and the dense
+    // items' column bitmaps (2^shift bits each), written by the count pass
+    // and read by the numeric one
     {
       int32_t ic[2] = {0, 0};
       magnus_status_t sr = readback(P, {{P->item_counts, 8}}, {ic});
       if (sr != MAGNUS_OK) return sr;
       P->n_dense_run = ic[0];
+      P->n_sort_run = ic[1];
       P->chunk_bm = (uint32_t*)palloc(
           P, (size_t)std::max<int64_t>(1, P->n_dense_run) * (((size_t)1 << P->shift) / 8));
       if (!P->chunk_bm) return MAGNUS_ERR_OOM;
     }
+    HIPCHK(launch_dense_order(P->g, P->n_dense_run, P->dense_items, P->item_counts, P->bin_row,
+                              P->xcd_cpx, P->xcd_start, P->xcd_cur, P->xcd_temp, P->st));
+    HIPCHK(launch_run_records(P->g, P->n_dense_run, P->dense_items, P->item_counts,
+                              P->bin_start, P->bin_cnt, P->bin_row, P->seg_beg, P->xcd_cpx,
+                              P->xcd_cur, P->run_rec, P->st));
     unsigned int* wk = P->work_ctr;
-    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    HIPCHK(launch_fill_i64((int64_t*)wk, N_XCD / 2, 0, P->st));
     {
       ProfScope ps(h, P->st, "run_count (symbolic, chunks from runs)",
                    (double)b.nip * P->s_col + (double)P->n_runs * 16 + (double)nbins * 40);
@@ -389,7 +400,7 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
                               P->run_rec, P->sort_items, P->item_counts, P->seg_beg,
                               P->seg_off, P->seg_b, P->seg_a, P->bin_nnz, nullptr, nullptr, 0,
                               nullptr, P->dense_block, wk, P->persistent_wgs_count, P->chunk_bm,
-                              P->st));
+                              P->n_sort_run, P->xcd_start, P->xcd_cpx, P->st));
     }
     HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, P->crp, nullptr, nullptr, false, P->st));
     return MAGNUS_OK;
@@ -448,8 +459,8 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
     const BatchArgs& b = P->batches[0];
     HIPCHK(launch_bin_rows(P->g, b.k0, b.k1, P->bin_nnz, nullptr, P->crp, P->bin_out, true,
                            P->st));
-    unsigned int* wk = P->work_ctr + 2;
-    HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
+    unsigned int* wk = P->work_ctr + N_XCD;
+    HIPCHK(launch_fill_i64((int64_t*)wk, N_XCD / 2, 0, P->st));
     // per product: B column and value; per run: its record and A value; per
     // output: C written
     ProfScope ps(h, P->st, "run_accum (numeric, chunks from runs)",
@@ -459,7 +470,8 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
     HIPCHK(launch_run_accum(P->M, P->g, b.nbins, true, P->bin_start, P->bin_cnt, P->bin_row,
                             P->run_rec, P->sort_items, P->item_counts, P->seg_beg, P->seg_off,
                             P->seg_b, P->seg_a, P->bin_nnz, P->bin_out, ccol, col64, cval,
-                            P->dense_block, wk, P->persistent_wgs, P->chunk_bm, P->st));
+                            P->dense_block, wk, P->persistent_wgs, P->chunk_bm, P->n_sort_run,
+                            P->xcd_start, P->xcd_cpx, P->st));
     return MAGNUS_OK;
   }
   for (size_t bi = 0; bi < P->batches.size(); ++bi) {
@@ -1235,6 +1247,7 @@ magnus_status_t plan_once(magnus_handle_t h, const magnus_csr_t* A, const magnus
   for (size_t b = 0; b < nbc; ++b) {
     P->co.b1[b].nent = cent[b + 1] - cent[b];
     P->co.b1[b].nnz_out = cnnz[b + 1] - cnnz[b];
+    P->co.cb[b].b2.n_sort = cicounts[2 * b + 1];
     P->info.n_dense_chunks += cicounts[2 * b];
     P->info.n_sort_groups += cicounts[2 * b + 1];
   }
@@ -1243,6 +1256,7 @@ magnus_status_t plan_once(magnus_handle_t h, const magnus_csr_t* A, const magnus
   for (size_t b = 0; b < P->batches.size(); ++b) {
     P->info.n_dense_chunks += icounts[2 * b];
     P->info.n_sort_groups += icounts[2 * b + 1];
+    P->batches[b].n_sort = icounts[2 * b + 1];
   }
   float ms = 0;
   (void)hipEventElapsedTime(&ms, ev0, ev1);

@@ -147,6 +147,11 @@ struct magnus_plan_s {
   int64_t* run_rec = nullptr;  // 6 int64 per dense item
   uint32_t* chunk_bm = nullptr;  // column bitmap of every dense item
   int64_t n_dense_run = 0;
+  int64_t n_sort_run = -1;  // sort items of the runs path (read back; -1: not known)
+  // dense items of the runs path in XCD order (see launch_dense_order)
+  int64_t xcd_cpx = 1;
+  int64_t *xcd_start = nullptr, *xcd_cur = nullptr;
+  void* xcd_temp = nullptr;
   uint32_t *bci_pos = nullptr, *bci_chunk = nullptr, *seg_b = nullptr, *seg_a = nullptr;
   int persistent_wgs_count = 512;  // count-mode accumulator workgroups (bitmap only in LDS)
   // CHUNKED rows

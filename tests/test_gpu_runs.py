@@ -113,9 +113,13 @@ def test_runs_chunk_boundaries_and_thresholds(ctx):
             rng.integers(-4, 5, int(rpB[-1])).astype(np.float64))
     A = CSR(2, 8, np.array([0, 8, 8], np.int64), np.arange(8, dtype=np.int32),
             rng.integers(1, 5, 8).astype(np.float64))
-    info = _runs(ctx, A, B, np.float64, True, chunk_shift=11)
+    # sorted chunks packed up to 512 products: {511, 1}, {2}, {512}, {513},
+    # {1023}, {1}; then the default packing (up to 1024 products)
+    info = _runs(ctx, A, B, np.float64, True, chunk_shift=11, sort_group_max=512)
     assert info["n_dense_chunks"] == 2 and info["n_sort_groups"] == 6
     assert info["n_bins"] == len(counts)
+    info = _runs(ctx, A, B, np.float64, True, chunk_shift=11)
+    assert info["n_dense_chunks"] == 2 and info["n_bins"] == len(counts)
 
 
 def test_runs_edge_cases(ctx):
