@@ -394,15 +394,21 @@ magnus_status_t magnus_batch_bound(magnus_handle_t h, int32_t count, const magnu
  * Serving: products of registered, device-resident operands submitted as
  * requests.  A scheduler thread owned by the server bounds each request's
  * memory from the setup phase's per-row count (magnus_batch_bound: C bytes
- * <= sum_i min(ip_i, columns) * (col + value bytes) + (n + 1) * 8, plus a
- * workspace bound), admits requests in arrival order while the bound fits the
- * unreserved budget and a slot is free (a request that does not fit may be
- * passed by at most max_bypass later ones), runs each admitted group as one
- * batch (magnus_batch_plan / magnus_batch_execute) on its own stream, so that
- * a group is planned while earlier groups execute, and stamps completion from
- * a host function enqueued behind the group.  A request whose bound alone
- * exceeds the budget is planned exactly first and rejected
- * (MAGNUS_ERR_REJECTED) only if its exact size does not fit either.  All
+ * <= sum_i min(ip_i, columns) * (col + value bytes) + (n + 1) * 8, plus an
+ * estimate of its planning memory), admits requests in arrival order while
+ * that reservation fits the unreserved budget and a slot is free (a request
+ * that does not fit may be passed by at most max_bypass later ones), runs
+ * each admitted group as one batch (magnus_batch_plan / magnus_batch_execute)
+ * on its own stream, so that a group is planned while earlier groups
+ * execute, and stamps completion from a host function enqueued behind the
+ * group.  A group's planning may allocate only its requests' planning
+ * estimates (allocations past that fail, and the plan retries with narrower
+ * row batches); a group that still does not fit goes back to the head of the
+ * queue with doubled estimates.  So the plans and results of admitted
+ * requests never hold more than the budget (the stats report the peak).  A
+ * request whose reservation alone exceeds the budget is planned exactly
+ * first, capped at the unreserved budget, and rejected (MAGNUS_ERR_REJECTED)
+ * only if it does not fit that way either with nothing else running.  All
  * operands of a server share value and index types.  The server's calls are
  * thread safe; its results stay valid until released.
  * ---------------------------------------------------------------------- */
@@ -415,6 +421,9 @@ typedef struct {
   int32_t max_batch;           /* requests per group (0: 32) */
   int32_t streams;             /* groups on the device at once (0: 2, at most 8) */
   int32_t max_bypass;          /* see above (0: 8) */
+  int32_t plan_estimate_pct;   /* scale of the planning-memory estimate, percent (0: 100): lower
+                                * admits more requests per group, and more groups are deferred */
+  int32_t _reserved;
 } magnus_server_config_t;
 
 typedef enum {
@@ -441,6 +450,10 @@ typedef struct {
   int64_t submitted, completed, rejected, failed;
   int64_t batches, batched_requests, exact_probes;
   int64_t reserved_bytes, budget_bytes, queued, running;
+  /* the largest reserved_bytes so far (never above budget_bytes), and the
+   * groups put back into the queue because their planning did not fit the
+   * memory reserved for it */
+  int64_t peak_reserved_bytes, deferred;
 } magnus_server_stats_t;
 
 void magnus_server_config_default(magnus_server_config_t* cfg);

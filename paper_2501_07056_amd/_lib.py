@@ -57,7 +57,7 @@ class PlanInfo(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", c_i64), ("workspace_cap_bytes", c_i64),
                 ("max_inflight", c_i32), ("max_batch", c_i32), ("streams", c_i32),
-                ("max_bypass", c_i32)]
+                ("max_bypass", c_i32), ("plan_estimate_pct", c_i32), ("_reserved", c_i32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -69,7 +69,8 @@ class RequestInfo(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, c_i64) for n in ("submitted", "completed", "rejected", "failed", "batches",
                                      "batched_requests", "exact_probes", "reserved_bytes",
-                                     "budget_bytes", "queued", "running")]
+                                     "budget_bytes", "queued", "running",
+                                     "peak_reserved_bytes", "deferred")]
 
 
 class Completion(ctypes.Structure):

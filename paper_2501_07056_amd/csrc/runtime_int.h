@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,6 +55,11 @@ struct magnus_handle_s {
   magnus_free_fn free_fn = nullptr;
   void* alloc_ctx = nullptr;
   std::string err;
+  // device bytes held by this handle's plans, and an optional cap on them: an
+  // allocation past the cap fails like any other (0: no cap).  A serving
+  // loop caps the planning of each group at the memory reserved for it.
+  std::atomic<int64_t> plan_live{0};
+  int64_t plan_cap = 0;
   int lds_max = 65536;
   int cus = 0;
   // pinned host buffers, kept until the handle is destroyed: freeing pinned
@@ -248,9 +254,13 @@ inline magnus_status_t fail_hip(magnus_handle_s* h, hipError_t e, const char* wh
 inline void* palloc(magnus_plan_s* P, size_t bytes) {
   magnus_handle_s* h = P->h;
   bytes = align256(bytes ? bytes : 1);
+  if (h->plan_cap > 0 && h->plan_live.load() + (int64_t)bytes > h->plan_cap) return nullptr;
   void* p = h->alloc_fn ? h->alloc_fn(bytes, (void*)P->st, h->alloc_ctx)
                         : default_alloc(bytes, nullptr, nullptr);
-  if (p) P->allocs.push_back({p, bytes});
+  if (p) {
+    P->allocs.push_back({p, bytes});
+    h->plan_live += (int64_t)bytes;
+  }
   return p;
 }
 
@@ -259,6 +269,7 @@ inline void plan_free_all(magnus_plan_s* P) {
   for (auto& a : P->allocs) {
     if (h && h->free_fn) h->free_fn(a.p, a.n, (void*)P->st, h->alloc_ctx);
     else default_free(a.p, a.n, nullptr, nullptr);
+    if (h) h->plan_live -= (int64_t)a.n;
   }
   P->allocs.clear();
 }

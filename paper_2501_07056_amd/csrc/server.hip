@@ -34,7 +34,9 @@ struct SrvReq {
   std::atomic<int> state{MAGNUS_REQ_QUEUED};
   std::atomic<double> t_done{0.0};
   double t_submit = 0, t_admit = 0;
-  int64_t bound_bytes = -1;  // admission estimate (C bound + workspace bound)
+  int64_t bound_bytes = -1;  // bytes reserved at admission: c_bound + plan_est
+  int64_t c_bound = 0;       // C at the setup phase's nnz bound
+  int64_t plan_est = 0;      // the memory its planning may use (doubled on deferral)
   int64_t held = 0;          // bytes reserved against the budget
   int64_t exact_bytes = 0, nnz = 0;
   int32_t batch_size = 0, skipped = 0;
@@ -44,6 +46,7 @@ struct SrvReq {
   magnus_csr_out_t C{};
   magnus_batch_plan_t pre = nullptr;  // exact plan of an oversized request
   int64_t pre_nnz = 0, pre_plan_bytes = 0;
+  int64_t probe_wait = -1;  // reserved bytes when its exact sizing last had to wait
 };
 
 struct SrvBatch {
@@ -204,6 +207,32 @@ int64_t c_bytes(const magnus_csr_t& A, const magnus_csr_t& B, int64_t nnz) {
 }
 
 // Fail the requests of a group that never reached the device.
+// Adds d to the reserved bytes (S->mu held) and keeps the peak.
+void reserve(magnus_server_s* S, int64_t d) {
+  S->reserved += d;
+  S->stats.peak_reserved_bytes = std::max(S->stats.peak_reserved_bytes, S->reserved);
+}
+
+// A group whose planning did not fit the memory reserved for it goes back to
+// the head of the queue, in order, each request with twice its planning
+// estimate (a request whose bound then exceeds the budget is sized exactly,
+// alone, next).
+void defer_group(magnus_server_s* S, std::vector<SrvReq*>& g, int sidx) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto it = g.rbegin(); it != g.rend(); ++it) {
+    SrvReq* r = *it;
+    S->reserved -= r->held;
+    r->held = 0;
+    r->plan_est *= 2;
+    r->bound_bytes = r->c_bound + r->plan_est;
+    r->state.store(MAGNUS_REQ_QUEUED);
+    S->pending.push_front(r);
+  }
+  S->running -= (int)g.size();
+  S->stats.deferred++;
+  if (sidx >= 0) S->stream_busy[sidx] = 0;
+}
+
 void fail_group(magnus_server_s* S, std::vector<SrvReq*>& g, int sidx, magnus_status_t st) {
   std::lock_guard<std::mutex> lk(S->mu);
   for (SrvReq* r : g) {
@@ -240,10 +269,16 @@ void compute_bounds(magnus_server_s* S, std::vector<SrvReq*>& need) {
       push_completion(S, r);
       continue;
     }
+    // planning memory: per-row arrays, the product workspace (capped) and
+    // per-chunk arrays; enforced while the group plans (plan_cap), and a
+    // group that needs more is put back with twice the estimate
     const int64_t vs = val_bytes(A[i]);
-    const int64_t ws = 192 * (A[i].nrows + 1) +
-                       std::min<int64_t>(S->cfg.workspace_cap_bytes, (2 + vs) * ip[i]) + (1 << 20);
-    r->bound_bytes = c_bytes(A[i], B[i], nb[i]) + ws;
+    r->plan_est = 192 * (A[i].nrows + 1) +
+                  std::min<int64_t>(S->cfg.workspace_cap_bytes, (2 + vs) * ip[i]) +
+                  ip[i] / 64 * 48 + (1 << 20);
+    r->plan_est = std::max<int64_t>(1 << 16, r->plan_est / 100 * S->cfg.plan_estimate_pct);
+    r->c_bound = c_bytes(A[i], B[i], nb[i]);
+    r->bound_bytes = r->c_bound + r->plan_est;
   }
   if (s != MAGNUS_OK) {
     for (auto it = S->pending.begin(); it != S->pending.end();)
@@ -253,38 +288,74 @@ void compute_bounds(magnus_server_s* S, std::vector<SrvReq*>& need) {
 }
 
 // Exact size of a request whose bound alone exceeds the budget: it is
-// planned on its own, and keeps that plan if it fits.
-void probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
+// planned on its own, with its planning capped at the memory not reserved,
+// and keeps that plan if the plan and its exact C fit.  Returns false when it
+// must wait for running groups to release memory.
+bool probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
   const magnus_csr_t& A = S->ops[r->a];
   const magnus_csr_t& B = S->ops[r->b];
+  int64_t room = 0;
+  bool others = false;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    room = S->budget - S->reserved;
+    others = S->reserved > 0;
+    // after a wait, sized again only once running groups released memory
+    const bool blocked = r->probe_wait >= 0 && S->reserved >= r->probe_wait;
+    if ((room <= 0 && others) || blocked) {
+      S->stream_busy[sidx] = 0;
+      r->probe_wait = S->reserved;
+      return false;
+    }
+  }
   magnus_batch_plan_t bp = nullptr;
   int64_t nnz = 0;
   magnus_plan_info_t info{};
-  magnus_status_t s = magnus_batch_plan(S->h, 1, &A, &B, nullptr, S->streams[sidx], &bp, &nnz, &info);
+  magnus_status_t s = MAGNUS_ERR_REJECTED;
+  if (room > 0) {
+    S->h->plan_cap = S->h->plan_live.load() + room;
+    s = magnus_batch_plan(S->h, 1, &A, &B, nullptr, S->streams[sidx], &bp, &nnz, &info);
+    S->h->plan_cap = 0;
+  }
   std::lock_guard<std::mutex> lk(S->mu);
   S->stream_busy[sidx] = 0;
+  if (s == MAGNUS_ERR_OOM && others) {  // again once memory is released
+    r->probe_wait = S->reserved;
+    return false;
+  }
+  if (s == MAGNUS_ERR_OOM) s = MAGNUS_ERR_REJECTED;  // does not fit even alone
   const int64_t total = (s == MAGNUS_OK) ? c_bytes(A, B, nnz) + info.plan_bytes : 0;
-  if (s != MAGNUS_OK || total > S->budget) {
+  if (s == MAGNUS_OK && S->reserved + total > S->budget) {
+    if (others) {  // it may fit once the running groups are done
+      magnus_batch_plan_destroy(bp);
+      r->probe_wait = S->reserved;
+      return false;
+    }
+    s = MAGNUS_ERR_REJECTED;
+  }
+  if (s != MAGNUS_OK) {
     if (bp) magnus_batch_plan_destroy(bp);
-    r->status = s != MAGNUS_OK ? s : MAGNUS_ERR_REJECTED;
-    r->state.store(s != MAGNUS_OK ? MAGNUS_REQ_FAILED : MAGNUS_REQ_REJECTED);
-    if (s != MAGNUS_OK) S->stats.failed++;
-    else S->stats.rejected++;
+    const bool rej = s == MAGNUS_ERR_REJECTED;
+    r->status = s;
+    r->state.store(rej ? MAGNUS_REQ_REJECTED : MAGNUS_REQ_FAILED);
+    if (rej) S->stats.rejected++;
+    else S->stats.failed++;
     push_completion(S, r);
     for (auto it = S->pending.begin(); it != S->pending.end(); ++it)
       if (*it == r) {
         S->pending.erase(it);
         break;
       }
-    return;
+    return true;
   }
   // the plan's memory is held from now on
   r->pre = bp;
   r->pre_nnz = nnz;
   r->pre_plan_bytes = info.plan_bytes;
-  S->reserved += info.plan_bytes;
+  reserve(S, info.plan_bytes);
   r->bound_bytes = c_bytes(A, B, nnz);
   S->stats.exact_probes++;
+  return true;
 }
 
 void launch_group(magnus_server_s* S, std::vector<SrvReq*> g, int sidx) {
@@ -306,9 +377,20 @@ void launch_group(magnus_server_s* S, std::vector<SrvReq*> g, int sidx) {
     nnz[0] = g[0]->pre_nnz;
     plan_bytes = g[0]->pre_plan_bytes;  // reserved when it was planned
   } else {
+    // the planning may use what was reserved for it: its allocations past
+    // that fail (the plan then retries with narrower row batches), and a
+    // group that still does not fit is deferred
+    int64_t allowance = 0;
+    for (SrvReq* r : g) allowance += r->plan_est;
+    S->h->plan_cap = S->h->plan_live.load() + allowance;
     magnus_plan_info_t info{};
     magnus_status_t s =
         magnus_batch_plan(S->h, n, A.data(), B.data(), nullptr, st, &bp, nnz.data(), &info);
+    S->h->plan_cap = 0;
+    if (s == MAGNUS_ERR_OOM) {
+      defer_group(S, g, sidx);
+      return;
+    }
     if (s != MAGNUS_OK) {
       fail_group(S, g, sidx, s);
       return;
@@ -344,18 +426,23 @@ void launch_group(magnus_server_s* S, std::vector<SrvReq*> g, int sidx) {
     O.val = base + a256((size_t)(A[i].nrows + 1) * 8) + a256((size_t)nnz[i] * col_bytes(B[i]));
   }
   {
+    // the requests' reservations become the plan and the exact C at once:
+    // plan_bytes <= the planning allowance and exact <= c_bound, so the
+    // change is never an increase (an exactly sized request's plan was
+    // reserved when it was planned)
     std::lock_guard<std::mutex> lk(S->mu);
-    if (!pre) S->reserved += plan_bytes;
+    int64_t delta = pre ? 0 : plan_bytes;
     for (int i = 0; i < n; ++i) {
       SrvReq* r = g[i];
       const int64_t exact = c_bytes(A[i], B[i], nnz[i]);
-      S->reserved += exact - r->held;
+      delta += exact - r->held;
       r->held = exact;
       r->exact_bytes = exact;
       r->nnz = nnz[i];
       r->batch_size = n;
       r->C = C[i];
     }
+    reserve(S, delta);
   }
   magnus_status_t s =
       magnus_batch_execute(S->h, bp, n, A.data(), B.data(), C.data(), MAGNUS_BATCH_EAGER, st);
@@ -462,7 +549,7 @@ void sched_loop(magnus_server_s* S) {
         for (size_t i : d.admit) {
           SrvReq* r = qr[i];
           r->held = r->bound_bytes;
-          S->reserved += r->bound_bytes;
+          reserve(S, r->bound_bytes);
           r->t_admit = now_s();
           r->state.store(MAGNUS_REQ_RUNNING);
           group.push_back(r);
@@ -486,8 +573,7 @@ void sched_loop(magnus_server_s* S) {
       }
     }
     if (probe) {
-      probe_exact(S, probe, sidx);
-      worked = true;
+      worked = probe_exact(S, probe, sidx);
     } else if (!group.empty()) {
       launch_group(S, group, sidx);
       worked = true;
@@ -516,8 +602,9 @@ magnus_status_t magnus_server_create(int device, const magnus_options_t* opts,
   magnus_server_config_t c{};
   if (cfg) c = *cfg;
   if (c.memory_budget_bytes < 0 || c.workspace_cap_bytes < 0 || c.max_inflight < 0 ||
-      c.max_batch < 0 || c.streams < 0 || c.max_bypass < 0)
+      c.max_batch < 0 || c.streams < 0 || c.max_bypass < 0 || c.plan_estimate_pct < 0)
     return MAGNUS_ERR_INVALID_ARG;
+  if (c.plan_estimate_pct == 0) c.plan_estimate_pct = 100;
   magnus_handle_t h = nullptr;
   magnus_status_t s = magnus_create(&h, device, opts);
   if (s != MAGNUS_OK) return s;

@@ -19,7 +19,11 @@ def _wait(srv, rids, timeout=60.0):
     pending = set(rids)
     while pending:
         pending = {r for r in pending if not srv.ready(r)}
-        assert time.time() - t0 < timeout, f"requests {sorted(pending)[:5]} not finished"
+        if time.time() - t0 >= timeout:
+            log(f"stats at timeout: {srv.stats()}")
+            for r in sorted(pending)[:8]:
+                log(f"request {r}: {srv.query(r)}")
+            raise AssertionError(f"requests {sorted(pending)[:5]} not finished")
         time.sleep(0.001)
 
 
@@ -116,7 +120,9 @@ def test_serving_small_budget_queues_and_random_values():
             time.sleep(0.001)
         st = srv.stats()
         assert st["completed"] == 20 and st["failed"] == 0, st
-        assert peak <= st["budget_bytes"] + (64 << 20)
+        assert peak <= st["budget_bytes"], (peak, st)
+        assert st["peak_reserved_bytes"] <= st["budget_bytes"], st
+        assert st["reserved_bytes"] == 0, st
     finally:
         srv.close()
 
@@ -147,7 +153,8 @@ def test_serving_exact_probe_and_rejection():
         rid = srv.submit(a, b)
         _wait(srv, [rid])
         assert srv.query(rid)["state"] == "done", srv.query(rid)
-        assert srv.stats()["exact_probes"] == 1
+        st = srv.stats()
+        assert st["exact_probes"] == 1 and st["peak_reserved_bytes"] <= st["budget_bytes"], st
         import torch
         C = srv.result(rid)
         torch.cuda.synchronize()
@@ -165,6 +172,67 @@ def test_serving_exact_probe_and_rejection():
             srv.result(rid)
         srv.release(rid)
         assert srv.stats()["rejected"] == 1
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("est_pct", [100, 1])
+def test_serving_tight_budget_with_chunked_requests(est_pct):
+    """Integer values: requests with CHUNKED rows (wide R-MAT rows) under a
+    budget that holds about one of them planned: groups whose planning does
+    not fit are put back and retried (forced with planning estimates at 1 %
+    of the default), every request finishes with the oracle's result, and
+    the reserved memory never exceeds the budget."""
+    import torch
+
+    import paper_2501_07056_amd as mg
+    ops = [wl.rmat(sc, wl.seed(310 + sc), val_kind="int", val_dtype=np.float64,
+                   rowptr_dtype=np.int32, col_dtype=np.int32) for sc in (13, 14)]
+    ops.append(wl.banded(5000, 64, 8, wl.seed(410), val_kind="int", val_dtype=np.float64,
+                         rowptr_dtype=np.int32, col_dtype=np.int32))
+    dev = [mg.DeviceCSR.from_host(X) for X in ops]
+    cap = 1 << 20
+    # the most one request needs alone: its exact plan and C
+    ctx = mg.Context(0, max_workspace_bytes=cap)
+    need = []
+    for d in dev:
+        p = ctx.plan(d, d)
+        need.append(p.info.as_dict()["plan_bytes"] + p.nnz * 12 + (d.nrows + 1) * 8)
+        p.destroy()
+    ctx.close()
+    srv = mg.Server(0, memory_budget_bytes=int(1.3 * max(need)), workspace_cap_bytes=cap,
+                    max_batch=4, streams=2, plan_estimate_pct=est_pct)
+    try:
+        ids = [srv.register(X) for X in dev]
+        pairs = [(i % 3, i % 3) for i in range(12)]
+        log(f"tight budget {srv.stats()['budget_bytes']} for {len(pairs)} requests")
+        refs = {i: oracle.spgemm(ops[i], ops[i]) for i in range(3)}
+        rids = [srv.submit(ids[a], ids[b]) for a, b in pairs]
+        # results hold their memory until released: check and release each
+        # one as it finishes, as a client would
+        done, t0 = set(), time.time()
+        while len(done) < len(rids):
+            for rid, (a, b) in zip(rids, pairs):
+                if rid in done or not srv.ready(rid):
+                    continue
+                info = srv.query(rid)
+                assert info["state"] == "done", info
+                C = srv.result(rid)
+                torch.cuda.synchronize()
+                compare(*_host(C), refs[a], np.float64, exact=True)
+                srv.release(rid)
+                done.add(rid)
+            if time.time() - t0 > 60:
+                log(f"stats at timeout: {srv.stats()}")
+                raise AssertionError(f"{len(rids) - len(done)} requests not finished")
+            time.sleep(0.001)
+        st = srv.stats()
+        log(f"tight budget stats {st}")
+        assert st["completed"] == 12 and st["failed"] == 0 and st["rejected"] == 0, st
+        assert st["peak_reserved_bytes"] <= st["budget_bytes"], st
+        assert st["reserved_bytes"] == 0, st
+        if est_pct == 1:
+            assert st["deferred"] > 0, st
     finally:
         srv.close()
 
