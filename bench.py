@@ -555,148 +555,208 @@ def batch_main(args, opts):
 
 def serve_main(args, opts):
     """Serving: a Poisson stream of C = A*B requests (n log-uniform in
-    [1e3, 1e6]; half R-MAT with scale round(log2 n), half banded with
-    bandwidth 64 and 9 entries per row; f64 values, int32 indices) replayed
-    at a fixed rate against (1) the server (admission by memory bound,
-    batching, overlapped groups) and (2) one call at a time in arrival
-    order.  Latency is arrival to C complete on the device."""
-    import numpy as np
+    [1e3, 1e6]; half R-MAT with scale round(log2 n), the operands of one
+    scale shared, A and B independent; half banded with bandwidth 64 and 9
+    entries per row, each request its own; f64 values, int32 indices).  The
+    serial saturation rate is measured first (all requests back to back, one
+    call at a time); then, at each fraction of it (--qps-fracs), the stream
+    is replayed against (1) the server (admission by memory bound, batching,
+    overlapped groups) and (2) one call at a time in arrival order.  Latency
+    is arrival to C complete on the device.  The first served run checks
+    every scale-20 request and every 8th other one against the oracle on
+    sampled rows."""
     import torch
 
     import oracle
     import paper_2501_07056_amd as mg
     import workloads as wl
 
-    reqs = wl.config5_requests(args.serve_count, args.qps)
+    reqs = wl.config5_requests(args.serve_count, 1.0)  # arrival times at rate 1, scaled per run
     t0 = time.time()
     host = {}
 
-    def operand(kind, n, which, seed_):
-        # R-MAT operands of one scale are shared (A and B differ); banded ones
-        # are the request's own
-        key = (kind, n, which) if kind == "rmat" else (kind, n, which, seed_)
-        if key not in host:
-            host[key] = wl.config5_operand(kind, n, seed_)
+    def operand(r, which):
+        if r.kind == "rmat":
+            sc = int(round(math.log2(r.n)))
+            key = ("rmat", sc, which)
+            if key not in host:
+                host[key] = wl.config5_operand("rmat", r.n, wl.seed(7000 + 2 * sc + (which == "B")))
+        else:
+            key = ("banded", r.rid, which)
+            host[key] = wl.config5_operand("banded", r.n, r.a_seed if which == "A" else r.b_seed)
         return key
 
-    keys = [(operand(r.kind, r.n, "A", r.a_seed), operand(r.kind, r.n, "B", r.b_seed)) for r in reqs]
-    log(f"[bench] {len(reqs)} requests over {reqs[-1].arrival_s:.1f} s, {len(host)} operands "
-        f"generated in {time.time() - t0:.1f} s")
+    keys = [(operand(r, "A"), operand(r, "B")) for r in reqs]
+    log(f"[bench] {len(reqs)} requests, {len(host)} operands generated in {time.time() - t0:.1f} s")
     dev = {k: mg.DeviceCSR.from_host(X) for k, X in host.items()}
     torch.cuda.synchronize()
     ctx = mg.Context(0, **opts)
-    # intermediate products of every request (for the GFLOP/s figures)
     ips = []
     for ka, kb in keys:
         ip, _ = ctx.batch_bound([(dev[ka], dev[kb])])
         ips.append(ip[0])
     total_flop = 2.0 * sum(ips)
-
-    check_ids = [i for i, r in enumerate(reqs) if r.n <= 50000][:6]
+    scale20 = [j for j, r in enumerate(reqs) if r.kind == "rmat" and r.n == 1 << 20]
+    check_ids = set(scale20) | {j for j in range(0, len(reqs), 8)}
 
     def pct(v, q):
         return float(np.percentile(np.array(v), q)) if v else None
 
-    # (1) served
-    srv = mg.Server(0, options=opts, max_batch=args.max_batch, streams=args.streams)
-    ids = {k: srv.register(X) for k, X in dev.items()}
-    lat, qms, bsz, states = {}, {}, {}, {}
-    parity = []
-    outstanding = {}
-    t_start = time.perf_counter()
-    i = 0
-    last_note, last_progress, n_done = 0.0, 0.0, 0
-    while i < len(reqs) or outstanding:
-        now = time.perf_counter() - t_start
-        if now - last_note >= 2.0:
-            log(f"[bench] served t={now:.1f} s: submitted {i}, finished {n_done}, "
-                f"outstanding {len(outstanding)}, reserved {srv.stats()['reserved_bytes'] / 1e9:.1f} GB")
-            last_note = now
-        if outstanding and now - last_progress > 90.0:
-            st = srv.stats()
-            states = {rid: srv.query(rid)["state"] for rid in list(outstanding)[:20]}
-            log(f"[bench] no request finished for 90 s; stats {st}; states {states}")
-            sys.stdout.flush()
-            os._exit(3)
-        while i < len(reqs) and reqs[i].arrival_s <= now:
-            ka, kb = keys[i]
-            outstanding[srv.submit(ids[ka], ids[kb])] = i
-            i += 1
-        for rid in list(outstanding):
-            if not srv.ready(rid):
-                continue
-            j = outstanding.pop(rid)
-            n_done += 1
-            last_progress = time.perf_counter() - t_start
-            info = srv.query(rid)
-            states[j] = info["state"]
-            if info["state"] == "done":
-                lat[j], qms[j], bsz[j] = info["latency_ms"], info["queue_ms"], info["batch_size"]
-                if j in check_ids:
-                    A, B = host[keys[j][0]], host[keys[j][1]]
-                    C = srv.result(rid)
-                    rp, col, val = (x.astype(np.float64) if k == 2 else x.astype(np.int64)
-                                    for k, x in enumerate(C.to_host()))
-                    rows = np.sort(np.random.default_rng(j).choice(A.nrows, min(200, A.nrows),
-                                                                   replace=False)).astype(np.int64)
-                    ref = oracle.spgemm(A, B, rows)
-                    gl = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
-                    ok = bool(np.array_equal(col[gl], ref.col))
-                    err = np.abs(val[gl] - ref.ref) / np.maximum(ref.abssum, 1e-300)
-                    parity.append(ok and bool((err <= 1e-12).all()))
-            srv.release(rid)
-        time.sleep(0.0005)
-    served_s = time.perf_counter() - t_start
-    st = srv.stats()
-    srv.close()
-    torch.cuda.synchronize()
-    log(f"[bench] served: {served_s:.2f} s, p50 {pct(list(lat.values()), 50):.1f} ms, "
-        f"p99 {pct(list(lat.values()), 99):.1f} ms, stats {st}")
-
-    # (2) one call at a time, arrival order
-    lat1 = {}
+    # serial saturation: every request back to back, one call at a time
     t_start = time.perf_counter()
     last_note = 0.0
-    for j, r in enumerate(reqs):
+    for j in range(len(reqs)):
         if time.perf_counter() - t_start - last_note >= 2.0:
             last_note = time.perf_counter() - t_start
-            log(f"[bench] serial t={last_note:.1f} s: request {j}")
-        while time.perf_counter() - t_start < r.arrival_s:
-            time.sleep(0.0002)
+            log(f"[bench] saturation t={last_note:.1f} s: request {j}")
         ka, kb = keys[j]
-        try:
-            C = ctx.spgemm(dev[ka], dev[kb])
-            torch.cuda.synchronize()
-            lat1[j] = 1e3 * (time.perf_counter() - t_start - r.arrival_s)
-            del C
-        except mg.MagnusError as e:
-            log(f"[bench] serial request {j} failed: {e}")
-    serial_s = time.perf_counter() - t_start
-    log(f"[bench] serial: {serial_s:.2f} s, p50 {pct(list(lat1.values()), 50):.1f} ms, "
-        f"p99 {pct(list(lat1.values()), 99):.1f} ms")
+        C = ctx.spgemm(dev[ka], dev[kb])
+        torch.cuda.synchronize()
+        del C
+    sat_s = time.perf_counter() - t_start
+    sat_rate = len(reqs) / sat_s
+    log(f"[bench] serial saturation: {len(reqs)} requests in {sat_s:.2f} s = {sat_rate:.2f} req/s, "
+        f"{total_flop / sat_s / 1e9:.2f} GFLOP/s")
 
-    served_flop = 2.0 * sum(ips[j] for j in lat)
-    out = {"metric": METRIC, "value": round(served_flop / served_s / 1e9, 2), "unit": "GFLOP/s",
-           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * served_s, 1),
+    def sampled_check(j, srv, rid):
+        """Sampled rows of a served C against the oracle (only those rows
+        are copied to the host)."""
+        A, B = host[keys[j][0]], host[keys[j][1]]
+        rows = np.sort(np.random.default_rng(j).choice(A.nrows, min(200, A.nrows),
+                                                       replace=False)).astype(np.int64)
+        rp, col, val = srv.result_rows(rid, rows)
+        rp = rp.astype(np.int64)
+        col = col.astype(np.int64)
+        val = val.astype(np.float64)
+        ref = oracle.spgemm(A, B, rows)
+        ok = bool(np.array_equal(col, ref.col) and
+                  np.array_equal(np.diff(ref.rowptr), rp[rows + 1] - rp[rows]))
+        err = np.abs(val - ref.ref) / np.maximum(ref.abssum, 1e-300)
+        return ok and bool((err <= 1e-12).all())
+
+    def served(qps, check):
+        # the server's budget: most of the memory the cached blocks of the
+        # one-at-a-time runs leave free
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info()
+        srv = mg.Server(0, options=opts, max_batch=args.max_batch, streams=args.streams,
+                        memory_budget_bytes=int(0.9 * free))
+        ids = {k: srv.register(X) for k, X in dev.items()}
+        lat, qms, bsz, states, parity = {}, {}, {}, {}, {}
+        outstanding = {}
+        t_start = time.perf_counter()
+        i = 0
+        last_note, last_progress, n_done = 0.0, 0.0, 0
+        while i < len(reqs) or outstanding:
+            now = time.perf_counter() - t_start
+            if now - last_note >= 2.0:
+                log(f"[bench] served {qps:.1f}/s t={now:.1f} s: submitted {i}, finished {n_done}, "
+                    f"outstanding {len(outstanding)}, reserved "
+                    f"{srv.stats()['reserved_bytes'] / 1e9:.1f} GB")
+                last_note = now
+            if outstanding and now - last_progress > 90.0:
+                st = srv.stats()
+                states = {rid: srv.query(rid)["state"] for rid in list(outstanding)[:20]}
+                log(f"[bench] no request finished for 90 s; stats {st}; states {states}")
+                sys.stdout.flush()
+                os._exit(3)
+            while i < len(reqs) and reqs[i].arrival_s / qps <= now:
+                ka, kb = keys[i]
+                outstanding[srv.submit(ids[ka], ids[kb])] = i
+                i += 1
+            for rid in list(outstanding):
+                if not srv.ready(rid):
+                    continue
+                j = outstanding.pop(rid)
+                n_done += 1
+                last_progress = time.perf_counter() - t_start
+                info = srv.query(rid)
+                states[j] = info["state"]
+                if info["state"] == "failed":
+                    log(f"[bench] request {j} ({reqs[j].kind}, n {reqs[j].n}) failed: {info}")
+                if info["state"] == "done":
+                    lat[j], qms[j], bsz[j] = info["latency_ms"], info["queue_ms"], info["batch_size"]
+                    if check and j in check_ids:
+                        parity[j] = sampled_check(j, srv, rid)
+                srv.release(rid)
+            time.sleep(0.0005)
+        secs = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        torch.cuda.synchronize()
+        flop = 2.0 * sum(ips[j] for j in lat)
+        log(f"[bench] served {qps:.1f}/s: {secs:.2f} s, p50 {pct(list(lat.values()), 50):.1f} ms, "
+            f"p99 {pct(list(lat.values()), 99):.1f} ms, stats {st}")
+        for j in sorted(lat, key=lambda j: -lat[j])[:6]:
+            log(f"[bench]   slowest: request {j} {reqs[j].kind} n {reqs[j].n} arrival "
+                f"{reqs[j].arrival_s / qps:.2f} s queue {qms[j]:.0f} ms latency {lat[j]:.0f} ms "
+                f"group {bsz[j]}")
+        return {"seconds": round(secs, 3), "req_per_s": round(len(lat) / secs, 2),
+                "GFLOPs": round(flop / secs / 1e9, 2),
+                "p50_ms": pct(list(lat.values()), 50), "p99_ms": pct(list(lat.values()), 99),
+                "mean_queue_ms": float(np.mean(list(qms.values()))) if qms else None,
+                "mean_batch": float(np.mean(list(bsz.values()))) if bsz else None,
+                "completed": len(lat), "rejected": sum(v == "rejected" for v in states.values()),
+                "failed": sum(v == "failed" for v in states.values()),
+                "peak_reserved_GB": round(st["peak_reserved_bytes"] / 1e9, 2),
+                "budget_GB": round(st["budget_bytes"] / 1e9, 2), "deferred": st["deferred"],
+                "exact_probes": st["exact_probes"]}, parity
+
+    def serial(qps):
+        lat1 = {}
+        t_start = time.perf_counter()
+        last_note = 0.0
+        for j, r in enumerate(reqs):
+            if time.perf_counter() - t_start - last_note >= 2.0:
+                last_note = time.perf_counter() - t_start
+                log(f"[bench] serial {qps:.1f}/s t={last_note:.1f} s: request {j}")
+            while time.perf_counter() - t_start < r.arrival_s / qps:
+                time.sleep(0.0002)
+            ka, kb = keys[j]
+            try:
+                C = ctx.spgemm(dev[ka], dev[kb])
+                torch.cuda.synchronize()
+                lat1[j] = 1e3 * (time.perf_counter() - t_start - r.arrival_s / qps)
+                del C
+            except mg.MagnusError as e:
+                log(f"[bench] serial request {j} failed: {e}")
+        secs = time.perf_counter() - t_start
+        log(f"[bench] serial {qps:.1f}/s: {secs:.2f} s, p50 {pct(list(lat1.values()), 50):.1f} ms, "
+            f"p99 {pct(list(lat1.values()), 99):.1f} ms")
+        return {"seconds": round(secs, 3), "req_per_s": round(len(lat1) / secs, 2),
+                "GFLOPs": round(2.0 * sum(ips[j] for j in lat1) / secs / 1e9, 2),
+                "p50_ms": pct(list(lat1.values()), 50), "p99_ms": pct(list(lat1.values()), 99),
+                "completed": len(lat1)}
+
+    fracs = [float(x) for x in args.qps_fracs.split(",")] if args.qps <= 0 else [None]
+    runs, parity = [], {}
+    for k, f in enumerate(fracs):
+        qps = args.qps if f is None else f * sat_rate
+        sv, par = served(qps, check=(k == 0))
+        parity.update(par)
+        runs.append({"fraction_of_saturation": f, "qps": round(qps, 3), "served": sv,
+                     "serial_fifo": serial(qps)})
+    head = runs[-1]
+    bad = sorted(j for j, ok in parity.items() if not ok)
+    out = {"metric": METRIC, "value": head["served"]["GFLOPs"], "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * head["served"]["seconds"], 1),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": f"{len(reqs)} Poisson requests at {args.qps} per second, "
-                                  "C = A*B, n log-uniform in [1e3, 1e6], half R-MAT (scale "
-                                  "round(log2 n)), half banded (w 64, 9 per row), f64, int32",
-                      "requests": len(reqs), "qps": args.qps, "operands": len(host),
+           "config": {"workload": f"{len(reqs)} Poisson requests, C = A*B, n log-uniform in "
+                                  "[1e3, 1e6], half R-MAT (scale round(log2 n), operands shared "
+                                  "per scale), half banded (w 64, 9 per row), f64, int32; served "
+                                  "at fractions of the serial saturation rate",
+                      "requests": len(reqs), "operands": len(host),
+                      "scale20_requests": len(scale20),
                       "intermediate_products": int(sum(ips)), "max_batch": args.max_batch,
                       "streams": args.streams},
-           "served": {"seconds": round(served_s, 3), "GFLOPs": round(served_flop / served_s / 1e9, 2),
-                      "p50_ms": pct(list(lat.values()), 50), "p99_ms": pct(list(lat.values()), 99),
-                      "mean_queue_ms": float(np.mean(list(qms.values()))) if qms else None,
-                      "mean_batch": float(np.mean(list(bsz.values()))) if bsz else None,
-                      "completed": len(lat), "rejected": sum(v == "rejected" for v in states.values()),
-                      "failed": sum(v == "failed" for v in states.values()), "server_stats": st},
-           "serial_fifo": {"seconds": round(serial_s, 3),
-                           "GFLOPs": round(total_flop / serial_s / 1e9, 2),
-                           "p50_ms": pct(list(lat1.values()), 50),
-                           "p99_ms": pct(list(lat1.values()), 99), "completed": len(lat1)},
-           "sample_parity": {"requests": len(parity), "all_within_rtol": all(parity), "rtol": 1e-12},
+           "serial_saturation": {"seconds": round(sat_s, 3), "req_per_s": round(sat_rate, 3),
+                                 "GFLOPs": round(total_flop / sat_s / 1e9, 2)},
+           "runs": runs,
+           "sample_parity": {"requests": len(parity), "scale20_checked": sum(j in parity for j in scale20),
+                             "all_within_rtol": not bad, "failed_requests": bad[:20], "rtol": 1e-12,
+                             "rows_per_request": 200},
            "src_sha": src_digest()}
     print(json.dumps(out), flush=True)
 
@@ -831,8 +891,12 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512,
                     help="products of the batch workload (--workload batch)")
     ap.add_argument("--no-tune", action="store_true", help="batch workload: library defaults")
-    ap.add_argument("--serve-count", type=int, default=200, help="requests of --workload serve")
-    ap.add_argument("--qps", type=float, default=10.0, help="arrival rate of --workload serve")
+    ap.add_argument("--serve-count", type=int, default=2000, help="requests of --workload serve")
+    ap.add_argument("--qps", type=float, default=0.0,
+                    help="arrival rate of --workload serve (0: fractions of the measured serial "
+                         "saturation rate, --qps-fracs)")
+    ap.add_argument("--qps-fracs", default="0.5,0.8,0.95",
+                    help="fractions of the serial saturation rate for --workload serve")
     ap.add_argument("--max-batch", type=int, default=32)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2501_07056_amd", "tuned",

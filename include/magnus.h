@@ -406,9 +406,11 @@ magnus_status_t magnus_batch_bound(magnus_handle_t h, int32_t count, const magnu
  * row batches); a group that still does not fit goes back to the head of the
  * queue with doubled estimates.  So the plans and results of admitted
  * requests never hold more than the budget (the stats report the peak).  A
- * request whose reservation alone exceeds the budget is planned exactly
- * first, capped at the unreserved budget, and rejected (MAGNUS_ERR_REJECTED)
- * only if it does not fit that way either with nothing else running.  All
+ * request whose reservation exceeds exact_above_pct of the budget is
+ * planned exactly first (the precise symbolic phase; the plan is kept for
+ * its run), capped at the unreserved budget, and then reserves its exact C;
+ * it is rejected (MAGNUS_ERR_REJECTED) only if it does not fit that way
+ * with nothing else running.  All
  * operands of a server share value and index types.  The server's calls are
  * thread safe; its results stay valid until released.
  * ---------------------------------------------------------------------- */
@@ -423,7 +425,8 @@ typedef struct {
   int32_t max_bypass;          /* see above (0: 8) */
   int32_t plan_estimate_pct;   /* scale of the planning-memory estimate, percent (0: 100): lower
                                 * admits more requests per group, and more groups are deferred */
-  int32_t _reserved;
+  int32_t exact_above_pct;     /* requests whose reservation exceeds this percentage of the
+                                * budget are sized exactly before admission (0: 25) */
 } magnus_server_config_t;
 
 typedef enum {

@@ -57,7 +57,7 @@ class PlanInfo(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", c_i64), ("workspace_cap_bytes", c_i64),
                 ("max_inflight", c_i32), ("max_batch", c_i32), ("streams", c_i32),
-                ("max_bypass", c_i32), ("plan_estimate_pct", c_i32), ("_reserved", c_i32)]
+                ("max_bypass", c_i32), ("plan_estimate_pct", c_i32), ("exact_above_pct", c_i32)]
 
 
 class RequestInfo(ctypes.Structure):

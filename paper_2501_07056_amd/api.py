@@ -474,6 +474,45 @@ class Server:
         torch.cuda.current_stream(dev).synchronize()
         return out
 
+    def result_rows(self, rid: int, rows):
+        """Row pointers of a finished request's C and the columns and values
+        of the given rows only, as host arrays (rowptr, col, val; col and val
+        concatenated in the order of rows), read from the server's memory
+        without copying C whole."""
+        import numpy as np
+        d = CsrOutDesc()
+        check(self.lib.magnus_server_result(self.ptr, rid, ctypes.byref(d)), "magnus_server_result")
+        if self._copier is None:
+            self._copier = Context(self.device)
+        dev = self.ops[0].rowptr.device
+        cb = 8 if d.col_type == 1 else 4
+        vb = 8 if d.val_type == 1 else 4
+        ct = torch.int64 if cb == 8 else torch.int32
+        vt = torch.float64 if vb == 8 else torch.float32
+        lib, h = self._copier.lib, self._copier.handle
+        s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+        def copy(dst: torch.Tensor, src: int, nbytes: int):
+            if nbytes:
+                check(lib.magnus_stream_copy(h, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src),
+                                             nbytes, s), "magnus_stream_copy")
+        rp_d = torch.empty(int(d.nrows) + 1, dtype=torch.int64, device=dev)
+        copy(rp_d, d.rowptr, rp_d.numel() * 8)
+        rp = rp_d.cpu().numpy()
+        rows = np.asarray(rows, dtype=np.int64)
+        lens = rp[rows + 1] - rp[rows]
+        tot = int(lens.sum())
+        col = torch.empty(tot, dtype=ct, device=dev)
+        val = torch.empty(tot, dtype=vt, device=dev)
+        o = 0
+        for r, ln in zip(rows.tolist(), lens.tolist()):
+            if ln:
+                copy(col[o:], d.col + int(rp[r]) * cb, ln * cb)
+                copy(val[o:], d.val + int(rp[r]) * vb, ln * vb)
+            o += ln
+        torch.cuda.current_stream(dev).synchronize()
+        return rp, col.cpu().numpy(), val.cpu().numpy()
+
     def poll(self, max_n: int = 64):
         """Final states reported since the last poll: a list of dicts
         (request_id, state, status, nnz, latency_ms)."""

@@ -7,10 +7,12 @@
 //     known yet stops the scan;
 //   - a request fits if reserved + bound <= budget; fitting requests join the
 //     group (at most max_batch, at most `slots`);
-//   - a request whose bound alone exceeds the budget is sized exactly first
-//     ("probe"), and only when it is at the head of the queue and the group is
-//     empty: at most one exactly planned request waits at any time, so the
-//     memory its plan holds cannot keep a second such request out forever;
+//   - a request whose bound exceeds exact_above (at most the budget: a large
+//     request's upper bound can reserve several times what it uses) is sized
+//     exactly first ("probe"), and only when it is at the head of the queue
+//     and the group is empty: at most one exactly planned request waits at
+//     any time, so the memory its plan holds cannot keep a second such
+//     request out forever;
 //   - an exactly planned request runs alone;
 //   - later requests may pass the oldest request that does not fit, but each
 //     pass is counted on it, and after max_bypass passes nothing is admitted
@@ -37,15 +39,16 @@ struct Decision {
 };
 
 inline Decision admit_pass(std::vector<QItem>& q, int64_t reserved, int64_t budget, int slots,
-                           int max_batch, int max_bypass) {
+                           int max_batch, int max_bypass, int64_t exact_above = -1) {
   Decision d;
+  if (exact_above < 0 || exact_above > budget) exact_above = budget;
   const size_t none = (size_t)-1;
   size_t blocker = none;
   for (size_t i = 0; i < q.size(); ++i) {
     if ((int)d.admit.size() >= max_batch || slots <= 0) break;
     QItem& r = q[i];
     if (r.bound < 0) break;
-    const bool oversized = r.bound > budget && !r.pre;
+    const bool oversized = r.bound > exact_above && !r.pre;
     if (oversized && i == 0 && d.admit.empty()) {
       d.probe = 0;
       break;

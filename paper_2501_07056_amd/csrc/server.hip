@@ -4,9 +4,9 @@
 // min(ip_i, columns) entries), admits requests while the bound fits the free
 // budget and a slot is free, groups admitted requests into one batched plan
 // and execution (the batch calls), and runs several such groups at once on
-// separate streams.  A request whose bound alone exceeds the budget is
-// planned exactly (precise symbolic phase, Section 2.1) and rejected only if
-// its exact size does not fit either.
+// separate streams.  A request whose bound exceeds a share of the budget is
+// planned exactly first (precise symbolic phase, Section 2.1), reserves its
+// exact size, and is rejected only if that does not fit either.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -215,8 +215,8 @@ void reserve(magnus_server_s* S, int64_t d) {
 
 // A group whose planning did not fit the memory reserved for it goes back to
 // the head of the queue, in order, each request with twice its planning
-// estimate (a request whose bound then exceeds the budget is sized exactly,
-// alone, next).
+// estimate (a request whose bound then exceeds the exact-sizing share of the
+// budget is sized exactly, alone, next).
 void defer_group(magnus_server_s* S, std::vector<SrvReq*>& g, int sidx) {
   std::lock_guard<std::mutex> lk(S->mu);
   for (auto it = g.rbegin(); it != g.rend(); ++it) {
@@ -301,10 +301,10 @@ bool probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
     room = S->budget - S->reserved;
     others = S->reserved > 0;
     // after a wait, sized again only once running groups released memory
-    const bool blocked = r->probe_wait >= 0 && S->reserved >= r->probe_wait;
+    const bool blocked = r->probe_wait > 0 && S->reserved >= r->probe_wait;
     if ((room <= 0 && others) || blocked) {
       S->stream_busy[sidx] = 0;
-      r->probe_wait = S->reserved;
+      r->probe_wait = S->reserved;  // > 0 here
       return false;
     }
   }
@@ -319,8 +319,10 @@ bool probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
   }
   std::lock_guard<std::mutex> lk(S->mu);
   S->stream_busy[sidx] = 0;
+  // results released by the client while it planned lower the reserved
+  // bytes: it waits for a release only while something else is reserved
   if (s == MAGNUS_ERR_OOM && others) {  // again once memory is released
-    r->probe_wait = S->reserved;
+    r->probe_wait = S->reserved > 0 ? S->reserved : -1;
     return false;
   }
   if (s == MAGNUS_ERR_OOM) s = MAGNUS_ERR_REJECTED;  // does not fit even alone
@@ -328,7 +330,7 @@ bool probe_exact(magnus_server_s* S, SrvReq* r, int sidx) {
   if (s == MAGNUS_OK && S->reserved + total > S->budget) {
     if (others) {  // it may fit once the running groups are done
       magnus_batch_plan_destroy(bp);
-      r->probe_wait = S->reserved;
+      r->probe_wait = S->reserved > 0 ? S->reserved : -1;
       return false;
     }
     s = MAGNUS_ERR_REJECTED;
@@ -403,7 +405,38 @@ void launch_group(magnus_server_s* S, std::vector<SrvReq*> g, int sidx) {
     void* p = nullptr;
     p = S->mem.alloc((size_t)bytes, st);
     if (!p) {
+      // the device is short of memory although the reservation fits (its
+      // memory is not only this server's): while other requests hold
+      // memory the group waits for them in the queue, else it fails
+      for (int k = 0; k < i; ++k) {
+        S->mem.release(g[k]->mem, st);
+        g[k]->mem = nullptr;
+      }
+      bool others = false;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        int64_t mine = pre ? plan_bytes : 0;
+        for (SrvReq* q : g) mine += q->held;
+        others = S->reserved > mine;
+      }
+      if (others && pre) {
+        g[0]->pre = bp;  // keeps its exact plan, which stays reserved
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->reserved -= g[0]->held;
+        g[0]->held = 0;
+        g[0]->state.store(MAGNUS_REQ_QUEUED);
+        S->pending.push_front(g[0]);
+        S->running -= 1;
+        S->stats.deferred++;
+        S->stream_busy[sidx] = 0;
+        return;
+      }
       magnus_batch_plan_destroy(bp);
+      if (others) {
+        for (SrvReq* q : g) q->plan_est /= 2;  // undone by the deferral's doubling
+        defer_group(S, g, sidx);
+        return;
+      }
       if (pre) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->reserved -= plan_bytes;
@@ -543,7 +576,8 @@ void sched_loop(magnus_server_s* S) {
         }
         mgsrv::Decision d = mgsrv::admit_pass(q, S->reserved, S->budget,
                                               S->cfg.max_inflight - S->running,
-                                              S->cfg.max_batch, S->cfg.max_bypass);
+                                              S->cfg.max_batch, S->cfg.max_bypass,
+                                              S->budget / 100 * S->cfg.exact_above_pct);
         for (size_t i = 0; i < q.size(); ++i) qr[i]->skipped = q[i].skipped;
         if (d.probe >= 0) probe = qr[(size_t)d.probe];
         for (size_t i : d.admit) {
@@ -602,9 +636,11 @@ magnus_status_t magnus_server_create(int device, const magnus_options_t* opts,
   magnus_server_config_t c{};
   if (cfg) c = *cfg;
   if (c.memory_budget_bytes < 0 || c.workspace_cap_bytes < 0 || c.max_inflight < 0 ||
-      c.max_batch < 0 || c.streams < 0 || c.max_bypass < 0 || c.plan_estimate_pct < 0)
+      c.max_batch < 0 || c.streams < 0 || c.max_bypass < 0 || c.plan_estimate_pct < 0 ||
+      c.exact_above_pct < 0 || c.exact_above_pct > 100)
     return MAGNUS_ERR_INVALID_ARG;
   if (c.plan_estimate_pct == 0) c.plan_estimate_pct = 100;
+  if (c.exact_above_pct == 0) c.exact_above_pct = 25;
   magnus_handle_t h = nullptr;
   magnus_status_t s = magnus_create(&h, device, opts);
   if (s != MAGNUS_OK) return s;

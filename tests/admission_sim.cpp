@@ -31,7 +31,7 @@ struct Group {
 };
 
 static void run(const char* name, std::vector<Req> R, int64_t budget, int streams, int max_batch,
-                int max_bypass, int slots_max) {
+                int max_bypass, int slots_max, int64_t exact_above = -1) {
   std::deque<int> q;
   std::vector<Group> running;
   int64_t reserved = 0, c_held = 0, c_max = 0;
@@ -79,7 +79,7 @@ static void run(const char* name, std::vector<Req> R, int64_t budget, int stream
       std::vector<mgsrv::QItem> items;
       for (int id : q) items.push_back({R[id].bound, R[id].pre, R[id].skipped});
       mgsrv::Decision d = mgsrv::admit_pass(items, reserved, budget, slots_max - nrun, max_batch,
-                                            max_bypass);
+                                            max_bypass, exact_above);
       for (size_t i = 0; i < items.size(); ++i) R[q[i]].skipped = items[i].skipped;
       if (d.probe >= 0) {
         running.push_back({{q[0]}, t + 0.001, 0, true});
@@ -154,6 +154,9 @@ int main() {
       R.push_back(r);
     }
     run("mix", R, 140 * GB, 2, 32, 8, 64);
+    // the same under a budget that holds two big requests exactly, with
+    // every request whose bound exceeds a quarter of it sized exactly first
+    run("mix_quarter", R, 280 * GB, 2, 32, 8, 64, 70 * GB);
   }
   // 2. two oversized requests back to back, each fitting only alone
   {

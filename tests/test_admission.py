@@ -31,6 +31,15 @@ def test_mix_completes_within_budget(sim):
     assert r["c_over_budget"] <= 0
 
 
+def test_exact_sizing_above_a_quarter_of_the_budget(sim):
+    """Requests whose bounds exceed a quarter of the budget are sized exactly
+    before admission (their bounds alone would fit): the mix still completes
+    within the budget, without rejections."""
+    r = sim["mix_quarter"]
+    assert r["deadlock"] == 0 and r["rejected"] == 0 and r["completed"] == 400
+    assert r["c_over_budget"] <= 0
+
+
 def test_oversized_requests_each_fitting_alone(sim):
     """Several requests whose bounds exceed the budget and whose exact sizes
     fit only one at a time: all are served, one after another."""
