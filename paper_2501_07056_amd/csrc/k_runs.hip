@@ -80,20 +80,39 @@ __global__ void __launch_bounds__(256)
     k_run_count(const RP* __restrict__ arp, const CI* __restrict__ acol, const int32_t* rows,
                 int64_t nrows, const int64_t* __restrict__ bptr, const int64_t* __restrict__ ip,
                 unsigned long long* out) {
-  const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / MG_WAVE;
-  if (k >= nrows) return;
-  const int32_t r = rows[k];
-  const int64_t a0 = arp[r], a1 = arp[r + 1];
-  unsigned long long s = 0;
-  for (int64_t e = a0 + lane(); e < a1; e += MG_WAVE) {
-    const int64_t j = acol[e];
-    s += (unsigned long long)(bptr[j + 1] - bptr[j] - 1);
+  // a wave per row, grid-stride; totals reduced per workgroup, then one
+  // atomic each (one per row serialised on the three counters)
+  __shared__ unsigned long long sh[4][3];
+  const int w = threadIdx.x / MG_WAVE;
+  unsigned long long runs = 0, amax = 0, prods = 0;
+  for (int64_t k = (int64_t)blockIdx.x * 4 + w; k < nrows; k += (int64_t)gridDim.x * 4) {
+    const int32_t r = rows[k];
+    const int64_t a0 = arp[r], a1 = arp[r + 1];
+    unsigned long long s = 0;
+    for (int64_t e = a0 + lane(); e < a1; e += MG_WAVE) {
+      const int64_t j = acol[e];
+      s += (unsigned long long)(bptr[j + 1] - bptr[j] - 1);
+    }
+    runs += wave_sum(s);
+    amax = amax > (unsigned long long)(a1 - a0) ? amax : (unsigned long long)(a1 - a0);
+    prods += (unsigned long long)ip[r];
   }
-  s = wave_sum(s);
   if (lane() == 0) {
-    atomicAdd(&out[0], s);
-    atomicMax(&out[1], (unsigned long long)(a1 - a0));
-    atomicAdd(&out[2], (unsigned long long)ip[r]);
+    sh[w][0] = runs;
+    sh[w][1] = amax;
+    sh[w][2] = prods;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t0 = 0, t1 = 0, t2 = 0;
+    for (int v = 0; v < 4; ++v) {
+      t0 += sh[v][0];
+      t1 = t1 > sh[v][1] ? t1 : sh[v][1];
+      t2 += sh[v][2];
+    }
+    atomicAdd(&out[0], t0);
+    atomicMax(&out[1], t1);
+    atomicAdd(&out[2], t2);
   }
 }
 
@@ -214,32 +233,79 @@ MG_INLINE int64_t bin_chunk(const ChunkGeom& g, const int32_t* bin_row, int64_t 
 }
 MG_INLINE int64_t xcd_key(int64_t c, int64_t cpx) { return (c % N_XCD) * cpx + c / N_XCD; }
 
-__global__ void k_dense_key_hist(ChunkGeom g, const int64_t* __restrict__ items,
-                                 const int32_t* item_counts, const int32_t* __restrict__ bin_row,
-                                 int64_t cpx, unsigned long long* cnt) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= item_counts[0]) return;
-  atomicAdd(&cnt[xcd_key(bin_chunk(g, bin_row, items[it]), cpx)], 1ull);
+// Both kernels take DK_ITEMS consecutive items per thread and aggregate the
+// keys of a workgroup in LDS (when the keys fit, dk_lds): one global atomic
+// per (workgroup, key) instead of one per item, which serialised on the few
+// chunk counters.
+constexpr int DK_BS = 1024, DK_ITEMS = 8, DK_MAXK = 4096;
+
+__global__ void __launch_bounds__(DK_BS)
+    k_dense_key_hist(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
+                     const int32_t* __restrict__ bin_row, int64_t cpx, unsigned long long* cnt) {
+  __shared__ unsigned int lh[DK_MAXK];
+  const int64_t nk = N_XCD * cpx, nit = item_counts[0];
+  const bool lds = nk <= DK_MAXK;
+  if (lds)
+    for (int64_t k = threadIdx.x; k < nk; k += DK_BS) lh[k] = 0u;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * DK_BS * DK_ITEMS;
+  for (int u = 0; u < DK_ITEMS; ++u) {
+    const int64_t it = i0 + (int64_t)u * DK_BS + threadIdx.x;
+    if (it >= nit) break;
+    const int64_t key = xcd_key(bin_chunk(g, bin_row, items[it]), cpx);
+    if (lds) atomicAdd(&lh[key], 1u);
+    else atomicAdd(&cnt[key], 1ull);
+  }
+  __syncthreads();
+  if (lds)
+    for (int64_t k = threadIdx.x; k < nk; k += DK_BS)
+      if (lh[k]) atomicAdd(&cnt[k], (unsigned long long)lh[k]);
 }
 
-__global__ void k_run_records(ChunkGeom g, const int64_t* __restrict__ items,
-                              const int32_t* item_counts, const int64_t* __restrict__ bin_start,
-                              const int64_t* __restrict__ bin_cnt,
-                              const int32_t* __restrict__ bin_row,
-                              const int64_t* __restrict__ seg_beg, int64_t cpx,
-                              unsigned long long* cur, int64_t* rec) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= item_counts[0]) return;
-  const int64_t gb = items[it];
-  const int64_t c = bin_chunk(g, bin_row, gb);
-  const int64_t pos = (int64_t)atomicAdd(&cur[xcd_key(c, cpx)], 1ull);
-  int64_t* r = rec + RUN_REC * pos;
-  r[0] = bin_start[gb];
-  r[1] = seg_beg[gb];
-  r[2] = bin_cnt[gb];
-  r[3] = seg_beg[gb + 1] - seg_beg[gb];
-  r[4] = c << g.shift;
-  r[5] = gb;
+__global__ void __launch_bounds__(DK_BS)
+    k_run_records(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
+                  const int64_t* __restrict__ bin_start, const int64_t* __restrict__ bin_cnt,
+                  const int32_t* __restrict__ bin_row, const int64_t* __restrict__ seg_beg,
+                  int64_t cpx, unsigned long long* cur, int64_t* rec) {
+  __shared__ unsigned int lh[DK_MAXK];
+  __shared__ unsigned long long lb[DK_MAXK];
+  const int64_t nk = N_XCD * cpx, nit = item_counts[0];
+  const bool lds = nk <= DK_MAXK;
+  const int64_t i0 = (int64_t)blockIdx.x * DK_BS * DK_ITEMS;
+  int64_t key[DK_ITEMS];
+  if (lds)
+    for (int64_t k = threadIdx.x; k < nk; k += DK_BS) lh[k] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < DK_ITEMS; ++u) {
+    const int64_t it = i0 + (int64_t)u * DK_BS + threadIdx.x;
+    key[u] = it < nit ? xcd_key(bin_chunk(g, bin_row, items[it]), cpx) : -1;
+    if (lds && key[u] >= 0) atomicAdd(&lh[key[u]], 1u);
+  }
+  __syncthreads();
+  if (lds) {
+    // reserve each key's range, then hand out ranks within it
+    for (int64_t k = threadIdx.x; k < nk; k += DK_BS) {
+      lb[k] = lh[k] ? atomicAdd(&cur[k], (unsigned long long)lh[k]) : 0ull;
+      lh[k] = 0u;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < DK_ITEMS; ++u) {
+    if (key[u] < 0) continue;
+    const int64_t it = i0 + (int64_t)u * DK_BS + threadIdx.x;
+    const int64_t gb = items[it];
+    const int64_t pos = lds ? (int64_t)(lb[key[u]] + atomicAdd(&lh[key[u]], 1u))
+                            : (int64_t)atomicAdd(&cur[key[u]], 1ull);
+    int64_t* r = rec + RUN_REC * pos;
+    r[0] = bin_start[gb];
+    r[1] = seg_beg[gb];
+    r[2] = bin_cnt[gb];
+    r[3] = seg_beg[gb + 1] - seg_beg[gb];
+    r[4] = bin_chunk(g, bin_row, gb) << g.shift;
+    r[5] = gb;
+  }
 }
 
 // runs staged per window: at most 512, so that two 1024-thread workgroups
@@ -638,13 +704,10 @@ hipError_t launch_bci(const Mats& M, int shift, bool fill, int64_t* cnt, const i
 
 hipError_t launch_run_count(const Mats& M, const int32_t* rows, int64_t nrows, const int64_t* bptr,
                             const int64_t* ip, unsigned long long* out, hipStream_t st) {
-  const int64_t cap = max_grid(256) * 4;
-  for (int64_t o = 0; o < nrows; o += cap) {
-    const int64_t n = std::min(cap, nrows - o);
-    MG_DISPATCH2(M, hipLaunchKernelGGL((k_run_count<RP, CI>), (unsigned)((n + 3) / 4), 256, 0, st,
-                                        (const RP*)M.arp, (const CI*)M.acol, rows + o, n, bptr,
-                                        ip, out));
-  }
+  if (nrows <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((nrows + 3) / 4, 4096);
+  MG_DISPATCH2(M, hipLaunchKernelGGL((k_run_count<RP, CI>), grid, 256, 0, st, (const RP*)M.arp,
+                                      (const CI*)M.acol, rows, nrows, bptr, ip, out));
   return hipGetLastError();
 }
 
@@ -676,8 +739,9 @@ hipError_t launch_dense_order(const ChunkGeom& g, int64_t nitems, const int64_t*
   const int64_t nk = N_XCD * cpx;
   hipError_t e = launch_fill_i64(xcd_start, nk + 1, 0, st);
   if (e != hipSuccess) return e;
+  const int64_t per = (int64_t)DK_BS * DK_ITEMS;
   if (nitems > 0)
-    hipLaunchKernelGGL(k_dense_key_hist, (unsigned)((nitems + 255) / 256), 256, 0, st, g,
+    hipLaunchKernelGGL(k_dense_key_hist, (unsigned)((nitems + per - 1) / per), DK_BS, 0, st, g,
                        dense_items, item_counts, bin_row, cpx, (unsigned long long*)xcd_start);
   e = scan_excl_i64(xcd_start, xcd_start, nk, xcd_start + nk, nullptr, temp, st);
   if (e != hipSuccess) return e;
@@ -691,8 +755,9 @@ hipError_t launch_run_records(const ChunkGeom& g, int64_t nitems, const int64_t*
                               const int64_t* seg_beg, int64_t cpx, int64_t* xcd_cur,
                               int64_t* rec, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_run_records, (unsigned)((nitems + 255) / 256), 256, 0, st, g, dense_items,
-                     item_counts, bin_start, bin_cnt, bin_row, seg_beg, cpx,
+  const int64_t per = (int64_t)DK_BS * DK_ITEMS;
+  hipLaunchKernelGGL(k_run_records, (unsigned)((nitems + per - 1) / per), DK_BS, 0, st, g,
+                     dense_items, item_counts, bin_start, bin_cnt, bin_row, seg_beg, cpx,
                      (unsigned long long*)xcd_cur, rec);
   return hipGetLastError();
 }
