@@ -528,16 +528,14 @@ MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
       for (int w = l; w < words; w += MG_WAVE) s_bm[w] = 0u;
       for (int64_t sb = sg0; sb < sg1; sb += MG_WAVE) {
         const int64_t s = sb + l;
-        if (s < sg1) {
-          w_x0[l] = (int32_t)(seg_off[s] - start);
-          w_b[l] = seg_b[s];
-        }
-        const int nv = (int)((sg1 - sb) < MG_WAVE ? (sg1 - sb) : MG_WAVE);
+        // lanes past the window's runs hold a start above every product
+        w_x0[l] = (s < sg1) ? (int32_t)(seg_off[s] - start) : INT32_MAX;
+        if (s < sg1) w_b[l] = seg_b[s];
         const int32_t xhi = (sb + MG_WAVE < sg1) ? (int32_t)(seg_off[sb + MG_WAVE] - start) : P;
         wave_sync_r();
         const int32_t xlo = w_x0[0];
         for (int32_t x = xlo + l; x < xhi; x += MG_WAVE) {
-          const int i = upper_index(w_x0, 0, nv, x);
+          const int i = upper_index64(w_x0, x);
           const uint32_t key = (uint32_t)((int64_t)bcol[w_b[i] + (uint32_t)(x - w_x0[i])] - colbase);
           atomicOr(&s_bm[key >> 5], 1u << (key & 31));
         }
@@ -558,12 +556,12 @@ MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
   for (int e = 0; e < E; ++e) k[e] = 0xFFFFFFFFu;
   for (int64_t sb = sg0; sb < sg1; sb += MG_WAVE) {
     const int64_t s = sb + l;
+    // lanes past the window's runs hold a start above every product
+    w_x0[l] = (s < sg1) ? (int32_t)(seg_off[s] - start) : INT32_MAX;
     if (s < sg1) {
-      w_x0[l] = (int32_t)(seg_off[s] - start);
       w_b[l] = seg_b[s];
       if (NUMERIC) w_av[l] = aval[seg_a[s]];
     }
-    const int nv = (int)((sg1 - sb) < MG_WAVE ? (sg1 - sb) : MG_WAVE);
     const int32_t xhi = (sb + MG_WAVE < sg1) ? (int32_t)(seg_off[sb + MG_WAVE] - start) : P;
     wave_sync_r();
     const int32_t xlo = w_x0[0];
@@ -571,7 +569,7 @@ MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
     for (int e = 0; e < E; ++e) {
       const int x = e * MG_WAVE + l;
       if (x >= xlo && x < xhi) {
-        const int i = upper_index(w_x0, 0, nv, x);
+        const int i = upper_index64(w_x0, x);
         const uint32_t b = w_b[i] + (uint32_t)(x - w_x0[i]);
         const uint32_t key = (uint32_t)((int64_t)bcol[b] - colbase);
         k[e] = NUMERIC ? ((key << IDXB) | (uint32_t)x) : key;
