@@ -1,5 +1,8 @@
 """Build the gfx950 HIP library in-tree: every csrc/*.hip is compiled by hipcc
-in parallel and linked into paper_2501_07056_amd/libmagnus.so."""
+in parallel and linked into paper_2501_07056_amd/libmagnus.so.  The checked
+build (checked=True) compiles the same sources with MG_CHECKED into
+libmagnus_checked.so: guard bytes around every plan allocation, verified
+after each plan and each numeric phase."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -12,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmagnus.so")
+OUT_CHECKED = os.path.join(HERE, "libmagnus_checked.so")
 OBJ = os.path.join(ROOT, "_build")
 # extra compiler flags and an alternative output, for experiment builds
 EXTRA = os.environ.get("MAGNUS_EXTRA_FLAGS", "").split()
@@ -34,12 +38,12 @@ def _hipcc():
     return "hipcc"
 
 
-def _compile(src: str, force: bool) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+def _compile(src: str, force: bool, objdir: str, flags: list) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
     deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(ROOT, "include", "magnus.h")]
     if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
         return obj
-    cmd = [_hipcc()] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [_hipcc()] + flags + ["-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
@@ -47,22 +51,26 @@ def _compile(src: str, force: bool) -> str:
     return obj
 
 
-def build(force: bool = True, jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(force: bool = True, jobs: int | None = None, verbose: bool = False,
+          checked: bool = False) -> str:
+    out = OUT_CHECKED if checked else OUT
+    objdir = os.path.join(OBJ, "checked") if checked else OBJ
+    flags = FLAGS + (["-DMG_CHECKED"] if checked else [])
+    os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, force), srcs))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, force, objdir, flags), srcs))
+    tmp = out + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(force="--force" in sys.argv, verbose=True)
+    build(force="--force" in sys.argv, verbose=True, checked="--checked" in sys.argv)

@@ -511,6 +511,14 @@ magnus_status_t magnus_batch_execute(magnus_handle_t h, magnus_batch_plan_t P, i
     }
   }
   (void)C;
+  if (MG_GUARD) {
+    // checked builds: the guards of the batch's and its alone products' plans
+    HIPCHK(hipStreamSynchronize(st));
+    magnus_status_t g = plan_check_guards(&P->core);
+    for (size_t b = 0; g == MAGNUS_OK && b < P->alone.size(); ++b)
+      if (P->alone[b]) g = plan_check_guards(P->alone[b]);
+    return g;
+  }
   return MAGNUS_OK;
 }
 

@@ -1316,6 +1316,13 @@ magnus_status_t magnus_plan(magnus_handle_t h, const magnus_csr_t* A, const magn
     s = plan_once(h, A, B, stream, out, info, div, &shrinkable);
     if (s != MAGNUS_ERR_OOM || !shrinkable) break;
   }
+  if (s == MAGNUS_OK && MG_GUARD) {
+    s = plan_check_guards(*out);
+    if (s != MAGNUS_OK) {
+      magnus_plan_destroy(*out);
+      *out = nullptr;
+    }
+  }
   return s;
 }
 
@@ -1354,6 +1361,13 @@ magnus_status_t magnus_execute(magnus_handle_t h, magnus_plan_t P, const magnus_
     if (r != MAGNUS_OK) return r;
   }
   HIPCHK(launch_write_rowptr(P->crp, P->n, C->rowptr, C->rowptr_type == MAGNUS_I64, P->st));
+  if (MG_GUARD) {
+    // checked builds: the guards after the numeric phase (not inside a
+    // graph capture, where the stream cannot be waited for)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(P->st, &cs));
+    if (cs == hipStreamCaptureStatusNone) return plan_check_guards(P);
+  }
   return MAGNUS_OK;
 }
 

@@ -251,28 +251,79 @@ inline magnus_status_t fail_hip(magnus_handle_s* h, hipError_t e, const char* wh
     if (e_ != hipSuccess) return fail_hip(h, e_, #expr);  \
   } while (0)
 
+// Checked builds (MG_CHECKED) put MG_GUARD bytes of a fixed pattern before
+// and after every plan allocation; plan_check_guards reads them back after
+// the plan's work and reports an overwrite.
+#ifdef MG_CHECKED
+constexpr size_t MG_GUARD = 256;
+constexpr int MG_GUARD_BYTE = 0xA5;
+#else
+constexpr size_t MG_GUARD = 0;
+#endif
+
 inline void* palloc(magnus_plan_s* P, size_t bytes) {
   magnus_handle_s* h = P->h;
   bytes = align256(bytes ? bytes : 1);
-  if (h->plan_cap > 0 && h->plan_live.load() + (int64_t)bytes > h->plan_cap) return nullptr;
-  void* p = h->alloc_fn ? h->alloc_fn(bytes, (void*)P->st, h->alloc_ctx)
-                        : default_alloc(bytes, nullptr, nullptr);
-  if (p) {
-    P->allocs.push_back({p, bytes});
-    h->plan_live += (int64_t)bytes;
+  const size_t total = bytes + 2 * MG_GUARD;
+  if (h->plan_cap > 0 && h->plan_live.load() + (int64_t)total > h->plan_cap) return nullptr;
+  void* base = h->alloc_fn ? h->alloc_fn(total, (void*)P->st, h->alloc_ctx)
+                           : default_alloc(total, nullptr, nullptr);
+  if (!base) return nullptr;
+  void* p = (char*)base + MG_GUARD;
+#ifdef MG_CHECKED
+  if (hipMemsetAsync(base, MG_GUARD_BYTE, MG_GUARD, P->st) != hipSuccess ||
+      hipMemsetAsync((char*)p + bytes, MG_GUARD_BYTE, MG_GUARD, P->st) != hipSuccess) {
+    if (h->free_fn) h->free_fn(base, total, (void*)P->st, h->alloc_ctx);
+    else default_free(base, total, nullptr, nullptr);
+    return nullptr;
   }
+#endif
+  P->allocs.push_back({p, bytes});
+  h->plan_live += (int64_t)total;
   return p;
 }
 
 inline void plan_free_all(magnus_plan_s* P) {
   magnus_handle_s* h = P->h;
   for (auto& a : P->allocs) {
-    if (h && h->free_fn) h->free_fn(a.p, a.n, (void*)P->st, h->alloc_ctx);
-    else default_free(a.p, a.n, nullptr, nullptr);
-    if (h) h->plan_live -= (int64_t)a.n;
+    void* base = (char*)a.p - MG_GUARD;
+    const size_t total = a.n + 2 * MG_GUARD;
+    if (h && h->free_fn) h->free_fn(base, total, (void*)P->st, h->alloc_ctx);
+    else default_free(base, total, nullptr, nullptr);
+    if (h) h->plan_live -= (int64_t)total;
   }
   P->allocs.clear();
 }
+
+// Checked builds: waits for the plan's stream and compares every guard with
+// its pattern; MAGNUS_ERR_INTERNAL (with the allocation named in the
+// handle's error text) on an overwrite.  Other builds: MAGNUS_OK.
+inline magnus_status_t plan_check_guards(magnus_plan_s* P) {
+#ifdef MG_CHECKED
+  if (hipStreamSynchronize(P->st) != hipSuccess) return fail_hip(P->h, hipGetLastError(), "guards");
+  std::vector<unsigned char> g(MG_GUARD);
+  for (size_t k = 0; k < P->allocs.size(); ++k) {
+    const Alloc& a = P->allocs[k];
+    for (int side = 0; side < 2; ++side) {
+      const char* at = side ? (const char*)a.p + a.n : (const char*)a.p - MG_GUARD;
+      if (hipMemcpy(g.data(), at, MG_GUARD, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail_hip(P->h, hipGetLastError(), "guards");
+      for (size_t i = 0; i < MG_GUARD; ++i)
+        if (g[i] != (unsigned char)MG_GUARD_BYTE) {
+          char msg[160];
+          snprintf(msg, sizeof msg, "guard %s allocation %zu of %zu (%zu bytes) overwritten",
+                   side ? "after" : "before", k, P->allocs.size(), a.n);
+          P->h->err = msg;
+          return MAGNUS_ERR_INTERNAL;
+        }
+    }
+  }
+#else
+  (void)P;
+#endif
+  return MAGNUS_OK;
+}
+
 
 // Brackets one launch (or a group of launches) with events when profiling.
 struct ProfScope {
