@@ -137,8 +137,7 @@ __global__ void __launch_bounds__(RR_BS)
                const int64_t* __restrict__ bptr, const uint32_t* __restrict__ bpos,
                const uint32_t* __restrict__ bchunk, int64_t k0, int64_t* bin_seg,
                int64_t* bin_cnt, int32_t* bin_row, const int64_t* __restrict__ seg_beg,
-               const int64_t* __restrict__ bin_start, uint32_t* seg_b, uint32_t* seg_a,
-               int64_t* seg_off) {
+               const int64_t* __restrict__ bin_start, run_t* runs) {
   extern __shared__ __align__(16) unsigned char dsm[];
   const int t = threadIdx.x;
   const int64_t k = k0 + blockIdx.x;
@@ -189,9 +188,9 @@ __global__ void __launch_bounds__(RR_BS)
       const unsigned long long o = atomicAdd(&ctr[c], (1ull << RUN_SHIFT) | len);
       if (!HIST) {
         const int64_t slot = sbase[c] + (int64_t)(o >> RUN_SHIFT);
-        seg_b[slot] = p;
-        seg_a[slot] = (uint32_t)(eb + i);
-        seg_off[slot] = pbase[c] + (int64_t)(o & RUN_PMASK);
+        const int64_t off = pbase[c] + (int64_t)(o & RUN_PMASK);
+        st_global(&runs[slot],
+                  run_t{(uint32_t)off, (uint32_t)((uint64_t)off >> 32), p, (uint32_t)(eb + i)});
       }
     }
     __syncthreads();
@@ -232,6 +231,13 @@ MG_INLINE int64_t bin_chunk(const ChunkGeom& g, const int32_t* bin_row, int64_t 
   return (g.minc[g.rows[kk]] >> g.shift) + (gb - g.binBase[kk]);
 }
 MG_INLINE int64_t xcd_key(int64_t c, int64_t cpx) { return (c % N_XCD) * cpx + c / N_XCD; }
+
+// a run record's product offset, from the record or from memory (its first
+// eight bytes)
+MG_INLINE int64_t run_off(const run_t& r) { return (int64_t)(((uint64_t)r.y << 32) | r.x); }
+MG_INLINE int64_t run_off_at(const run_t* runs, int64_t s) {
+  return ld_global((const int64_t*)(runs + s));
+}
 
 // Both kernels take DK_ITEMS consecutive items per thread and aggregate the
 // keys of a workgroup in LDS (when the keys fit, dk_lds): one global atomic
@@ -321,8 +327,7 @@ size_t run_dense_lds(int f64, int shift, int block) {
 template <typename CI, typename V, bool NUMERIC>
 __global__ void __launch_bounds__(1024)
     k_run_dense(ChunkGeom g, const int64_t* __restrict__ rec, const int32_t* item_counts,
-                const int64_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_b,
-                const uint32_t* __restrict__ seg_a, const V* __restrict__ aval,
+                const run_t* __restrict__ runs, const V* __restrict__ aval,
                 const CI* __restrict__ bcol, const V* __restrict__ bval, int64_t* bin_nnz,
                 const int64_t* __restrict__ bin_out, void* ccol_, int col64, V* cval,
                 unsigned int* work, uint32_t* chunk_bm, const int64_t* __restrict__ xcd_start,
@@ -397,12 +402,13 @@ __global__ void __launch_bounds__(1024)
     for (int64_t sb = sg0; sb < sg1; sb += WR) {
       const int64_t s = sb + t;
       if (t < WR && s < sg1) {
-        w_pre[t] = (int32_t)(seg_off[s] - s0);
-        w_b[t] = seg_b[s];
-        if (NUMERIC) w_av[t] = aval[seg_a[s]];
+        const run_t r = ld_global(&runs[s]);
+        w_pre[t] = (int32_t)(run_off(r) - s0);
+        w_b[t] = r.z;
+        if (NUMERIC) w_av[t] = aval[r.w];
       }
       const int nvalid = (int)((sg1 - sb) < WR ? (sg1 - sb) : WR);
-      const int32_t wend = (sb + WR < sg1) ? (int32_t)(seg_off[sb + WR] - s0) : (int32_t)cnt;
+      const int32_t wend = (sb + WR < sg1) ? (int32_t)(run_off_at(runs, sb + WR) - s0) : (int32_t)cnt;
       __syncthreads();
       const int32_t wstart = w_pre[0];
       for (int32_t q0 = wstart; q0 < wend; q0 += SC) {
@@ -467,7 +473,36 @@ __global__ void __launch_bounds__(1024)
       }
       continue;
     }
-    int64_t pos = bin_out[gb] + before + inc - my;
+    const int64_t obase = bin_out[gb];
+    if (nwords <= WR && (nwords & 1) == 0) {
+      // every word's first output (w_pre, free here) and the bitmap (bits)
+      // in LDS; then each wave writes 64 columns at a time, lane l the
+      // column l of the pair of words, at its word's start plus the set bits
+      // below it: one store instruction covers consecutive outputs
+      int32_t o = (int32_t)(before + inc - my);
+      for (int64_t w = w0; w < w1; ++w) {
+        const uint32_t bb = gbm[w];
+        bits[w] = bb;
+        w_pre[w] = o;
+        o += __popc(bb);
+      }
+      __syncthreads();
+      const int hl = lane() >> 5, bit = lane() & 31;
+      for (int64_t pw = 2 * wv; pw < nwords; pw += 2 * nw) {
+        const int64_t w = pw + hl;
+        const uint32_t bb = bits[w];
+        if ((bb >> bit) & 1u) {
+          const int64_t lc = w * 32 + bit;
+          const int64_t pos = obase + w_pre[w] + __popc(bb & ((1u << bit) - 1u));
+          if (col64) st_stream<HINT_C_STORE>(&((int64_t*)ccol_)[pos], (int64_t)(colbase + lc));
+          else st_stream<HINT_C_STORE>(&((int32_t*)ccol_)[pos], (int32_t)(colbase + lc));
+          st_stream<HINT_C_STORE>(&cval[pos], acc[lc]);
+          acc[lc] = (V)0;
+        }
+      }
+      continue;
+    }
+    int64_t pos = obase + before + inc - my;
     for (int64_t w = w0; w < w1; ++w) {
       uint32_t bb = gbm[w];
       while (bb) {
@@ -504,9 +539,7 @@ MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
                              const int64_t* __restrict__ bin_cnt,
                              const int32_t* __restrict__ bin_row,
                              const int64_t* __restrict__ seg_beg,
-                             const int64_t* __restrict__ seg_off,
-                             const uint32_t* __restrict__ seg_b,
-                             const uint32_t* __restrict__ seg_a, const V* __restrict__ aval,
+                             const run_t* __restrict__ runs, const V* __restrict__ aval,
                              const CI* __restrict__ bcol, const V* __restrict__ bval,
                              int64_t* bin_nnz, const int64_t* __restrict__ bin_out, void* ccol_,
                              int col64, V* cval, int32_t* w_x0, uint32_t* w_b, V* w_av,
@@ -529,9 +562,15 @@ MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
       for (int64_t sb = sg0; sb < sg1; sb += MG_WAVE) {
         const int64_t s = sb + l;
         // lanes past the window's runs hold a start above every product
-        w_x0[l] = (s < sg1) ? (int32_t)(seg_off[s] - start) : INT32_MAX;
-        if (s < sg1) w_b[l] = seg_b[s];
-        const int32_t xhi = (sb + MG_WAVE < sg1) ? (int32_t)(seg_off[sb + MG_WAVE] - start) : P;
+        if (s < sg1) {
+          const run_t r = ld_global(&runs[s]);
+          w_x0[l] = (int32_t)(run_off(r) - start);
+          w_b[l] = r.z;
+        } else {
+          w_x0[l] = INT32_MAX;
+        }
+        const int32_t xhi =
+            (sb + MG_WAVE < sg1) ? (int32_t)(run_off_at(runs, sb + MG_WAVE) - start) : P;
         wave_sync_r();
         const int32_t xlo = w_x0[0];
         for (int32_t x = xlo + l; x < xhi; x += MG_WAVE) {
@@ -557,12 +596,16 @@ MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
   for (int64_t sb = sg0; sb < sg1; sb += MG_WAVE) {
     const int64_t s = sb + l;
     // lanes past the window's runs hold a start above every product
-    w_x0[l] = (s < sg1) ? (int32_t)(seg_off[s] - start) : INT32_MAX;
     if (s < sg1) {
-      w_b[l] = seg_b[s];
-      if (NUMERIC) w_av[l] = aval[seg_a[s]];
+      const run_t r = ld_global(&runs[s]);
+      w_x0[l] = (int32_t)(run_off(r) - start);
+      w_b[l] = r.z;
+      if (NUMERIC) w_av[l] = aval[r.w];
+    } else {
+      w_x0[l] = INT32_MAX;
     }
-    const int32_t xhi = (sb + MG_WAVE < sg1) ? (int32_t)(seg_off[sb + MG_WAVE] - start) : P;
+    const int32_t xhi =
+        (sb + MG_WAVE < sg1) ? (int32_t)(run_off_at(runs, sb + MG_WAVE) - start) : P;
     wave_sync_r();
     const int32_t xlo = w_x0[0];
 #pragma unroll
@@ -652,8 +695,7 @@ __global__ void __launch_bounds__(RS_WAVES * MG_WAVE)
     k_run_sort(ChunkGeom g, const int64_t* __restrict__ items, const int32_t* item_counts,
                const int64_t* __restrict__ bin_start, const int64_t* __restrict__ bin_cnt,
                const int32_t* __restrict__ bin_row, const int64_t* __restrict__ seg_beg,
-               const int64_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_b,
-               const uint32_t* __restrict__ seg_a, const V* __restrict__ aval,
+               const run_t* __restrict__ runs, const V* __restrict__ aval,
                const CI* __restrict__ bcol, const V* __restrict__ bval, int64_t* bin_nnz,
                const int64_t* __restrict__ bin_out, void* ccol_, int col64, V* cval,
                int64_t it0) {
@@ -670,8 +712,8 @@ __global__ void __launch_bounds__(RS_WAVES * MG_WAVE)
   const int nbg = (int)items[2 * it + 1];
   const int64_t P = bin_start[g0 + nbg - 1] + bin_cnt[g0 + nbg - 1] - bin_start[g0];
 #define MG_RS(E)                                                                                  \
-  run_sort_item<CI, V, E, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, seg_beg, seg_off,    \
-                                   seg_b, seg_a, aval, bcol, bval, bin_nnz, bin_out, ccol_,      \
+  run_sort_item<CI, V, E, NUMERIC>(g, g0, nbg, bin_start, bin_cnt, bin_row, seg_beg, runs,       \
+                                   aval, bcol, bval, bin_nnz, bin_out, ccol_,                    \
                                    col64, cval, s_x0[w], s_b[w], s_av[w], s_cnt[w], s_v[w],  \
                                    s_bm[w])
   if (P <= 64) MG_RS(1);
@@ -712,8 +754,8 @@ hipError_t launch_run_count(const Mats& M, const int32_t* rows, int64_t nrows, c
 hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const int64_t* bptr,
                            const uint32_t* bpos, const uint32_t* bchunk, int64_t max_nb,
                            int64_t* bin_seg, int64_t* bin_cnt, int32_t* bin_row,
-                           const int64_t* seg_beg, const int64_t* bin_start, uint32_t* seg_b,
-                           uint32_t* seg_a, int64_t* seg_off, hipStream_t st) {
+                           const int64_t* seg_beg, const int64_t* bin_start, run_t* runs,
+                           hipStream_t st) {
   if (g.nch <= 0) return hipSuccess;
   const size_t lds = run_rows_lds(max_nb);
   const int64_t cap = max_grid(RR_BS);
@@ -724,8 +766,7 @@ hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const i
       (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
       hipLaunchKernelGGL(kf, grid, RR_BS, lds, st, (const RP*)M.arp, (const CI*)M.acol, g, bptr,
-                         bpos, bchunk, o, bin_seg, bin_cnt, bin_row, seg_beg, bin_start, seg_b,
-                         seg_a, seg_off);
+                         bpos, bchunk, o, bin_seg, bin_cnt, bin_row, seg_beg, bin_start, runs);
     });
   }
   return hipGetLastError();
@@ -764,8 +805,8 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             const int64_t* bin_start, const int64_t* bin_cnt,
                             const int32_t* bin_row, const int64_t* dense_rec,
                             const int64_t* sort_items, const int32_t* item_counts,
-                            const int64_t* seg_beg, const int64_t* seg_off, const uint32_t* seg_b,
-                            const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
+                            const int64_t* seg_beg, const run_t* runs, int64_t* bin_nnz,
+                            const int64_t* bin_out,
                             void* ccol, int col64, void* cval, int dense_block,
                             unsigned int* work, int persistent_wgs, uint32_t* chunk_bm,
                             int64_t n_sort_items, const int64_t* xcd_start, int64_t cpx,
@@ -786,14 +827,14 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
     auto kd = numeric ? k_run_dense<CI, V, true> : k_run_dense<CI, V, false>;                     \
     (void)hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize,        \
                               (int)lds);                                                          \
-    hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_rec, item_counts, seg_off, seg_b,   \
-                       seg_a, (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval, bin_nnz,     \
+    hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_rec, item_counts, runs,             \
+                       (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval, bin_nnz,     \
                        bin_out, ccol, col64, (V*)cval, work, chunk_bm, xcd_start, cpx);           \
     auto ks = numeric ? k_run_sort<CI, V, true> : k_run_sort<CI, V, false>;                       \
     for (int64_t o = 0; o < gs_all; o += gcap)                                                    \
       hipLaunchKernelGGL(ks, (unsigned)std::min(gcap, gs_all - o), RS_WAVES * MG_WAVE, 0, st, g,  \
-                         sort_items, item_counts, bin_start, bin_cnt, bin_row, seg_beg, seg_off,  \
-                         seg_b, seg_a, (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval,     \
+                         sort_items, item_counts, bin_start, bin_cnt, bin_row, seg_beg, runs,     \
+                         (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval,     \
                          bin_nnz, bin_out, ccol, col64, (V*)cval, o * RS_WAVES);                  \
   }
   if (M.col64) {

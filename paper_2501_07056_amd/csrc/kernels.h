@@ -286,15 +286,21 @@ hipError_t launch_bci(const Mats& M, int shift, bool fill, int64_t* cnt, const i
 // row); out[2] += their products (ip, by row id)
 hipError_t launch_run_count(const Mats& M, const int32_t* rows, int64_t nrows, const int64_t* bptr,
                             const int64_t* ip, unsigned long long* out, hipStream_t st);
+// One run of a chunk, 16 bytes written and read whole: the product offset
+// of its first product (64 bits, low word first), its start in B's column
+// array and its A entry.  One record instead of three arrays halves the
+// partly written cache lines of the scatter, whose runs of one chunk land
+// a few at a time.
+typedef uint32_t run_t __attribute__((ext_vector_type(4)));
 // hist: runs and products per chunk (bin_seg, bin_cnt) and each chunk's row;
-// otherwise the runs' scatter: B position, A entry and product offset of
-// every run, the runs of chunk b at [seg_beg[b], seg_beg[b + 1])
+// otherwise the runs' scatter: every run's record, the runs of chunk b at
+// [seg_beg[b], seg_beg[b + 1])
 size_t run_rows_lds(int64_t max_nb);
 hipError_t launch_run_rows(const Mats& M, const ChunkGeom& g, bool hist, const int64_t* bptr,
                            const uint32_t* bpos, const uint32_t* bchunk, int64_t max_nb,
                            int64_t* bin_seg, int64_t* bin_cnt, int32_t* bin_row,
-                           const int64_t* seg_beg, const int64_t* bin_start, uint32_t* seg_b,
-                           uint32_t* seg_a, int64_t* seg_off, hipStream_t st);
+                           const int64_t* seg_beg, const int64_t* bin_start, run_t* runs,
+                           hipStream_t st);
 // Dense items are dealt to the XCDs by column chunk: chunk index c goes to
 // XCD c % N_XCD, and each XCD's items are ordered by c, so the workgroups of
 // one XCD (ids congruent mod N_XCD: the dispatcher deals workgroups to the
@@ -323,8 +329,8 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             const int64_t* bin_start, const int64_t* bin_cnt,
                             const int32_t* bin_row, const int64_t* dense_rec,
                             const int64_t* sort_items, const int32_t* item_counts,
-                            const int64_t* seg_beg, const int64_t* seg_off, const uint32_t* seg_b,
-                            const uint32_t* seg_a, int64_t* bin_nnz, const int64_t* bin_out,
+                            const int64_t* seg_beg, const run_t* runs, int64_t* bin_nnz,
+                            const int64_t* bin_out,
                             void* ccol, int col64, void* cval, int dense_block,
                             unsigned int* work, int persistent_wgs, uint32_t* chunk_bm,
                             int64_t n_sort_items, const int64_t* xcd_start, int64_t cpx,

@@ -252,14 +252,12 @@ magnus_status_t runs_setup(magnus_plan_s* P, bool& chosen) {
   // products / dense_min of them
   P->run_rec = (int64_t*)palloc(
       P, sizeof(int64_t) * 6 * std::max<int64_t>(1, std::min(nbins, tots[0] / std::max<int64_t>(1, P->dense_min) + 1)));
-  P->seg_b = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, runs));
-  P->seg_a = (uint32_t*)palloc(P, sizeof(uint32_t) * std::max<int64_t>(1, runs));
-  P->seg_off = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, runs));
+  P->run_list = (run_t*)palloc(P, sizeof(run_t) * std::max<int64_t>(1, runs));
   P->ent = (int64_t*)palloc(P, sizeof(int64_t) * (4 * nch + 2));
   if (!P->aoff) P->aoff = (int64_t*)palloc(P, sizeof(int64_t) * std::max<int64_t>(1, P->a_nnz));
   if (!P->scan_temp || !P->work_ctr || !P->bin_start || !P->bin_cnt || !P->bin_nnz ||
       !P->bin_out || !P->bin_row || !P->bin_seg || !P->seg_beg || !P->dense_items ||
-      !P->sort_items || !P->item_counts || !P->seg_b || !P->seg_a || !P->seg_off || !P->ent ||
+      !P->sort_items || !P->item_counts || !P->run_list || !P->ent ||
       !P->run_rec ||
       !P->aoff)
     return MAGNUS_ERR_OOM;
@@ -362,14 +360,14 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
                        (double)P->n_runs * 16 + (double)nbins * 36);
       HIPCHK(launch_run_rows(P->M, P->g, true, P->bci_ptr, P->bci_pos, P->bci_chunk, P->max_nb,
                              P->bin_seg, P->bin_cnt, P->bin_row, nullptr, nullptr, nullptr,
-                             nullptr, nullptr, P->st));
+                             P->st));
       HIPCHK(scan_excl_i64(P->bin_cnt, P->bin_start, nbins, nullptr, nullptr, P->scan_temp,
                            P->st));
       HIPCHK(scan_excl_i64(P->bin_seg, P->seg_beg, nbins, P->seg_beg + nbins, nullptr,
                            P->scan_temp, P->st));
       HIPCHK(launch_run_rows(P->M, P->g, false, P->bci_ptr, P->bci_pos, P->bci_chunk, P->max_nb,
-                             nullptr, nullptr, nullptr, P->seg_beg, P->bin_start, P->seg_b,
-                             P->seg_a, P->seg_off, P->st));
+                             nullptr, nullptr, nullptr, P->seg_beg, P->bin_start,
+                             P->run_list, P->st));
     }
     HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
                             P->sort_items, P->item_counts, P->st));
@@ -398,7 +396,7 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
                    (double)b.nip * P->s_col + (double)P->n_runs * 16 + (double)nbins * 40);
       HIPCHK(launch_run_accum(P->M, P->g, nbins, false, P->bin_start, P->bin_cnt, P->bin_row,
                               P->run_rec, P->sort_items, P->item_counts, P->seg_beg,
-                              P->seg_off, P->seg_b, P->seg_a, P->bin_nnz, nullptr, nullptr, 0,
+                              P->run_list, P->bin_nnz, nullptr, nullptr, 0,
                               nullptr, P->dense_block, wk, P->persistent_wgs_count, P->chunk_bm,
                               P->n_sort_run, P->xcd_start, P->xcd_cpx, P->st));
     }
@@ -468,8 +466,8 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
                      (double)P->n_runs * (16 + P->s_val) +
                      (double)b.nnz_out * (P->s_col + P->s_val));
     HIPCHK(launch_run_accum(P->M, P->g, b.nbins, true, P->bin_start, P->bin_cnt, P->bin_row,
-                            P->run_rec, P->sort_items, P->item_counts, P->seg_beg, P->seg_off,
-                            P->seg_b, P->seg_a, P->bin_nnz, P->bin_out, ccol, col64, cval,
+                            P->run_rec, P->sort_items, P->item_counts, P->seg_beg,
+                            P->run_list, P->bin_nnz, P->bin_out, ccol, col64, cval,
                             P->dense_block, wk, P->persistent_wgs, P->chunk_bm, P->n_sort_run,
                             P->xcd_start, P->xcd_cpx, P->st));
     return MAGNUS_OK;

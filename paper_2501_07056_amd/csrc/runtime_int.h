@@ -149,7 +149,8 @@ struct magnus_plan_s {
   // and product offset
   bool runs = false;
   int64_t n_runs = 0;
-  int64_t *bci_ptr = nullptr, *bin_seg = nullptr, *seg_beg = nullptr, *seg_off = nullptr;
+  int64_t *bci_ptr = nullptr, *bin_seg = nullptr, *seg_beg = nullptr;
+  run_t* run_list = nullptr;  // every run's record, grouped by chunk
   int64_t* run_rec = nullptr;  // 6 int64 per dense item
   uint32_t* chunk_bm = nullptr;  // column bitmap of every dense item
   int64_t n_dense_run = 0;
@@ -158,7 +159,7 @@ struct magnus_plan_s {
   int64_t xcd_cpx = 1;
   int64_t *xcd_start = nullptr, *xcd_cur = nullptr;
   void* xcd_temp = nullptr;
-  uint32_t *bci_pos = nullptr, *bci_chunk = nullptr, *seg_b = nullptr, *seg_a = nullptr;
+  uint32_t *bci_pos = nullptr, *bci_chunk = nullptr;
   int persistent_wgs_count = 512;  // count-mode accumulator workgroups (bitmap only in LDS)
   // CHUNKED rows
   int64_t nch = 0, max_nb = 1;
