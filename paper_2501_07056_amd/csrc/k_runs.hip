@@ -215,8 +215,15 @@ __global__ void __launch_bounds__(RR_BS)
 // column).  The write-out is that of the product reorder's dense
 // accumulator: ascending columns, touched slots cleared as they are read.
 // ---------------------------------------------------------------------------
+// Products per thread whose loads are in flight together: numeric 12 (the
+// 512-thread workgroups are held to two per CU by the LDS, so the registers
+// are there; uniform 2^20 columns, chunks of 16K products: run_accum 47.3 ->
+// 42.1 ms against 8, R-MAT scale 20 unchanged), count mode 4 (8: no gain).
 #ifndef MG_RUN_UNROLL
-#define MG_RUN_UNROLL 8
+#define MG_RUN_UNROLL 12
+#endif
+#ifndef MG_RUN_UNROLL_C
+#define MG_RUN_UNROLL_C 4
 #endif
 
 // Per dense item, everything its workgroup needs before the first product:
@@ -337,7 +344,7 @@ __global__ void __launch_bounds__(1024)
   // Items (records in XCD order) are taken from this XCD's counter work[x],
   // then, when it is done, from the others' in turn.
   extern __shared__ __align__(16) unsigned char dsm[];
-  constexpr int U = NUMERIC ? MG_RUN_UNROLL : 4;
+  constexpr int U = NUMERIC ? MG_RUN_UNROLL : MG_RUN_UNROLL_C;
   const int BS = blockDim.x;
   const int WR = BS < RUN_WIN ? BS : RUN_WIN;
   const int64_t L = (int64_t)1 << g.shift;
@@ -530,8 +537,11 @@ __global__ void __launch_bounds__(1024)
 // ---------------------------------------------------------------------------
 constexpr int RS_WAVES = 4;
 // count mode: an item whose chunks span at most this many bitmap words (one
-// bit per column) counts its distinct columns in a per-wave LDS bitmap
-constexpr int RS_BM_WORDS = 2048;
+// bit per column) counts its distinct columns in a per-wave LDS bitmap.  4
+// KiB per wave leaves the LDS for 32 waves per CU (8 KiB held it to 16:
+// R-MAT scale 20, run_count 70.9 -> 62.4 ms; the items over four chunks of
+// 2^13 columns that now take the sort cost less than that occupancy)
+constexpr int RS_BM_WORDS = 1024;
 
 template <typename CI, typename V, int E, bool NUMERIC>
 MG_INLINE void run_sort_item(const ChunkGeom& g, int64_t g0, int nbg,
@@ -812,10 +822,12 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
                             int64_t n_sort_items, const int64_t* xcd_start, int64_t cpx,
                             hipStream_t st) {
   if (nbins <= 0) return hipSuccess;
-  // count mode keeps no values in LDS
-  const size_t lds = run_dense_lds(M.f64, g.shift, dense_block) -
+  // count mode keeps no values in LDS and runs RUN_COUNT_BLOCK threads per
+  // workgroup
+  const int db = numeric ? dense_block : RUN_COUNT_BLOCK;
+  const size_t lds = run_dense_lds(M.f64, g.shift, db) -
                      (numeric ? 0 : ((size_t)1 << g.shift) * (M.f64 ? 8 : 4) +
-                                        (size_t)std::min(dense_block, RUN_WIN) * (M.f64 ? 8 : 4));
+                                        (size_t)std::min(db, RUN_WIN) * (M.f64 ? 8 : 4));
   const unsigned gd = (unsigned)std::min<int64_t>(nbins, persistent_wgs);
   // one wave per sort item: the count the host read back (the grid is not
   // sized by the bins, mostly empty waves), the bins when it is not known
@@ -827,7 +839,7 @@ hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bo
     auto kd = numeric ? k_run_dense<CI, V, true> : k_run_dense<CI, V, false>;                     \
     (void)hipFuncSetAttribute((const void*)kd, hipFuncAttributeMaxDynamicSharedMemorySize,        \
                               (int)lds);                                                          \
-    hipLaunchKernelGGL(kd, gd, dense_block, lds, st, g, dense_rec, item_counts, runs,             \
+    hipLaunchKernelGGL(kd, gd, db, lds, st, g, dense_rec,          item_counts, runs,             \
                        (const V*)M.aval, (const CI*)M.bcol, (const V*)M.bval, bin_nnz,     \
                        bin_out, ccol, col64, (V*)cval, work, chunk_bm, xcd_start, cpx);           \
     auto ks = numeric ? k_run_sort<CI, V, true> : k_run_sort<CI, V, false>;                       \

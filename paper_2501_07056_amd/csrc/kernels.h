@@ -323,7 +323,11 @@ hipError_t launch_run_records(const ChunkGeom& g, int64_t nitems, const int64_t*
                               const int64_t* seg_beg, int64_t cpx, int64_t* xcd_cur,
                               int64_t* rec, hipStream_t st);
 // the accumulators over chunks whose products are read through their runs
-// (count mode: bin_nnz; numeric: C at bin_out)
+// (count mode: bin_nnz; numeric: C at bin_out).  The dense items' workgroups
+// have dense_block threads in numeric mode and RUN_COUNT_BLOCK in count
+// mode, whose LDS (the bitmap and the run window) allows eight per CU:
+// persistent_wgs is the grid of the mode launched.
+constexpr int RUN_COUNT_BLOCK = 256;
 size_t run_dense_lds(int f64, int shift, int block);
 hipError_t launch_run_accum(const Mats& M, const ChunkGeom& g, int64_t nbins, bool numeric,
                             const int64_t* bin_start, const int64_t* bin_cnt,

@@ -218,9 +218,13 @@ magnus_status_t runs_setup(magnus_plan_s* P, bool& chosen) {
     const size_t dl = run_dense_lds(P->M.f64, P->shift, P->dense_block);
     const int per_cu = std::max<int>(1, (int)(h->lds_max / std::max<size_t>(dl, 1)));
     P->persistent_wgs = std::max(1, h->cus) * std::min(per_cu, 2048 / P->dense_block);
-    const size_t dlc = ((size_t)1 << P->shift) / 8 + (size_t)P->dense_block * 8 + 4096;
+  }
+  {
+    // count mode: 256-thread workgroups whatever dense_block is (R-MAT scale
+    // 20: run_count 62.4 -> 60.0 ms against the numeric phase's 512)
+    const size_t dlc = ((size_t)1 << P->shift) / 8 + (size_t)RUN_COUNT_BLOCK * 8 + 4096;
     const int per_cu_c = std::max<int>(1, (int)(h->lds_max / dlc));
-    P->persistent_wgs_count = std::max(1, h->cus) * std::min(per_cu_c, 2048 / P->dense_block);
+    P->persistent_wgs_count = std::max(1, h->cus) * std::min(per_cu_c, 2048 / RUN_COUNT_BLOCK);
   }
 
   // the chunk geometry of one batch of all CHUNKED rows
