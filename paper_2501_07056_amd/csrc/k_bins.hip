@@ -412,21 +412,31 @@ MG_INLINE void block_excl_scan(const int32_t* a, int32_t* out, int64_t n, int32_
 
 // Chunk-local columns go out as 16-bit words (chunks of <= 2^16 columns) or,
 // for the coarse level's chunks, as 32-bit words.
-// With `sorted`, the staged tile is permuted into chunk order in LDS before
-// the write-out (as in the level-2 reorder below), so that a wave stores
-// consecutive addresses of one chunk's run even where the expansion order
-// interleaves many chunks.
-size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb, int lc32, int sorted) {
+// With `sorted`, the staged tile is written out in chunk order (as in the
+// level-2 reorder below), so that a wave stores consecutive addresses of one
+// chunk's run even where the expansion order interleaves many chunks: a
+// 16-bit index per position of the chunk-ordered tile names the staged
+// product to store there (2 bytes per product instead of a second copy of
+// the tile, so that tiles twice as long fit and the runs per chunk double).
+// The chunk-ordered reorder of 32-bit columns (the coarse level's first
+// reorder, where a tile spreads over hundreds of chunks and one tile fills
+// the LDS of a CU) runs `block` threads (256, 512 or 1024), so that the
+// gathers of more waves are in flight; the other modes run BIN_BS.
+static int scatter2_block(int lc32, int sorted, int block) {
+  return (lc32 && sorted && block > 0) ? block : BIN_BS;
+}
+
+size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb, int lc32, int sorted, int block) {
   const size_t vs = f64 ? 8 : 4;
   const size_t w = 4 + (lc32 ? 2 : 0);
-  size_t b = BIN_BS * (8 + 8 + 8) + (size_t)max_nb * (4 + 8) + 16 + (size_t)tile * (4 + w) + 16 +
+  size_t b = (size_t)scatter2_block(lc32, sorted, block) * (8 + 8 + 8) + (size_t)max_nb * (4 + 8) + 16 + (size_t)tile * (4 + w) + 16 +
              (size_t)tile * vs + 64;
-  if (sorted) b += (size_t)max_nb * 4 + 16 + (size_t)tile * w + 16 + (size_t)tile * vs + 16;
+  if (sorted) b += (size_t)max_nb * 4 + 16 + (size_t)tile * 2 + 16;
   return b;
 }
 
-template <typename RP, typename CI, typename V, typename LC, bool NUMERIC, bool SORTED>
-__global__ void __launch_bounds__(BIN_BS)
+template <int BS, typename RP, typename CI, typename V, typename LC, bool NUMERIC, bool SORTED>
+__global__ void __launch_bounds__(BS)
     k_bin_scatter2(const RP* __restrict__ arp, const CI* __restrict__ acol, const V* __restrict__ aval,
                    const RP* __restrict__ brp, const CI* __restrict__ bcol, const V* __restrict__ bval,
                    ChunkGeom g, BatchArgs b, const int32_t* __restrict__ tile_row,
@@ -436,29 +446,28 @@ __global__ void __launch_bounds__(BIN_BS)
   constexpr bool W16 = sizeof(LC) == 2;
   extern __shared__ __align__(16) unsigned char dsm[];
   int32_t* w_pre = (int32_t*)dsm;
-  int64_t* w_b0 = (int64_t*)(dsm + BIN_BS * 8);
-  V* w_av = (V*)(w_b0 + BIN_BS);
+  int64_t* w_b0 = (int64_t*)(dsm + BS * 8);
+  V* w_av = (V*)(w_b0 + BS);
   TileCtx c;
   tile_setup<RP>(g, b, tile_row, arp, aoff, c, tile_e0);
-  int32_t* hist = (int32_t*)((char*)w_av + BIN_BS * 8);
+  int32_t* hist = (int32_t*)((char*)w_av + BS * 8);
   int64_t* dst = (int64_t*)(((uintptr_t)(hist + c.nbk) + 15) & ~(uintptr_t)15);
   uint32_t* u_word = (uint32_t*)(dst + c.nbk);
   uint32_t* u_rank = u_word + g.tile;
   uint16_t* u_bin = (uint16_t*)(u_rank + g.tile);  // 32-bit columns: the chunk apart
   V* u_val = (V*)(((uintptr_t)(u_bin + (W16 ? 0 : g.tile)) + 15) & ~(uintptr_t)15);
-  // chunk-ordered copy of the tile (SORTED)
+  // chunk order of the tile (SORTED): each chunk's first position, and the
+  // staged product at every position
   int32_t* loff = (int32_t*)(u_val + g.tile);
-  uint32_t* s_word = (uint32_t*)(((uintptr_t)(loff + c.nbk) + 15) & ~(uintptr_t)15);
-  uint16_t* s_bin = (uint16_t*)(s_word + g.tile);
-  V* s_val = (V*)(((uintptr_t)(s_bin + (W16 ? 0 : g.tile)) + 15) & ~(uintptr_t)15);
-  __shared__ int32_t s_tmp[BIN_BS / MG_WAVE];
+  uint16_t* s_idx = (uint16_t*)(((uintptr_t)(loff + c.nbk) + 15) & ~(uintptr_t)15);
+  __shared__ int32_t s_tmp[BS / MG_WAVE];
 
-  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) hist[q] = 0;
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BS) hist[q] = 0;
   __syncthreads();
   const int64_t lmask = ((int64_t)1 << g.shift) - 1;
   // gather once; the chunk counter's old value is the product's rank inside
   // this tile's run of that chunk
-  expand_products<BIN_BS, RP, CI, V, NUMERIC>(
+  expand_products<BS, RP, CI, V, NUMERIC>(
       c.p0, c.p1, c.e0, c.a1, acol, aval, brp, bcol, bval, aoff, w_pre, w_b0, w_av,
       [&](int32_t q, CI col, V pv) {
         const uint32_t bin = (uint32_t)(col >> g.shift) - (uint32_t)c.base_bin;
@@ -477,10 +486,10 @@ __global__ void __launch_bounds__(BIN_BS)
         if (NUMERIC) u_val[q] = pv;
       });
   __syncthreads();
-  if (SORTED) block_excl_scan<BIN_BS>(hist, loff, c.nbk, s_tmp);
+  if (SORTED) block_excl_scan<BS>(hist, loff, c.nbk, s_tmp);
   // reserve each chunk's run inside its bin with one atomic add
   const int64_t gb = g.binBase[c.k];
-  for (int64_t q = threadIdx.x; q < c.nbk; q += BIN_BS) {
+  for (int64_t q = threadIdx.x; q < c.nbk; q += BS) {
     const int h = hist[q];
     if (h > 0) {
       const unsigned long long r = atomicAdd(&bin_cursor[gb + q], (unsigned long long)h);
@@ -489,26 +498,24 @@ __global__ void __launch_bounds__(BIN_BS)
   }
   const int32_t nloc = (int32_t)(c.p1 - c.p0);
   if (SORTED) {
-    for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
+    for (int32_t q = threadIdx.x; q < nloc; q += BS) {
       const uint32_t w = u_word[q];
       const uint32_t bin = W16 ? (w >> 16) : (uint32_t)u_bin[q];
-      const int32_t p = loff[bin] + (int32_t)u_rank[q];
-      s_word[p] = w;
-      if (!W16) s_bin[p] = (uint16_t)bin;
-      if (NUMERIC) s_val[p] = u_val[q];
+      s_idx[loff[bin] + (int32_t)u_rank[q]] = (uint16_t)q;
     }
   }
   __syncthreads();
   if (SORTED) {
-    for (int32_t p = threadIdx.x; p < nloc; p += BIN_BS) {
-      const uint32_t w = s_word[p];
-      const uint32_t bin = W16 ? (w >> 16) : (uint32_t)s_bin[p];
+    for (int32_t p = threadIdx.x; p < nloc; p += BS) {
+      const int32_t q = s_idx[p];
+      const uint32_t w = u_word[q];
+      const uint32_t bin = W16 ? (w >> 16) : (uint32_t)u_bin[q];
       const int64_t d = dst[bin] + (p - loff[bin]);
       st_stream<HINT_WS_STORE>(&ws_col[d], W16 ? (LC)(w & 0xFFFFu) : (LC)w);
-      if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], s_val[p]);
+      if (NUMERIC) st_stream<HINT_WS_STORE>(&ws_val[d], u_val[q]);
     }
   } else {
-    for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
+    for (int32_t q = threadIdx.x; q < nloc; q += BS) {
       const uint32_t w = u_word[q];
       const uint32_t bin = W16 ? (w >> 16) : (uint32_t)u_bin[q];
       const int64_t d = dst[bin] + u_rank[q];
@@ -1697,35 +1704,46 @@ hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile
 }
 
 hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
-                               int lc32, int sorted, const int32_t* tile_row, const int64_t* aoff,
+                               int lc32, int sorted, int block, const int32_t* tile_row, const int64_t* aoff,
                                const int64_t* tile_e0, const int64_t* bin_start,
                                unsigned long long* bin_cursor, void* ws_col, void* ws_val,
                                int64_t max_nb, hipStream_t st) {
   if (b.ntiles <= 0) return hipSuccess;
-  const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb, lc32, sorted);
-  const int64_t cap = max_grid(BIN_BS);
+  // the chunk-order index is 16-bit
+  if (sorted && g.tile > 65536) return hipErrorInvalidValue;
+  const size_t lds = bin_scatter2_lds(M.f64, g.tile, max_nb, lc32, sorted, block);
+  const int bs = scatter2_block(lc32, sorted, block);
+  if (bs != 256 && bs != 512 && bs != 1024) return hipErrorInvalidValue;
+  const int64_t cap = max_grid(bs);
   for (int64_t o = 0; o < b.ntiles; o += cap) {
     BatchArgs bp = b;
     bp.tile0 = b.tile0 + o;
     bp.ntiles = std::min(cap, b.ntiles - o);
-#define MG_SC2(V, LC)                                                                             \
+    // 32-bit columns: the chunk-ordered form at bs threads
+#define MG_SC2_BS(BSZ, V, LC)                                                                     \
   MG_DISPATCH2(M, {                                                                               \
-    auto kf = numeric ? (sorted ? k_bin_scatter2<RP, CI, V, LC, true, true>                        \
-                                : k_bin_scatter2<RP, CI, V, LC, true, false>)                      \
-                      : (sorted ? k_bin_scatter2<RP, CI, V, LC, false, true>                       \
-                                : k_bin_scatter2<RP, CI, V, LC, false, false>);                    \
+    auto kf = numeric ? (sorted ? k_bin_scatter2<BSZ, RP, CI, V, LC, true, true>                   \
+                                : k_bin_scatter2<BIN_BS, RP, CI, V, LC, true, false>)              \
+                      : (sorted ? k_bin_scatter2<BSZ, RP, CI, V, LC, false, true>                  \
+                                : k_bin_scatter2<BIN_BS, RP, CI, V, LC, false, false>);            \
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-    hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, (const RP*)M.arp,                \
+    hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, bs, lds, st, (const RP*)M.arp,                    \
                        (const CI*)M.acol, (const V*)M.aval, (const RP*)M.brp, (const CI*)M.bcol,  \
                        (const V*)M.bval, g, bp, tile_row, aoff, tile_e0, bin_start, bin_cursor,   \
                        (LC*)ws_col, (V*)ws_val);                                                  \
   });
     if (lc32) {
-      if (M.f64) { MG_SC2(double, uint32_t) } else { MG_SC2(float, uint32_t) }
+      if (bs == 1024) {
+        if (M.f64) { MG_SC2_BS(1024, double, uint32_t) } else { MG_SC2_BS(1024, float, uint32_t) }
+      } else if (bs == 512) {
+        if (M.f64) { MG_SC2_BS(512, double, uint32_t) } else { MG_SC2_BS(512, float, uint32_t) }
+      } else {
+        if (M.f64) { MG_SC2_BS(256, double, uint32_t) } else { MG_SC2_BS(256, float, uint32_t) }
+      }
     } else {
-      if (M.f64) { MG_SC2(double, uint16_t) } else { MG_SC2(float, uint16_t) }
+      if (M.f64) { MG_SC2_BS(BIN_BS, double, uint16_t) } else { MG_SC2_BS(BIN_BS, float, uint16_t) }
     }
-#undef MG_SC2
+#undef MG_SC2_BS
   }
   return hipGetLastError();
 }

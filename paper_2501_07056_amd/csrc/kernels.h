@@ -210,12 +210,13 @@ hipError_t launch_row_bitmap(const Mats& M, const ChunkGeom& g, const int64_t* a
                              int64_t* rownnz, hipStream_t st);
 // reorder with chunk ranges reserved by atomic adds on bin cursors (count
 // mode: columns only); ws_col holds uint16 (lc32 = 0) or uint32 (lc32 = 1)
-// chunk-local columns
-// chunk-local columns; sorted = 1 permutes each tile into chunk order in LDS
-// before the write-out
-size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb, int lc32, int sorted);
+// chunk-local columns; sorted = 1 writes each tile out in chunk order
+// (an index permutation in LDS).  block: the workgroup size of the sorted
+// 32-bit form (256, 512 or 1024; 0 for the default), BIN_BS otherwise
+size_t bin_scatter2_lds(int f64, int tile, int64_t max_nb, int lc32, int sorted, int block);
 hipError_t launch_bin_scatter2(const Mats& M, const ChunkGeom& g, const BatchArgs& b, bool numeric,
-                               int lc32, int sorted, const int32_t* tile_row, const int64_t* aoff,
+                               int lc32, int sorted, int block, const int32_t* tile_row,
+                               const int64_t* aoff,
                                const int64_t* tile_e0, const int64_t* bin_start,
                                unsigned long long* bin_cursor, void* ws_col, void* ws_val,
                                int64_t max_nb, hipStream_t st);

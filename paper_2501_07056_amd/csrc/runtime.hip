@@ -439,7 +439,7 @@ magnus_status_t chunked_symbolic(magnus_plan_s* P) {
     HIPCHK(launch_bin_group(P->g, b, P->bin_cnt, P->dense_min, P->group_max, P->dense_items,
                             P->sort_items, ic, P->st));
     HIPCHK(launch_fill_i64((int64_t*)P->bin_cursor + b.bin0, b.nbins, 0, P->st));
-    HIPCHK(launch_bin_scatter2(P->M, P->g, b, false, 0, P->sorted_out, P->tile_row, P->aoff,
+    HIPCHK(launch_bin_scatter2(P->M, P->g, b, false, 0, P->sorted_out, 0, P->tile_row, P->aoff,
                                P->tile_e0, P->bin_start, P->bin_cursor, P->ws_col, P->ws_val,
                                P->max_nb, P->st));
     unsigned int* wk = P->work_ctr + 4 * bi;
@@ -496,7 +496,7 @@ magnus_status_t chunked_numeric(magnus_plan_s* P, void* ccol, int col64, void* c
                                       P->ws_val, P->max_nb, P->st));
       } else {
         ProfScope ps(h, P->st, "bin_scatter (numeric reorder)", bytes);
-        HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, 0, P->sorted_out, P->tile_row, P->aoff,
+        HIPCHK(launch_bin_scatter2(P->M, P->g, b, true, 0, P->sorted_out, 0, P->tile_row, P->aoff,
                                    P->tile_e0, P->bin_start, P->bin_cursor, P->ws_col, P->ws_val,
                                    P->max_nb, P->st));
       }
@@ -713,7 +713,8 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
                            C.scan_temp, P->st));
       HIPCHK(launch_fill_i64((int64_t*)C.cur1 + b.bin0, b.nbins, 0, P->st));
       HIPCHK(launch_bin_scatter2(P->M, g1, b, C.keep_ws1, 1,
-                                 C.keep_ws1 ? C.sorted1 : C.sorted1_sym, C.tile_row1, P->aoff,
+                                 C.keep_ws1 ? C.sorted1 : C.sorted1_sym, C.block1, C.tile_row1,
+                                 P->aoff,
                                  C.tile_e0, C.start1, C.cur1, w1c, w1v, C.max_nb1, P->st));
     }
     cb.big = C.big_all + b.bin0;
@@ -794,7 +795,7 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
       ProfScope ps(h, P->st, "coarse_scatter (numeric, level 1)",
                    (double)b.nip * (P->s_col + vs + 4 + vs) +
                        (double)b.nent * (P->s_col + vs + 8 + P->s_rp));
-      HIPCHK(launch_bin_scatter2(P->M, C.g1, b, true, 1, C.sorted1, C.tile_row1, P->aoff,
+      HIPCHK(launch_bin_scatter2(P->M, C.g1, b, true, 1, C.sorted1, C.block1, C.tile_row1, P->aoff,
                                  C.tile_e0, C.start1, C.cur1, w1c, w1v, C.max_nb1, P->st));
     }
     {
@@ -1155,7 +1156,7 @@ magnus_status_t plan_once(magnus_handle_t h, const magnus_csr_t* A, const magnus
     // the reorder kernels keep per-chunk counters of a row in LDS: shrink the
     // tile if they and the staged tile do not fit
     auto fits = [&](int tile) {
-      return bin_scatter2_lds(M.f64, tile, P->max_nb, 0, P->sorted_out) <= (size_t)h->lds_max &&
+      return bin_scatter2_lds(M.f64, tile, P->max_nb, 0, P->sorted_out, 0) <= (size_t)h->lds_max &&
              (!P->det || bin_scatter_det_lds(M.f64, tile, P->max_nb) <= (size_t)h->lds_max);
     };
     while (P->tile > 256 && !fits(P->tile)) P->tile /= 2;
@@ -1179,14 +1180,33 @@ magnus_status_t plan_once(magnus_handle_t h, const magnus_csr_t* A, const magnus
     // beyond
     Co.sorted1 = Co.max_nb1 > MG_COARSE_SORTED_MIN ? 1 : 0;
     Co.sorted1_sym = Co.max_nb1 > MG_COARSE_SORTED_SYM_MIN ? 1 : 0;
-    Co.tile1 = Co.sorted1 ? 4096 : 1024;
+    // chunk-ordered tiles fill the LDS of a CU, one workgroup each: the
+    // longest tile (up to 8192 products, longer runs per chunk) that fits
+    // with 1024 threads, else with 512 (the gathers of more waves in flight).
+    // Uniform 2^28 columns, first reorder: 8192 x 256 threads 86.7 ms, 8192 x
+    // 512 58.9, 8192 x 1024 48.0; 2^30: 8192 x 512 72.8, 4096 x 1024 103.9
+    Co.tile1 = Co.sorted1 ? 8192 : 1024;
+    Co.block1 = 0;
     if (o.tile_products > 0) Co.tile1 = P->tile;
-    while (Co.tile1 > 256 &&
-           bin_scatter2_lds(M.f64, Co.tile1, Co.max_nb1, 1, Co.sorted1) > (size_t)h->lds_max)
+    if (Co.sorted1) {
+      auto fits1 = [&](int t, int bk) {
+        return bin_scatter2_lds(M.f64, t, Co.max_nb1, 1, 1, bk) <= (size_t)h->lds_max;
+      };
+      const int t0 = Co.tile1;
+      Co.block1 = 256;
+      for (int t = t0; t >= 256; t /= 2) {
+        if (fits1(t, 1024)) { Co.tile1 = t; Co.block1 = 1024; break; }
+        if (fits1(t, 512)) { Co.tile1 = t; Co.block1 = 512; break; }
+        if (o.tile_products > 0) break;  // the set tile at 256 threads
+      }
+    }
+    while (Co.tile1 > 256 && bin_scatter2_lds(M.f64, Co.tile1, Co.max_nb1, 1, Co.sorted1,
+                                              Co.block1) > (size_t)h->lds_max)
       Co.tile1 /= 2;
     while (Co.tile2 > 256 && l2_scatter_lds(M.f64, Co.tile2, Co.max_nb2) > (size_t)h->lds_max)
       Co.tile2 /= 2;
-    if (bin_scatter2_lds(M.f64, Co.tile1, Co.max_nb1, 1, Co.sorted1) > (size_t)h->lds_max ||
+    if (bin_scatter2_lds(M.f64, Co.tile1, Co.max_nb1, 1, Co.sorted1, Co.block1) >
+            (size_t)h->lds_max ||
         l2_scatter_lds(M.f64, Co.tile2, Co.max_nb2) > (size_t)h->lds_max) {
       h->err = "too many coarse chunks per row for the LDS";
       return cleanup(MAGNUS_ERR_INVALID_ARG);

@@ -20,10 +20,12 @@
 #define MG_SORTED_OUT 0
 #endif
 // the coarse level's first reorder writes in chunk order when rows span more
-// coarse chunks than this (short runs per chunk in the expansion order); the
-// symbolic phase's reorder (columns only) gains from it only further on
+// coarse chunks than this (short runs per chunk in the expansion order;
+// uniform 2^26 columns, 66 coarse chunks: 133.4 -> 124.0 ms per step, 2^27:
+// 158.2 -> 132.2); the symbolic phase's reorder (columns only) gains from
+// it only further on
 #ifndef MG_COARSE_SORTED_MIN
-#define MG_COARSE_SORTED_MIN 256
+#define MG_COARSE_SORTED_MIN 32
 #endif
 #ifndef MG_COARSE_SORTED_SYM_MIN
 #define MG_COARSE_SORTED_SYM_MIN 512
@@ -209,6 +211,7 @@ struct magnus_plan_s {
   struct Coarse {
     int64_t nrows = 0, coarse_range = 0, max_nb1 = 1, max_nb2 = 1, nv = 0, nbins2 = 0;
     int cshift = 20, tile1 = 4096, tile2 = MG_L2_TILE, sorted1 = 1, sorted1_sym = 1;
+    int block1 = 0;  // workgroup size of the chunk-ordered first reorder (0: default)
     ChunkGeom g1{};
     std::vector<BatchArgs> b1;  // level-1 batches
     std::vector<CBatch> cb;     // their level-2 parts
