@@ -837,20 +837,26 @@ __global__ void __launch_bounds__(VB_BS)
 // lanes store consecutive addresses of one chunk's run (the staging order
 // interleaves the chunks: inside a coarse chunk, neighbouring products
 // seldom share a fine chunk).  16-bit chunk-local columns.
+// The level-2 reorder writes each tile out in fine-chunk order through a
+// 16-bit index per position (as the first reorder), MG_L2_BS threads per
+// tile.
+#ifndef MG_L2_BS
+#define MG_L2_BS 1024
+#endif
 size_t l2_scatter_lds(int f64, int tile, int64_t max_nb2) {
   const size_t vs = f64 ? 8 : 4;
   return (size_t)max_nb2 * (4 + 4 + 8) + 3 * 16 + (size_t)tile * (4 + 4 + vs) +
-         (size_t)tile * (4 + vs) + 16 + (BIN_BS / MG_WAVE) * 4 + 64;
+         (size_t)tile * 2 + 16 + 64;
 }
 
-template <typename V, bool NUMERIC>
-__global__ void __launch_bounds__(BIN_BS)
+template <int BS, typename V, bool NUMERIC>
+__global__ void __launch_bounds__(BS)
     k_l2_scatter(ChunkGeom g2, BatchArgs b2, const int32_t* __restrict__ tile_row2,
                  const int64_t* __restrict__ start1, const uint32_t* __restrict__ ws1_col,
                  const V* __restrict__ ws1_val, const int64_t* __restrict__ bin_start2,
                  unsigned long long* bin_cursor2, uint16_t* ws2_col, V* ws2_val) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  __shared__ int32_t s_tmp[BIN_BS / MG_WAVE];
+  __shared__ int32_t s_tmp[BS / MG_WAVE];
   const int64_t tg = b2.tile0 + blockIdx.x;
   const int64_t k = tile_row2[tg];
   const int64_t ti = tg - g2.tileBase[k];
@@ -869,22 +875,21 @@ __global__ void __launch_bounds__(BIN_BS)
   uint32_t* u_word = (uint32_t*)(dst + nbk);
   uint32_t* u_rank = u_word + g2.tile;
   V* u_val = (V*)al16(u_rank + g2.tile);
-  uint32_t* s_word = (uint32_t*)(u_val + g2.tile);
-  V* s_val = (V*)al16(s_word + g2.tile);
-  for (int64_t q = threadIdx.x; q < nbk; q += BIN_BS) hist[q] = 0;
+  uint16_t* s_idx = (uint16_t*)al16(u_val + g2.tile);  // staged product at each position
+  for (int64_t q = threadIdx.x; q < nbk; q += BS) hist[q] = 0;
   __syncthreads();
-  for (int32_t qb = threadIdx.x; qb < nloc; qb += 4 * BIN_BS) {
+  for (int32_t qb = threadIdx.x; qb < nloc; qb += 4 * BS) {
     uint32_t c4[4];
     V v4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int32_t q = qb + u * BIN_BS;
+      const int32_t q = qb + u * BS;
       c4[u] = (q < nloc) ? ld_stream<HINT_WS_LOAD>(&ws1_col[s0 + q]) : 0u;
       v4[u] = (NUMERIC && q < nloc) ? ld_stream<HINT_WS_LOAD>(&ws1_val[s0 + q]) : (V)0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int32_t q = qb + u * BIN_BS;
+      const int32_t q = qb + u * BS;
       if (q < nloc) {
         const uint32_t f = c4[u] >> sh;
         int hl, len;
@@ -899,27 +904,26 @@ __global__ void __launch_bounds__(BIN_BS)
     }
   }
   __syncthreads();
-  block_excl_scan<BIN_BS>(hist, loff, nbk, s_tmp);
-  for (int64_t q = threadIdx.x; q < nbk; q += BIN_BS) {
+  block_excl_scan<BS>(hist, loff, nbk, s_tmp);
+  for (int64_t q = threadIdx.x; q < nbk; q += BS) {
     const int h = hist[q];
     if (h > 0) {
       const unsigned long long r = atomicAdd(&bin_cursor2[gb + q], (unsigned long long)h);
       dst[q] = bin_start2[gb + q] + (int64_t)r;
     }
   }
-  for (int32_t q = threadIdx.x; q < nloc; q += BIN_BS) {
+  for (int32_t q = threadIdx.x; q < nloc; q += BS) {
     const uint32_t w = u_word[q];
-    const int32_t p = loff[w >> 16] + (int32_t)u_rank[q];
-    s_word[p] = w;
-    if (NUMERIC) s_val[p] = u_val[q];
+    s_idx[loff[w >> 16] + (int32_t)u_rank[q]] = (uint16_t)q;
   }
   __syncthreads();
-  for (int32_t p = threadIdx.x; p < nloc; p += BIN_BS) {
-    const uint32_t w = s_word[p];
+  for (int32_t p = threadIdx.x; p < nloc; p += BS) {
+    const int32_t q = s_idx[p];
+    const uint32_t w = u_word[q];
     const uint32_t f = w >> 16;
     const int64_t d = dst[f] + (p - loff[f]);
     st_stream<HINT_WS_STORE>(&ws2_col[d], (uint16_t)(w & 0xFFFFu));
-    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws2_val[d], s_val[p]);
+    if (NUMERIC) st_stream<HINT_WS_STORE>(&ws2_val[d], u_val[q]);
   }
 }
 
@@ -1849,17 +1853,18 @@ hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool nume
                              const int64_t* bin_start2, unsigned long long* bin_cursor2,
                              uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, hipStream_t st) {
   if (b2.ntiles <= 0) return hipSuccess;
+  if (g2.tile > 65536) return hipErrorInvalidValue;  // 16-bit positions
   const size_t lds = l2_scatter_lds(f64, g2.tile, max_nb2);
-  const int64_t cap = max_grid(BIN_BS);
+  const int64_t cap = max_grid(MG_L2_BS);
 #define MG_L2(V)                                                                                  \
   {                                                                                               \
-    auto kf = numeric ? k_l2_scatter<V, true> : k_l2_scatter<V, false>;                           \
+    auto kf = numeric ? k_l2_scatter<MG_L2_BS, V, true> : k_l2_scatter<MG_L2_BS, V, false>;       \
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     for (int64_t o = 0; o < b2.ntiles; o += cap) {                                                \
       BatchArgs bp = b2;                                                                          \
       bp.tile0 = b2.tile0 + o;                                                                    \
       bp.ntiles = std::min(cap, b2.ntiles - o);                                                   \
-      hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BIN_BS, lds, st, g2, bp, tile_row2, start1,     \
+      hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, MG_L2_BS, lds, st, g2, bp, tile_row2, start1,   \
                          ws1_col, (const V*)ws1_val, bin_start2, bin_cursor2, ws2_col,            \
                          (V*)ws2_val);                                                            \
     }                                                                                             \
