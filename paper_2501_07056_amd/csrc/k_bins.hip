@@ -861,8 +861,8 @@ __global__ void __launch_bounds__(VB_BS)
 // interleaves the chunks: inside a coarse chunk, neighbouring products
 // seldom share a fine chunk).  16-bit chunk-local columns.
 // The level-2 reorder writes each tile out in fine-chunk order through a
-// 16-bit index per position (as the first reorder), MG_L2_BS threads per
-// tile.
+// 16-bit index per position (as the first reorder), 1024 threads per tile
+// (MG_L2_BS) unless the caller asks for 256.
 #ifndef MG_L2_BS
 #define MG_L2_BS 1024
 #endif
@@ -1874,25 +1874,32 @@ hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool nume
                              const int32_t* tile_row2, const int64_t* start1,
                              const uint32_t* ws1_col, const void* ws1_val,
                              const int64_t* bin_start2, unsigned long long* bin_cursor2,
-                             uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, hipStream_t st) {
+                             uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, int block,
+                             hipStream_t st) {
   if (b2.ntiles <= 0) return hipSuccess;
   if (g2.tile > 65536) return hipErrorInvalidValue;  // 16-bit positions
+  const int bs = block > 0 ? block : MG_L2_BS;
+  if (bs != 256 && bs != 1024) return hipErrorInvalidValue;
   const size_t lds = l2_scatter_lds(f64, g2.tile, max_nb2);
-  const int64_t cap = max_grid(MG_L2_BS);
-#define MG_L2(V)                                                                                  \
+  const int64_t cap = max_grid(bs);
+#define MG_L2(BSZ, V)                                                                             \
   {                                                                                               \
-    auto kf = numeric ? k_l2_scatter<MG_L2_BS, V, true> : k_l2_scatter<MG_L2_BS, V, false>;       \
+    auto kf = numeric ? k_l2_scatter<BSZ, V, true> : k_l2_scatter<BSZ, V, false>;                 \
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
     for (int64_t o = 0; o < b2.ntiles; o += cap) {                                                \
       BatchArgs bp = b2;                                                                          \
       bp.tile0 = b2.tile0 + o;                                                                    \
       bp.ntiles = std::min(cap, b2.ntiles - o);                                                   \
-      hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, MG_L2_BS, lds, st, g2, bp, tile_row2, start1,   \
+      hipLaunchKernelGGL(kf, (unsigned)bp.ntiles, BSZ, lds, st, g2, bp, tile_row2, start1,        \
                          ws1_col, (const V*)ws1_val, bin_start2, bin_cursor2, ws2_col,            \
                          (V*)ws2_val);                                                            \
     }                                                                                             \
   }
-  if (f64) MG_L2(double) else MG_L2(float)
+  if (bs == 1024) {
+    if (f64) MG_L2(1024, double) else MG_L2(1024, float)
+  } else {
+    if (f64) MG_L2(256, double) else MG_L2(256, float)
+  }
 #undef MG_L2
   return hipGetLastError();
 }

@@ -257,13 +257,14 @@ hipError_t launch_vrow_bitmap(const ChunkGeom& g2, int cshift, int64_t k0, int64
                               int64_t* bin_cnt2, int64_t* bin_nnz2, int32_t* bin_row2,
                               int64_t* vnnz, hipStream_t st);
 // level-2 reorder of the tiles of b2 (first workspace -> second; count
-// mode: columns only)
+// mode: columns only); block: 256 or 1024 threads per tile (0: 1024)
 size_t l2_scatter_lds(int f64, int tile, int64_t max_nb2);
 hipError_t launch_l2_scatter(const ChunkGeom& g2, const BatchArgs& b2, bool numeric, int f64,
                              const int32_t* tile_row2, const int64_t* start1,
                              const uint32_t* ws1_col, const void* ws1_val,
                              const int64_t* bin_start2, unsigned long long* bin_cursor2,
-                             uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, hipStream_t st);
+                             uint16_t* ws2_col, void* ws2_val, int64_t max_nb2, int block,
+                             hipStream_t st);
 // first A entry of every tile
 hipError_t launch_tile_e0(const Mats& M, const ChunkGeom& g, const int32_t* tile_row,
                           const int64_t* aoff, int64_t ntiles, int64_t* tile_e0, hipStream_t st);

@@ -579,6 +579,16 @@ magnus_status_t setup_coarse(magnus_plan_s* P) {
   // all the coarse rows' products fit the workspace cap (max_workspace_bytes,
   // else a quarter of the device memory)
   C.ip_total = tots[0];
+  // coarse chunks of few products on average (rows over 512 coarse chunks
+  // wide): level-2 tiles of 2048 products at 256 threads, where one coarse
+  // chunk of about a thousand products would leave most of 1024 threads idle
+  // (uniform 2^30 columns: level-2 count and reorder 42.6 + 12.9 ms at
+  // 2048 x 256, 51.7 + 22.4 at 4096 x 1024)
+  C.l2_block = 1024;
+  if (C.ip_total < (int64_t)MG_L2_SMALL * std::max<int64_t>(1, nv)) {
+    C.tile2 = std::min(C.tile2, 2048);
+    C.l2_block = 256;
+  }
   {
     int64_t cap = h->opts.max_workspace_bytes;
     if (cap <= 0) {
@@ -759,7 +769,8 @@ magnus_status_t coarse_symbolic(magnus_plan_s* P) {
                                 cb.sort2, ic, P->st));
         HIPCHK(launch_fill_i64((int64_t*)cb.cur2, b2.nbins, 0, P->st));
         HIPCHK(launch_l2_scatter(g2, b2, false, P->M.f64, cb.tile_row2, C.start1, w1c, w1v,
-                                 cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2, P->st));
+                                 cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2, C.l2_block,
+                                 P->st));
         unsigned int* wk = C.work + 4 * bi + 2;
         HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));
         HIPCHK(launch_bin_accum(g2, b2, false, P->M.f64, cb.start2, cb.cnt2, cb.row2, cb.dense2,
@@ -816,7 +827,8 @@ magnus_status_t coarse_numeric(magnus_plan_s* P, void* ccol, int col64, void* cv
       ProfScope ps(h, P->st, "fine_scatter (numeric, level 2)",
                    (double)b2.nip * (4 + vs + 2 + vs));
       HIPCHK(launch_l2_scatter(cb.g2, b2, true, P->M.f64, cb.tile_row2, C.start1, w1c, w1v,
-                               cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2, P->st));
+                               cb.start2, cb.cur2, C.ws2_col, C.ws2_val, C.max_nb2, C.l2_block,
+                               P->st));
     }
     unsigned int* wk = C.work + 4 * bi;
     HIPCHK(launch_fill_i64((int64_t*)wk, 1, 0, P->st));

@@ -36,6 +36,11 @@
 #ifndef MG_L2_TILE
 #define MG_L2_TILE 4096
 #endif
+// below this many products per coarse chunk on average, level-2 tiles of
+// 2048 at 256 threads
+#ifndef MG_L2_SMALL
+#define MG_L2_SMALL 2048
+#endif
 // coarse chunks with at least 2^cshift / MG_BITMAP_DENSITY products (on
 // average) are counted with a bitmap in the symbolic phase (measured on
 // uniform rows: the bitmap is faster at 1/128, the count-mode accumulators
@@ -215,6 +220,7 @@ struct magnus_plan_s {
     int64_t nrows = 0, coarse_range = 0, max_nb1 = 1, max_nb2 = 1, nv = 0, nbins2 = 0;
     int cshift = 20, tile1 = 4096, tile2 = MG_L2_TILE, sorted1 = 1, sorted1_sym = 1;
     int block1 = 0;  // workgroup size of the chunk-ordered first reorder (0: default)
+    int l2_block = 1024;  // workgroup size of the level-2 reorder
     ChunkGeom g1{};
     std::vector<BatchArgs> b1;  // level-1 batches
     std::vector<CBatch> cb;     // their level-2 parts

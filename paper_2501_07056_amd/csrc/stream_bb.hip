@@ -114,7 +114,7 @@ extern "C" magnus_status_t magnus_stream_chunks(magnus_handle_t h, const uint32_
   // reorder
   SB(launch_fill_i64((int64_t*)cursor, nb, 0, tmp.st));
   SB(launch_l2_scatter(g, b, true, f64, tile_row, geo + 9, cols, vals, start, cursor, ws_col,
-                       ws_val, nb, tmp.st));
+                       ws_val, nb, 0, tmp.st));
   SB(hipEventRecord(ev[3], tmp.st));
   // chunks to work items: dense chunks, packed sorts of small ones
   SB(launch_bin_group(g, b, cnt, dmin, SORT_CAP, dense_items, sort_items, item_counts, tmp.st));
