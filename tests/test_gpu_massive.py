@@ -15,7 +15,8 @@ from test_gpu_fullsize import _check_rows
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("log_mc,coarse", [(18, 0), (22, 0), (27, 0), (27, -1), (28, 0), (31, 0)])
+@pytest.mark.parametrize("log_mc,coarse",
+                         [(18, 0), (22, 0), (27, 0), (27, -1), (28, 0), (30, 0), (31, 0)])
 def test_massive_er_sampled(log_mc, coarse):
     import torch
 
@@ -32,10 +33,14 @@ def test_massive_er_sampled(log_mc, coarse):
         p.destroy()
         assert info["ip_total"] == 1024 * 512 * 512
         # one coarse chunk spans 2^20 columns under the full LDS budget;
-        # coarse chunks of <= 1024 products skip the fine level (2^31: about
-        # 128 products each)
+        # coarse chunks of <= 1024 products skip the fine level (2^30: about
+        # 256 products each, 2^31: about 128).  The first reorder runs its
+        # longest tiles at 1024 threads up to 2^28 columns, at 512 threads
+        # at 2^30 (over 512 coarse chunks per row); the level-2 reorder runs
+        # 1024 threads at 2^22 and 256 at 2^27 and 2^28 (coarse chunks of
+        # about 2^11 and 2^10 products)
         assert (info["coarse_rows"] > 0) == (coarse == 0 and log_mc > 20)
-        if log_mc == 31:
+        if log_mc in (30, 31):
             assert info["coarse_fine_chunks"] == 0
         if log_mc in (22, 27) and coarse == 0:
             assert info["coarse_fine_chunks"] > 0
