@@ -16,6 +16,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "admission.h"
 #include "runtime_int.h"
@@ -70,84 +71,175 @@ void done_cb(void* p) {
   B->done.store(1);
 }
 
-// Device memory of the server: a caching allocator over hipMalloc.  Large
-// blocks (C of a big request, CHUNKED workspaces) are recycled instead of
-// being returned to the driver, which would clear fresh pages again on the
-// next allocation.  A freed block records an event on the stream that last
-// used it; a later allocation on another stream waits for that event on the
-// device (no host wait).  Blocks go back to the driver only when hipMalloc
-// fails, and when the server is destroyed.
+// Device memory of the server: a caching allocator over hipMalloc that
+// splits and coalesces.  Memory is taken from the driver in slabs (at least
+// SLAB bytes, so that small plan arrays share one), handed out best fit
+// from the free spans of all slabs (a span larger than the request is
+// split), and given back as a span that merges with its free neighbours in
+// the same slab.  Freed memory records an event on the stream that last
+// used it; a later allocation on another stream waits for it on the device
+// (no host wait).  Slabs go back to the driver only when wholly free and
+// hipMalloc fails, and when the server is destroyed.  (A cache of whole
+// blocks reused only at up to twice their size called hipMalloc and hipFree
+// hundreds of times in a serving run, seconds on the scheduler thread.)
 struct DevCache {
-  struct Blk {
-    void* p;
-    size_t n;
-    hipEvent_t ev;
-  };
-  std::mutex mu;
-  std::multimap<size_t, Blk> free_;
-  std::unordered_map<void*, size_t> live;
-
-  static size_t round(size_t n) {
-    const size_t g = n < ((size_t)1 << 24) ? 256 : ((size_t)2 << 20);
-    return (n + g - 1) / g * g;
-  }
-  void drop_free_locked() {
-    for (auto& kv : free_) {
-      if (kv.second.ev) {
-        (void)hipEventSynchronize(kv.second.ev);
-        (void)hipEventDestroy(kv.second.ev);
-      }
-      (void)hipFree(kv.second.p);
+  struct Ev {
+    hipEvent_t e = nullptr;
+    ~Ev() {
+      if (e) (void)hipEventDestroy(e);
     }
-    free_.clear();
+  };
+  using EvList = std::vector<std::shared_ptr<Ev>>;
+  struct Slab {
+    char* base;
+    size_t n;
+  };
+  struct Span {
+    size_t n;
+    Slab* slab;
+    EvList ev;
+  };
+  static constexpr size_t SLAB = (size_t)1 << 30;
+  std::mutex mu;
+  std::vector<std::unique_ptr<Slab>> slabs;
+  std::map<char*, Span> free_;               // by address
+  std::multimap<size_t, char*> by_size;      // free spans by size
+  std::unordered_map<void*, std::pair<size_t, Slab*>> live;
+
+  static size_t round(size_t n) { return (n + 255) & ~(size_t)255; }
+  void erase_size(size_t n, char* p) {
+    auto r = by_size.equal_range(n);
+    for (auto it = r.first; it != r.second; ++it)
+      if (it->second == p) {
+        by_size.erase(it);
+        return;
+      }
+  }
+  static void prune(EvList& ev) {
+    EvList keep;
+    for (auto& e : ev)
+      if (e && e->e && hipEventQuery(e->e) != hipSuccess) keep.push_back(e);
+    ev.swap(keep);
+  }
+  void put(char* p, Span sp) {
+    prune(sp.ev);
+    by_size.emplace(sp.n, p);
+    free_.emplace(p, std::move(sp));
+  }
+  // slabs wholly free go back to the driver
+  void drop_free_locked() {
+    for (auto it = slabs.begin(); it != slabs.end();) {
+      Slab* sl = it->get();
+      auto f = free_.find(sl->base);
+      if (f != free_.end() && f->second.n == sl->n) {
+        for (auto& e : f->second.ev)
+          if (e && e->e) (void)hipEventSynchronize(e->e);
+        erase_size(f->second.n, f->first);
+        free_.erase(f);
+        (void)hipFree(sl->base);
+        it = slabs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  void add_slab(void* p, size_t n) {
+    slabs.emplace_back(new Slab{(char*)p, n});
+    put((char*)p, Span{n, slabs.back().get(), {}});
+  }
+  // a new slab that holds n bytes: SLAB for small requests, else n rounded
+  // up to 2 MiB; when the driver refuses, the wholly free slabs go back and
+  // the slab, then the exact size, is tried again
+  bool grow(size_t n) {
+    const size_t g = (size_t)2 << 20;
+    const size_t sn = n < SLAB ? SLAB : (n + g - 1) / g * g;
+    void* p = nullptr;
+    if (hipMalloc(&p, sn) == hipSuccess) {
+      add_slab(p, sn);
+      return true;
+    }
+    (void)hipGetLastError();
+    drop_free_locked();
+    if (hipMalloc(&p, sn) == hipSuccess) {
+      add_slab(p, sn);
+      return true;
+    }
+    (void)hipGetLastError();
+    if (sn != n && hipMalloc(&p, n) == hipSuccess) {
+      add_slab(p, n);
+      return true;
+    }
+    (void)hipGetLastError();
+    return false;
   }
   void* alloc(size_t n, hipStream_t st) {
     n = round(n ? n : 1);
     std::lock_guard<std::mutex> lk(mu);
-    // best fit, without spending a block more than twice the size (or
-    // 64 MiB above it) on a smaller request
-    auto it = free_.lower_bound(n);
-    if (it != free_.end() && it->first <= std::max(2 * n, n + ((size_t)64 << 20))) {
-      Blk b = it->second;
-      free_.erase(it);
-      if (b.ev) {
-        if (hipEventQuery(b.ev) != hipSuccess) (void)hipStreamWaitEvent(st, b.ev, 0);
-        (void)hipEventDestroy(b.ev);
-      }
-      live[b.p] = b.n;
-      return b.p;
+    auto it = by_size.lower_bound(n);
+    if (it == by_size.end()) {
+      if (!grow(n)) return nullptr;
+      it = by_size.lower_bound(n);
+      if (it == by_size.end()) return nullptr;
     }
-    void* p = nullptr;
-    if (hipMalloc(&p, n) != hipSuccess) {
-      (void)hipGetLastError();
-      drop_free_locked();
-      if (hipMalloc(&p, n) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-      }
-    }
-    live[p] = n;
+    char* p = it->second;
+    by_size.erase(it);
+    auto f = free_.find(p);
+    Span sp = std::move(f->second);
+    free_.erase(f);
+    for (auto& e : sp.ev)
+      if (e && e->e && hipEventQuery(e->e) != hipSuccess) (void)hipStreamWaitEvent(st, e->e, 0);
+    if (sp.n > n) put(p + n, Span{sp.n - n, sp.slab, sp.ev});
+    live[p] = {n, sp.slab};
     return p;
   }
-  void release(void* p, hipStream_t st) {
-    if (!p) return;
+  void release(void* vp, hipStream_t st) {
+    if (!vp) return;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = live.find(p);
+    auto it = live.find(vp);
     if (it == live.end()) return;
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
-        hipEventRecord(ev, st) != hipSuccess) {
-      (void)hipEventDestroy(ev);
-      ev = nullptr;
+    char* p = (char*)vp;
+    Span sp{it->second.first, it->second.second, {}};
+    live.erase(it);
+    auto ev = std::make_shared<Ev>();
+    if (hipEventCreateWithFlags(&ev->e, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(ev->e, st) == hipSuccess) {
+      sp.ev.push_back(ev);
+    } else {
       (void)hipStreamSynchronize(st);
     }
-    free_.emplace(it->second, Blk{p, it->second, ev});
-    live.erase(it);
+    // merge with the free span after it, then with the one before it, in
+    // the same slab
+    auto nx = free_.find(p + sp.n);
+    if (nx != free_.end() && nx->second.slab == sp.slab) {
+      sp.n += nx->second.n;
+      sp.ev.insert(sp.ev.end(), nx->second.ev.begin(), nx->second.ev.end());
+      erase_size(nx->second.n, nx->first);
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(p);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->second.slab == sp.slab && pv->first + pv->second.n == p) {
+        char* q = pv->first;
+        Span m = std::move(pv->second);
+        erase_size(m.n, q);
+        free_.erase(pv);
+        m.n += sp.n;
+        m.ev.insert(m.ev.end(), sp.ev.begin(), sp.ev.end());
+        put(q, std::move(m));
+        return;
+      }
+    }
+    put(p, std::move(sp));
   }
   ~DevCache() {
     std::lock_guard<std::mutex> lk(mu);
-    drop_free_locked();
-    for (auto& kv : live) (void)hipFree(kv.first);
+    (void)hipDeviceSynchronize();
+    free_.clear();
+    by_size.clear();
+    live.clear();
+    for (auto& sl : slabs) (void)hipFree(sl->base);
+    slabs.clear();
   }
 };
 
